@@ -1,0 +1,307 @@
+"""Benchmark of the MDF-LBM hot path on one MI355X.
+
+Workload (the configuration the metric is quoted on): lid-driven cavity
+1024 x 1024, D2Q5 with three distribution sets (ubar_0, u, v), FP32
+storage, Re = 1000, lid speed 0.1, halfway anti-bounce-back walls; every
+step emits the vorticity and the strain rate from the first moments of the
+non-equilibrium populations; every 100 steps the FP64 K-interval residual
+is evaluated inside the last step of the chunk and read back (the loop of a
+steady solve).  A step is one pass of all of that over the grid.
+
+Prints one JSON line: MLUPS (whole job), the roofline of the step kernel
+(algorithmic bytes per launch over the HIP-event-timed average launch
+duration, against 8 TB/s) and the FP64 CPU oracle timed on a bounded sample
+of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("mdf_kernels.hip", "mdf_internal.h"):
+        with open(os.path.join(ROOT, "paper_2108_08591_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_key, launches_bytes):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    ent = data.get(kernel_key)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(spec, target_s=15.0):
+    """The FP64 oracle as it stands, timed on a bounded sample of the same
+    cavity (full 1024^2 grid, a few steps)."""
+    import numpy as np
+    from oracle import oracle as O
+
+    case = O.Case(spec.lattice, spec.shape, spec.s1, bc=spec.bc, wall_u=spec.wall_velocity())
+    o = O.Oracle(case)
+    o.init(0.0, np.zeros((2,) + spec.fshape))
+    t0 = time.perf_counter()
+    o.run(2)
+    dt = (time.perf_counter() - t0) / 2
+    steps = max(2, int(target_s / max(dt, 1e-3)))
+    t0 = time.perf_counter()
+    o.run(steps)
+    o.fields()   # the fields the GPU emits every step, evaluated once here
+    el = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": round(spec.nodes * steps / el / 1e6, 3),
+        "unit": "MLUPS",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"FP64 oracle, same 1024^2 cavity, {steps} steps (collide+stream per step, fields once)",
+        "seconds": round(el, 2),
+    }
+
+
+def copy_calibration():
+    """A plain device-to-device copy of known size (256 MiB read + 256 MiB
+    written per launch, beyond the Infinity Cache), run under the HBM traffic
+    counters to calibrate them."""
+    import torch
+    n = 64 * 1024 * 1024
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(10):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(20):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / 20
+    print(json.dumps({"copy_bytes_per_launch": 2 * 4 * n, "copy_ms": round(ms, 4),
+                      "copy_GBps": round(2 * 4 * n / (ms / 1e3) / 1e9, 1)}), flush=True)
+
+
+def _short_kernel_name(name):
+    base = name[5:] if name.startswith("void ") else name
+    base = base.replace("(anonymous namespace)::", "").replace("mdf::", "")
+    return base.split("(")[0]
+
+
+def summarize_trace(db_path, command):
+    """Markdown summary of a rocprofv3 --kernel-trace --stats database."""
+    import sqlite3
+    cur = sqlite3.connect(db_path).cursor()
+    rows = list(cur.execute("select name, total_calls, total_duration, average, percentage "
+                            "from top_kernels order by total_duration desc"))
+    out = ["# rocprofv3 kernel trace", "", "Command (run from the repository root on the GPU box):", "",
+           "```", command, "```", "",
+           "| kernel | calls | total (us) | average (us) | % |", "|---|---|---|---|---|"]
+    for name, calls, tot, avg, pct in rows:
+        out.append(f"| `{_short_kernel_name(name)}` | {calls} | {tot:.1f} | {avg:.3f} | {pct:.2f} |")
+    return "\n".join(out) + "\n"
+
+
+def counter_means(db_path, counter):
+    import sqlite3
+    import statistics
+    cur = sqlite3.connect(db_path).cursor()
+    acc = {}
+    for name, val in cur.execute("select kernel_name, value from counters_collection where counter_name=?",
+                                 (counter,)):
+        acc.setdefault(_short_kernel_name(name), []).append(val)
+    return {k: (len(v), statistics.mean(v)) for k, v in acc.items()}
+
+
+def summarize_traffic(fetch_db, write_db, copy_fetch_db, copy_write_db, kernel_prefix, alg_bytes,
+                      kernel_key, commands):
+    """Calibrated HBM bytes per launch of one kernel from FETCH_SIZE and
+    WRITE_SIZE runs (KiB per dispatch), each scaled by what the same counter
+    reads for a plain copy of known size."""
+    f = counter_means(fetch_db, "FETCH_SIZE")
+    w = counter_means(write_db, "WRITE_SIZE")
+    cf = counter_means(copy_fetch_db, "FETCH_SIZE")
+    cw = counter_means(copy_write_db, "WRITE_SIZE")
+    copy_kib = 256 * 1024
+    ck = [k for k in cf if "copyBuffer" in k][0]
+    fetch_scale = copy_kib / cf[ck][1]
+    write_scale = copy_kib / cw[ck][1]
+    kf = [k for k in f if k.startswith(kernel_prefix)][0]
+    kw = [k for k in w if k.startswith(kernel_prefix)][0]
+    fetch_b = f[kf][1] * 1024 * fetch_scale
+    write_b = w[kw][1] * 1024 * write_scale
+    total = fetch_b + write_b
+    md = ["# HBM traffic of `" + kernel_prefix + "`", "", "Commands (repository root, GPU box):", "", "```"]
+    md += commands + ["```", "",
+                      f"* copy calibration (256 MiB read + 256 MiB written per launch): FETCH_SIZE reads "
+                      f"{cf[ck][1]:.1f} KiB (scale {fetch_scale:.4f}), WRITE_SIZE reads {cw[ck][1]:.1f} KiB "
+                      f"(scale {write_scale:.4f})",
+                      f"* kernel: FETCH_SIZE {f[kf][1]:.1f} KiB over {f[kf][0]} dispatches, WRITE_SIZE "
+                      f"{w[kw][1]:.1f} KiB over {w[kw][0]} dispatches",
+                      f"* calibrated bytes per launch: read {fetch_b / 1e6:.2f} MB + write {write_b / 1e6:.2f} MB "
+                      f"= {total / 1e6:.2f} MB; algorithmic {alg_bytes / 1e6:.2f} MB "
+                      f"(ratio {total / alg_bytes:.3f})", ""]
+    ent = {"bytes_per_launch": round(total), "read_bytes": round(fetch_b), "write_bytes": round(write_b),
+           "algorithmic_bytes": alg_bytes, "fetch_scale": fetch_scale, "write_scale": write_scale,
+           "source_hash": kernel_source_hash()}
+    return "\n".join(md) + "\n", {kernel_key: ent}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--launch", default="64x4", help="threads per block, BXxBY")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain copy of known size (traffic-counter calibration)")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("DB", "OUT_MD"),
+                    help="write a markdown summary of a rocprofv3 kernel-trace database")
+    ap.add_argument("--summarize-traffic", nargs=5,
+                    metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB", "OUT_MD"),
+                    help="calibrated HBM traffic of the step kernel from rocprofv3 counter databases")
+    ap.add_argument("--command", default="", help="command recorded in a summary")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.summarize_trace:
+        with open(args.summarize_trace[1], "w") as fh:
+            fh.write(summarize_trace(args.summarize_trace[0], args.command))
+        return
+    if args.summarize_traffic:
+        fdb, wdb, cfdb, cwdb, out_md = args.summarize_traffic
+        nodes = 1024 * 1024
+        md, ent = summarize_traffic(fdb, wdb, cfdb, cwdb, "k_step<LatD2Q5, 1, true, false, false>", nodes * (2 * 15 * 4 + 4 * 4),
+                                    "k_step<D2Q5,F32,emit>_cavity1024", args.command.split(" ;; "))
+        with open(out_md, "w") as fh:
+            fh.write(md)
+        path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+        data = json.load(open(path)) if os.path.exists(path) else {}
+        data.update(ent)
+        with open(path, "w") as fh:
+            json.dump(data, fh, indent=1)
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; the multi-GPU path is a design "
+                                   "(slab decomposition with halo exchange) and is not built",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2108_08591_amd import cases as C
+    from paper_2108_08591_amd import mdf
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    spec = C.cavity_case(N=1024, Re=1000.0, U=0.1)
+    fields = mdf.FIELD_VORT | mdf.FIELD_STRAIN
+    stream = torch.cuda.Stream(device=dev)
+    solver = mdf.Solver([spec], storage="f32", device=dev, stream=stream)
+    bx, by = (int(v) for v in args.launch.lower().split("x"))
+    solver.set_launch(bx, by)
+    out = solver.new_field_buffers(fields)
+    K = 100
+    nodes = spec.nodes
+
+    # warm-up (also the first residual snapshot)
+    solver.run_steady(1e-300, K, max(args.warmup, 1), fields, out)
+    torch.cuda.synchronize()
+
+    # timed region: whole job, inputs resident in HBM
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    status, steps_done, res = solver.run_steady(1e-300, K, args.steps, fields, out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    assert int(steps_done[0]) == args.steps and status[0] != 1, (status, steps_done, res)
+    elapsed = max(wall, gpu_ms / 1e3)
+    mlups = nodes * args.steps / elapsed / 1e6
+
+    # average launch duration of the step kernel: HIP events on the stream
+    # the kernel runs on, around batches of back-to-back launches (no other
+    # work in between)
+    nlaunch, reps = 500, 5
+    durs = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        solver.step_emit(nlaunch, fields, out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        durs.append(e0.elapsed_time(e1) / nlaunch)
+    durs.sort()
+    avg_ms = sum(durs) / len(durs)
+    bytes_per_node = 2 * 15 * 4 + 4 * 4          # populations read+write, 4 emitted FP32 fields
+    alg_bytes = nodes * bytes_per_node
+    achieved = alg_bytes / (avg_ms / 1e3) / 1e9
+    kernel_key = "k_step<D2Q5,F32,emit>_cavity1024"
+    traffic = measured_traffic(kernel_key, alg_bytes)
+
+    result = {
+        "metric": "MLUPS (lattice-node updates per second, millions)",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed * 1e3 / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "lid-driven cavity 1024x1024, D2Q5 x 3 sets, FP32 storage, Re=1000, lid 0.1, "
+                        "per-step vorticity+strain emission, FP64 residual every 100 steps",
+            "nodes": nodes, "Re": 1000, "lid_u": 0.1, "storage": "f32", "launch": f"{bx}x{by}",
+        },
+        "hbm_roofline_pct": round(100.0 * mlups * 1e6 * bytes_per_node / (HBM_PEAK_GBS * 1e9), 2),
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": kernel_key,
+            "bytes_per_launch": alg_bytes,
+            "avg_launch_ms": round(avg_ms, 5),
+            "launch_timing": f"HIP events around {reps} x {nlaunch} back-to-back launches",
+            "note": "working set 120 MiB + 16 MiB of emitted fields fits the 256 MB Infinity Cache",
+        },
+        "residual_after": float(res[0]),
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(spec)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

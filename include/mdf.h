@@ -1,0 +1,217 @@
+/*
+ * mdf.h -- C ABI of the MI355X (gfx950) library for the multiple-
+ * distribution-function MRT lattice Boltzmann method of Chai, Shi & Zhan,
+ * "Multiple-distribution-function lattice Boltzmann method for convection-
+ * diffusion-system based incompressible Navier-Stokes equations"
+ * (arXiv 2108.08591).
+ *
+ * The method treats the incompressible Navier-Stokes equations as d+1 coupled
+ * convection-diffusion equations (eq. 2-2) for ubar = (rho0, u_1..u_d) and
+ * advances one distribution set per equation with the evolution of Remark I
+ * (eq. 3-21):
+ *     f_{i,a}(x + c_i, t + 1) = f_{i,a} - sum_k L_{ik}(f_{k,a} - f^eq_{k,a}) + w_i Fbar_a
+ * on the D2Q5 (eq. d2q5) or D3Q7 (eq. d3q7) lattice, with L = M^{-1} S_d M
+ * (eq. 4-1..4-3), the linear equilibrium of eq. 2-4, the pressure of eq. 3-15
+ * and the local velocity gradient, divergence, strain rate, stress and
+ * vorticity of eq. 3-16..3-19.  Lattice units: dx = dt = c = 1.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every call returns an mdf_status; nothing is thrown across the ABI.
+ *   Arguments are validated on the host before any launch; a rejected call
+ *   launches nothing and leaves the context unchanged.  The message of the
+ *   last failure of a context is available from mdf_last_error().
+ * - Device memory is owned by the caller: the workspace, masks, initial
+ *   data and output buffers are device pointers the caller allocates (e.g.
+ *   torch tensors) and keeps alive until the stream has passed the call.
+ *   The library never allocates device memory; it owns only the host-side
+ *   context, released by mdf_destroy().
+ * - Work is enqueued on the HIP stream passed as `stream` (hipStream_t;
+ *   NULL = the null stream).  Only mdf_run_steady, mdf_check and
+ *   mdf_invariants wait for the device.
+ * - Compute dtype: FP64 for MDF_F64 storage, FP32 for every other storage.
+ *   All field inputs and outputs are in the compute dtype, contiguous,
+ *   channel-major: out[ch][z][y][x] with x fastest and no padding.
+ * - Time: mdf_init sets time 0; mdf_step(n) advances it by n.  Fields
+ *   reported "at time t" are computed from the pre-collision populations
+ *   f(x, t) (the state right after streaming into time t).
+ * - Calls that overlap on one context race; contexts are independent.
+ */
+#ifndef MDF_H
+#define MDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MDF_OK = 0,
+    MDF_EINVAL = -1,     /* invalid argument (nothing launched)            */
+    MDF_ENOMEM = -2,     /* workspace too small                            */
+    MDF_EDEVICE = -3,    /* HIP runtime error (latched in the context)     */
+    MDF_EUNSTABLE = -4,  /* non-finite values found at a check             */
+    MDF_ESTATE = -5      /* call not valid in the context's current state  */
+} mdf_status;
+
+typedef enum { MDF_D2Q5 = 0, MDF_D3Q7 = 1 } mdf_lattice;
+
+/* Storage of the populations.  MDF_F16DEV / MDF_BF16DEV keep
+ * (f - f_rest) / u_ref in 16 bits (round to nearest even on store), with
+ * f_rest_{i,0} = w_i rho0 and f_rest_{i,a>=1} = 0, and collide in FP32. */
+typedef enum { MDF_F64 = 0, MDF_F32 = 1, MDF_F16DEV = 2, MDF_BF16DEV = 3 } mdf_storage;
+
+typedef enum { MDF_PERIODIC = 0, MDF_WALL = 1 } mdf_bc;
+
+/* Field selection bits.  Channels are written in the order of the bits:
+ *   MOMENTS: ubar_0 .. ubar_d (eq. 2-7), then P (eq. 3-15)      d + 2
+ *   GRAD:    d u_a / d x_b at (a-1)*d + b (eq. 3-16)            d * d
+ *   DIV:     div u (eq. 3-16a)                                  1
+ *   STRAIN:  S (eq. 3-17), upper triangle row by row            d(d+1)/2
+ *            (xx, xy, yy) in 2D, (xx, xy, xz, yy, yz, zz) in 3D
+ *   STRESS:  sigma (eq. 3-17a), same order as STRAIN            d(d+1)/2
+ *   VORT:    omega = dv/dx - du/dy in 2D; curl u in 3D          1 or 3
+ *            (eq. 3-18 with eq. 3-19)                                    */
+#define MDF_FIELD_MOMENTS 0x01u
+#define MDF_FIELD_GRAD 0x02u
+#define MDF_FIELD_DIV 0x04u
+#define MDF_FIELD_STRAIN 0x08u
+#define MDF_FIELD_STRESS 0x10u
+#define MDF_FIELD_VORT 0x20u
+#define MDF_FIELD_ALL 0x3fu
+
+/* Initial state kinds for mdf_init (init_data[case] is a device pointer in
+ * the compute dtype, channel-major, unpadded):
+ *   REST:        P = 0, u = 0, ubar_0 = rho0; init_data ignored.
+ *   FIELDS:      [P][u_1]..[u_d]; f = f^eq (eq. 2-4).
+ *   FIELDS_GRAD: [P][u_1]..[u_d][grad u: d*d, (a-1)*d + b]; f = f^eq + f^ne
+ *                with f^ne_{i,a} = -(1/s1) w_i c_i . grad u_a, which is the
+ *                inverse of eq. 3-16 (the set a = 0 gets none).
+ *   POPULATIONS: f(x, 0) itself, [set a][direction i][z][y][x]. */
+typedef enum {
+    MDF_INIT_REST = 0,
+    MDF_INIT_FIELDS = 1,
+    MDF_INIT_FIELDS_GRAD = 2,
+    MDF_INIT_POPULATIONS = 3
+} mdf_init_kind;
+
+/* One case (lattice units).  Velocity directions are ordered
+ *   D2Q5: 0, +x, +y, -x, -y          (eq. d2q5)
+ *   D3Q7: 0, +x, -x, +y, -y, +z, -z  (eq. d3q7)                        */
+typedef struct {
+    int32_t nx, ny, nz;     /* nodes per axis; nz = 1 for D2Q5             */
+    double s0, s1, s2;      /* S_d = diag(s0, s1.., s2..) (eq. 4-3); 0 < s1 < 2;
+                               s2 <= 0 selects 8(2 - s1)/(8 - s1); the
+                               viscosity is nu = (1/s1 - 1/2) cs^2 (eq. 3-13a) */
+    int32_t bc[6];          /* faces -x,+x,-y,+y,-z,+z: MDF_PERIODIC or MDF_WALL;
+                               periodic faces come in pairs                */
+    double wall_u[6][3];    /* velocity of each wall face                  */
+    double force[3];        /* uniform body force F_a (eq. 2-1b, eq. 2-6)   */
+    double R;               /* uniform mass source R (eq. 2-1a); Fbar_0 = R */
+    double rho0;            /* constant density (eq. 2-2, eq. 3-17a); > 0  */
+    double u_ref;           /* 16-bit storage scale; <= 0 selects 1        */
+} mdf_case;
+
+typedef struct mdf_ctx mdf_ctx;
+
+/* Bytes of device workspace that mdf_init needs for these cases (0 if the
+ * arguments are invalid).  has_solid != 0 reserves room for obstacle masks. */
+size_t mdf_workspace_size(mdf_lattice lattice, mdf_storage storage, const mdf_case *cases,
+                          int32_t ncases, int32_t has_solid);
+
+/* Create a context over `ncases` independent cases and set time 0.
+ *   workspace/ws_bytes: caller-owned device memory of at least
+ *       mdf_workspace_size() bytes, 256-byte aligned, kept until mdf_destroy.
+ *   solid: NULL, or per case a device uint8 mask [z][y][x] (non-zero =
+ *       solid node) or NULL; links into solid nodes follow the halfway wall
+ *       rule with zero wall velocity.  Copied; need not outlive the call.
+ *   init_kind/init_data: see mdf_init_kind; init_data is NULL for REST or
+ *       holds one device pointer per case.  Read before the call returns on
+ *       the stream's timeline.
+ * The wall rule on a link from behind a wall face or from a solid node is
+ * the halfway anti-bounce-back of Section 4 (formula not printed there):
+ *   a >= 1: f_{i,a}(x, t+1) = -f*_{ibar,a}(x, t) + 2 w_i U_{w,a}
+ *   a = 0 : f_{i,0}(x, t+1) =  f*_{ibar,0}(x, t)
+ * Errors: MDF_EINVAL (bad lattice/storage/sizes/rates/bc pairing/pointers),
+ * MDF_ENOMEM (ws_bytes too small), MDF_EDEVICE. */
+mdf_status mdf_init(mdf_ctx **out, mdf_lattice lattice, mdf_storage storage,
+                    const mdf_case *cases, int32_t ncases, void *workspace, size_t ws_bytes,
+                    const uint8_t *const *solid, int32_t init_kind,
+                    const void *const *init_data, void *stream);
+
+/* Advance every case by nsteps time steps of eq. 3-21 (fused pull
+ * streaming, wall rule, moments, equilibrium, MRT collision and forcing). */
+mdf_status mdf_step(mdf_ctx *ctx, int32_t nsteps, void *stream);
+
+/* As mdf_step, and every step also writes the selected fields (MDF_FIELD_*)
+ * at the new time into out[case] (channel-major, compute dtype, overwritten
+ * each step: on return they hold the fields at the final time). */
+mdf_status mdf_step_emit(mdf_ctx *ctx, int32_t nsteps, uint32_t fields, void *const *out,
+                         void *stream);
+
+/* ubar_0 .. ubar_d and P at the current time (eq. 2-7, eq. 3-15) into `out`
+ * (d + 2 channels).  Bitwise equal to MDF_FIELD_MOMENTS of mdf_step_emit. */
+mdf_status mdf_moments(const mdf_ctx *ctx, int32_t case_id, void *out, void *stream);
+
+/* The fields selected by `fields` at the current time (eq. 3-16..3-19) into
+ * `out`.  Bitwise equal to the same selection from mdf_step_emit. */
+mdf_status mdf_gradients(const mdf_ctx *ctx, int32_t case_id, uint32_t fields, void *out,
+                         void *stream);
+
+/* Pre-collision populations f(x, t) at the current time into `out`,
+ * [set][direction][z][y][x], compute dtype. */
+mdf_status mdf_populations(const mdf_ctx *ctx, int32_t case_id, void *out, void *stream);
+
+/* Residual check, waits for the device.  Computes, per case, over fluid
+ * nodes and in FP64:
+ *   res[c] = |u(t) - u(t_prev)|_2 / ((t - t_prev) |u(t)|_2)
+ * against the velocity snapshot of the previous check (t_prev; +inf on the
+ * first check), then stores u(t) as the new snapshot.  Sets status[c] to 1
+ * when a non-finite value was seen.  res/status: host arrays of ncases, or
+ * NULL.  Returns MDF_EUNSTABLE if any case is non-finite. */
+mdf_status mdf_check(mdf_ctx *ctx, double *res, int32_t *status, void *stream);
+
+/* Run until every case reaches res < tol (the residual of mdf_check,
+ * evaluated every K steps inside the last step of each K-step chunk), goes
+ * non-finite, or max_steps steps were taken.  Waits for the device once per
+ * chunk.  fields/out: as mdf_step_emit (every step writes the selected
+ * fields), or 0/NULL.  case_status (host, ncases or NULL): 0 converged,
+ * 1 non-finite, 2 not converged.  steps_taken/final_res: host arrays of
+ * ncases or NULL.  Cases that converge stop advancing; the others continue.
+ * Returns MDF_EUNSTABLE if any case went non-finite. */
+mdf_status mdf_run_steady(mdf_ctx *ctx, double tol, int32_t K, int64_t max_steps,
+                          uint32_t fields, void *const *out, int32_t *case_status,
+                          int64_t *steps_taken, double *final_res, void *stream);
+
+/* Global sums over fluid nodes at the current time, in FP64, host output
+ * of d + 2 doubles: sum ubar_a for a = 0..d, then sum_{a>=1} J_{a,a} with
+ * J_{a,b} = sum_i c_{i,b} f_{i,a}.  Waits for the device. */
+mdf_status mdf_invariants(const mdf_ctx *ctx, int32_t case_id, double *out, void *stream);
+
+/* Threads per block of the step and read kernels: bx along x (a multiple
+ * of 32) and by along y, bx * by a multiple of 64 up to 256 (whole
+ * wavefronts).  Default 64 x 4.  MDF_EINVAL otherwise.  Any
+ * shape gives bitwise identical results except the FP64 sums of mdf_check,
+ * mdf_run_steady and mdf_invariants, whose summation order follows the
+ * blocks. */
+mdf_status mdf_set_launch(mdf_ctx *ctx, int32_t bx, int32_t by);
+
+/* Current time of a case (steps taken since mdf_init; cases stopped by
+ * mdf_run_steady stay at their stopping time).  -1 on a bad argument. */
+int64_t mdf_time(const mdf_ctx *ctx, int32_t case_id);
+
+/* Message of the last failed call on this context ("" if none).  Valid
+ * until the next call on the context.  ctx may be NULL (last failure of
+ * mdf_init / mdf_workspace_size on this thread). */
+const char *mdf_last_error(const mdf_ctx *ctx);
+
+/* Release the host-side context.  The workspace stays the caller's. */
+mdf_status mdf_destroy(mdf_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDF_H */

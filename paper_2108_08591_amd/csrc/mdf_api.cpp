@@ -1,0 +1,516 @@
+// mdf_api.cpp -- host side of the C ABI declared in include/mdf.h.
+//
+// Owns only the host context: argument validation, the workspace layout
+// (the caller's device memory), the ping-pong state of every case, kernel
+// launches on the caller's stream and the FP64 residual / invariant
+// read-back.  It never allocates device memory.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mdf.h"
+#include "mdf_internal.h"
+
+using mdf::CaseBufs;
+using mdf::KCase;
+using mdf::LaunchShape;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+int lat_d(int lattice) { return lattice == MDF_D2Q5 ? 2 : 3; }
+int lat_q(int lattice) { return lattice == MDF_D2Q5 ? 5 : 7; }
+double lat_cs2(int lattice) { return lattice == MDF_D2Q5 ? 1.0 / 3.0 : 1.0 / 4.0; }
+size_t storage_bytes(int storage)
+{
+    switch (storage) {
+    case MDF_F64: return 8;
+    case MDF_F32: return 4;
+    default: return 2;
+    }
+}
+size_t compute_bytes(int storage) { return storage == MDF_F64 ? 8 : 4; }
+
+// Row pitch: a whole number of 128-byte lines.
+int row_pitch(int nx, int storage)
+{
+    const int per_line = int(128 / storage_bytes(storage));
+    return (nx + per_line - 1) / per_line * per_line;
+}
+
+struct CaseLayout {
+    size_t pop[2], links, snap, partial, result;
+    int max_blocks;
+};
+
+// Blocks of the largest grid any allowed launch shape produces
+// (bx >= 32, bx * by >= 64): at most ceil(nx/32) * ny * nz.
+int max_blocks_of(const mdf_case &c) { return (c.nx + 31) / 32 * c.ny * c.nz; }
+
+bool validate_case(int lattice, const mdf_case &c, std::string &why)
+{
+    char buf[256];
+    const int d = lat_d(lattice);
+    if (c.nx < 1 || c.ny < 1 || c.nz < 1) { why = "grid sizes must be >= 1"; return false; }
+    if (d == 2 && c.nz != 1) { why = "D2Q5 needs nz = 1"; return false; }
+    const double nodes = double(c.nx) * c.ny * c.nz;
+    if (nodes * lat_q(lattice) * (d + 1) > 2.0e9) { why = "case too large (>2e9 populations)"; return false; }
+    if (!(c.s1 > 0.0 && c.s1 < 2.0)) {
+        snprintf(buf, sizeof buf, "s1 = %g outside (0, 2)", c.s1);
+        why = buf;
+        return false;
+    }
+    if (!(std::isfinite(c.s0) && c.s0 > 0.0 && c.s0 < 2.0)) { why = "s0 outside (0, 2)"; return false; }
+    const double s2 = c.s2 > 0.0 ? c.s2 : 8.0 * (2.0 - c.s1) / (8.0 - c.s1);
+    if (!(s2 > 0.0 && s2 < 2.0)) { why = "s2 outside (0, 2)"; return false; }
+    if (!(c.rho0 > 0.0) || !std::isfinite(c.rho0)) { why = "rho0 must be > 0"; return false; }
+    for (int f = 0; f < 6; ++f) {
+        if (c.bc[f] != MDF_PERIODIC && c.bc[f] != MDF_WALL) { why = "bc must be PERIODIC or WALL"; return false; }
+        for (int b = 0; b < 3; ++b)
+            if (!std::isfinite(c.wall_u[f][b])) { why = "non-finite wall velocity"; return false; }
+    }
+    for (int ax = 0; ax < 3; ++ax)
+        if ((c.bc[2 * ax] == MDF_PERIODIC) != (c.bc[2 * ax + 1] == MDF_PERIODIC)) {
+            why = "a periodic face must be paired with a periodic face";
+            return false;
+        }
+    if (d == 2 && (c.bc[4] != MDF_PERIODIC || c.bc[5] != MDF_PERIODIC)) {
+        why = "D2Q5 cases need periodic z faces";
+        return false;
+    }
+    for (int b = 0; b < 3; ++b)
+        if (!std::isfinite(c.force[b])) { why = "non-finite force"; return false; }
+    if (!std::isfinite(c.R)) { why = "non-finite R"; return false; }
+    return true;
+}
+
+size_t layout(int lattice, int storage, const mdf_case *cases, int ncases, bool has_solid,
+              std::vector<CaseLayout> *out)
+{
+    const int d = lat_d(lattice), q = lat_q(lattice);
+    size_t off = 0;
+    if (out) out->resize(ncases);
+    for (int k = 0; k < ncases; ++k) {
+        const mdf_case &c = cases[k];
+        CaseLayout L;
+        const size_t pitch = row_pitch(c.nx, storage);
+        const size_t plane = pitch * c.ny * c.nz;
+        const size_t popb = size_t(d + 1) * q * plane * storage_bytes(storage);
+        const size_t nodes = size_t(c.nx) * c.ny * c.nz;
+        for (int b = 0; b < 2; ++b) { L.pop[b] = off; off = align256(off + popb); }
+        L.links = off;
+        if (has_solid) off = align256(off + plane);
+        L.snap = off;
+        off = align256(off + size_t(d) * nodes * compute_bytes(storage));
+        L.max_blocks = max_blocks_of(c);
+        L.partial = off;
+        off = align256(off + size_t(L.max_blocks) * mdf::kNRed * sizeof(double));
+        L.result = off;
+        off = align256(off + mdf::kNRed * sizeof(double));
+        if (out) (*out)[k] = L;
+    }
+    return off;
+}
+
+}  // namespace
+
+struct mdf_ctx {
+    int lattice = 0, storage = 0, d = 2, q = 5, ncases = 0;
+    std::vector<KCase> kc;
+    std::vector<CaseBufs> bufs;
+    std::vector<int> cur;              // buffer holding f*(., t)
+    std::vector<int64_t> time;
+    std::vector<int64_t> snap_time;    // time of the velocity snapshot, -1 = none
+    LaunchShape shape{64, 4};
+    hipError_t latched = hipSuccess;
+    std::string err;
+    std::vector<double> host_red;
+};
+
+namespace {
+
+mdf_status fail(mdf_ctx *ctx, mdf_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    else g_last_error = buf;
+    return st;
+}
+
+mdf_status device_error(mdf_ctx *ctx, hipError_t e, const char *where)
+{
+    if (ctx) ctx->latched = e;
+    return fail(ctx, MDF_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool case_ok(const mdf_ctx *ctx, int32_t case_id) { return case_id >= 0 && case_id < ctx->ncases; }
+
+KCase make_kcase(int lattice, int storage, const mdf_case &c)
+{
+    KCase p;
+    std::memset(&p, 0, sizeof p);
+    p.nx = c.nx;
+    p.ny = c.ny;
+    p.nz = c.nz;
+    p.pitch = row_pitch(c.nx, storage);
+    p.dstride = (long long)p.pitch * c.ny * c.nz;
+    p.s0 = c.s0;
+    p.s1 = c.s1;
+    p.s2 = c.s2 > 0.0 ? c.s2 : 8.0 * (2.0 - c.s1) / (8.0 - c.s1);
+    p.rho0 = c.rho0;
+    p.R = c.R;
+    p.fbar[0] = c.R;
+    for (int b = 0; b < lat_d(lattice); ++b) p.fbar[b + 1] = c.force[b];
+    for (int f = 0; f < 6; ++f) {
+        p.bc[f] = c.bc[f];
+        for (int b = 0; b < 3; ++b) p.wallu[f][b] = c.wall_u[f][b];
+    }
+    const double scale = (storage == MDF_F16DEV || storage == MDF_BF16DEV) && c.u_ref > 0.0 ? c.u_ref : 1.0;
+    p.scale = float(scale);
+    p.inv_scale = float(1.0 / scale);
+    return p;
+}
+
+// Reduce the per-block partials of the last check/sums launch of case k and
+// copy the kNRed results to the host.
+mdf_status finalize_and_fetch(mdf_ctx *ctx, int k, int nblocks, hipStream_t st, double *out)
+{
+    hipError_t e = mdf::launch_finalize(ctx->bufs[k], nblocks, st);
+    if (e != hipSuccess) return device_error(ctx, e, "finalize launch");
+    e = hipMemcpyAsync(out, ctx->bufs[k].result, mdf::kNRed * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return device_error(ctx, e, "result copy");
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return device_error(ctx, e, "stream synchronize");
+    return MDF_OK;
+}
+
+mdf_status step_case(mdf_ctx *ctx, int k, bool check, uint32_t fields, void *out, hipStream_t st,
+                     int *nblocks)
+{
+    if (check && mdf::grid_blocks(ctx->kc[k], ctx->shape) > ctx->bufs[k].max_blocks)
+        return fail(ctx, MDF_EINVAL, "launch grid exceeds the reduction workspace");
+    hipError_t e = mdf::launch_step(ctx->lattice, ctx->storage, ctx->kc[k], ctx->bufs[k], ctx->cur[k], check,
+                                    fields, out, ctx->shape, nblocks, st);
+    if (e != hipSuccess) return device_error(ctx, e, "step launch");
+    ctx->cur[k] ^= 1;
+    ctx->time[k] += 1;
+    return MDF_OK;
+}
+
+// Residual of case k from the reduced slots and the snapshot bookkeeping.
+double residual_of(const mdf_ctx *ctx, int k, const double *red)
+{
+    const int64_t dt = ctx->time[k] - ctx->snap_time[k];
+    if (ctx->snap_time[k] < 0 || dt <= 0) return INFINITY;
+    const double den = std::sqrt(red[1]);
+    if (!(den > 0.0)) return red[0] > 0.0 ? INFINITY : 0.0;
+    return std::sqrt(red[0]) / (double(dt) * den);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mdf_workspace_size(mdf_lattice lattice, mdf_storage storage, const mdf_case *cases, int32_t ncases,
+                          int32_t has_solid)
+{
+    if ((lattice != MDF_D2Q5 && lattice != MDF_D3Q7) || storage < MDF_F64 || storage > MDF_BF16DEV ||
+        !cases || ncases < 1) {
+        fail(nullptr, MDF_EINVAL, "mdf_workspace_size: invalid lattice, storage or cases");
+        return 0;
+    }
+    std::string why;
+    for (int k = 0; k < ncases; ++k)
+        if (!validate_case(lattice, cases[k], why)) {
+            fail(nullptr, MDF_EINVAL, "mdf_workspace_size: case %d: %s", k, why.c_str());
+            return 0;
+        }
+    return layout(lattice, storage, cases, ncases, has_solid != 0, nullptr);
+}
+
+mdf_status mdf_init(mdf_ctx **out, mdf_lattice lattice, mdf_storage storage, const mdf_case *cases,
+                    int32_t ncases, void *workspace, size_t ws_bytes, const uint8_t *const *solid,
+                    int32_t init_kind, const void *const *init_data, void *stream)
+{
+    if (!out) return fail(nullptr, MDF_EINVAL, "mdf_init: out is NULL");
+    *out = nullptr;
+    if (lattice != MDF_D2Q5 && lattice != MDF_D3Q7) return fail(nullptr, MDF_EINVAL, "mdf_init: bad lattice");
+    if (storage < MDF_F64 || storage > MDF_BF16DEV) return fail(nullptr, MDF_EINVAL, "mdf_init: bad storage");
+    if (!cases || ncases < 1) return fail(nullptr, MDF_EINVAL, "mdf_init: no cases");
+    if (init_kind < MDF_INIT_REST || init_kind > MDF_INIT_POPULATIONS)
+        return fail(nullptr, MDF_EINVAL, "mdf_init: bad init_kind");
+    if (!workspace) return fail(nullptr, MDF_EINVAL, "mdf_init: workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return fail(nullptr, MDF_EINVAL, "mdf_init: workspace not 256-byte aligned");
+    std::string why;
+    for (int k = 0; k < ncases; ++k)
+        if (!validate_case(lattice, cases[k], why))
+            return fail(nullptr, MDF_EINVAL, "mdf_init: case %d: %s", k, why.c_str());
+    if (init_kind != MDF_INIT_REST) {
+        if (!init_data) return fail(nullptr, MDF_EINVAL, "mdf_init: init_data is NULL");
+        for (int k = 0; k < ncases; ++k)
+            if (!init_data[k]) return fail(nullptr, MDF_EINVAL, "mdf_init: init_data[%d] is NULL", k);
+    }
+    bool has_solid = false;
+    if (solid)
+        for (int k = 0; k < ncases; ++k) has_solid = has_solid || solid[k] != nullptr;
+    std::vector<CaseLayout> lay;
+    const size_t need = layout(lattice, storage, cases, ncases, has_solid, &lay);
+    if (ws_bytes < need)
+        return fail(nullptr, MDF_ENOMEM, "mdf_init: workspace of %zu bytes, %zu needed", ws_bytes, need);
+
+    mdf_ctx *ctx = new mdf_ctx;
+    ctx->lattice = lattice;
+    ctx->storage = storage;
+    ctx->d = lat_d(lattice);
+    ctx->q = lat_q(lattice);
+    ctx->ncases = ncases;
+    ctx->kc.resize(ncases);
+    ctx->bufs.resize(ncases);
+    ctx->cur.assign(ncases, 0);
+    ctx->time.assign(ncases, 0);
+    ctx->snap_time.assign(ncases, -1);
+    ctx->host_red.assign(mdf::kNRed, 0.0);
+    char *ws = static_cast<char *>(workspace);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (int k = 0; k < ncases; ++k) {
+        ctx->kc[k] = make_kcase(lattice, storage, cases[k]);
+        CaseBufs &b = ctx->bufs[k];
+        b.pop[0] = ws + lay[k].pop[0];
+        b.pop[1] = ws + lay[k].pop[1];
+        b.links = (solid && solid[k]) ? reinterpret_cast<uint8_t *>(ws + lay[k].links) : nullptr;
+        b.snap = ws + lay[k].snap;
+        b.partial = reinterpret_cast<double *>(ws + lay[k].partial);
+        b.result = reinterpret_cast<double *>(ws + lay[k].result);
+        b.max_blocks = lay[k].max_blocks;
+        hipError_t e;
+        if (b.links) {
+            e = mdf::launch_links(lattice, ctx->kc[k], solid[k], b.links, st);
+            if (e != hipSuccess) {
+                mdf_status s = device_error(nullptr, e, "mdf_init: links launch");
+                delete ctx;
+                return s;
+            }
+        }
+        e = mdf::launch_init(lattice, storage, ctx->kc[k], b, 0, init_kind,
+                             init_kind == MDF_INIT_REST ? nullptr : init_data[k], st);
+        if (e != hipSuccess) {
+            mdf_status s = device_error(nullptr, e, "mdf_init: init launch");
+            delete ctx;
+            return s;
+        }
+    }
+    *out = ctx;
+    return MDF_OK;
+}
+
+mdf_status mdf_set_launch(mdf_ctx *ctx, int32_t bx, int32_t by)
+{
+    if (!ctx) return fail(nullptr, MDF_EINVAL, "mdf_set_launch: ctx is NULL");
+    if (bx < 32 || bx % 32 != 0 || by < 1 || bx * by > 256 || (bx * by) % 64 != 0)
+        return fail(ctx, MDF_EINVAL,
+                    "mdf_set_launch: need bx %% 32 == 0 and bx*by a multiple of 64 up to 256 (got %d x %d)", bx, by);
+    ctx->shape = LaunchShape{bx, by};
+    return MDF_OK;
+}
+
+static mdf_status step_impl(mdf_ctx *ctx, int32_t nsteps, uint32_t fields, void *const *out, void *stream)
+{
+    if (!ctx) return fail(nullptr, MDF_EINVAL, "mdf_step: ctx is NULL");
+    if (ctx->latched != hipSuccess) return fail(ctx, MDF_EDEVICE, "earlier device error: %s",
+                                                hipGetErrorString(ctx->latched));
+    if (nsteps < 0) return fail(ctx, MDF_EINVAL, "mdf_step: nsteps < 0");
+    if (fields & ~MDF_FIELD_ALL) return fail(ctx, MDF_EINVAL, "mdf_step_emit: unknown field bits");
+    if (fields) {
+        if (!out) return fail(ctx, MDF_EINVAL, "mdf_step_emit: out is NULL");
+        for (int k = 0; k < ctx->ncases; ++k)
+            if (!out[k]) return fail(ctx, MDF_EINVAL, "mdf_step_emit: out[%d] is NULL", k);
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (int s = 0; s < nsteps; ++s)
+        for (int k = 0; k < ctx->ncases; ++k) {
+            mdf_status r = step_case(ctx, k, false, fields, fields ? out[k] : nullptr, st, nullptr);
+            if (r != MDF_OK) return r;
+        }
+    return MDF_OK;
+}
+
+mdf_status mdf_step(mdf_ctx *ctx, int32_t nsteps, void *stream) { return step_impl(ctx, nsteps, 0, nullptr, stream); }
+
+mdf_status mdf_step_emit(mdf_ctx *ctx, int32_t nsteps, uint32_t fields, void *const *out, void *stream)
+{
+    if (fields == 0) return fail(ctx, MDF_EINVAL, "mdf_step_emit: no fields selected");
+    return step_impl(ctx, nsteps, fields, out, stream);
+}
+
+static mdf_status read_impl(const mdf_ctx *cctx, int32_t case_id, int mode, uint32_t fields, void *out,
+                            void *stream, int *nblocks)
+{
+    mdf_ctx *ctx = const_cast<mdf_ctx *>(cctx);
+    if (!ctx) return fail(nullptr, MDF_EINVAL, "read: ctx is NULL");
+    if (ctx->latched != hipSuccess) return fail(ctx, MDF_EDEVICE, "earlier device error: %s",
+                                                hipGetErrorString(ctx->latched));
+    if (!case_ok(ctx, case_id)) return fail(ctx, MDF_EINVAL, "case_id %d out of range", case_id);
+    if ((mode == mdf::kReadFields || mode == mdf::kReadPops) && !out)
+        return fail(ctx, MDF_EINVAL, "out is NULL");
+    if (mode == mdf::kReadFields && (fields == 0 || (fields & ~MDF_FIELD_ALL)))
+        return fail(ctx, MDF_EINVAL, "bad field selection 0x%x", fields);
+    const int k = case_id;
+    if ((mode == mdf::kReadCheck || mode == mdf::kReadSums) &&
+        mdf::grid_blocks(ctx->kc[k], ctx->shape) > ctx->bufs[k].max_blocks)
+        return fail(ctx, MDF_EINVAL, "launch grid exceeds the reduction workspace");
+    const bool pull = ctx->time[k] > 0;
+    hipError_t e = mdf::launch_read(ctx->lattice, ctx->storage, ctx->kc[k], ctx->bufs[k], ctx->cur[k] ^ 1, pull,
+                                    mode, fields, out, ctx->shape, nblocks, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return device_error(ctx, e, "read launch");
+    return MDF_OK;
+}
+
+mdf_status mdf_moments(const mdf_ctx *ctx, int32_t case_id, void *out, void *stream)
+{
+    return read_impl(ctx, case_id, mdf::kReadFields, MDF_FIELD_MOMENTS, out, stream, nullptr);
+}
+
+mdf_status mdf_gradients(const mdf_ctx *ctx, int32_t case_id, uint32_t fields, void *out, void *stream)
+{
+    return read_impl(ctx, case_id, mdf::kReadFields, fields, out, stream, nullptr);
+}
+
+mdf_status mdf_populations(const mdf_ctx *ctx, int32_t case_id, void *out, void *stream)
+{
+    return read_impl(ctx, case_id, mdf::kReadPops, 0, out, stream, nullptr);
+}
+
+mdf_status mdf_check(mdf_ctx *ctx, double *res, int32_t *status, void *stream)
+{
+    if (!ctx) return fail(nullptr, MDF_EINVAL, "mdf_check: ctx is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    bool unstable = false;
+    for (int k = 0; k < ctx->ncases; ++k) {
+        int nb = 0;
+        mdf_status r = read_impl(ctx, k, mdf::kReadCheck, 0, nullptr, stream, &nb);
+        if (r != MDF_OK) return r;
+        r = finalize_and_fetch(ctx, k, nb, st, ctx->host_red.data());
+        if (r != MDF_OK) return r;
+        const double rr = residual_of(ctx, k, ctx->host_red.data());
+        ctx->snap_time[k] = ctx->time[k];
+        const bool bad = ctx->host_red[7] != 0.0 || !std::isfinite(ctx->host_red[1]);
+        unstable = unstable || bad;
+        if (res) res[k] = rr;
+        if (status) status[k] = bad ? 1 : 0;
+    }
+    if (unstable) return fail(ctx, MDF_EUNSTABLE, "mdf_check: non-finite values");
+    return MDF_OK;
+}
+
+mdf_status mdf_run_steady(mdf_ctx *ctx, double tol, int32_t K, int64_t max_steps, uint32_t fields,
+                          void *const *out, int32_t *case_status, int64_t *steps_taken, double *final_res,
+                          void *stream)
+{
+    if (!ctx) return fail(nullptr, MDF_EINVAL, "mdf_run_steady: ctx is NULL");
+    if (!(tol > 0.0) || K < 1 || max_steps < 0) return fail(ctx, MDF_EINVAL, "mdf_run_steady: bad tol/K/max_steps");
+    if (fields & ~MDF_FIELD_ALL) return fail(ctx, MDF_EINVAL, "mdf_run_steady: unknown field bits");
+    if (fields) {
+        if (!out) return fail(ctx, MDF_EINVAL, "mdf_run_steady: out is NULL");
+        for (int k = 0; k < ctx->ncases; ++k)
+            if (!out[k]) return fail(ctx, MDF_EINVAL, "mdf_run_steady: out[%d] is NULL", k);
+    }
+    if (ctx->latched != hipSuccess) return fail(ctx, MDF_EDEVICE, "earlier device error: %s",
+                                                hipGetErrorString(ctx->latched));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int n = ctx->ncases;
+    std::vector<int> state(n, 2);              // 0 converged, 1 non-finite, 2 running
+    std::vector<double> res(n, INFINITY);
+    std::vector<int64_t> start(ctx->time.begin(), ctx->time.end());
+    // first snapshot
+    for (int k = 0; k < n; ++k) {
+        if (ctx->snap_time[k] >= 0 && ctx->snap_time[k] == ctx->time[k]) continue;
+        int nb = 0;
+        mdf_status r = read_impl(ctx, k, mdf::kReadCheck, 0, nullptr, stream, &nb);
+        if (r != MDF_OK) return r;
+        r = finalize_and_fetch(ctx, k, nb, st, ctx->host_red.data());
+        if (r != MDF_OK) return r;
+        ctx->snap_time[k] = ctx->time[k];
+        if (ctx->host_red[7] != 0.0) state[k] = 1;
+    }
+    bool any_running = true;
+    while (any_running) {
+        any_running = false;
+        for (int k = 0; k < n; ++k) {
+            if (state[k] != 2) continue;
+            const int64_t done = ctx->time[k] - start[k];
+            if (done >= max_steps) continue;
+            const int64_t chunk = std::min<int64_t>(K, max_steps - done);
+            int nb = 0;
+            for (int64_t s = 0; s < chunk; ++s) {
+                mdf_status r = step_case(ctx, k, s == chunk - 1, fields, fields ? out[k] : nullptr, st, &nb);
+                if (r != MDF_OK) return r;
+            }
+            mdf_status r = finalize_and_fetch(ctx, k, nb, st, ctx->host_red.data());
+            if (r != MDF_OK) return r;
+            res[k] = residual_of(ctx, k, ctx->host_red.data());
+            ctx->snap_time[k] = ctx->time[k];
+            if (ctx->host_red[7] != 0.0 || !std::isfinite(ctx->host_red[1])) state[k] = 1;
+            else if (res[k] < tol) state[k] = 0;
+            else any_running = any_running || (ctx->time[k] - start[k] < max_steps);
+        }
+    }
+    bool unstable = false;
+    for (int k = 0; k < n; ++k) {
+        if (case_status) case_status[k] = state[k];
+        if (steps_taken) steps_taken[k] = ctx->time[k] - start[k];
+        if (final_res) final_res[k] = res[k];
+        unstable = unstable || state[k] == 1;
+    }
+    if (unstable) return fail(ctx, MDF_EUNSTABLE, "mdf_run_steady: non-finite values");
+    return MDF_OK;
+}
+
+mdf_status mdf_invariants(const mdf_ctx *cctx, int32_t case_id, double *out, void *stream)
+{
+    mdf_ctx *ctx = const_cast<mdf_ctx *>(cctx);
+    if (!ctx) return fail(nullptr, MDF_EINVAL, "mdf_invariants: ctx is NULL");
+    if (!out) return fail(ctx, MDF_EINVAL, "mdf_invariants: out is NULL");
+    int nb = 0;
+    mdf_status r = read_impl(ctx, case_id, mdf::kReadSums, 0, nullptr, stream, &nb);
+    if (r != MDF_OK) return r;
+    double red[mdf::kNRed];
+    r = finalize_and_fetch(ctx, case_id, nb, static_cast<hipStream_t>(stream), red);
+    if (r != MDF_OK) return r;
+    for (int a = 0; a <= ctx->d; ++a) out[a] = red[2 + a];
+    out[ctx->d + 1] = red[6];
+    if (red[7] != 0.0) return fail(ctx, MDF_EUNSTABLE, "mdf_invariants: non-finite values");
+    return MDF_OK;
+}
+
+int64_t mdf_time(const mdf_ctx *ctx, int32_t case_id)
+{
+    if (!ctx || !case_ok(ctx, case_id)) return -1;
+    return ctx->time[case_id];
+}
+
+const char *mdf_last_error(const mdf_ctx *ctx)
+{
+    if (!ctx) return g_last_error.c_str();
+    return ctx->err.c_str();
+}
+
+mdf_status mdf_destroy(mdf_ctx *ctx)
+{
+    delete ctx;
+    return MDF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,64 @@
+// mdf_internal.h -- declarations shared by the host API (mdf_api.cpp) and the
+// HIP kernels (mdf_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "mdf.h"
+
+namespace mdf {
+
+// Number of FP64 reduction slots per check:
+//   0: sum |u - u_snap|^2   1: sum |u|^2   2..5: sum ubar_a (a = 0..d)
+//   6: sum_{a>=1} J_aa      7: count of nodes with a non-finite moment
+constexpr int kNRed = 8;
+
+// Per-case parameters as the kernels see them (passed by value).
+struct KCase {
+    int nx, ny, nz;
+    int pitch;              // row stride of the population planes, elements
+    long long dstride;      // elements per (set, direction) plane = nz*ny*pitch
+    double s0, s1, s2;
+    double rho0;
+    double R;
+    double fbar[4];         // Fbar_a, a = 0..d  (Fbar_0 = R, Fbar_a = F_a)
+    double wallu[6][3];
+    int bc[6];
+    float scale, inv_scale; // 16-bit deviation storage: f = rest + scale * stored
+};
+
+// Device pointers of one case inside the workspace.
+struct CaseBufs {
+    void *pop[2];           // ping-pong population buffers (storage dtype)
+    uint8_t *links;         // bit 7: solid node; bit i: upstream of direction i is solid
+    void *snap;             // d * nodes velocity snapshot (compute dtype)
+    double *partial;        // per-block reduction slots (kNRed each)
+    double *result;         // kNRed reduced values
+    int max_blocks;         // capacity of `partial`, in blocks
+};
+
+struct LaunchShape {
+    int bx, by;             // threads per block along x and y (bx * by <= 256)
+};
+
+enum ReadMode { kReadFields = 0, kReadPops = 1, kReadCheck = 2, kReadSums = 3 };
+
+// Launchers (implemented in mdf_kernels.hip).  All enqueue on `stream` and
+// return the hipError_t of the launch.
+hipError_t launch_links(int lattice, const KCase &p, const uint8_t *solid, uint8_t *links,
+                        hipStream_t stream);
+hipError_t launch_init(int lattice, int storage, const KCase &p, const CaseBufs &b, int cur,
+                       int kind, const void *data, hipStream_t stream);
+hipError_t launch_step(int lattice, int storage, const KCase &p, const CaseBufs &b, int src,
+                       bool check, uint32_t fields, void *out, LaunchShape shape,
+                       int *nblocks_out, hipStream_t stream);
+hipError_t launch_read(int lattice, int storage, const KCase &p, const CaseBufs &b, int src,
+                       bool pull, int mode, uint32_t fields, void *out, LaunchShape shape,
+                       int *nblocks_out, hipStream_t stream);
+hipError_t launch_finalize(const CaseBufs &b, int nblocks, hipStream_t stream);
+
+int grid_blocks(const KCase &p, LaunchShape shape);
+
+}  // namespace mdf

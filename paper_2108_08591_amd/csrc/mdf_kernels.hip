@@ -1,0 +1,822 @@
+// mdf_kernels.hip -- gfx950 kernels of the MDF-LBM hot path.
+//
+// Method (Chai, Shi & Zhan, arXiv 2108.08591): d+1 distribution sets a = 0..d,
+// one per convection-diffusion equation of eq. 2-2 (ubar_0 = rho0, ubar_a = u_a),
+// advanced by the diffusive-scaling evolution of Remark I (eq. 3-21)
+//     f_{i,a}(x + c_i, t + 1) = f_{i,a} - sum_k L_{ik} (f_{k,a} - f^eq_{k,a}) + w_i Fbar_a.
+//
+// Data layout in HBM (structure of arrays): one plane per (set a, direction i),
+//     pop[(a*Q + i) * dstride + (z*ny + y) * pitch + x],
+// x fastest, rows padded so that a row is a whole number of 128-byte lines.
+// Two such buffers ping-pong: buffer `src` holds the post-collision state
+// f*(., t) of every node, a step pulls f_{i,a}(x, t+1) = f*_{i,a}(x - c_i, t)
+// (so every lane's loads of one plane are consecutive addresses), collides it
+// at the node and writes f*(x, t+1) to `dst` at the same node.  One thread
+// owns one node; the kernel reads and writes each population exactly once,
+// so it is bound by HBM bandwidth (2 Q (d+1) s bytes per node and step).
+//
+// Collision: the paper's matrix L = M^{-1} S_d M (eq. 4-1..4-3) is applied in
+// its exact projection form.  M has mutually orthogonal rows; S_d gives s0 to
+// the conserved row e, s1 to the d velocity rows (odd under c -> -c) and s2
+// to every remaining row (even), so
+//     L n = s1 P_odd n + s2 P_even n + (s0 - s2) (e.n / Q) e,
+// with (P_odd n)_i = (n_i - n_ibar)/2, (P_even n)_i = (n_i + n_ibar)/2 for
+// i != 0, (P_odd n)_0 = 0, (P_even n)_0 = n_0.  For n = f - f^eq the last
+// term vanishes (e.n = 0, eq. 3-8); see collide_set().
+//
+// Walls: a link whose upstream node lies behind a wall face or in a solid
+// node takes the halfway wall rule (Section 4 names an anti-bounce-back rule
+// without printing it; read as)
+//     a >= 1: f_{i,a}(x, t+1) = -f*_{ibar,a}(x, t) + 2 w_i U_{w,a}
+//     a = 0 : f_{i,0}(x, t+1) =  f*_{ibar,0}(x, t).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mdf_internal.h"
+
+namespace mdf {
+namespace {
+
+// ----------------------------------------------------------------- lattices
+
+// D2Q5 (eq. d2q5) with w_0 = 1/3 as used in Section 4.
+struct LatD2Q5 {
+    static constexpr int D = 2, Q = 5, NS = 3;
+    static constexpr int cx[5] = {0, 1, 0, -1, 0};
+    static constexpr int cy[5] = {0, 0, 1, 0, -1};
+    static constexpr int cz[5] = {0, 0, 0, 0, 0};
+    static constexpr int opp[5] = {0, 3, 4, 1, 2};
+    static constexpr double w0 = 1.0 / 3.0, w1 = 1.0 / 6.0;
+    static constexpr double cs2 = 1.0 / 3.0, inv_cs2 = 3.0;
+};
+
+// D3Q7 (eq. d3q7).
+struct LatD3Q7 {
+    static constexpr int D = 3, Q = 7, NS = 4;
+    static constexpr int cx[7] = {0, 1, -1, 0, 0, 0, 0};
+    static constexpr int cy[7] = {0, 0, 0, 1, -1, 0, 0};
+    static constexpr int cz[7] = {0, 0, 0, 0, 0, 1, -1};
+    static constexpr int opp[7] = {0, 2, 1, 4, 3, 6, 5};
+    static constexpr double w0 = 1.0 / 4.0, w1 = 1.0 / 8.0;
+    static constexpr double cs2 = 1.0 / 4.0, inv_cs2 = 4.0;
+};
+
+template <class L>
+__device__ __forceinline__ constexpr int cdir(int i, int b)
+{
+    return b == 0 ? L::cx[i] : (b == 1 ? L::cy[i] : L::cz[i]);
+}
+
+// ----------------------------------------------------------------- storage
+
+// Storage codes follow mdf_storage.
+template <int ST> struct Store;
+
+template <> struct Store<MDF_F64> {
+    using T = double;
+    using C = double;
+    static __device__ __forceinline__ C load(const T *p, long long k, C, float) { return p[k]; }
+    static __device__ __forceinline__ void store(T *p, long long k, C v, C, float) { p[k] = v; }
+};
+
+template <> struct Store<MDF_F32> {
+    using T = float;
+    using C = float;
+    static __device__ __forceinline__ C load(const T *p, long long k, C, float) { return p[k]; }
+    static __device__ __forceinline__ void store(T *p, long long k, C v, C, float) { p[k] = v; }
+};
+
+// 16-bit deviation storage: stored = (f - rest) / scale, round to nearest even.
+template <> struct Store<MDF_F16DEV> {
+    using T = _Float16;
+    using C = float;
+    static __device__ __forceinline__ C load(const T *p, long long k, C rest, float scale)
+    {
+        return rest + scale * static_cast<float>(p[k]);
+    }
+    static __device__ __forceinline__ void store(T *p, long long k, C v, C rest, float inv_scale)
+    {
+        p[k] = static_cast<_Float16>((v - rest) * inv_scale);
+    }
+};
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float v)
+{
+    uint32_t u = __float_as_uint(v);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <> struct Store<MDF_BF16DEV> {
+    using T = uint16_t;
+    using C = float;
+    static __device__ __forceinline__ C load(const T *p, long long k, C rest, float scale)
+    {
+        return rest + scale * __uint_as_float(((uint32_t)p[k]) << 16);
+    }
+    static __device__ __forceinline__ void store(T *p, long long k, C v, C rest, float inv_scale)
+    {
+        p[k] = f32_to_bf16_rne((v - rest) * inv_scale);
+    }
+};
+
+// rest state of a population: w_i rho0 for the set a = 0, zero otherwise
+// (pressure gauge P = 0).
+template <class L, class C>
+__device__ __forceinline__ C rest_value(const KCase &p, int a, int i)
+{
+    if (a != 0) return C(0);
+    return C((i == 0 ? L::w0 : L::w1) * p.rho0);
+}
+
+// ----------------------------------------------------------------- node state
+
+template <class L, class C>
+struct Node {
+    C f[L::NS][L::Q];       // pre-collision populations f(x, t)
+};
+
+template <class L, class C>
+struct Moments {
+    C ubar[L::NS];          // eq. 2-7
+    C u[L::D];
+    C P;                    // eq. 3-15
+    C trJ;                  // sum_{a>=1} J_{a,a}
+};
+
+// Pull the populations of node (x, y, z) at time t+1 out of the
+// post-collision planes of time t (or, with PULL = false, read the node's
+// own stored pre-collision values).  Returns false for a solid node.
+template <class L, int ST, bool MASK, bool PULL>
+__device__ __forceinline__ bool gather(const KCase &p, const typename Store<ST>::T *__restrict__ src,
+                                       const uint8_t *__restrict__ links, int x, int y, int z,
+                                       Node<L, typename Store<ST>::C> &n)
+{
+    using S = Store<ST>;
+    using C = typename S::C;
+    const long long own = ((long long)z * p.ny + y) * p.pitch + x;
+    unsigned lb = 0;
+    if (MASK) {
+        lb = links[own];
+        if (lb & 0x80u) return false;
+    }
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        int sx = x - L::cx[i], sy = y - L::cy[i], sz = z - L::cz[i];
+        int face = -1;
+        if (PULL) {
+            if (L::cx[i] != 0) {
+                if (sx < 0) { if (p.bc[0] == MDF_WALL) face = 0; else sx += p.nx; }
+                else if (sx >= p.nx) { if (p.bc[1] == MDF_WALL) face = 1; else sx -= p.nx; }
+            }
+            if (L::cy[i] != 0) {
+                if (sy < 0) { if (p.bc[2] == MDF_WALL) face = 2; else sy += p.ny; }
+                else if (sy >= p.ny) { if (p.bc[3] == MDF_WALL) face = 3; else sy -= p.ny; }
+            }
+            if (L::cz[i] != 0) {
+                if (sz < 0) { if (p.bc[4] == MDF_WALL) face = 4; else sz += p.nz; }
+                else if (sz >= p.nz) { if (p.bc[5] == MDF_WALL) face = 5; else sz -= p.nz; }
+            }
+            if (MASK && face < 0 && ((lb >> i) & 1u)) face = 6;
+        } else {
+            sx = x; sy = y; sz = z;
+        }
+        const C w = C(i == 0 ? L::w0 : L::w1);
+        if (face < 0) {
+            const long long k = ((long long)sz * p.ny + sy) * p.pitch + sx;
+#pragma unroll
+            for (int a = 0; a < L::NS; ++a)
+                n.f[a][i] = S::load(src + (long long)(a * L::Q + i) * p.dstride, k,
+                                    rest_value<L, C>(p, a, i), p.scale);
+        } else {
+            const int j = L::opp[i];
+#pragma unroll
+            for (int a = 0; a < L::NS; ++a) {
+                C v = S::load(src + (long long)(a * L::Q + j) * p.dstride, own,
+                              rest_value<L, C>(p, a, j), p.scale);
+                if (a == 0) {
+                    n.f[a][i] = v;
+                } else {
+                    C uw = (face < 6) ? C(p.wallu[face][a - 1]) : C(0);
+                    n.f[a][i] = -v + C(2) * w * uw;
+                }
+            }
+        }
+    }
+    return true;
+}
+
+// eq. 2-7 and eq. 3-15.
+template <class L, class C>
+__device__ __forceinline__ void moments(const KCase &p, const Node<L, C> &n, Moments<L, C> &m)
+{
+#pragma unroll
+    for (int a = 0; a < L::NS; ++a) {
+        C s = n.f[a][0];
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) s += n.f[a][i];
+        m.ubar[a] = s;
+    }
+#pragma unroll
+    for (int b = 0; b < L::D; ++b) m.u[b] = m.ubar[b + 1];
+    C trJ = C(0), u2 = C(0);
+#pragma unroll
+    for (int a = 1; a < L::NS; ++a) {
+        C j = C(0);
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) {
+            if (cdir<L>(i, a - 1) > 0) j += n.f[a][i];
+            else if (cdir<L>(i, a - 1) < 0) j -= n.f[a][i];
+        }
+        trJ += j;
+        u2 += m.u[a - 1] * m.u[a - 1];
+    }
+    m.trJ = trJ;
+    m.P = (trJ + C(L::cs2) * C(p.R) / C(p.s1) - u2) * C(1.0 / L::D);
+}
+
+// Equilibrium of one set (eq. 2-4), f^eq_i = w_i [ubar + c_i . flux / cs^2]
+// with flux = ubar u + P E_a, evaluated in a form that is exact in any
+// precision where the weights are not: on both lattices w_i / cs^2 = 1/2
+// for i != 0, and the rest weight is taken as w_0 = 1 - sum_{i>0} w_i, so
+// f^eq_0 = ubar - sum_{i>0} w_i ubar.  (With w_0 = 1/3 and w_1 = 1/6 rounded
+// to FP32, sum_i w_i differs from 1 by ~3e-8, and the zeroth moment would
+// drift by that fraction every step.)
+template <class L, class C>
+__device__ __forceinline__ void equilibrium(C ub, const C (&flux)[L::D], C (&feq)[L::Q])
+{
+    const C even = C(L::w1) * ub;
+    C rest = ub;
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+        C cf = C(0);
+#pragma unroll
+        for (int b = 0; b < L::D; ++b) {
+            if (cdir<L>(i, b) > 0) cf += flux[b];
+            else if (cdir<L>(i, b) < 0) cf -= flux[b];
+        }
+        feq[i] = even + C(L::w1 * L::inv_cs2) * cf;
+        rest -= even;
+    }
+    feq[0] = rest;
+}
+
+// Non-equilibrium part n_{i,a} = f_{i,a} - f^eq_{i,a} of one set.
+template <class L, class C>
+__device__ __forceinline__ void nonequilibrium(const Node<L, C> &n, const Moments<L, C> &m, int a,
+                                               C (&ne)[L::Q])
+{
+    const C ub = m.ubar[a];
+    C flux[L::D];
+#pragma unroll
+    for (int b = 0; b < L::D; ++b) flux[b] = ub * m.u[b] + ((a >= 1 && b == a - 1) ? m.P : C(0));
+    C feq[L::Q];
+    equilibrium<L, C>(ub, flux, feq);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) ne[i] = n.f[a][i] - feq[i];
+}
+
+// Post-collision populations of one set (right-hand side of eq. 3-21).
+// The s0 part of L n multiplies sum_i n_i, which vanishes identically
+// (eq. 3-8); the moving populations take s1 on the odd and s2 on the even part
+// of n.  Each population is advanced by a small increment d_i computed first,
+// f*_i = f_i + d_i, and the rest population takes d_0 = Fbar - sum_{i>0} d_i,
+// which is the zeroth-moment identity sum_i f*_i = ubar + Fbar (eq. 3-9 with
+// eq. 3-7c).  In exact arithmetic this is the matrix product; in FP32 every
+// stored value is rounded once, and the zeroth moment is conserved up to
+// unbiased rounding (forming s0 sum_i n_i, or subtracting large partial sums,
+// rounds the same way every step and drifts by ~1e-5 in a few thousand).
+template <class L, class C>
+__device__ __forceinline__ void collide_set(const KCase &p, const Node<L, C> &n, int a,
+                                            const C (&ne)[L::Q], C (&out)[L::Q])
+{
+    const C s1 = C(p.s1), s2 = C(p.s2);
+    const C fb = C(p.fbar[a]);
+    const C wf = C(L::w1) * fb;
+    C dsum = C(0);
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+        const int j = L::opp[i];
+        const C odd = C(0.5) * (ne[i] - ne[j]);
+        const C even = C(0.5) * (ne[i] + ne[j]);
+        const C d = (-s1 * odd - s2 * even) + wf;
+        out[i] = n.f[a][i] + d;
+        dsum += d;
+    }
+    out[0] = n.f[a][0] + (fb - dsum);
+}
+
+// Derived fields of eq. 3-16..3-19 written channel-major for the selection
+// `fields` (order of the MDF_FIELD_* bits).
+template <class L, class C>
+__device__ __forceinline__ void write_fields(const KCase &p, const Node<L, C> &n,
+                                             const Moments<L, C> &m, uint32_t fields, C *__restrict__ out,
+                                             long long node, long long nodes)
+{
+    constexpr int D = L::D;
+    // first moment of the non-equilibrium part, mne[a][b] = sum_i c_{i,b} n_{i,a}
+    C mne[D][D];
+#pragma unroll
+    for (int a = 1; a < L::NS; ++a) {
+        C ne[L::Q];
+        nonequilibrium<L, C>(n, m, a, ne);
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            C s = C(0);
+#pragma unroll
+            for (int i = 1; i < L::Q; ++i) {
+                if (cdir<L>(i, b) > 0) s += ne[i];
+                else if (cdir<L>(i, b) < 0) s -= ne[i];
+            }
+            mne[a - 1][b] = s;
+        }
+    }
+    const C gscale = -C(p.s1) * C(L::inv_cs2);           // eq. 3-16
+    C G[D][D];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) G[a][b] = gscale * mne[a][b];
+    long long ch = 0;
+    if (fields & MDF_FIELD_MOMENTS) {
+#pragma unroll
+        for (int a = 0; a < L::NS; ++a) out[(ch++) * nodes + node] = m.ubar[a];
+        out[(ch++) * nodes + node] = m.P;
+    }
+    if (fields & MDF_FIELD_GRAD) {
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = 0; b < D; ++b) out[(ch++) * nodes + node] = G[a][b];
+    }
+    if (fields & MDF_FIELD_DIV) {
+        C dv = G[0][0];
+#pragma unroll
+        for (int a = 1; a < D; ++a) dv += G[a][a];
+        out[(ch++) * nodes + node] = dv;                  // eq. 3-16a
+    }
+    if (fields & MDF_FIELD_STRAIN) {
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = a; b < D; ++b)
+                out[(ch++) * nodes + node] = C(0.5) * (G[a][b] + G[b][a]);   // eq. 3-17
+    }
+    if (fields & MDF_FIELD_STRESS) {
+        const C sc = -C(p.rho0) * (C(1) - C(0.5) * C(p.s1));                // eq. 3-17a
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = a; b < D; ++b) out[(ch++) * nodes + node] = sc * (mne[a][b] + mne[b][a]);
+    }
+    if (fields & MDF_FIELD_VORT) {
+        // omega = curl u; Omega_ab = (G_ab - G_ba)/2 (eq. 3-18) and
+        // Omega_ab = -eps_abg omega_g / 2 (eq. 3-19)
+        if (D == 2) {
+            out[(ch++) * nodes + node] = G[1][0] - G[0][1];
+        } else {
+            out[(ch++) * nodes + node] = G[2 % D][1 % D] - G[1 % D][2 % D];
+            out[(ch++) * nodes + node] = G[0][2 % D] - G[2 % D][0];
+            out[(ch++) * nodes + node] = G[1 % D][0] - G[0][1 % D];
+        }
+    }
+}
+
+// ----------------------------------------------------------------- reductions
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Fixed-order block reduction of kNRed doubles into partial[block].
+__device__ __forceinline__ void block_reduce_store(double (&v)[kNRed], double *__restrict__ partial)
+{
+    __shared__ double red[kNRed][16];
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int nwaves = (blockDim.x * blockDim.y + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < kNRed; ++k) {
+        double s = wave_sum(v[k]);
+        if (lane == 0) red[k][wave] = s;
+    }
+    __syncthreads();
+    if (tid < kNRed) {
+        double s = 0.0;
+        for (int w = 0; w < nwaves; ++w) s += red[tid][w];
+        const long long blk = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
+        partial[blk * kNRed + tid] = s;
+    }
+}
+
+template <class L, class C, bool SNAP>
+__device__ __forceinline__ void check_values(const Moments<L, C> &m, bool valid, C *__restrict__ snap,
+                                             long long node, long long nodes, double (&v)[kNRed])
+{
+#pragma unroll
+    for (int k = 0; k < kNRed; ++k) v[k] = 0.0;
+    if (!valid) return;
+    bool finite = isfinite((double)m.P) && isfinite((double)m.trJ);
+#pragma unroll
+    for (int b = 0; b < L::D; ++b) {
+        const double u = (double)m.u[b];
+        v[1] += u * u;
+        if (SNAP) {
+            const double du = u - (double)snap[b * nodes + node];
+            v[0] += du * du;
+            snap[b * nodes + node] = m.u[b];
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < L::NS; ++a) {
+        v[2 + a] = (double)m.ubar[a];
+        finite = finite && isfinite((double)m.ubar[a]);
+    }
+    v[6] = (double)m.trJ;
+    v[7] = finite ? 0.0 : 1.0;
+}
+
+// ----------------------------------------------------------------- kernels
+
+// One time step: pull, wall rule, moments, optional fields and check,
+// collision + forcing, write.
+template <class L, int ST, bool EMIT, bool CHECK, bool MASK>
+__global__ void __launch_bounds__(256)
+k_step(KCase p, const typename Store<ST>::T *__restrict__ src, typename Store<ST>::T *__restrict__ dst,
+       const uint8_t *__restrict__ links, uint32_t fields, typename Store<ST>::C *__restrict__ out,
+       typename Store<ST>::C *__restrict__ snap, double *__restrict__ partial)
+{
+    using S = Store<ST>;
+    using C = typename S::C;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    const bool inside = (x < p.nx) && (y < p.ny);
+    Node<L, C> n;
+    Moments<L, C> m;
+    bool fluid = false;
+    if (inside) fluid = gather<L, ST, MASK, true>(p, src, links, x, y, z, n);
+    const long long nodes = (long long)p.nx * p.ny * p.nz;
+    const long long node = ((long long)z * p.ny + y) * p.nx + x;
+    if (fluid) {
+        moments<L, C>(p, n, m);
+        if (EMIT) write_fields<L, C>(p, n, m, fields, out, node, nodes);
+        const long long own = ((long long)z * p.ny + y) * p.pitch + x;
+#pragma unroll
+        for (int a = 0; a < L::NS; ++a) {
+            C ne[L::Q], fo[L::Q];
+            nonequilibrium<L, C>(n, m, a, ne);
+            collide_set<L, C>(p, n, a, ne, fo);
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i)
+                S::store(dst + (long long)(a * L::Q + i) * p.dstride, own, fo[i],
+                         rest_value<L, C>(p, a, i), p.inv_scale);
+        }
+    } else if (EMIT && inside) {
+        // solid node: every emitted channel is zero
+        int nch = 0;
+        if (fields & MDF_FIELD_MOMENTS) nch += L::NS + 1;
+        if (fields & MDF_FIELD_GRAD) nch += L::D * L::D;
+        if (fields & MDF_FIELD_DIV) nch += 1;
+        if (fields & MDF_FIELD_STRAIN) nch += L::D * (L::D + 1) / 2;
+        if (fields & MDF_FIELD_STRESS) nch += L::D * (L::D + 1) / 2;
+        if (fields & MDF_FIELD_VORT) nch += (L::D == 2 ? 1 : 3);
+        for (int ch = 0; ch < nch; ++ch) out[ch * nodes + node] = C(0);
+    }
+    if (CHECK) {
+        double v[kNRed];
+        check_values<L, C, true>(m, fluid, snap, node, nodes, v);
+        block_reduce_store(v, partial);
+    }
+}
+
+// Read-only pass at the current time: fields, populations or a check.
+template <class L, int ST, bool MASK, bool PULL, int MODE>
+__global__ void __launch_bounds__(256)
+k_read(KCase p, const typename Store<ST>::T *__restrict__ src, const uint8_t *__restrict__ links,
+       uint32_t fields, typename Store<ST>::C *__restrict__ out, typename Store<ST>::C *__restrict__ snap,
+       double *__restrict__ partial)
+{
+    using S = Store<ST>;
+    using C = typename S::C;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    const bool inside = (x < p.nx) && (y < p.ny);
+    Node<L, C> n;
+    Moments<L, C> m;
+    bool fluid = false;
+    if (inside) fluid = gather<L, ST, MASK, PULL>(p, src, links, x, y, z, n);
+    const long long nodes = (long long)p.nx * p.ny * p.nz;
+    const long long node = ((long long)z * p.ny + y) * p.nx + x;
+    if (fluid) moments<L, C>(p, n, m);
+    if (MODE == kReadFields && inside) {
+        if (fluid) {
+            write_fields<L, C>(p, n, m, fields, out, node, nodes);
+        } else {
+            int nch = 0;
+            if (fields & MDF_FIELD_MOMENTS) nch += L::NS + 1;
+            if (fields & MDF_FIELD_GRAD) nch += L::D * L::D;
+            if (fields & MDF_FIELD_DIV) nch += 1;
+            if (fields & MDF_FIELD_STRAIN) nch += L::D * (L::D + 1) / 2;
+            if (fields & MDF_FIELD_STRESS) nch += L::D * (L::D + 1) / 2;
+            if (fields & MDF_FIELD_VORT) nch += (L::D == 2 ? 1 : 3);
+            for (int ch = 0; ch < nch; ++ch) out[ch * nodes + node] = C(0);
+        }
+    }
+    if (MODE == kReadPops && inside) {
+#pragma unroll
+        for (int a = 0; a < L::NS; ++a)
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i)
+                out[(long long)(a * L::Q + i) * nodes + node] = fluid ? n.f[a][i] : C(0);
+    }
+    if (MODE == kReadCheck || MODE == kReadSums) {
+        double v[kNRed];
+        check_values<L, C, MODE == kReadCheck>(m, fluid, snap, node, nodes, v);
+        block_reduce_store(v, partial);
+    }
+}
+
+// Initial state: f(x, 0) from fields (eq. 2-4, plus the inverse of eq. 3-16
+// when a gradient is given) or from given populations.  Writes f(x, 0) into
+// buffer `pre` (unshifted, read back locally at time 0) and the
+// post-collision state f*(x, 0) into buffer `post`.
+template <class L, int ST, bool MASK>
+__global__ void __launch_bounds__(256)
+k_init(KCase p, typename Store<ST>::T *__restrict__ pre, typename Store<ST>::T *__restrict__ post,
+       const uint8_t *__restrict__ links, int kind, const typename Store<ST>::C *__restrict__ data)
+{
+    using S = Store<ST>;
+    using C = typename S::C;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= p.nx || y >= p.ny) return;
+    const long long own = ((long long)z * p.ny + y) * p.pitch + x;
+    const long long nodes = (long long)p.nx * p.ny * p.nz;
+    const long long node = ((long long)z * p.ny + y) * p.nx + x;
+    if (MASK && (links[own] & 0x80u)) {
+        for (int a = 0; a < L::NS; ++a)
+            for (int i = 0; i < L::Q; ++i) {
+                const long long k = (long long)(a * L::Q + i) * p.dstride + own;
+                S::store(pre, k, rest_value<L, C>(p, a, i), rest_value<L, C>(p, a, i), p.inv_scale);
+                S::store(post, k, rest_value<L, C>(p, a, i), rest_value<L, C>(p, a, i), p.inv_scale);
+            }
+        return;
+    }
+    Node<L, C> n;
+    if (kind == MDF_INIT_POPULATIONS) {
+#pragma unroll
+        for (int a = 0; a < L::NS; ++a)
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) n.f[a][i] = data[(long long)(a * L::Q + i) * nodes + node];
+    } else {
+        C P = C(0), u[L::D];
+#pragma unroll
+        for (int b = 0; b < L::D; ++b) u[b] = C(0);
+        if (kind != MDF_INIT_REST) {
+            P = data[node];
+#pragma unroll
+            for (int b = 0; b < L::D; ++b) u[b] = data[(1 + b) * nodes + node];
+        }
+#pragma unroll
+        for (int a = 0; a < L::NS; ++a) {
+            const C ub = (a == 0) ? C(p.rho0) : u[a - 1];
+            C flux[L::D], feq[L::Q];
+#pragma unroll
+            for (int b = 0; b < L::D; ++b) flux[b] = ub * u[b] + ((a >= 1 && b == a - 1) ? P : C(0));
+            equilibrium<L, C>(ub, flux, feq);
+            n.f[a][0] = feq[0];
+#pragma unroll
+            for (int i = 1; i < L::Q; ++i) {
+                C cg = C(0);
+#pragma unroll
+                for (int b = 0; b < L::D; ++b) {
+                    C g = C(0);
+                    if (kind == MDF_INIT_FIELDS_GRAD && a >= 1)
+                        g = data[(1 + L::D + (a - 1) * L::D + b) * nodes + node];
+                    if (cdir<L>(i, b) > 0) cg += g;
+                    else if (cdir<L>(i, b) < 0) cg -= g;
+                }
+                // f^eq (eq. 2-4) + f^ne with f^ne = -(1/s1) w_i c_i . grad u_a
+                n.f[a][i] = feq[i] - (C(1) / C(p.s1)) * C(L::w1) * cg;
+            }
+        }
+    }
+    Moments<L, C> m;
+    moments<L, C>(p, n, m);
+#pragma unroll
+    for (int a = 0; a < L::NS; ++a) {
+        C ne[L::Q], fo[L::Q];
+        nonequilibrium<L, C>(n, m, a, ne);
+        collide_set<L, C>(p, n, a, ne, fo);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const long long k = (long long)(a * L::Q + i) * p.dstride + own;
+            S::store(pre, k, n.f[a][i], rest_value<L, C>(p, a, i), p.inv_scale);
+            S::store(post, k, fo[i], rest_value<L, C>(p, a, i), p.inv_scale);
+        }
+    }
+}
+
+// Solid flags and upstream-solid link bits of every node.
+template <class L>
+__global__ void __launch_bounds__(256) k_links(KCase p, const uint8_t *__restrict__ solid, uint8_t *__restrict__ links)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= p.nx || y >= p.ny) return;
+    const long long node = ((long long)z * p.ny + y) * p.nx + x;
+    unsigned bits = solid[node] ? 0x80u : 0u;
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+        int s[3] = {x - L::cx[i], y - L::cy[i], z - L::cz[i]};
+        const int nn[3] = {p.nx, p.ny, p.nz};
+        bool outside = false;
+        for (int b = 0; b < 3; ++b) {
+            if (s[b] < 0) { if (p.bc[2 * b] == MDF_WALL) outside = true; else s[b] += nn[b]; }
+            else if (s[b] >= nn[b]) { if (p.bc[2 * b + 1] == MDF_WALL) outside = true; else s[b] -= nn[b]; }
+        }
+        if (!outside && solid[((long long)s[2] * p.ny + s[1]) * p.nx + s[0]]) bits |= (1u << i);
+    }
+    links[((long long)z * p.ny + y) * p.pitch + x] = (uint8_t)bits;
+}
+
+// Fixed-order sum of the per-block partials.
+__global__ void __launch_bounds__(256) k_finalize(const double *__restrict__ partial, int nblocks, double *__restrict__ result)
+{
+    __shared__ double red[kNRed][256];
+    const int t = threadIdx.x;
+    double acc[kNRed];
+#pragma unroll
+    for (int k = 0; k < kNRed; ++k) acc[k] = 0.0;
+    for (int b = t; b < nblocks; b += 256)
+#pragma unroll
+        for (int k = 0; k < kNRed; ++k) acc[k] += partial[(long long)b * kNRed + k];
+#pragma unroll
+    for (int k = 0; k < kNRed; ++k) red[k][t] = acc[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s)
+#pragma unroll
+            for (int k = 0; k < kNRed; ++k) red[k][t] += red[k][t + s];
+        __syncthreads();
+    }
+    if (t < kNRed) result[t] = red[t][0];
+}
+
+// ----------------------------------------------------------------- dispatch
+
+dim3 grid_of(const KCase &p, LaunchShape s)
+{
+    return dim3((p.nx + s.bx - 1) / s.bx, (p.ny + s.by - 1) / s.by, p.nz);
+}
+
+template <class L, int ST>
+hipError_t step_dispatch(const KCase &p, const CaseBufs &b, int src, bool check, uint32_t fields,
+                         void *out, LaunchShape s, hipStream_t stream)
+{
+    using S = Store<ST>;
+    using T = typename S::T;
+    using C = typename S::C;
+    const T *in = static_cast<const T *>(b.pop[src]);
+    T *o = static_cast<T *>(b.pop[src ^ 1]);
+    C *emit = static_cast<C *>(out);
+    C *snap = static_cast<C *>(b.snap);
+    const dim3 grid = grid_of(p, s), block(s.bx, s.by, 1);
+    const bool emit_on = (fields != 0) && out != nullptr;
+    const bool mask = b.links != nullptr;
+#define MDF_STEP_LAUNCH(E, K, M) \
+    hipLaunchKernelGGL((k_step<L, ST, E, K, M>), grid, block, 0, stream, p, in, o, b.links, fields, emit, snap, b.partial)
+    if (mask) {
+        if (emit_on) { if (check) MDF_STEP_LAUNCH(true, true, true); else MDF_STEP_LAUNCH(true, false, true); }
+        else { if (check) MDF_STEP_LAUNCH(false, true, true); else MDF_STEP_LAUNCH(false, false, true); }
+    } else {
+        if (emit_on) { if (check) MDF_STEP_LAUNCH(true, true, false); else MDF_STEP_LAUNCH(true, false, false); }
+        else { if (check) MDF_STEP_LAUNCH(false, true, false); else MDF_STEP_LAUNCH(false, false, false); }
+    }
+#undef MDF_STEP_LAUNCH
+    return hipGetLastError();
+}
+
+template <class L, int ST>
+hipError_t read_dispatch(const KCase &p, const CaseBufs &b, int src, bool pull, int mode, uint32_t fields,
+                         void *out, LaunchShape s, hipStream_t stream)
+{
+    using S = Store<ST>;
+    using T = typename S::T;
+    using C = typename S::C;
+    const T *in = static_cast<const T *>(b.pop[src]);
+    C *o = static_cast<C *>(out);
+    C *snap = static_cast<C *>(b.snap);
+    const dim3 grid = grid_of(p, s), block(s.bx, s.by, 1);
+    const bool mask = b.links != nullptr;
+#define MDF_READ_LAUNCH(M, PL, MD) \
+    hipLaunchKernelGGL((k_read<L, ST, M, PL, MD>), grid, block, 0, stream, p, in, b.links, fields, o, snap, b.partial)
+#define MDF_READ_MODE(M, PL)                                              \
+    do {                                                                  \
+        if (mode == kReadFields) MDF_READ_LAUNCH(M, PL, kReadFields);     \
+        else if (mode == kReadPops) MDF_READ_LAUNCH(M, PL, kReadPops);    \
+        else if (mode == kReadCheck) MDF_READ_LAUNCH(M, PL, kReadCheck);  \
+        else MDF_READ_LAUNCH(M, PL, kReadSums);                           \
+    } while (0)
+    if (mask) { if (pull) MDF_READ_MODE(true, true); else MDF_READ_MODE(true, false); }
+    else { if (pull) MDF_READ_MODE(false, true); else MDF_READ_MODE(false, false); }
+#undef MDF_READ_MODE
+#undef MDF_READ_LAUNCH
+    return hipGetLastError();
+}
+
+template <class L, int ST>
+hipError_t init_dispatch(const KCase &p, const CaseBufs &b, int cur, int kind, const void *data,
+                         hipStream_t stream)
+{
+    using S = Store<ST>;
+    using T = typename S::T;
+    using C = typename S::C;
+    T *post = static_cast<T *>(b.pop[cur]);
+    T *pre = static_cast<T *>(b.pop[cur ^ 1]);
+    const LaunchShape s{64, 4};
+    const dim3 grid = grid_of(p, s), block(s.bx, s.by, 1);
+    if (b.links)
+        hipLaunchKernelGGL((k_init<L, ST, true>), grid, block, 0, stream, p, pre, post, b.links, kind,
+                           static_cast<const C *>(data));
+    else
+        hipLaunchKernelGGL((k_init<L, ST, false>), grid, block, 0, stream, p, pre, post, b.links, kind,
+                           static_cast<const C *>(data));
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int grid_blocks(const KCase &p, LaunchShape s)
+{
+    const dim3 g = grid_of(p, s);
+    return (int)(g.x * g.y * g.z);
+}
+
+#define MDF_DISPATCH(lattice, storage, FN, ...)                                              \
+    do {                                                                                     \
+        if (lattice == MDF_D2Q5) {                                                           \
+            switch (storage) {                                                               \
+            case MDF_F64: return FN<LatD2Q5, MDF_F64>(__VA_ARGS__);                          \
+            case MDF_F32: return FN<LatD2Q5, MDF_F32>(__VA_ARGS__);                          \
+            case MDF_F16DEV: return FN<LatD2Q5, MDF_F16DEV>(__VA_ARGS__);                    \
+            case MDF_BF16DEV: return FN<LatD2Q5, MDF_BF16DEV>(__VA_ARGS__);                  \
+            }                                                                                \
+        } else {                                                                             \
+            switch (storage) {                                                               \
+            case MDF_F64: return FN<LatD3Q7, MDF_F64>(__VA_ARGS__);                          \
+            case MDF_F32: return FN<LatD3Q7, MDF_F32>(__VA_ARGS__);                          \
+            case MDF_F16DEV: return FN<LatD3Q7, MDF_F16DEV>(__VA_ARGS__);                    \
+            case MDF_BF16DEV: return FN<LatD3Q7, MDF_BF16DEV>(__VA_ARGS__);                  \
+            }                                                                                \
+        }                                                                                    \
+        return hipErrorInvalidValue;                                                         \
+    } while (0)
+
+hipError_t launch_step(int lattice, int storage, const KCase &p, const CaseBufs &b, int src, bool check,
+                       uint32_t fields, void *out, LaunchShape shape, int *nblocks_out, hipStream_t stream)
+{
+    if (nblocks_out) *nblocks_out = grid_blocks(p, shape);
+    MDF_DISPATCH(lattice, storage, step_dispatch, p, b, src, check, fields, out, shape, stream);
+}
+
+hipError_t launch_read(int lattice, int storage, const KCase &p, const CaseBufs &b, int src, bool pull,
+                       int mode, uint32_t fields, void *out, LaunchShape shape, int *nblocks_out,
+                       hipStream_t stream)
+{
+    if (nblocks_out) *nblocks_out = grid_blocks(p, shape);
+    MDF_DISPATCH(lattice, storage, read_dispatch, p, b, src, pull, mode, fields, out, shape, stream);
+}
+
+hipError_t launch_init(int lattice, int storage, const KCase &p, const CaseBufs &b, int cur, int kind,
+                       const void *data, hipStream_t stream)
+{
+    MDF_DISPATCH(lattice, storage, init_dispatch, p, b, cur, kind, data, stream);
+}
+
+hipError_t launch_links(int lattice, const KCase &p, const uint8_t *solid, uint8_t *links, hipStream_t stream)
+{
+    const LaunchShape s{64, 4};
+    const dim3 grid = grid_of(p, s), block(s.bx, s.by, 1);
+    if (lattice == MDF_D2Q5)
+        hipLaunchKernelGGL((k_links<LatD2Q5>), grid, block, 0, stream, p, solid, links);
+    else
+        hipLaunchKernelGGL((k_links<LatD3Q7>), grid, block, 0, stream, p, solid, links);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const CaseBufs &b, int nblocks, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, stream, b.partial, nblocks, b.result);
+    return hipGetLastError();
+}
+
+}  // namespace mdf

@@ -1,0 +1,105 @@
+"""Host-side checks of the C ABI (no GPU needed, no compute calls).
+
+The library loads, exports every function include/mdf.h declares, and the
+host validation rejects bad arguments before anything is launched.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2108_08591_amd import cases as C
+from paper_2108_08591_amd import mdf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "mdf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mdf_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = mdf.lib()
+    declared = _declared_functions()
+    assert "mdf_init" in declared and "mdf_step" in declared
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(mdf.EXPORTED) == declared
+
+
+def _ws(spec, storage=mdf.F32, solid=0):
+    c = (mdf.MdfCase * 1)(mdf._case_struct(spec))
+    return mdf.lib().mdf_workspace_size(spec.lattice, storage, c, 1, solid)
+
+
+def test_workspace_size_scales_with_storage_and_grid():
+    spec = C.cavity_case(N=128, Re=100)
+    w64, w32, w16 = _ws(spec, mdf.F64), _ws(spec, mdf.F32), _ws(spec, mdf.F16DEV)
+    assert w64 > w32 > w16 > 0
+    # two population buffers dominate: 2 * 15 * 128^2 * bytes
+    assert w32 >= 2 * 15 * 128 * 128 * 4
+    assert _ws(spec, mdf.F32, solid=1) > w32
+    big = C.cavity_case(N=256, Re=100)
+    assert _ws(big) > 3.5 * w32
+
+
+@pytest.mark.parametrize("mutate,msg", [
+    (lambda s: setattr(s, "s1", 2.0), "s1"),
+    (lambda s: setattr(s, "s1", 0.0), "s1"),
+    (lambda s: setattr(s, "bc", (0, 1, 0, 0, 0, 0)), "periodic"),
+    (lambda s: setattr(s, "shape", (0, 8)), "grid"),
+    (lambda s: setattr(s, "rho0", -1.0), "rho0"),
+])
+def test_invalid_cases_are_rejected(mutate, msg):
+    spec = C.cavity_case(N=16, Re=10)
+    mutate(spec)
+    assert _ws(spec) == 0
+    err = mdf.lib().mdf_last_error(None).decode()
+    assert msg in err
+
+
+def test_init_rejects_before_touching_the_device():
+    L = mdf.lib()
+    spec = C.cavity_case(N=16, Re=10)
+    cases = (mdf.MdfCase * 1)(mdf._case_struct(spec))
+    ctx = ctypes.c_void_p()
+    # NULL workspace
+    st = L.mdf_init(ctypes.byref(ctx), mdf.D2Q5, mdf.F32, cases, 1, None, 0, None, 0, None, None)
+    assert st == mdf.EINVAL and not ctx.value
+    # misaligned workspace
+    st = L.mdf_init(ctypes.byref(ctx), mdf.D2Q5, mdf.F32, cases, 1, ctypes.c_void_p(16), 1 << 30,
+                    None, 0, None, None)
+    assert st == mdf.EINVAL and "aligned" in L.mdf_last_error(None).decode()
+    # workspace too small
+    st = L.mdf_init(ctypes.byref(ctx), mdf.D2Q5, mdf.F32, cases, 1, ctypes.c_void_p(256), 1024,
+                    None, 0, None, None)
+    assert st == mdf.ENOMEM
+    # bad lattice / storage / init kind
+    assert L.mdf_init(ctypes.byref(ctx), 7, mdf.F32, cases, 1, ctypes.c_void_p(256), 1 << 30,
+                      None, 0, None, None) == mdf.EINVAL
+    assert L.mdf_init(ctypes.byref(ctx), mdf.D2Q5, 9, cases, 1, ctypes.c_void_p(256), 1 << 30,
+                      None, 0, None, None) == mdf.EINVAL
+    assert L.mdf_init(ctypes.byref(ctx), mdf.D2Q5, mdf.F32, cases, 1, ctypes.c_void_p(256), 1 << 30,
+                      None, 1, None, None) == mdf.EINVAL
+    # D2Q5 case with nz != 1
+    bad = (mdf.MdfCase * 1)(mdf._case_struct(spec))
+    bad[0].nz = 2
+    assert L.mdf_init(ctypes.byref(ctx), mdf.D2Q5, mdf.F32, bad, 1, ctypes.c_void_p(256), 1 << 30,
+                      None, 0, None, None) == mdf.EINVAL
+
+
+def test_null_context_calls_fail_cleanly():
+    L = mdf.lib()
+    assert L.mdf_step(None, 1, None) == mdf.EINVAL
+    assert L.mdf_set_launch(None, 64, 4) == mdf.EINVAL
+    assert L.mdf_time(None, 0) == -1
+    assert L.mdf_destroy(None) == mdf.OK
+
+
+def test_field_layout_channel_counts():
+    assert mdf.n_channels(2, mdf.FIELD_ALL) == 4 + 4 + 1 + 3 + 3 + 1
+    assert mdf.n_channels(3, mdf.FIELD_ALL) == 5 + 9 + 1 + 6 + 6 + 3
+    assert mdf.n_channels(2, mdf.FIELD_VORT | mdf.FIELD_STRAIN) == 4
