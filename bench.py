@@ -166,13 +166,91 @@ def summarize_traffic(fetch_db, write_db, copy_fetch_db, copy_write_db, kernel_p
     return "\n".join(md) + "\n", {kernel_key: ent}
 
 
+def parse_launch(text):
+    t = text.lower()
+    groups = 1
+    if "g" in t:
+        t, g = t.split("g")
+        groups = int(g)
+    bx, by = (int(v) for v in t.split("x"))
+    return bx, by, groups
+
+
+def time_launches(solver, stream, n, fields=0, out=None, reps=3):
+    """Average duration of one step-kernel launch (HIP events around n
+    back-to-back launches on the kernel's stream), in ms."""
+    import torch
+    res = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        if fields:
+            solver.step_emit(n, fields, out)
+        else:
+            solver.step(n)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res.append(e0.elapsed_time(e1) / n)
+    return min(res)
+
+
+def sweep(out_path):
+    """Step-kernel timing over grid sizes (incl. working sets far beyond the
+    256 MB Infinity Cache), storages, lattices and launch shapes."""
+    import torch
+    from paper_2108_08591_amd import cases as C
+    from paper_2108_08591_amd import mdf
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    sb = {"f64": 8, "f32": 4, "f16dev": 2, "bf16dev": 2}
+    runs = []
+    for N in (1024, 2048, 4096, 8192):
+        for st in ("f32", "f64", "f16dev", "bf16dev"):
+            runs.append(("d2q5", N, st))
+    for N in (128, 256, 384):
+        for st in ("f32", "f64", "f16dev", "bf16dev"):
+            runs.append(("d3q7", N, st))
+    shapes = [(64, 4, 8), (64, 4, 1), (256, 1, 8), (128, 2, 8), (64, 2, 8), (64, 1, 8)]
+    with open(out_path, "w") as fh:
+        for lat, N, st in runs:
+            if lat == "d2q5":
+                spec = C.cavity_case(N=N, Re=1000.0)
+                q, ns = 5, 3
+            else:
+                spec = C.tgv3d_case(N=N, u0=0.05, Re=100.0)
+                q, ns = 7, 4
+            try:
+                solver = mdf.Solver([spec], storage=st, device=dev, stream=stream, u_ref=0.1)
+            except Exception as e:           # out of memory on the largest grids
+                print(json.dumps({"lattice": lat, "N": N, "storage": st, "error": str(e)[:100]}), file=fh)
+                continue
+            nodes = spec.nodes
+            alg = nodes * 2 * q * ns * sb[st]
+            n = max(5, min(400, int(2e10 / alg)))
+            for bx, by, g in shapes:
+                solver.set_launch(bx, by, g)
+                solver.step(2)
+                ms = time_launches(solver, stream, n)
+                rec = {"lattice": lat, "N": N, "storage": st, "launch": f"{bx}x{by}g{g}",
+                       "ms": round(ms, 5), "MLUPS": round(nodes / ms / 1e3, 1),
+                       "GBps": round(alg / ms / 1e6, 1), "frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4),
+                       "working_set_MB": round(2 * alg / 2 / 1e6, 1)}
+                print(json.dumps(rec), file=fh, flush=True)
+                print(json.dumps(rec), flush=True)
+            del solver
+            torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--launch", default="64x4", help="threads per block, BXxBY")
+    ap.add_argument("--launch", default="64x4g8", help="threads per block and XCD groups, BXxBYgG")
+    ap.add_argument("--sweep", metavar="OUT_JSONL",
+                    help="time the step kernel over grid sizes, storages and launch shapes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain copy of known size (traffic-counter calibration)")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("DB", "OUT_MD"),
@@ -184,6 +262,9 @@ def main():
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.sweep:
+        sweep(args.sweep)
         return
     if args.summarize_trace:
         with open(args.summarize_trace[1], "w") as fh:
@@ -218,8 +299,8 @@ def main():
     fields = mdf.FIELD_VORT | mdf.FIELD_STRAIN
     stream = torch.cuda.Stream(device=dev)
     solver = mdf.Solver([spec], storage="f32", device=dev, stream=stream)
-    bx, by = (int(v) for v in args.launch.lower().split("x"))
-    solver.set_launch(bx, by)
+    bx, by, groups = parse_launch(args.launch)
+    solver.set_launch(bx, by, groups)
     out = solver.new_field_buffers(fields)
     K = 100
     nodes = spec.nodes
@@ -247,17 +328,7 @@ def main():
     # the kernel runs on, around batches of back-to-back launches (no other
     # work in between)
     nlaunch, reps = 500, 5
-    durs = []
-    for _ in range(reps):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        solver.step_emit(nlaunch, fields, out)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        durs.append(e0.elapsed_time(e1) / nlaunch)
-    durs.sort()
-    avg_ms = sum(durs) / len(durs)
+    avg_ms = time_launches(solver, stream, nlaunch, fields, out, reps)
     bytes_per_node = 2 * 15 * 4 + 4 * 4          # populations read+write, 4 emitted FP32 fields
     alg_bytes = nodes * bytes_per_node
     achieved = alg_bytes / (avg_ms / 1e3) / 1e9
@@ -280,7 +351,7 @@ def main():
         "config": {
             "workload": "lid-driven cavity 1024x1024, D2Q5 x 3 sets, FP32 storage, Re=1000, lid 0.1, "
                         "per-step vorticity+strain emission, FP64 residual every 100 steps",
-            "nodes": nodes, "Re": 1000, "lid_u": 0.1, "storage": "f32", "launch": f"{bx}x{by}",
+            "nodes": nodes, "Re": 1000, "lid_u": 0.1, "storage": "f32", "launch": f"{bx}x{by}g{groups}",
         },
         "hbm_roofline_pct": round(100.0 * mlups * 1e6 * bytes_per_node / (HBM_PEAK_GBS * 1e9), 2),
         "roofline": {
@@ -293,7 +364,7 @@ def main():
             "kernel": kernel_key,
             "bytes_per_launch": alg_bytes,
             "avg_launch_ms": round(avg_ms, 5),
-            "launch_timing": f"HIP events around {reps} x {nlaunch} back-to-back launches",
+            "launch_timing": f"HIP events around {nlaunch} back-to-back launches, best of {reps}",
             "note": "working set 120 MiB + 16 MiB of emitted fields fits the 256 MB Infinity Cache",
         },
         "residual_after": float(res[0]),

@@ -190,13 +190,14 @@ mdf_status mdf_run_steady(mdf_ctx *ctx, double tol, int32_t K, int64_t max_steps
  * J_{a,b} = sum_i c_{i,b} f_{i,a}.  Waits for the device. */
 mdf_status mdf_invariants(const mdf_ctx *ctx, int32_t case_id, double *out, void *stream);
 
-/* Threads per block of the step and read kernels: bx along x (a multiple
- * of 32) and by along y, bx * by a multiple of 64 up to 256 (whole
- * wavefronts).  Default 64 x 4.  MDF_EINVAL otherwise.  Any
- * shape gives bitwise identical results except the FP64 sums of mdf_check,
- * mdf_run_steady and mdf_invariants, whose summation order follows the
- * blocks. */
-mdf_status mdf_set_launch(mdf_ctx *ctx, int32_t bx, int32_t by);
+/* Launch shape of the step and read kernels: tiles of bx (a multiple of 32)
+ * by by threads, bx * by a multiple of 64 up to 256 (whole wavefronts), and
+ * `groups` > 1 hands the tiles out in that many contiguous bands, one per
+ * XCD (8 on MI355X), so neighbouring tiles share an L2; 0 or 1 keeps plain
+ * order.  Default 64 x 4, 8 groups.  MDF_EINVAL otherwise.  Any shape gives
+ * bitwise identical populations and fields; only the summation order of the
+ * FP64 sums of mdf_check, mdf_run_steady and mdf_invariants follows it. */
+mdf_status mdf_set_launch(mdf_ctx *ctx, int32_t bx, int32_t by, int32_t groups);
 
 /* Current time of a case (steps taken since mdf_init; cases stopped by
  * mdf_run_steady stay at their stopping time).  -1 on a bad argument. */

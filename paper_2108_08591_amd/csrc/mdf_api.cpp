@@ -129,7 +129,7 @@ struct mdf_ctx {
     std::vector<int> cur;              // buffer holding f*(., t)
     std::vector<int64_t> time;
     std::vector<int64_t> snap_time;    // time of the velocity snapshot, -1 = none
-    LaunchShape shape{64, 4};
+    LaunchShape shape{64, 4, 8};
     hipError_t latched = hipSuccess;
     std::string err;
     std::vector<double> host_red;
@@ -316,13 +316,14 @@ mdf_status mdf_init(mdf_ctx **out, mdf_lattice lattice, mdf_storage storage, con
     return MDF_OK;
 }
 
-mdf_status mdf_set_launch(mdf_ctx *ctx, int32_t bx, int32_t by)
+mdf_status mdf_set_launch(mdf_ctx *ctx, int32_t bx, int32_t by, int32_t groups)
 {
     if (!ctx) return fail(nullptr, MDF_EINVAL, "mdf_set_launch: ctx is NULL");
     if (bx < 32 || bx % 32 != 0 || by < 1 || bx * by > 256 || (bx * by) % 64 != 0)
         return fail(ctx, MDF_EINVAL,
                     "mdf_set_launch: need bx %% 32 == 0 and bx*by a multiple of 64 up to 256 (got %d x %d)", bx, by);
-    ctx->shape = LaunchShape{bx, by};
+    if (groups < 0 || groups > 64) return fail(ctx, MDF_EINVAL, "mdf_set_launch: groups outside [0, 64]");
+    ctx->shape = LaunchShape{bx, by, groups};
     return MDF_OK;
 }
 

@@ -41,6 +41,13 @@ struct CaseBufs {
 
 struct LaunchShape {
     int bx, by;             // threads per block along x and y (bx * by <= 256)
+    int groups;             // > 1: hand out tiles in `groups` contiguous bands, one per XCD
+};
+
+// Tile grid of one launch: gx * gy * gz tiles of bx * by threads, launched
+// as a 1D grid of nb = gx * gy * gz blocks.
+struct Tiling {
+    int gx, gy, nb, groups;
 };
 
 enum ReadMode { kReadFields = 0, kReadPops = 1, kReadCheck = 2, kReadSums = 3 };

@@ -67,6 +67,22 @@ __device__ __forceinline__ constexpr int cdir(int i, int b)
     return b == 0 ? L::cx[i] : (b == 1 ? L::cy[i] : L::cz[i]);
 }
 
+// ----------------------------------------------------------------- tiling
+
+// Tile handled by this block.  Workgroups of a 1D grid are dealt to the
+// XCDs round-robin (block b runs on XCD b % groups); with groups > 1 the
+// tiles are renumbered so that each XCD receives one contiguous band of
+// tiles, so that the x- and y-neighbours a tile's pulls straddle into sit in
+// the same L2.  A bijection on [0, nb) for any nb.
+__device__ __forceinline__ int block_tile(const Tiling &t)
+{
+    const int b = blockIdx.x;
+    if (t.groups <= 1) return b;
+    const int q = t.nb / t.groups, r = t.nb % t.groups;
+    const int g = b % t.groups, k = b / t.groups;
+    return (g < r) ? g * (q + 1) + k : r * (q + 1) + (g - r) * q + k;
+}
+
 // ----------------------------------------------------------------- storage
 
 // Storage codes follow mdf_storage.
@@ -392,8 +408,8 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Fixed-order block reduction of kNRed doubles into partial[block].
-__device__ __forceinline__ void block_reduce_store(double (&v)[kNRed], double *__restrict__ partial)
+// Fixed-order block reduction of kNRed doubles into partial[tile].
+__device__ __forceinline__ void block_reduce_store(double (&v)[kNRed], double *__restrict__ partial, int tile)
 {
     __shared__ double red[kNRed][16];
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
@@ -408,8 +424,7 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[kNRed], double *_
     if (tid < kNRed) {
         double s = 0.0;
         for (int w = 0; w < nwaves; ++w) s += red[tid][w];
-        const long long blk = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
-        partial[blk * kNRed + tid] = s;
+        partial[(long long)tile * kNRed + tid] = s;
     }
 }
 
@@ -446,15 +461,17 @@ __device__ __forceinline__ void check_values(const Moments<L, C> &m, bool valid,
 // collision + forcing, write.
 template <class L, int ST, bool EMIT, bool CHECK, bool MASK>
 __global__ void __launch_bounds__(256)
-k_step(KCase p, const typename Store<ST>::T *__restrict__ src, typename Store<ST>::T *__restrict__ dst,
+k_step(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, typename Store<ST>::T *__restrict__ dst,
        const uint8_t *__restrict__ links, uint32_t fields, typename Store<ST>::C *__restrict__ out,
        typename Store<ST>::C *__restrict__ snap, double *__restrict__ partial)
 {
     using S = Store<ST>;
     using C = typename S::C;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
+    const int tile = block_tile(tl);
+    const int tx = tile % tl.gx, rest = tile / tl.gx;
+    const int x = tx * blockDim.x + threadIdx.x;
+    const int y = (rest % tl.gy) * blockDim.y + threadIdx.y;
+    const int z = rest / tl.gy;
     const bool inside = (x < p.nx) && (y < p.ny);
     Node<L, C> n;
     Moments<L, C> m;
@@ -490,22 +507,24 @@ k_step(KCase p, const typename Store<ST>::T *__restrict__ src, typename Store<ST
     if (CHECK) {
         double v[kNRed];
         check_values<L, C, true>(m, fluid, snap, node, nodes, v);
-        block_reduce_store(v, partial);
+        block_reduce_store(v, partial, tile);
     }
 }
 
 // Read-only pass at the current time: fields, populations or a check.
 template <class L, int ST, bool MASK, bool PULL, int MODE>
 __global__ void __launch_bounds__(256)
-k_read(KCase p, const typename Store<ST>::T *__restrict__ src, const uint8_t *__restrict__ links,
+k_read(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, const uint8_t *__restrict__ links,
        uint32_t fields, typename Store<ST>::C *__restrict__ out, typename Store<ST>::C *__restrict__ snap,
        double *__restrict__ partial)
 {
     using S = Store<ST>;
     using C = typename S::C;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
+    const int tile = block_tile(tl);
+    const int tx = tile % tl.gx, rest = tile / tl.gx;
+    const int x = tx * blockDim.x + threadIdx.x;
+    const int y = (rest % tl.gy) * blockDim.y + threadIdx.y;
+    const int z = rest / tl.gy;
     const bool inside = (x < p.nx) && (y < p.ny);
     Node<L, C> n;
     Moments<L, C> m;
@@ -538,7 +557,7 @@ k_read(KCase p, const typename Store<ST>::T *__restrict__ src, const uint8_t *__
     if (MODE == kReadCheck || MODE == kReadSums) {
         double v[kNRed];
         check_values<L, C, MODE == kReadCheck>(m, fluid, snap, node, nodes, v);
-        block_reduce_store(v, partial);
+        block_reduce_store(v, partial, tile);
     }
 }
 
@@ -678,6 +697,16 @@ dim3 grid_of(const KCase &p, LaunchShape s)
     return dim3((p.nx + s.bx - 1) / s.bx, (p.ny + s.by - 1) / s.by, p.nz);
 }
 
+Tiling tiling_of(const KCase &p, LaunchShape s)
+{
+    Tiling t;
+    t.gx = (p.nx + s.bx - 1) / s.bx;
+    t.gy = (p.ny + s.by - 1) / s.by;
+    t.nb = t.gx * t.gy * p.nz;
+    t.groups = s.groups > 1 ? s.groups : 1;
+    return t;
+}
+
 template <class L, int ST>
 hipError_t step_dispatch(const KCase &p, const CaseBufs &b, int src, bool check, uint32_t fields,
                          void *out, LaunchShape s, hipStream_t stream)
@@ -689,11 +718,12 @@ hipError_t step_dispatch(const KCase &p, const CaseBufs &b, int src, bool check,
     T *o = static_cast<T *>(b.pop[src ^ 1]);
     C *emit = static_cast<C *>(out);
     C *snap = static_cast<C *>(b.snap);
-    const dim3 grid = grid_of(p, s), block(s.bx, s.by, 1);
+    const Tiling tl = tiling_of(p, s);
+    const dim3 grid(tl.nb, 1, 1), block(s.bx, s.by, 1);
     const bool emit_on = (fields != 0) && out != nullptr;
     const bool mask = b.links != nullptr;
 #define MDF_STEP_LAUNCH(E, K, M) \
-    hipLaunchKernelGGL((k_step<L, ST, E, K, M>), grid, block, 0, stream, p, in, o, b.links, fields, emit, snap, b.partial)
+    hipLaunchKernelGGL((k_step<L, ST, E, K, M>), grid, block, 0, stream, p, tl, in, o, b.links, fields, emit, snap, b.partial)
     if (mask) {
         if (emit_on) { if (check) MDF_STEP_LAUNCH(true, true, true); else MDF_STEP_LAUNCH(true, false, true); }
         else { if (check) MDF_STEP_LAUNCH(false, true, true); else MDF_STEP_LAUNCH(false, false, true); }
@@ -715,10 +745,11 @@ hipError_t read_dispatch(const KCase &p, const CaseBufs &b, int src, bool pull, 
     const T *in = static_cast<const T *>(b.pop[src]);
     C *o = static_cast<C *>(out);
     C *snap = static_cast<C *>(b.snap);
-    const dim3 grid = grid_of(p, s), block(s.bx, s.by, 1);
+    const Tiling tl = tiling_of(p, s);
+    const dim3 grid(tl.nb, 1, 1), block(s.bx, s.by, 1);
     const bool mask = b.links != nullptr;
 #define MDF_READ_LAUNCH(M, PL, MD) \
-    hipLaunchKernelGGL((k_read<L, ST, M, PL, MD>), grid, block, 0, stream, p, in, b.links, fields, o, snap, b.partial)
+    hipLaunchKernelGGL((k_read<L, ST, M, PL, MD>), grid, block, 0, stream, p, tl, in, b.links, fields, o, snap, b.partial)
 #define MDF_READ_MODE(M, PL)                                              \
     do {                                                                  \
         if (mode == kReadFields) MDF_READ_LAUNCH(M, PL, kReadFields);     \
@@ -742,7 +773,7 @@ hipError_t init_dispatch(const KCase &p, const CaseBufs &b, int cur, int kind, c
     using C = typename S::C;
     T *post = static_cast<T *>(b.pop[cur]);
     T *pre = static_cast<T *>(b.pop[cur ^ 1]);
-    const LaunchShape s{64, 4};
+    const LaunchShape s{64, 4, 1};
     const dim3 grid = grid_of(p, s), block(s.bx, s.by, 1);
     if (b.links)
         hipLaunchKernelGGL((k_init<L, ST, true>), grid, block, 0, stream, p, pre, post, b.links, kind,
@@ -757,8 +788,7 @@ hipError_t init_dispatch(const KCase &p, const CaseBufs &b, int cur, int kind, c
 
 int grid_blocks(const KCase &p, LaunchShape s)
 {
-    const dim3 g = grid_of(p, s);
-    return (int)(g.x * g.y * g.z);
+    return tiling_of(p, s).nb;
 }
 
 #define MDF_DISPATCH(lattice, storage, FN, ...)                                              \
@@ -804,7 +834,7 @@ hipError_t launch_init(int lattice, int storage, const KCase &p, const CaseBufs 
 
 hipError_t launch_links(int lattice, const KCase &p, const uint8_t *solid, uint8_t *links, hipStream_t stream)
 {
-    const LaunchShape s{64, 4};
+    const LaunchShape s{64, 4, 1};
     const dim3 grid = grid_of(p, s), block(s.bx, s.by, 1);
     if (lattice == MDF_D2Q5)
         hipLaunchKernelGGL((k_links<LatD2Q5>), grid, block, 0, stream, p, solid, links);

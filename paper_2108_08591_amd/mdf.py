@@ -79,7 +79,7 @@ def lib():
         L.mdf_run_steady.argtypes = [vp, dbl, i32, i64, ctypes.c_uint32, ctypes.POINTER(vp),
                                      ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(dbl), vp]
         L.mdf_invariants.argtypes = [vp, i32, ctypes.POINTER(dbl), vp]
-        L.mdf_set_launch.argtypes = [vp, i32, i32]
+        L.mdf_set_launch.argtypes = [vp, i32, i32, i32]
         L.mdf_time.argtypes = [vp, i32]
         L.mdf_time.restype = i64
         L.mdf_last_error.argtypes = [vp]
@@ -251,8 +251,8 @@ class Solver:
             self._ctx = None
 
     # -------------------------------------------------------------- stepping
-    def set_launch(self, bx: int, by: int):
-        _check(lib().mdf_set_launch(self._ctx, bx, by), self._ctx)
+    def set_launch(self, bx: int, by: int, groups: int = 8):
+        _check(lib().mdf_set_launch(self._ctx, bx, by, groups), self._ctx)
 
     def step(self, nsteps: int = 1):
         _check(lib().mdf_step(self._ctx, int(nsteps), _stream_ptr(self.stream)), self._ctx)

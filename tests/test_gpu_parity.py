@@ -262,10 +262,10 @@ def test_launch_shapes_bitwise_identical():
     spec = C.cavity_case(N=100, Re=100.0)
     spec.shape = (100, 70)
     pops = []
-    for bx, by in ((64, 4), (256, 1), (128, 2), (32, 2), (64, 1)):
-        _say(f"[gpu] launch shape {bx}x{by}")
+    for bx, by, g in ((64, 4, 8), (64, 4, 1), (256, 1, 8), (128, 2, 3), (32, 2, 8), (64, 1, 1)):
+        _say(f"[gpu] launch shape {bx}x{by} groups {g}")
         s = mdf.Solver([spec], storage="f32", device=DEV)
-        s.set_launch(bx, by)
+        s.set_launch(bx, by, g)
         s.step(50)
         pops.append(s.populations())
     for p in pops[1:]:
@@ -313,7 +313,7 @@ def test_full_size_cavity_sampled_parity():
     spec = C.cavity_case(N=1024, Re=1000.0)
     _say("[parity] full-size cavity 1024^2 sampled")
     s = mdf.Solver([spec], storage="f32", device=DEV)
-    s.set_launch(64, 4)
+    s.set_launch(64, 4, 8)
     s.step(300)
     f_t = _np(s.populations())
     s.step(1)
