@@ -142,7 +142,12 @@ mdf_status mdf_init(mdf_ctx **out, mdf_lattice lattice, mdf_storage storage,
                     const void *const *init_data, void *stream);
 
 /* Advance every case by nsteps time steps of eq. 3-21 (fused pull
- * streaming, wall rule, moments, equilibrium, MRT collision and forcing). */
+ * streaming, wall rule, moments, equilibrium, MRT collision and forcing).
+ * A context of several cases advances all of them in one persistent launch
+ * per step over the flattened (case, tile) list; K-step chunks on a
+ * non-null stream are captured once as a HIP graph and replayed.  The
+ * results are bitwise those of one context per case with the same launch
+ * shape. */
 mdf_status mdf_step(mdf_ctx *ctx, int32_t nsteps, void *stream);
 
 /* As mdf_step, and every step also writes the selected fields (MDF_FIELD_*)
@@ -198,6 +203,16 @@ mdf_status mdf_invariants(const mdf_ctx *ctx, int32_t case_id, double *out, void
  * bitwise identical populations and fields; only the summation order of the
  * FP64 sums of mdf_check, mdf_run_steady and mdf_invariants follows it. */
 mdf_status mdf_set_launch(mdf_ctx *ctx, int32_t bx, int32_t by, int32_t groups);
+
+/* Choose the launch shape of this context by timing candidate shapes
+ * (tiles 64x4, 128x2, 256x1, 64x2, 64x1, 32x8, 128x1 with XCD bands, and
+ * 64x4 without) on `trial_steps` real steps each and keeping the fastest.
+ * Every case advances by (trial_steps + 1) steps per candidate (results
+ * are bitwise independent of the shape).  chosen: host int[3] (bx, by,
+ * groups) or NULL; best_ms: host double, time per step, or NULL.  Waits for
+ * the device. */
+mdf_status mdf_autotune(mdf_ctx *ctx, int32_t trial_steps, int32_t *chosen, double *best_ms,
+                        void *stream);
 
 /* Current time of a case (steps taken since mdf_init; cases stopped by
  * mdf_run_steady stay at their stopping time).  -1 on a bad argument. */

@@ -51,6 +51,11 @@ struct CaseLayout {
     int max_blocks;
 };
 
+// Context-wide regions of the workspace (batched launches).
+struct SharedLayout {
+    size_t table, meta, tile_start, active;
+};
+
 // Blocks of the largest grid any allowed launch shape produces
 // (bx >= 32, bx * by >= 64): at most ceil(nx/32) * ny * nz.
 int max_blocks_of(const mdf_case &c) { return (c.nx + 31) / 32 * c.ny * c.nz; }
@@ -93,11 +98,24 @@ bool validate_case(int lattice, const mdf_case &c, std::string &why)
 }
 
 size_t layout(int lattice, int storage, const mdf_case *cases, int ncases, bool has_solid,
-              std::vector<CaseLayout> *out)
+              std::vector<CaseLayout> *out, SharedLayout *shared = nullptr)
 {
     const int d = lat_d(lattice), q = lat_q(lattice);
     size_t off = 0;
     if (out) out->resize(ncases);
+    // per-case FP64 results, contiguous (one read-back for a whole batch)
+    const size_t results = off;
+    off = align256(off + size_t(ncases) * mdf::kNRed * sizeof(double));
+    SharedLayout sh;
+    sh.table = off;
+    off = align256(off + size_t(ncases) * sizeof(mdf::BatchEntry));
+    sh.meta = off;
+    off = align256(off + 4 * sizeof(int));
+    sh.tile_start = off;
+    off = align256(off + size_t(ncases + 1) * sizeof(int));
+    sh.active = off;
+    off = align256(off + size_t(ncases) * sizeof(int));
+    if (shared) *shared = sh;
     for (int k = 0; k < ncases; ++k) {
         const mdf_case &c = cases[k];
         CaseLayout L;
@@ -113,14 +131,21 @@ size_t layout(int lattice, int storage, const mdf_case *cases, int ncases, bool 
         L.max_blocks = max_blocks_of(c);
         L.partial = off;
         off = align256(off + size_t(L.max_blocks) * mdf::kNRed * sizeof(double));
-        L.result = off;
-        off = align256(off + mdf::kNRed * sizeof(double));
+        L.result = results + size_t(k) * mdf::kNRed * sizeof(double);
         if (out) (*out)[k] = L;
     }
     return off;
 }
 
 }  // namespace
+
+struct GraphKey {
+    int len, check, emit, parity;
+    bool operator==(const GraphKey &o) const
+    {
+        return len == o.len && check == o.check && emit == o.emit && parity == o.parity;
+    }
+};
 
 struct mdf_ctx {
     int lattice = 0, storage = 0, d = 2, q = 5, ncases = 0;
@@ -133,6 +158,20 @@ struct mdf_ctx {
     hipError_t latched = hipSuccess;
     std::string err;
     std::vector<double> host_red;
+    // batched launches (ncases > 1)
+    bool batched = false;
+    bool any_mask = false;
+    mdf::BatchEntry *d_tab = nullptr;
+    int *d_meta = nullptr, *d_tile_start = nullptr, *d_active = nullptr;
+    double *d_results = nullptr;
+    std::vector<mdf::BatchEntry> h_tab;
+    std::vector<int> h_tile_start, h_active, h_meta;
+    std::vector<double> h_results;
+    int steps_since_upload = 0;
+    int uploaded_fields = -1;
+    int num_cu = 0;
+    std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
+    bool use_graphs = true;
 };
 
 namespace {
@@ -219,6 +258,161 @@ double residual_of(const mdf_ctx *ctx, int k, const double *red)
     return std::sqrt(red[0]) / (double(dt) * den);
 }
 
+// ---------------------------------------------------------------- batched path
+
+void drop_graphs(mdf_ctx *ctx)
+{
+    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+    ctx->graphs.clear();
+}
+
+mdf_status batch_capacity_grid(mdf_ctx *ctx, int *grid)
+{
+    if (ctx->num_cu == 0) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return device_error(ctx, e, "device query");
+    }
+    int per_cu = 0;
+    hipError_t e = mdf::batch_blocks_per_cu(ctx->lattice, ctx->storage, ctx->shape, ctx->any_mask, &per_cu);
+    if (e != hipSuccess) return device_error(ctx, e, "occupancy query");
+    if (per_cu < 1) per_cu = 1;
+    *grid = ctx->num_cu * per_cu;
+    return MDF_OK;
+}
+
+// Fill the host mirror of the case table for the given active cases and
+// emission targets, and copy it to the device.  Waits for the copies.
+mdf_status batch_upload(mdf_ctx *ctx, const std::vector<int> &active, uint32_t fields, void *const *out,
+                        hipStream_t st)
+{
+    const int n = ctx->ncases;
+    ctx->h_tab.resize(n);
+    for (int k = 0; k < n; ++k) {
+        mdf::BatchEntry &e = ctx->h_tab[k];
+        std::memset(&e, 0, sizeof e);
+        e.p = ctx->kc[k];
+        e.pop[0] = ctx->bufs[k].pop[0];
+        e.pop[1] = ctx->bufs[k].pop[1];
+        e.links = ctx->bufs[k].links;
+        e.snap = ctx->bufs[k].snap;
+        e.partial = ctx->bufs[k].partial;
+        e.result = ctx->bufs[k].result;
+        e.out = (fields && out) ? out[k] : nullptr;
+        e.gx = (e.p.nx + ctx->shape.bx - 1) / ctx->shape.bx;
+        e.gy = (e.p.ny + ctx->shape.by - 1) / ctx->shape.by;
+        e.ntiles = e.gx * e.gy * e.p.nz;
+        e.cur = ctx->cur[k];
+        if (e.ntiles > ctx->bufs[k].max_blocks)
+            return fail(ctx, MDF_EINVAL, "launch grid exceeds the reduction workspace");
+    }
+    ctx->h_active = active;
+    ctx->h_tile_start.assign(active.size() + 1, 0);
+    long long total = 0;
+    for (size_t i = 0; i < active.size(); ++i) {
+        ctx->h_tile_start[i] = int(total);
+        total += ctx->h_tab[active[i]].ntiles;
+    }
+    if (total > 0x7fffffffLL) return fail(ctx, MDF_EINVAL, "batch has too many tiles");
+    ctx->h_tile_start[active.size()] = int(total);
+    ctx->h_meta = {int(active.size()), int(total), 0, 0};
+    hipError_t e = hipMemcpyAsync(ctx->d_tab, ctx->h_tab.data(), sizeof(mdf::BatchEntry) * n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->d_meta, ctx->h_meta.data(), sizeof(int) * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !active.empty()) {
+        e = hipMemcpyAsync(ctx->d_tile_start, ctx->h_tile_start.data(), sizeof(int) * (active.size() + 1),
+                           hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ctx->d_active, active.data(), sizeof(int) * active.size(), hipMemcpyHostToDevice, st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return device_error(ctx, e, "batch table upload");
+    ctx->steps_since_upload = 0;
+    ctx->uploaded_fields = int(fields);
+    return MDF_OK;
+}
+
+mdf::BatchLaunch batch_args(mdf_ctx *ctx, uint32_t fields, int grid)
+{
+    mdf::BatchLaunch bl;
+    bl.tab = ctx->d_tab;
+    bl.meta = ctx->d_meta;
+    bl.tile_start = ctx->d_tile_start;
+    bl.active = ctx->d_active;
+    bl.parity = 0;
+    bl.fields = fields;
+    bl.grid = grid;
+    bl.mask = ctx->any_mask;
+    bl.shape = ctx->shape;
+    return bl;
+}
+
+// nsteps batched steps of the uploaded active cases; the last one fused with
+// the check when `check`.  A chunk whose length, check flag, emission and
+// starting parity were seen before replays a captured graph.
+mdf_status batch_steps(mdf_ctx *ctx, int nsteps, bool check, uint32_t fields, hipStream_t st)
+{
+    if (nsteps <= 0) return MDF_OK;
+    int grid = 0;
+    mdf_status r = batch_capacity_grid(ctx, &grid);
+    if (r != MDF_OK) return r;
+    mdf::BatchLaunch bl = batch_args(ctx, fields, grid);
+    const int p0 = ctx->steps_since_upload & 1;
+    const GraphKey key{nsteps, check ? 1 : 0, int(fields), p0};
+    hipGraphExec_t exec = nullptr;
+    for (auto &g : ctx->graphs)
+        if (g.first == key) exec = g.second;
+    if (!exec && ctx->use_graphs && st != nullptr && nsteps >= 4) {
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
+        if (e == hipSuccess) {
+            for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
+                bl.parity = (p0 + s) & 1;
+                e = mdf::launch_step_batch(ctx->lattice, ctx->storage, bl, check && s == nsteps - 1, st);
+            }
+            hipError_t e2 = hipStreamEndCapture(st, &graph);
+            if (e == hipSuccess) e = e2;
+            if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (e == hipSuccess) ctx->graphs.push_back({key, exec});
+            else exec = nullptr;
+            if (e != hipSuccess) {
+                (void)hipGetLastError();     // capture unsupported here: plain launches
+                ctx->use_graphs = false;
+            }
+        }
+    }
+    if (exec) {
+        hipError_t e = hipGraphLaunch(exec, st);
+        if (e != hipSuccess) return device_error(ctx, e, "graph launch");
+    } else {
+        for (int s = 0; s < nsteps; ++s) {
+            bl.parity = (p0 + s) & 1;
+            hipError_t e = mdf::launch_step_batch(ctx->lattice, ctx->storage, bl, check && s == nsteps - 1, st);
+            if (e != hipSuccess) return device_error(ctx, e, "batched step launch");
+        }
+    }
+    ctx->steps_since_upload += nsteps;
+    for (int k : ctx->h_active) {
+        ctx->time[k] += nsteps;
+        if (nsteps & 1) ctx->cur[k] ^= 1;
+    }
+    return MDF_OK;
+}
+
+// Reduce the fused check of the active cases and read every result back.
+mdf_status batch_fetch_results(mdf_ctx *ctx, hipStream_t st)
+{
+    hipError_t e = mdf::launch_finalize_batch(ctx->d_tab, ctx->d_meta, ctx->d_active, int(ctx->h_active.size()), st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->h_results.data(), ctx->d_results, sizeof(double) * ctx->h_results.size(),
+                           hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return device_error(ctx, e, "batch results");
+    return MDF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -267,7 +461,8 @@ mdf_status mdf_init(mdf_ctx **out, mdf_lattice lattice, mdf_storage storage, con
     if (solid)
         for (int k = 0; k < ncases; ++k) has_solid = has_solid || solid[k] != nullptr;
     std::vector<CaseLayout> lay;
-    const size_t need = layout(lattice, storage, cases, ncases, has_solid, &lay);
+    SharedLayout shl;
+    const size_t need = layout(lattice, storage, cases, ncases, has_solid, &lay, &shl);
     if (ws_bytes < need)
         return fail(nullptr, MDF_ENOMEM, "mdf_init: workspace of %zu bytes, %zu needed", ws_bytes, need);
 
@@ -284,13 +479,23 @@ mdf_status mdf_init(mdf_ctx **out, mdf_lattice lattice, mdf_storage storage, con
     ctx->snap_time.assign(ncases, -1);
     ctx->host_red.assign(mdf::kNRed, 0.0);
     char *ws = static_cast<char *>(workspace);
+    ctx->batched = ncases > 1;
+    ctx->any_mask = has_solid;
+    ctx->d_tab = reinterpret_cast<mdf::BatchEntry *>(ws + shl.table);
+    ctx->d_meta = reinterpret_cast<int *>(ws + shl.meta);
+    ctx->d_tile_start = reinterpret_cast<int *>(ws + shl.tile_start);
+    ctx->d_active = reinterpret_cast<int *>(ws + shl.active);
+    ctx->d_results = reinterpret_cast<double *>(ws + lay[0].result);
+    ctx->h_results.assign(size_t(ncases) * mdf::kNRed, 0.0);
     hipStream_t st = static_cast<hipStream_t>(stream);
     for (int k = 0; k < ncases; ++k) {
         ctx->kc[k] = make_kcase(lattice, storage, cases[k]);
         CaseBufs &b = ctx->bufs[k];
         b.pop[0] = ws + lay[k].pop[0];
         b.pop[1] = ws + lay[k].pop[1];
-        b.links = (solid && solid[k]) ? reinterpret_cast<uint8_t *>(ws + lay[k].links) : nullptr;
+        // with obstacles in any case, every case carries link bits (zero
+        // where it has no mask), so batched launches read valid memory
+        b.links = has_solid ? reinterpret_cast<uint8_t *>(ws + lay[k].links) : nullptr;
         b.snap = ws + lay[k].snap;
         b.partial = reinterpret_cast<double *>(ws + lay[k].partial);
         b.result = reinterpret_cast<double *>(ws + lay[k].result);
@@ -324,6 +529,7 @@ mdf_status mdf_set_launch(mdf_ctx *ctx, int32_t bx, int32_t by, int32_t groups)
                     "mdf_set_launch: need bx %% 32 == 0 and bx*by a multiple of 64 up to 256 (got %d x %d)", bx, by);
     if (groups < 0 || groups > 64) return fail(ctx, MDF_EINVAL, "mdf_set_launch: groups outside [0, 64]");
     ctx->shape = LaunchShape{bx, by, groups};
+    drop_graphs(ctx);
     return MDF_OK;
 }
 
@@ -340,6 +546,13 @@ static mdf_status step_impl(mdf_ctx *ctx, int32_t nsteps, uint32_t fields, void 
             if (!out[k]) return fail(ctx, MDF_EINVAL, "mdf_step_emit: out[%d] is NULL", k);
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (ctx->batched) {
+        std::vector<int> all(ctx->ncases);
+        for (int k = 0; k < ctx->ncases; ++k) all[k] = k;
+        mdf_status r = batch_upload(ctx, all, fields, out, st);
+        if (r != MDF_OK) return r;
+        return batch_steps(ctx, nsteps, false, fields, st);
+    }
     for (int s = 0; s < nsteps; ++s)
         for (int k = 0; k < ctx->ncases; ++k) {
             mdf_status r = step_case(ctx, k, false, fields, fields ? out[k] : nullptr, st, nullptr);
@@ -446,7 +659,38 @@ mdf_status mdf_run_steady(mdf_ctx *ctx, double tol, int32_t K, int64_t max_steps
         ctx->snap_time[k] = ctx->time[k];
         if (ctx->host_red[7] != 0.0) state[k] = 1;
     }
-    bool any_running = true;
+    if (ctx->batched) {
+        std::vector<int> active;
+        for (int k = 0; k < n; ++k)
+            if (state[k] == 2) active.push_back(k);
+        int64_t done = 0;
+        bool need_upload = true;
+        while (!active.empty() && done < max_steps) {
+            if (need_upload) {
+                mdf_status r = batch_upload(ctx, active, fields, out, st);
+                if (r != MDF_OK) return r;
+                need_upload = false;
+            }
+            const int chunk = int(std::min<int64_t>(K, max_steps - done));
+            mdf_status r = batch_steps(ctx, chunk, true, fields, st);
+            if (r != MDF_OK) return r;
+            done += chunk;
+            r = batch_fetch_results(ctx, st);
+            if (r != MDF_OK) return r;
+            std::vector<int> still;
+            for (int k : active) {
+                const double *red = ctx->h_results.data() + size_t(k) * mdf::kNRed;
+                res[k] = residual_of(ctx, k, red);
+                ctx->snap_time[k] = ctx->time[k];
+                if (red[7] != 0.0 || !std::isfinite(red[1])) state[k] = 1;
+                else if (res[k] < tol) state[k] = 0;
+                else still.push_back(k);
+            }
+            if (still.size() != active.size()) need_upload = true;
+            active.swap(still);
+        }
+    }
+    bool any_running = !ctx->batched;
     while (any_running) {
         any_running = false;
         for (int k = 0; k < n; ++k) {
@@ -496,6 +740,46 @@ mdf_status mdf_invariants(const mdf_ctx *cctx, int32_t case_id, double *out, voi
     return MDF_OK;
 }
 
+mdf_status mdf_autotune(mdf_ctx *ctx, int32_t trial_steps, int32_t *chosen, double *best_ms, void *stream)
+{
+    if (!ctx) return fail(nullptr, MDF_EINVAL, "mdf_autotune: ctx is NULL");
+    if (trial_steps < 1) return fail(ctx, MDF_EINVAL, "mdf_autotune: trial_steps < 1");
+    static const int cand[][3] = {{64, 4, 8}, {128, 2, 8}, {256, 1, 8}, {64, 2, 8},
+                                  {64, 1, 8}, {64, 4, 1}, {128, 1, 8}, {32, 8, 8}};
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return device_error(ctx, e, "event create");
+    float best = 1e30f;
+    int bi = 0;
+    mdf_status r = MDF_OK;
+    for (int c = 0; c < int(sizeof cand / sizeof cand[0]) && r == MDF_OK; ++c) {
+        r = mdf_set_launch(ctx, cand[c][0], cand[c][1], cand[c][2]);
+        if (r != MDF_OK) break;
+        r = step_impl(ctx, 1, 0, nullptr, stream);           // warm-up (and graph capture)
+        if (r != MDF_OK) break;
+        e = hipEventRecord(e0, st);
+        if (e == hipSuccess) {
+            r = step_impl(ctx, trial_steps, 0, nullptr, stream);
+            if (r != MDF_OK) break;
+            e = hipEventRecord(e1, st);
+        }
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) { r = device_error(ctx, e, "autotune timing"); break; }
+        if (ms < best) { best = ms; bi = c; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (r != MDF_OK) return r;
+    r = mdf_set_launch(ctx, cand[bi][0], cand[bi][1], cand[bi][2]);
+    if (chosen) { chosen[0] = cand[bi][0]; chosen[1] = cand[bi][1]; chosen[2] = cand[bi][2]; }
+    if (best_ms) *best_ms = double(best) / trial_steps;
+    return r;
+}
+
 int64_t mdf_time(const mdf_ctx *ctx, int32_t case_id)
 {
     if (!ctx || !case_ok(ctx, case_id)) return -1;
@@ -510,6 +794,7 @@ const char *mdf_last_error(const mdf_ctx *ctx)
 
 mdf_status mdf_destroy(mdf_ctx *ctx)
 {
+    if (ctx) drop_graphs(ctx);
     delete ctx;
     return MDF_OK;
 }

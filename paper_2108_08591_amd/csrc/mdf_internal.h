@@ -52,6 +52,33 @@ struct Tiling {
 
 enum ReadMode { kReadFields = 0, kReadPops = 1, kReadCheck = 2, kReadSums = 3 };
 
+// One case of a batched context, as the batched kernel reads it from device
+// memory (the host keeps a mirror and uploads it before batched launches).
+struct BatchEntry {
+    KCase p;
+    void *pop[2];
+    const uint8_t *links;
+    void *snap;
+    double *partial;
+    double *result;
+    void *out;              // emitted fields of the current call, or null
+    int gx, gy, ntiles;     // tile grid of the case for the batch launch shape
+    int cur;                // buffer holding f*(t) when the table was uploaded
+};
+
+// Arguments of one batched launch.
+struct BatchLaunch {
+    const BatchEntry *tab;  // device table (all cases)
+    const int *meta;        // device: {active cases, total tiles}
+    const int *tile_start;  // device: prefix offsets of the active cases' tiles
+    const int *active;      // device: case ids of the active cases
+    int parity;             // steps since the table upload, mod 2
+    uint32_t fields;        // emitted fields (0: none)
+    int grid;               // blocks of the persistent launch
+    bool mask;              // any case has obstacles
+    LaunchShape shape;
+};
+
 // Launchers (implemented in mdf_kernels.hip).  All enqueue on `stream` and
 // return the hipError_t of the launch.
 hipError_t launch_links(int lattice, const KCase &p, const uint8_t *solid, uint8_t *links,
@@ -65,6 +92,10 @@ hipError_t launch_read(int lattice, int storage, const KCase &p, const CaseBufs 
                        bool pull, int mode, uint32_t fields, void *out, LaunchShape shape,
                        int *nblocks_out, hipStream_t stream);
 hipError_t launch_finalize(const CaseBufs &b, int nblocks, hipStream_t stream);
+hipError_t launch_step_batch(int lattice, int storage, const BatchLaunch &bl, bool check, hipStream_t stream);
+hipError_t batch_blocks_per_cu(int lattice, int storage, LaunchShape shape, bool mask, int *blocks_per_cu);
+hipError_t launch_finalize_batch(const BatchEntry *tab, const int *meta, const int *active, int nactive,
+                                 hipStream_t stream);
 
 int grid_blocks(const KCase &p, LaunchShape shape);
 

@@ -457,21 +457,22 @@ __device__ __forceinline__ void check_values(const Moments<L, C> &m, bool valid,
 
 // ----------------------------------------------------------------- kernels
 
-// One time step: pull, wall rule, moments, optional fields and check,
-// collision + forcing, write.
+// One tile of one time step: pull, wall rule, moments, optional fields and
+// check, collision + forcing, write.  Shared by the single-case and the
+// batched kernels, so both produce bitwise identical populations.
 template <class L, int ST, bool EMIT, bool CHECK, bool MASK>
-__global__ void __launch_bounds__(256)
-k_step(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, typename Store<ST>::T *__restrict__ dst,
-       const uint8_t *__restrict__ links, uint32_t fields, typename Store<ST>::C *__restrict__ out,
-       typename Store<ST>::C *__restrict__ snap, double *__restrict__ partial)
+__device__ __forceinline__ void step_tile(const KCase &p, int gx, int gy, int tile,
+                                          const typename Store<ST>::T *__restrict__ src,
+                                          typename Store<ST>::T *__restrict__ dst, const uint8_t *__restrict__ links,
+                                          uint32_t fields, typename Store<ST>::C *__restrict__ out,
+                                          typename Store<ST>::C *__restrict__ snap, double *__restrict__ partial)
 {
     using S = Store<ST>;
     using C = typename S::C;
-    const int tile = block_tile(tl);
-    const int tx = tile % tl.gx, rest = tile / tl.gx;
+    const int tx = tile % gx, rest = tile / gx;
     const int x = tx * blockDim.x + threadIdx.x;
-    const int y = (rest % tl.gy) * blockDim.y + threadIdx.y;
-    const int z = rest / tl.gy;
+    const int y = (rest % gy) * blockDim.y + threadIdx.y;
+    const int z = rest / gy;
     const bool inside = (x < p.nx) && (y < p.ny);
     Node<L, C> n;
     Moments<L, C> m;
@@ -509,6 +510,76 @@ k_step(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, typena
         check_values<L, C, true>(m, fluid, snap, node, nodes, v);
         block_reduce_store(v, partial, tile);
     }
+}
+
+template <class L, int ST, bool EMIT, bool CHECK, bool MASK>
+__global__ void __launch_bounds__(256)
+k_step(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, typename Store<ST>::T *__restrict__ dst,
+       const uint8_t *__restrict__ links, uint32_t fields, typename Store<ST>::C *__restrict__ out,
+       typename Store<ST>::C *__restrict__ snap, double *__restrict__ partial)
+{
+    step_tile<L, ST, EMIT, CHECK, MASK>(p, tl.gx, tl.gy, block_tile(tl), src, dst, links, fields, out, snap,
+                                        partial);
+}
+
+// Batched step: one persistent launch advances every active case of a
+// context by one step.  The tiles of all active cases form one flat list
+// (case k owns tiles tile_start[k] .. tile_start[k+1]-1); the grid is sized
+// to the resident capacity of the chip and each block walks the list.  Tiles
+// are dealt in XCD bands: blocks b with b % groups == g take the g-th
+// contiguous band of the list, so neighbouring tiles of a case share an L2.
+template <class L, int ST, bool EMIT, bool CHECK, bool MASK>
+__global__ void __launch_bounds__(256)
+k_step_batch(const BatchEntry *__restrict__ tab, const int *__restrict__ meta, const int *__restrict__ tile_start,
+             const int *__restrict__ active, int parity, uint32_t fields, int groups)
+{
+    const int nact = meta[0], total = meta[1];
+    const int G = gridDim.x;
+    const int ng = (groups > 1 && G % groups == 0) ? groups : 1;
+    const int g = blockIdx.x % ng, per = G / ng, slot = blockIdx.x / ng;
+    const int band_lo = (int)((long long)total * g / ng), band_hi = (int)((long long)total * (g + 1) / ng);
+    for (int t = band_lo + slot; t < band_hi; t += per) {
+        int lo = 0, hi = nact - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tile_start[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchEntry &e = tab[active[lo]];
+        const int sel = (e.cur + parity) & 1;
+        using T = typename Store<ST>::T;
+        using C = typename Store<ST>::C;
+        step_tile<L, ST, EMIT, CHECK, MASK>(e.p, e.gx, e.gy, t - tile_start[lo], static_cast<const T *>(e.pop[sel]),
+                                            static_cast<T *>(e.pop[sel ^ 1]), e.links, fields,
+                                            static_cast<C *>(e.out), static_cast<C *>(e.snap), e.partial);
+        if (CHECK) __syncthreads();   // the block reduction's LDS is reused by the next tile
+    }
+}
+
+// Fixed-order sum of each active case's per-tile partials (one block per case).
+__global__ void __launch_bounds__(256)
+k_finalize_batch(const BatchEntry *__restrict__ tab, const int *__restrict__ meta, const int *__restrict__ active)
+{
+    __shared__ double red[kNRed][256];
+    if ((int)blockIdx.x >= meta[0]) return;
+    const BatchEntry &e = tab[active[blockIdx.x]];
+    const int t = threadIdx.x;
+    double acc[kNRed];
+#pragma unroll
+    for (int k = 0; k < kNRed; ++k) acc[k] = 0.0;
+    for (int b = t; b < e.ntiles; b += 256)
+#pragma unroll
+        for (int k = 0; k < kNRed; ++k) acc[k] += e.partial[(long long)b * kNRed + k];
+#pragma unroll
+    for (int k = 0; k < kNRed; ++k) red[k][t] = acc[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s)
+#pragma unroll
+            for (int k = 0; k < kNRed; ++k) red[k][t] += red[k][t + s];
+        __syncthreads();
+    }
+    if (t < kNRed) e.result[t] = red[t][0];
 }
 
 // Read-only pass at the current time: fields, populations or a check.
@@ -643,7 +714,8 @@ k_init(KCase p, typename Store<ST>::T *__restrict__ pre, typename Store<ST>::T *
     }
 }
 
-// Solid flags and upstream-solid link bits of every node.
+// Solid flags and upstream-solid link bits of every node (all zero when
+// `solid` is null: a case without obstacles in a context where others have them).
 template <class L>
 __global__ void __launch_bounds__(256) k_links(KCase p, const uint8_t *__restrict__ solid, uint8_t *__restrict__ links)
 {
@@ -652,7 +724,7 @@ __global__ void __launch_bounds__(256) k_links(KCase p, const uint8_t *__restric
     const int z = blockIdx.z;
     if (x >= p.nx || y >= p.ny) return;
     const long long node = ((long long)z * p.ny + y) * p.nx + x;
-    unsigned bits = solid[node] ? 0x80u : 0u;
+    unsigned bits = (solid && solid[node]) ? 0x80u : 0u;
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
         int s[3] = {x - L::cx[i], y - L::cy[i], z - L::cz[i]};
@@ -662,7 +734,7 @@ __global__ void __launch_bounds__(256) k_links(KCase p, const uint8_t *__restric
             if (s[b] < 0) { if (p.bc[2 * b] == MDF_WALL) outside = true; else s[b] += nn[b]; }
             else if (s[b] >= nn[b]) { if (p.bc[2 * b + 1] == MDF_WALL) outside = true; else s[b] -= nn[b]; }
         }
-        if (!outside && solid[((long long)s[2] * p.ny + s[1]) * p.nx + s[0]]) bits |= (1u << i);
+        if (!outside && solid && solid[((long long)s[2] * p.ny + s[1]) * p.nx + s[0]]) bits |= (1u << i);
     }
     links[((long long)z * p.ny + y) * p.pitch + x] = (uint8_t)bits;
 }
@@ -784,6 +856,36 @@ hipError_t init_dispatch(const KCase &p, const CaseBufs &b, int cur, int kind, c
     return hipGetLastError();
 }
 
+template <class L, int ST>
+hipError_t batch_dispatch(const BatchLaunch &bl, bool check, bool emit, hipStream_t stream)
+{
+    const dim3 grid(bl.grid, 1, 1), block(bl.shape.bx, bl.shape.by, 1);
+#define MDF_BATCH_LAUNCH(E, K, M)                                                                      \
+    hipLaunchKernelGGL((k_step_batch<L, ST, E, K, M>), grid, block, 0, stream, bl.tab, bl.meta, bl.tile_start, \
+                       bl.active, bl.parity, bl.fields, bl.shape.groups)
+    if (bl.mask) {
+        if (emit) { if (check) MDF_BATCH_LAUNCH(true, true, true); else MDF_BATCH_LAUNCH(true, false, true); }
+        else { if (check) MDF_BATCH_LAUNCH(false, true, true); else MDF_BATCH_LAUNCH(false, false, true); }
+    } else {
+        if (emit) { if (check) MDF_BATCH_LAUNCH(true, true, false); else MDF_BATCH_LAUNCH(true, false, false); }
+        else { if (check) MDF_BATCH_LAUNCH(false, true, false); else MDF_BATCH_LAUNCH(false, false, false); }
+    }
+#undef MDF_BATCH_LAUNCH
+    return hipGetLastError();
+}
+
+template <class L, int ST>
+hipError_t batch_capacity(LaunchShape shape, bool mask, int *blocks_per_cu)
+{
+    // resident blocks per CU of the heaviest variant (emit + check)
+    const int threads = shape.bx * shape.by;
+    if (mask)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_step_batch<L, ST, true, true, true>,
+                                                            threads, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_step_batch<L, ST, true, true, false>,
+                                                        threads, 0);
+}
+
 }  // namespace
 
 int grid_blocks(const KCase &p, LaunchShape s)
@@ -846,6 +948,29 @@ hipError_t launch_links(int lattice, const KCase &p, const uint8_t *solid, uint8
 hipError_t launch_finalize(const CaseBufs &b, int nblocks, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, stream, b.partial, nblocks, b.result);
+    return hipGetLastError();
+}
+
+}  // namespace mdf
+
+namespace mdf {
+
+hipError_t launch_step_batch(int lattice, int storage, const BatchLaunch &bl, bool check, hipStream_t stream)
+{
+    const bool emit = bl.fields != 0;
+    MDF_DISPATCH(lattice, storage, batch_dispatch, bl, check, emit, stream);
+}
+
+hipError_t batch_blocks_per_cu(int lattice, int storage, LaunchShape shape, bool mask, int *blocks_per_cu)
+{
+    MDF_DISPATCH(lattice, storage, batch_capacity, shape, mask, blocks_per_cu);
+}
+
+hipError_t launch_finalize_batch(const BatchEntry *tab, const int *meta, const int *active, int nactive,
+                                 hipStream_t stream)
+{
+    if (nactive <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finalize_batch, dim3(nactive), dim3(256), 0, stream, tab, meta, active);
     return hipGetLastError();
 }
 

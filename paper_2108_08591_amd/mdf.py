@@ -31,7 +31,7 @@ STORAGE_NAMES = {"f64": F64, "f32": F32, "f16dev": F16DEV, "bf16dev": BF16DEV}
 
 EXPORTED = ["mdf_workspace_size", "mdf_init", "mdf_step", "mdf_step_emit", "mdf_moments",
             "mdf_gradients", "mdf_populations", "mdf_check", "mdf_run_steady", "mdf_invariants",
-            "mdf_set_launch", "mdf_time", "mdf_last_error", "mdf_destroy"]
+            "mdf_set_launch", "mdf_autotune", "mdf_time", "mdf_last_error", "mdf_destroy"]
 
 
 class MdfError(RuntimeError):
@@ -80,6 +80,7 @@ def lib():
                                      ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(dbl), vp]
         L.mdf_invariants.argtypes = [vp, i32, ctypes.POINTER(dbl), vp]
         L.mdf_set_launch.argtypes = [vp, i32, i32, i32]
+        L.mdf_autotune.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl), vp]
         L.mdf_time.argtypes = [vp, i32]
         L.mdf_time.restype = i64
         L.mdf_last_error.argtypes = [vp]
@@ -87,7 +88,7 @@ def lib():
         L.mdf_destroy.argtypes = [vp]
         for name in ("mdf_init", "mdf_step", "mdf_step_emit", "mdf_moments", "mdf_gradients",
                      "mdf_populations", "mdf_check", "mdf_run_steady", "mdf_invariants",
-                     "mdf_set_launch", "mdf_destroy"):
+                     "mdf_set_launch", "mdf_autotune", "mdf_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -241,6 +242,17 @@ class Solver:
     def _sync(self):
         (self.stream or torch.cuda.current_stream()).synchronize()
 
+    def _handoff(self, *tensors):
+        """Outputs written on the solver's own stream become safe to use on
+        torch's current stream (and are kept alive for the allocator)."""
+        if self.stream is None:
+            return
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
+            for t in tensors:
+                t.record_stream(self.stream)
+
     def __del__(self):
         ctx = getattr(self, "_ctx", None)
         if ctx is not None and ctx.value:
@@ -253,6 +265,14 @@ class Solver:
     # -------------------------------------------------------------- stepping
     def set_launch(self, bx: int, by: int, groups: int = 8):
         _check(lib().mdf_set_launch(self._ctx, bx, by, groups), self._ctx)
+
+    def autotune(self, trial_steps: int = 20):
+        """Pick the fastest launch shape on real steps (advances time)."""
+        chosen = (ctypes.c_int32 * 3)()
+        best = ctypes.c_double()
+        _check(lib().mdf_autotune(self._ctx, int(trial_steps), chosen, ctypes.byref(best),
+                                  _stream_ptr(self.stream)), self._ctx)
+        return tuple(chosen[:]), best.value
 
     def step(self, nsteps: int = 1):
         _check(lib().mdf_step(self._ctx, int(nsteps), _stream_ptr(self.stream)), self._ctx)
@@ -268,6 +288,7 @@ class Solver:
         arr = (ctypes.c_void_p * len(out))(*[t.data_ptr() for t in out])
         _check(lib().mdf_step_emit(self._ctx, int(nsteps), int(fields), arr,
                                    _stream_ptr(self.stream)), self._ctx)
+        self._handoff(*out)
         return out
 
     def time(self, case: int = 0) -> int:
@@ -279,12 +300,14 @@ class Solver:
                           device=self.device)
         _check(lib().mdf_gradients(self._ctx, case, int(fields), ctypes.c_void_p(out.data_ptr()),
                                    _stream_ptr(self.stream)), self._ctx)
+        self._handoff(out)
         return out
 
     def moments(self, case: int = 0) -> torch.Tensor:
         out = torch.empty((self.d + 2,) + self.specs[case].fshape, dtype=self.dtype, device=self.device)
         _check(lib().mdf_moments(self._ctx, case, ctypes.c_void_p(out.data_ptr()),
                                  _stream_ptr(self.stream)), self._ctx)
+        self._handoff(out)
         return out
 
     def fields(self, fields: int = FIELD_ALL, case: int = 0) -> Dict[str, torch.Tensor]:
@@ -295,6 +318,7 @@ class Solver:
                           device=self.device)
         _check(lib().mdf_populations(self._ctx, case, ctypes.c_void_p(out.data_ptr()),
                                      _stream_ptr(self.stream)), self._ctx)
+        self._handoff(out)
         return out
 
     def check(self):
