@@ -242,6 +242,155 @@ def sweep(out_path):
             torch.cuda.empty_cache()
 
 
+def _rel(ref, got, scale=None):
+    import torch
+    num = torch.linalg.vector_norm((ref - got.to(ref.dtype)).reshape(-1)).item()
+    den = torch.linalg.vector_norm(ref.reshape(-1)).item()
+    if scale is not None:
+        den = max(den, scale)
+    return num / den if den > 0 else num
+
+
+def precision_study(out_path, N=256, steps=(1000, 2500, 5000)):
+    """3D Taylor-Green on a periodic N^3 box, D3Q7 x 4 sets, u0 = 0.05,
+    Re = 100 and 1600: FP32, FP16- and BF16-deviation storage against the
+    FP64-storage run of the same kernels (whose parity with the FP64 oracle
+    is tested at small sizes), relative L2 error per field at each step
+    count, and the step time of each storage."""
+    import numpy as np
+    import torch
+    from paper_2108_08591_amd import cases as C
+    from paper_2108_08591_amd import mdf
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    fields = mdf.FIELD_MOMENTS | mdf.FIELD_VORT
+    res = []
+    P, u = C.taylor_green_3d_initial(N, 0.05)
+    init64 = torch.tensor(np.concatenate([P[None], u], axis=0))
+    del P, u
+    for Re in (100.0, 1600.0):
+        spec = C.tgv3d_case(N=N, u0=0.05, Re=Re)
+        ref = {}
+        for st in ("f64", "f32", "f16dev", "bf16dev"):
+            dt = torch.float64 if st == "f64" else torch.float32
+            solver = mdf.Solver([spec], storage=st, device=dev, stream=stream, u_ref=0.05,
+                                init=("fields", [init64.to(dt)]))
+            rec = {"Re": Re, "N": N, "s1": spec.s1, "storage": st, "errors": {}}
+            t_total, done = 0.0, 0
+            for t in steps:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                solver.step(t - done)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                t_total += e0.elapsed_time(e1) / 1e3
+                done = t
+                f = solver.fields(fields)
+                torch.cuda.synchronize()
+                cur = {"u": f["u"].double(), "P": f["P"].double(), "vort": f["vort"].double()}
+                finite = all(bool(torch.isfinite(v).all()) for v in cur.values())
+                if st == "f64":
+                    ref[t] = cur
+                    rec["errors"][str(t)] = {"finite": finite,
+                                             "u_rms": float(cur["u"].pow(2).mean().sqrt())}
+                else:
+                    uscale = torch.linalg.vector_norm(ref[t]["u"].reshape(-1)).item()
+                    rec["errors"][str(t)] = {
+                        "finite": finite,
+                        "u": _rel(ref[t]["u"], cur["u"]),
+                        "P": _rel(ref[t]["P"], cur["P"], scale=uscale),
+                        "vort": _rel(ref[t]["vort"], cur["vort"]),
+                    }
+            rec["ms_per_step"] = round(t_total * 1e3 / steps[-1], 4)
+            rec["MLUPS"] = round(spec.nodes * steps[-1] / t_total / 1e6, 1)
+            res.append(rec)
+            print(json.dumps(rec), flush=True)
+            del solver
+            torch.cuda.empty_cache()
+        ref.clear()
+    with open(out_path, "w") as fh:
+        json.dump(res, fh, indent=1)
+
+
+def batch_study(out_path, ncases=512, max_steps=300000):
+    """The seeded uneven batch: 512 cavity/channel cases, N in {64..512},
+    Re log-uniform in [10, 1000], FP32, one persistent launch per step;
+    autotuned launch shape, throughput, then every case run to residual
+    1e-8 (checked every 100 steps)."""
+    import numpy as np
+    import torch
+    from paper_2108_08591_amd import cases as C
+    from paper_2108_08591_amd import mdf
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    bc = C.batch_cases(n=ncases)
+    specs = [c.spec for c in bc]
+    nodes = sum(s.nodes for s in specs)
+    t0 = time.perf_counter()
+    solver = mdf.Solver(specs, storage="f32", device=dev, stream=stream)
+    chosen, tuned_ms = solver.autotune(trial_steps=20)
+    torch.cuda.synchronize()
+    rec = {"cases": ncases, "nodes": nodes, "autotune_shape": chosen, "autotune_ms_per_step": tuned_ms}
+    n = 500
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    solver.step(n)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / n
+    rec["throughput_MLUPS"] = round(nodes / ms / 1e3, 1)
+    rec["ms_per_batched_step"] = round(ms, 4)
+    print(json.dumps(rec), flush=True)
+    t1 = time.perf_counter()
+    st, steps, res = solver.run_steady(1e-8, 100, max_steps)
+    wall = time.perf_counter() - t1
+    node_steps = float(sum(sp.nodes * int(k) for sp, k in zip(specs, steps)))
+    rec.update({
+        "steady_wall_s": round(wall, 2),
+        "init_to_steady_wall_s": round(time.perf_counter() - t0, 2),
+        "converged": int((st == 0).sum()), "nonfinite": int((st == 1).sum()), "not_converged": int((st == 2).sum()),
+        "steps_min": int(steps.min()), "steps_median": int(np.median(steps)), "steps_max": int(steps.max()),
+        "node_steps": node_steps, "effective_MLUPS": round(node_steps / wall / 1e6, 1),
+        "nonfinite_cases": [{"kind": bc[k].kind, "N": bc[k].N, "Re": round(bc[k].Re, 1), "U": round(bc[k].U, 4)}
+                            for k in range(ncases) if st[k] == 1][:20],
+        "unconverged_cases": [{"kind": bc[k].kind, "N": bc[k].N, "Re": round(bc[k].Re, 1),
+                               "residual": float(res[k])} for k in range(ncases) if st[k] == 2][:20],
+    })
+    print(json.dumps(rec), flush=True)
+    with open(out_path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+
+
+def steady_study(out_path):
+    """Wall time from initialisation to residual 1e-8 (K = 100) for the
+    channel and the cavities of the benchmark configuration (FP32, vorticity
+    and strain rate emitted every step for the cavities)."""
+    import torch
+    from paper_2108_08591_amd import cases as C
+    from paper_2108_08591_amd import mdf
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    out = []
+    runs = [("poiseuille 256x64", C.poiseuille_case(256, 64), 0),
+            ("cavity 1024^2 Re=100", C.cavity_case(N=1024, Re=100.0), mdf.FIELD_VORT | mdf.FIELD_STRAIN),
+            ("cavity 1024^2 Re=1000", C.cavity_case(N=1024, Re=1000.0), mdf.FIELD_VORT | mdf.FIELD_STRAIN)]
+    for name, spec, fields in runs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solver = mdf.Solver([spec], storage="f32", device=dev, stream=stream)
+        bufs = solver.new_field_buffers(fields) if fields else None
+        st, steps, res = solver.run_steady(1e-8, 100, 5_000_000, fields, bufs)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        rec = {"case": name, "status": int(st[0]), "steps": int(steps[0]), "residual": float(res[0]),
+               "wall_s": round(wall, 3), "MLUPS": round(spec.nodes * int(steps[0]) / wall / 1e6, 1)}
+        print(json.dumps(rec), flush=True)
+        out.append(rec)
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,12 +408,24 @@ def main():
                     metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB", "OUT_MD"),
                     help="calibrated HBM traffic of the step kernel from rocprofv3 counter databases")
     ap.add_argument("--command", default="", help="command recorded in a summary")
+    ap.add_argument("--precision-study", metavar="OUT_JSON", help="FP16/BF16/FP32 vs FP64 storage, 3D TGV")
+    ap.add_argument("--batch-study", metavar="OUT_JSON", help="512-case uneven batch to steady state")
+    ap.add_argument("--steady-study", metavar="OUT_JSON", help="wall time to residual 1e-8")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
         return
     if args.sweep:
         sweep(args.sweep)
+        return
+    if args.precision_study:
+        precision_study(args.precision_study)
+        return
+    if args.batch_study:
+        batch_study(args.batch_study)
+        return
+    if args.steady_study:
+        steady_study(args.steady_study)
         return
     if args.summarize_trace:
         with open(args.summarize_trace[1], "w") as fh:

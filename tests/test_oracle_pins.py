@@ -455,3 +455,19 @@ def test_poiseuille_3d_channel():
     off = fl["u"][0][0, :, 0] - ex["u1"]
     assert np.ptp(off) < 1e-15 and 0 < -off[0] < 1e-6
     assert np.allclose(fl["grad"][0, 1][0, :, 0], ex["du1dy"], atol=1e-15)
+
+
+def test_vortex_finder_on_closed_form():
+    """The vortex-centre tool used on GPU results: for psi = -sin(pi x) sin(pi y)
+    (u = d psi/dy) the primary centre is (0.5, 0.5) and the vorticity there
+    is -laplacian(psi) = -2 pi^2 (in units of the side)."""
+    from vortex import find_vortex, stream_function
+    n = 128
+    c = (np.arange(n) + 0.5) / n
+    X, Y = np.meshgrid(c, c, indexing="xy")
+    u = -np.pi * np.sin(np.pi * X) * np.cos(np.pi * Y) / n     # u per node spacing
+    vort = -2 * np.pi ** 2 * np.sin(np.pi * X) * np.sin(np.pi * Y)
+    psi = stream_function(u)
+    w, x, y = find_vortex(psi, vort, (0.2, 0.8, 0.2, 0.8), "min")
+    assert abs(x - 0.5) < 1e-3 and abs(y - 0.5) < 1e-3
+    assert abs(w / (-2 * np.pi ** 2) - 1) < 1e-3
