@@ -270,12 +270,18 @@ def precision_study(out_path, N=256, steps=(1000, 2500, 5000)):
     del P, u
     for Re in (100.0, 1600.0):
         spec = C.tgv3d_case(N=N, u0=0.05, Re=Re)
+        if Re > 1000.0:
+            # s1 = 1.98 here; the even-moment rate 8(2-s1)/(8-s1) = 0.027 of
+            # the paper's D2Q5 runs diverges within 500 steps, s2 >= 1.2 is
+            # stable through 5000 (probe at the same cell Reynolds number)
+            spec.s2 = 1.5
         ref = {}
         for st in ("f64", "f32", "f16dev", "bf16dev"):
             dt = torch.float64 if st == "f64" else torch.float32
             solver = mdf.Solver([spec], storage=st, device=dev, stream=stream, u_ref=0.05,
                                 init=("fields", [init64.to(dt)]))
-            rec = {"Re": Re, "N": N, "s1": spec.s1, "storage": st, "errors": {}}
+            rec = {"Re": Re, "N": N, "s1": spec.s1, "s2": spec.s2 if spec.s2 > 0 else 8 * (2 - spec.s1) / (8 - spec.s1),
+                   "storage": st, "errors": {}}
             t_total, done = 0.0, 0
             for t in steps:
                 e0 = torch.cuda.Event(enable_timing=True)
@@ -313,7 +319,7 @@ def precision_study(out_path, N=256, steps=(1000, 2500, 5000)):
         json.dump(res, fh, indent=1)
 
 
-def batch_study(out_path, ncases=512, max_steps=300000):
+def batch_study(out_path, ncases=512, max_steps=400000, wall_budget_s=420.0):
     """The seeded uneven batch: 512 cavity/channel cases, N in {64..512},
     Re log-uniform in [10, 1000], FP32, one persistent launch per step;
     autotuned launch shape, throughput, then every case run to residual
@@ -343,10 +349,32 @@ def batch_study(out_path, ncases=512, max_steps=300000):
     rec["ms_per_batched_step"] = round(ms, 4)
     print(json.dumps(rec), flush=True)
     t1 = time.perf_counter()
-    st, steps, res = solver.run_steady(1e-8, 100, max_steps)
+    # windows of run_steady: finished cases are retired between windows and
+    # progress is reported (the residual snapshot carries over)
+    n = len(specs)
+    st = np.full(n, 2)
+    steps = np.zeros(n, np.int64)
+    res = np.full(n, np.inf)
+    active = np.ones(n, bool)
+    window, done = 20000, 0
+    while active.any() and done < max_steps and time.perf_counter() - t1 < wall_budget_s:
+        solver.set_active(active)
+        w_st, w_steps, w_res = solver.run_steady(1e-8, 100, min(window, max_steps - done))
+        done += window
+        for k in np.nonzero(active)[0]:
+            steps[k] += w_steps[k]
+            res[k] = w_res[k]
+            if w_st[k] in (0, 1):
+                st[k] = w_st[k]
+                active[k] = False
+        print(json.dumps({"progress_steps": done, "converged": int((st == 0).sum()),
+                          "nonfinite": int((st == 1).sum()), "running": int(active.sum()),
+                          "running_nodes": int(sum(specs[k].nodes for k in np.nonzero(active)[0])),
+                          "wall_s": round(time.perf_counter() - t1, 1)}), flush=True)
     wall = time.perf_counter() - t1
     node_steps = float(sum(sp.nodes * int(k) for sp, k in zip(specs, steps)))
     rec.update({
+        "max_steps": max_steps, "wall_budget_s": wall_budget_s,
         "steady_wall_s": round(wall, 2),
         "init_to_steady_wall_s": round(time.perf_counter() - t0, 2),
         "converged": int((st == 0).sum()), "nonfinite": int((st == 1).sum()), "not_converged": int((st == 2).sum()),

@@ -183,7 +183,7 @@ mdf_status mdf_check(mdf_ctx *ctx, double *res, int32_t *status, void *stream);
  * non-finite, or max_steps steps were taken.  Waits for the device once per
  * chunk.  fields/out: as mdf_step_emit (every step writes the selected
  * fields), or 0/NULL.  case_status (host, ncases or NULL): 0 converged,
- * 1 non-finite, 2 not converged.  steps_taken/final_res: host arrays of
+ * 1 non-finite, 2 not converged, 3 disabled (mdf_set_active).  steps_taken/final_res: host arrays of
  * ncases or NULL.  Cases that converge stop advancing; the others continue.
  * Returns MDF_EUNSTABLE if any case went non-finite. */
 mdf_status mdf_run_steady(mdf_ctx *ctx, double tol, int32_t K, int64_t max_steps,
@@ -203,6 +203,13 @@ mdf_status mdf_invariants(const mdf_ctx *ctx, int32_t case_id, double *out, void
  * bitwise identical populations and fields; only the summation order of the
  * FP64 sums of mdf_check, mdf_run_steady and mdf_invariants follows it. */
 mdf_status mdf_set_launch(mdf_ctx *ctx, int32_t bx, int32_t by, int32_t groups);
+
+/* Enable or disable cases.  Disabled cases are skipped by mdf_step,
+ * mdf_step_emit, mdf_run_steady and mdf_autotune: their populations and
+ * time stay unchanged (a disabled case gets status 3 from mdf_run_steady).
+ * active: host int32[ncases], non-zero = enabled.  All cases start enabled.
+ * Read-outs (mdf_moments, mdf_gradients, ...) work on any case. */
+mdf_status mdf_set_active(mdf_ctx *ctx, const int32_t *active);
 
 /* Choose the launch shape of this context by timing candidate shapes
  * (tiles 64x4, 128x2, 256x1, 64x2, 64x1, 32x8, 128x1 with XCD bands, and

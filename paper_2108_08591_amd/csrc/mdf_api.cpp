@@ -154,6 +154,7 @@ struct mdf_ctx {
     std::vector<int> cur;              // buffer holding f*(., t)
     std::vector<int64_t> time;
     std::vector<int64_t> snap_time;    // time of the velocity snapshot, -1 = none
+    std::vector<uint8_t> enabled;      // mdf_set_active
     LaunchShape shape{64, 4, 8};
     hipError_t latched = hipSuccess;
     std::string err;
@@ -477,6 +478,7 @@ mdf_status mdf_init(mdf_ctx **out, mdf_lattice lattice, mdf_storage storage, con
     ctx->cur.assign(ncases, 0);
     ctx->time.assign(ncases, 0);
     ctx->snap_time.assign(ncases, -1);
+    ctx->enabled.assign(ncases, 1);
     ctx->host_red.assign(mdf::kNRed, 0.0);
     char *ws = static_cast<char *>(workspace);
     ctx->batched = ncases > 1;
@@ -547,14 +549,17 @@ static mdf_status step_impl(mdf_ctx *ctx, int32_t nsteps, uint32_t fields, void 
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (ctx->batched) {
-        std::vector<int> all(ctx->ncases);
-        for (int k = 0; k < ctx->ncases; ++k) all[k] = k;
+        std::vector<int> all;
+        for (int k = 0; k < ctx->ncases; ++k)
+            if (ctx->enabled[k]) all.push_back(k);
+        if (all.empty()) return MDF_OK;
         mdf_status r = batch_upload(ctx, all, fields, out, st);
         if (r != MDF_OK) return r;
         return batch_steps(ctx, nsteps, false, fields, st);
     }
     for (int s = 0; s < nsteps; ++s)
         for (int k = 0; k < ctx->ncases; ++k) {
+            if (!ctx->enabled[k]) continue;
             mdf_status r = step_case(ctx, k, false, fields, fields ? out[k] : nullptr, st, nullptr);
             if (r != MDF_OK) return r;
         }
@@ -645,11 +650,14 @@ mdf_status mdf_run_steady(mdf_ctx *ctx, double tol, int32_t K, int64_t max_steps
                                                 hipGetErrorString(ctx->latched));
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int n = ctx->ncases;
-    std::vector<int> state(n, 2);              // 0 converged, 1 non-finite, 2 running
+    std::vector<int> state(n, 2);              // 0 converged, 1 non-finite, 2 running, 3 disabled
     std::vector<double> res(n, INFINITY);
     std::vector<int64_t> start(ctx->time.begin(), ctx->time.end());
+    for (int k = 0; k < n; ++k)
+        if (!ctx->enabled[k]) state[k] = 3;
     // first snapshot
     for (int k = 0; k < n; ++k) {
+        if (state[k] != 2) continue;
         if (ctx->snap_time[k] >= 0 && ctx->snap_time[k] == ctx->time[k]) continue;
         int nb = 0;
         mdf_status r = read_impl(ctx, k, mdf::kReadCheck, 0, nullptr, stream, &nb);
@@ -737,6 +745,14 @@ mdf_status mdf_invariants(const mdf_ctx *cctx, int32_t case_id, double *out, voi
     for (int a = 0; a <= ctx->d; ++a) out[a] = red[2 + a];
     out[ctx->d + 1] = red[6];
     if (red[7] != 0.0) return fail(ctx, MDF_EUNSTABLE, "mdf_invariants: non-finite values");
+    return MDF_OK;
+}
+
+mdf_status mdf_set_active(mdf_ctx *ctx, const int32_t *active)
+{
+    if (!ctx) return fail(nullptr, MDF_EINVAL, "mdf_set_active: ctx is NULL");
+    if (!active) return fail(ctx, MDF_EINVAL, "mdf_set_active: active is NULL");
+    for (int k = 0; k < ctx->ncases; ++k) ctx->enabled[k] = active[k] != 0;
     return MDF_OK;
 }
 

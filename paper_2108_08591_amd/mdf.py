@@ -31,7 +31,8 @@ STORAGE_NAMES = {"f64": F64, "f32": F32, "f16dev": F16DEV, "bf16dev": BF16DEV}
 
 EXPORTED = ["mdf_workspace_size", "mdf_init", "mdf_step", "mdf_step_emit", "mdf_moments",
             "mdf_gradients", "mdf_populations", "mdf_check", "mdf_run_steady", "mdf_invariants",
-            "mdf_set_launch", "mdf_autotune", "mdf_time", "mdf_last_error", "mdf_destroy"]
+            "mdf_set_launch", "mdf_set_active", "mdf_autotune", "mdf_time", "mdf_last_error",
+            "mdf_destroy"]
 
 
 class MdfError(RuntimeError):
@@ -81,6 +82,7 @@ def lib():
         L.mdf_invariants.argtypes = [vp, i32, ctypes.POINTER(dbl), vp]
         L.mdf_set_launch.argtypes = [vp, i32, i32, i32]
         L.mdf_autotune.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl), vp]
+        L.mdf_set_active.argtypes = [vp, ctypes.POINTER(i32)]
         L.mdf_time.argtypes = [vp, i32]
         L.mdf_time.restype = i64
         L.mdf_last_error.argtypes = [vp]
@@ -88,7 +90,7 @@ def lib():
         L.mdf_destroy.argtypes = [vp]
         for name in ("mdf_init", "mdf_step", "mdf_step_emit", "mdf_moments", "mdf_gradients",
                      "mdf_populations", "mdf_check", "mdf_run_steady", "mdf_invariants",
-                     "mdf_set_launch", "mdf_autotune", "mdf_destroy"):
+                     "mdf_set_launch", "mdf_set_active", "mdf_autotune", "mdf_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -265,6 +267,11 @@ class Solver:
     # -------------------------------------------------------------- stepping
     def set_launch(self, bx: int, by: int, groups: int = 8):
         _check(lib().mdf_set_launch(self._ctx, bx, by, groups), self._ctx)
+
+    def set_active(self, active):
+        """Enable (non-zero) or disable (0) each case."""
+        arr = (ctypes.c_int32 * len(self.specs))(*[int(bool(a)) for a in active])
+        _check(lib().mdf_set_active(self._ctx, arr), self._ctx)
 
     def autotune(self, trial_steps: int = 20):
         """Pick the fastest launch shape on real steps (advances time)."""

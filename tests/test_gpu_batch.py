@@ -114,3 +114,21 @@ def test_autotune_keeps_results():
     ref.step(n)
     for k in range(len(specs)):
         assert torch.equal(a.populations(k), ref.populations(k))
+
+
+def test_set_active_freezes_disabled_cases():
+    specs = _mixed_cases()[:3]
+    stream = torch.cuda.Stream()
+    _say("[batch] set_active")
+    b = mdf.Solver(specs, storage="f32", device=DEV, stream=stream)
+    b.step(6)
+    frozen = b.populations(1).clone()
+    b.set_active([1, 0, 1])
+    b.step(9)
+    assert b.time(1) == 6 and b.time(0) == 15 and b.time(2) == 15
+    assert torch.equal(b.populations(1), frozen)
+    st, steps, res = b.run_steady(1e-30, 50, 100)
+    assert st[1] == 3 and steps[1] == 0 and b.time(1) == 6
+    ref = mdf.Solver([specs[0]], storage="f32", device=DEV, stream=stream)
+    ref.step(115)
+    assert torch.equal(b.populations(0), ref.populations())
