@@ -419,6 +419,83 @@ def steady_study(out_path):
         json.dump(out, fh, indent=1)
 
 
+def warmstart_study(out_path, n_train=1024, n_test=32, N=128, epochs=30, batch=16):
+    """Learned warm start (cavities with obstacles, N^2): training data from
+    the batched FP32 solver (residual 1e-7), training of the encoder-decoder
+    with the project's kernels, then cold vs warm FP64 solves of held-out
+    cases to residual 1e-8, and the ablation with f^eq-only warm starts."""
+    import numpy as np
+    import torch
+    from paper_2108_08591_amd import nn
+    from paper_2108_08591_amd import warmstart as WS
+    log = lambda m: print(m, flush=True)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    rec = {"N": N, "n_train": n_train, "n_test": n_test, "epochs": epochs, "batch": batch}
+    tr = WS.warmstart_cases(n_train, N, seed=20210819)
+    te = WS.warmstart_cases(n_test, N, seed=20210820)
+    solver, st, steps, res, wall = WS.solve(tr, "f32", tol=1e-7, max_steps=300000, stream=stream, log=log)
+    good = [k for k in range(n_train) if st[k] == 0]
+    rec.update({"datagen_wall_s": round(wall, 1), "datagen_converged": len(good),
+                "datagen_nonfinite": int((st == 1).sum()), "datagen_steps_median": int(np.median(steps))})
+    log(json.dumps({k: rec[k] for k in ("datagen_wall_s", "datagen_converged", "datagen_nonfinite")}))
+    data = WS.dataset([tr[k] for k in good], _Subset(solver, good))
+    del solver
+    torch.cuda.empty_cache()
+    model = nn.UNet(device="cuda:0", seed=0)
+    rec["params"] = model.nparams
+    t0 = time.perf_counter()
+    hist = WS.train(model, data, epochs=epochs, batch=batch, lr=2e-3, log=log)
+    torch.cuda.synchronize()
+    rec["train_wall_s"] = round(time.perf_counter() - t0, 1)
+    rec["loss_history"] = [round(h, 6) for h in hist]
+    np.savez(os.path.join(os.path.dirname(out_path), "warmstart_model.npz"), **model.state_dict())
+    # held-out: cold vs warm, FP64
+    cold, cst, csteps, cres, cwall = WS.solve(te, "f64", tol=1e-8, max_steps=600000, stream=stream, log=log)
+    t0 = time.perf_counter()
+    init = WS.predict(model, te, with_grad=True)
+    torch.cuda.synchronize()
+    t_inf = time.perf_counter() - t0
+    warm, wst, wsteps, wres, wwall = WS.solve(te, "f64", tol=1e-8, max_steps=600000, init=init, stream=stream,
+                                              log=log)
+    init_eq = WS.predict(model, te, with_grad=False)
+    weq, est, esteps, eres, ewall = WS.solve(te, "f64", tol=1e-8, max_steps=600000, init=init_eq, stream=stream,
+                                             log=log)
+    ok = [k for k in range(n_test) if cst[k] == 0 and wst[k] == 0]
+    errs = [WS.field_error(cold, warm, k) for k in ok]
+    cases_out = []
+    for k in range(n_test):
+        cases_out.append({"Re": round(te[k]["Re"], 1), "U": round(te[k]["U"], 4),
+                          "obstacle_frac": round(float(te[k]["mask"].mean()), 4),
+                          "cold_steps": int(csteps[k]), "warm_steps": int(wsteps[k]), "warm_feq_steps": int(esteps[k]),
+                          "cold_status": int(cst[k]), "warm_status": int(wst[k])})
+    rec.update({
+        "cold_wall_s": round(cwall, 2), "warm_wall_s": round(wwall + t_inf, 2), "inference_s": round(t_inf, 3),
+        "warm_feq_wall_s": round(ewall + t_inf, 2),
+        "speedup_wall": round(cwall / (wwall + t_inf), 3),
+        "speedup_steps_total": round(float(csteps[ok].sum()) / max(1.0, float(wsteps[ok].sum())), 3),
+        "speedup_steps_median_case": round(float(np.median(csteps[ok] / np.maximum(wsteps[ok], 1))), 3),
+        "ablation_feq_only_speedup_steps_total": round(float(csteps[ok].sum()) / max(1.0, float(esteps[ok].sum())), 3),
+        "field_rel_l2_warm_vs_cold_max": max(errs) if errs else None,
+        "field_rel_l2_warm_vs_cold_median": float(np.median(errs)) if errs else None,
+        "fallbacks_needed": int(sum(1 for k in range(n_test) if wst[k] != 0)),
+        "cases": cases_out,
+    })
+    log(json.dumps({k: v for k, v in rec.items() if k not in ("cases", "loss_history")}))
+    with open(out_path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+
+
+class _Subset:
+    """Read-outs of selected cases of a solver, renumbered from 0."""
+
+    def __init__(self, solver, idx):
+        self.solver, self.idx = solver, idx
+
+    def fields(self, fields, k):
+        return self.solver.fields(fields, self.idx[k])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -439,6 +516,10 @@ def main():
     ap.add_argument("--precision-study", metavar="OUT_JSON", help="FP16/BF16/FP32 vs FP64 storage, 3D TGV")
     ap.add_argument("--batch-study", metavar="OUT_JSON", help="512-case uneven batch to steady state")
     ap.add_argument("--steady-study", metavar="OUT_JSON", help="wall time to residual 1e-8")
+    ap.add_argument("--warmstart-study", metavar="OUT_JSON", help="learned warm start vs cold start")
+    ap.add_argument("--ws-train", type=int, default=1024)
+    ap.add_argument("--ws-epochs", type=int, default=30)
+    ap.add_argument("--ws-n", type=int, default=128)
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -454,6 +535,9 @@ def main():
         return
     if args.steady_study:
         steady_study(args.steady_study)
+        return
+    if args.warmstart_study:
+        warmstart_study(args.warmstart_study, n_train=args.ws_train, N=args.ws_n, epochs=args.ws_epochs)
         return
     if args.summarize_trace:
         with open(args.summarize_trace[1], "w") as fh:

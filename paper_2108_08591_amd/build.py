@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmdf.so")
 
-SOURCES = ["mdf_kernels.hip", "mdf_api.cpp"]
+SOURCES = ["mdf_kernels.hip", "mdf_api.cpp", "nn_kernels.hip"]
 
 # Packed-FP32 instructions are disabled for every HIP source of the project.
 # No floating-point contraction: every kernel that evaluates the same

@@ -1,0 +1,163 @@
+"""Learned warm start of steady cavity solves: data generation with the
+batched solver, training of the encoder-decoder of nn.py on the GPU, and the
+warm-versus-cold comparison.
+
+The solver decides the answer in both cases: a warm start only replaces the
+rest state by f^eq + f^ne built from the predicted (P, u, grad u) (inverse
+of eq. 3-16); the cold start from rest is the fallback whenever the warm
+solve goes non-finite or does not converge.
+"""
+from __future__ import annotations
+
+import json
+import math
+import time
+from typing import Callable, Dict, List, Optional
+
+import numpy as np
+import torch
+
+from . import cases as C
+from . import mdf
+from . import nn
+
+FIELDS = mdf.FIELD_MOMENTS | mdf.FIELD_GRAD
+
+
+def warmstart_cases(n: int, N: int = 128, seed: int = 20210819) -> List[dict]:
+    """Seeded lid-driven cavities with 0..3 circular/rectangular obstacles:
+    Re log-uniform in [10, 1000], lid speed uniform in [0.05, 0.1]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        Re = float(10.0 ** rng.uniform(1.0, 3.0))
+        U = float(rng.uniform(0.05, 0.1))
+        mask = C.obstacle_mask(N, rng)
+        spec = C.cavity_case(N=N, Re=Re, U=U)
+        out.append({"spec": spec, "mask": mask, "Re": Re, "U": U, "N": N})
+    return out
+
+
+def solve(cases: List[dict], storage="f32", tol=1e-8, K=100, max_steps=400000, init=None, stream=None,
+          window=20000, log: Optional[Callable[[str], None]] = None):
+    """Run every case to residual `tol` in one batched context.  init: None
+    (rest) or a list of channel-major field arrays [P, u, v, (grad 4)] per
+    case.  Returns (solver, status, steps, residual, wall seconds)."""
+    specs = [c["spec"] for c in cases]
+    masks = [c["mask"] for c in cases]
+    t0 = time.perf_counter()
+    if init is None:
+        solver = mdf.Solver(specs, storage=storage, solid=masks, stream=stream)
+    else:
+        kind = "fields_grad" if init[0].shape[0] == 7 else "fields"
+        solver = mdf.Solver(specs, storage=storage, solid=masks, init=(kind, [torch.tensor(a) for a in init]),
+                            stream=stream)
+    n = len(cases)
+    st = np.full(n, 2)
+    steps = np.zeros(n, np.int64)
+    res = np.full(n, np.inf)
+    active = np.ones(n, bool)
+    done = 0
+    while active.any() and done < max_steps:
+        solver.set_active(active)
+        w = min(window, max_steps - done)
+        s, k, r = solver.run_steady(tol, K, w)
+        done += w
+        for i in np.nonzero(active)[0]:
+            steps[i] += k[i]
+            res[i] = r[i]
+            if s[i] in (0, 1):
+                st[i] = s[i]
+                active[i] = False
+        if log:
+            log(json.dumps({"solve_steps": done, "converged": int((st == 0).sum()), "nonfinite": int((st == 1).sum()),
+                            "running": int(active.sum()), "wall_s": round(time.perf_counter() - t0, 1)}))
+    torch.cuda.synchronize()
+    return solver, st, steps, res, time.perf_counter() - t0
+
+
+def dataset(cases: List[dict], solver) -> Dict[str, torch.Tensor]:
+    """Inputs (bf16 [n, N, N, IN_CH]), raw targets (f32 [n, N*N, OUT_CH])
+    and fluid weights (f32 [n, N*N]) from solved cases."""
+    X, T, Wt = [], [], []
+    for k, c in enumerate(cases):
+        N = c["N"]
+        X.append(torch.tensor(nn.input_features(N, c["mask"], c["Re"], c["U"])))
+        f = solver.fields(FIELDS, k)
+        T.append(nn.raw_targets(f, N, c["U"]).reshape(N * N, nn.OUT_CH).cpu())
+        Wt.append(torch.tensor((c["mask"] == 0).astype(np.float32).reshape(-1)))
+    torch.cuda.synchronize()
+    return {"X": torch.stack(X), "T": torch.stack(T), "W": torch.stack(Wt)}
+
+
+def fit_normalisation(T, W):
+    """Per-channel mean/std of the raw targets over fluid nodes."""
+    w = W.reshape(-1, 1)
+    t = T.reshape(-1, T.shape[-1])
+    mean = (t * w).sum(0) / w.sum()
+    std = torch.sqrt(((t - mean) ** 2 * w).sum(0) / w.sum()).clamp_min(1e-6)
+    return {"mean": mean.numpy().astype(np.float32), "std": std.numpy().astype(np.float32)}
+
+
+def train(model: nn.UNet, data: Dict[str, torch.Tensor], epochs=30, batch=16, lr=2e-3, seed=0,
+          log: Optional[Callable[[str], None]] = None):
+    """Adam on the weighted MSE of the normalised targets; inputs and
+    targets are moved to the device once.  Returns the per-epoch losses."""
+    dev = model.device
+    model.norm = fit_normalisation(data["T"], data["W"])
+    mean = torch.tensor(model.norm["mean"], device=dev)
+    std = torch.tensor(model.norm["std"], device=dev)
+    X = nn.to_bf16(data["X"].to(dev))
+    T = ((data["T"].to(dev) - mean) / std).contiguous()
+    W = data["W"].to(dev).contiguous()
+    n = X.shape[0]
+    rng = np.random.default_rng(seed)
+    history = []
+    steps_per_epoch = max(1, n // batch)
+    total = epochs * steps_per_epoch
+    it = 0
+    for ep in range(epochs):
+        perm = rng.permutation(n)
+        acc = 0.0
+        for b in range(steps_per_epoch):
+            idx = torch.tensor(perm[b * batch:(b + 1) * batch], device=dev)
+            xb = X.index_select(0, idx).contiguous()
+            tb = T.index_select(0, idx).reshape(-1, nn.OUT_CH).contiguous()
+            wb = W.index_select(0, idx).reshape(-1).contiguous()
+            model.forward(xb)
+            loss, g = model.loss_and_grad(tb, wb)
+            model.backward(g)
+            # cosine learning-rate schedule
+            cur = lr * 0.5 * (1 + math.cos(math.pi * it / total))
+            model.adam_step(cur)
+            it += 1
+            acc += float(loss.item())
+        history.append(acc / steps_per_epoch)
+        if log:
+            log(json.dumps({"epoch": ep + 1, "loss": round(history[-1], 6)}))
+    return history
+
+
+def predict(model: nn.UNet, cases: List[dict], with_grad=True, batch=16) -> List[np.ndarray]:
+    """Initial fields per case from the network ([P, u, v] or
+    [P, u, v, grad(4)], channel-major float64)."""
+    out = []
+    dev = model.device
+    for s in range(0, len(cases), batch):
+        part = cases[s:s + batch]
+        N = part[0]["N"]
+        X = torch.stack([torch.tensor(nn.input_features(N, c["mask"], c["Re"], c["U"])) for c in part])
+        y = model.forward(nn.to_bf16(X.to(dev)))
+        y = y.reshape(len(part), N, N, nn.OUT_CH).cpu().numpy()
+        for k, c in enumerate(part):
+            fl = nn.fields_from_prediction(y[k], N, c["U"], c["mask"], model.norm)
+            out.append(fl if with_grad else fl[:3].copy())
+    return out
+
+
+def field_error(solver_a, solver_b, k) -> float:
+    """Relative L2 distance of the velocity fields of case k in two solvers."""
+    ua = solver_a.fields(mdf.FIELD_MOMENTS, k)["u"].double()
+    ub = solver_b.fields(mdf.FIELD_MOMENTS, k)["u"].double()
+    torch.cuda.synchronize()
+    return float(torch.linalg.vector_norm(ua - ub) / torch.linalg.vector_norm(ua))

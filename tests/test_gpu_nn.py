@@ -1,0 +1,240 @@
+"""The encoder-decoder kernels (include/mdfnn.h) against the FP64 layer
+oracle.  Inputs and weights are rounded to BF16 first, so a kernel and the
+oracle differ only by FP32 accumulation order (bar 1e-5 relative) or, for
+BF16 outputs, by the output rounding (2^-8 relative).  The whole network's
+gradient is checked against the FP64 composition of the oracle layers with
+the kernels' BF16 storage rounding emulated at the same places (bar 1e-2;
+without the emulation the BF16 activations alone move it by ~2.4e-2)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import conv_oracle as R
+from paper_2108_08591_amd import nn
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _bf(a):
+    """Round to bf16 (nearest even) and return (float64 values, device bf16 tensor)."""
+    t = torch.tensor(np.asarray(a, np.float32), device=DEV)
+    b = nn.to_bf16(t)
+    torch.cuda.synchronize()
+    return nn.to_f32(b).cpu().double().numpy(), b
+
+
+def _rel(ref, got):
+    ref = np.asarray(ref, np.float64)
+    return float(np.linalg.norm((ref - np.asarray(got, np.float64)).ravel()) / np.linalg.norm(ref.ravel()))
+
+
+@pytest.mark.parametrize("shape", [(2, 9, 13, 32, 0, 32), (1, 17, 10, 64, 32, 64), (3, 8, 8, 32, 64, 96)])
+def test_conv_forward_and_gradients(shape):
+    B, H, W, c1, c2, co = shape
+    _say(f"[nn] conv {shape}")
+    rng = np.random.default_rng(B * 100 + H)
+    x1, x1d = _bf(rng.normal(size=(B, H, W, c1)))
+    x2, x2d = (_bf(rng.normal(size=(B, H, W, c2))) if c2 else (None, None))
+    w, wd = _bf(rng.normal(size=(co, 9, c1 + c2)) * 0.1)
+    bias = rng.normal(size=co).astype(np.float32)
+    bd = torch.tensor(bias, device=DEV)
+    xin = x1 if x2 is None else np.concatenate([x1, x2], axis=3)
+    # forward, FP32 output
+    yf = torch.empty((B, H, W, co), dtype=torch.float32, device=DEV)
+    nn.conv_fwd(x1d, x2d, wd, bd, False, out_f32=yf)
+    torch.cuda.synchronize()
+    ref = R.conv3x3(xin, w, bias)
+    assert _rel(ref, yf.cpu().numpy()) < 1e-5
+    # forward with ReLU, BF16 output
+    yb = nn.bf16_empty((B, H, W, co), DEV)
+    nn.conv_fwd(x1d, x2d, wd, bd, True, out_bf16=yb)
+    torch.cuda.synchronize()
+    got = nn.to_f32(yb).cpu().numpy()
+    assert _rel(np.maximum(ref, 0), got) < 2 ** -8
+    # data gradient through the flipped weights, masked by a ReLU output
+    gy, gyd = _bf(rng.normal(size=(B, H, W, co)))
+    wt = nn.bf16_empty((c1 + c2, 9, co), DEV)
+    nn.conv_flip(wd, wt)
+    m, md = _bf(rng.normal(size=(B, H, W, c1)))
+    gx = torch.empty((B, H, W, c1), dtype=torch.float32, device=DEV)
+    nn.conv_fwd(gyd, None, wt[:c1], None, False, mask=md, out_f32=gx)
+    torch.cuda.synchronize()
+    dref = R.conv3x3_dgrad(gy, w)
+    assert _rel(dref[..., :c1] * (m > 0), gx.cpu().numpy()) < 1e-5
+    if c2:
+        gx2 = torch.empty((B, H, W, c2), dtype=torch.float32, device=DEV)
+        nn.conv_fwd(gyd, None, wt[c1:], None, False, out_f32=gx2)
+        torch.cuda.synchronize()
+        assert _rel(dref[..., c1:], gx2.cpu().numpy()) < 1e-5
+    # weight and bias gradients
+    dw = torch.empty((co, 9, c1 + c2), dtype=torch.float32, device=DEV)
+    db = torch.empty(co, dtype=torch.float32, device=DEV)
+    scratch = torch.empty(nn.wgrad_scratch_bytes(B, H, W, c1 + c2, co), dtype=torch.uint8, device=DEV)
+    nn.conv_wgrad(x1d, x2d, gyd, dw, db, scratch)
+    torch.cuda.synchronize()
+    dwr, dbr = R.conv3x3_wgrad(xin, gy)
+    assert _rel(dwr, dw.cpu().numpy()) < 1e-5
+    assert _rel(dbr, db.cpu().numpy()) < 1e-5
+
+
+def test_pool_upsample_add():
+    rng = np.random.default_rng(5)
+    x, xd = _bf(rng.normal(size=(2, 6, 10, 32)))
+    y = nn.bf16_empty((2, 3, 5, 32), DEV)
+    nn.avgpool2(xd, y)
+    up = nn.bf16_empty((2, 12, 20, 32), DEV)
+    nn.upsample2(xd, up)
+    g, gd = _bf(rng.normal(size=(2, 3, 5, 32)))
+    dx = nn.bf16_empty((2, 6, 10, 32), DEV)
+    nn.avgpool2_bwd(gd, dx)
+    gu, gud = _bf(rng.normal(size=(2, 12, 20, 32)))
+    du = nn.bf16_empty((2, 6, 10, 32), DEV)
+    nn.upsample2_bwd(gud, du)
+    s = nn.bf16_empty((2, 6, 10, 32), DEV)
+    nn.add(xd, dx, xd, s)
+    torch.cuda.synchronize()
+    f = lambda t: nn.to_f32(t).cpu().numpy()
+    assert _rel(R.avgpool2(x), f(y)) < 2 ** -8
+    assert np.array_equal(R.upsample2(x), f(up))
+    assert _rel(R.avgpool2_bwd(g), f(dx)) < 2 ** -8
+    assert _rel(R.upsample2_bwd(gu), f(du)) < 2 ** -8
+    assert _rel((x + f(dx)) * (x > 0), f(s)) < 2 ** -7
+
+
+def test_head_loss_adam():
+    rng = np.random.default_rng(6)
+    P, cin, co = 1000, 32, 7
+    x, xd = _bf(rng.normal(size=(P, cin)))
+    w = rng.normal(size=(co, cin)).astype(np.float32)
+    b = rng.normal(size=co).astype(np.float32)
+    t = rng.normal(size=(P, co)).astype(np.float32)
+    wt = (rng.random(P) < 0.8).astype(np.float32)
+    wd, bd = torch.tensor(w, device=DEV), torch.tensor(b, device=DEV)
+    td, wtd = torch.tensor(t, device=DEV), torch.tensor(wt, device=DEV)
+    y = torch.empty((P, co), dtype=torch.float32, device=DEV)
+    nn.head_fwd(xd, wd, bd, y)
+    dy = torch.empty_like(y)
+    loss = torch.zeros(1, dtype=torch.float32, device=DEV)
+    scratch = torch.empty(max(nn.loss_scratch_bytes(P), nn.head_scratch_bytes(P, cin, co)), dtype=torch.uint8,
+                          device=DEV)
+    nn.mse(y, td, wtd, dy, loss, scratch)
+    torch.cuda.synchronize()
+    yr = R.head(x, w.astype(np.float64), b.astype(np.float64))
+    assert _rel(yr, y.cpu().numpy()) < 1e-6
+    Lr, dyr = R.mse(yr, t.astype(np.float64), wt.astype(np.float64))
+    assert abs(loss.item() / Lr - 1) < 1e-5
+    assert _rel(dyr, dy.cpu().numpy()) < 1e-5
+    dx = nn.bf16_empty((P, cin), DEV)
+    dw = torch.empty((co, cin), dtype=torch.float32, device=DEV)
+    db = torch.empty(co, dtype=torch.float32, device=DEV)
+    nn.head_bwd(xd, dy, wd, xd, dx, dw, db, scratch)
+    torch.cuda.synchronize()
+    dxr, dwr, dbr = R.head_bwd(x, dy.cpu().double().numpy(), w.astype(np.float64))
+    assert _rel(dxr * (x > 0), nn.to_f32(dx).cpu().numpy()) < 2 ** -8
+    assert _rel(dwr, dw.cpu().numpy()) < 1e-5
+    assert _rel(dbr, db.cpu().numpy()) < 1e-5
+    # Adam, three steps
+    p = rng.normal(size=500).astype(np.float32)
+    pd = torch.tensor(p, device=DEV)
+    m = torch.zeros_like(pd)
+    v = torch.zeros_like(pd)
+    pb = nn.bf16_empty((500,), DEV)
+    pr, mr, vr = p.astype(np.float64), np.zeros(500), np.zeros(500)
+    for t_ in range(1, 4):
+        g = rng.normal(size=500).astype(np.float32)
+        nn.adam(pd, torch.tensor(g, device=DEV), m, v, 1e-2, t_, pb)
+        pr, mr, vr = R.adam(pr, g.astype(np.float64), mr, vr, t_, 1e-2)
+    torch.cuda.synchronize()
+    assert np.allclose(pd.cpu().numpy(), pr, rtol=1e-5, atol=1e-6)
+
+
+def _rb(a):
+    """Round to bfloat16 (nearest even), as the kernels store activations."""
+    u = np.asarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _oracle_unet(model, x, target, wt):
+    """The same network composed from FP64 oracle layers, with the weights
+    read back as BF16 values and every activation / activation gradient
+    rounded to BF16 where the kernels store it; returns the loss and the
+    gradient of every parameter."""
+    P = {k: model.view(k, "bf16") for k in model.layout if k.endswith(".w") and not k.startswith("head")}
+    Wb = {k: nn.to_f32(v).cpu().double().numpy() for k, v in P.items()}
+    B = {k: model.view(k).cpu().double().numpy() for k in model.layout if k.endswith(".b")}
+    Hw = model.view("head.w").cpu().double().numpy()
+    nl = len(model.levels)
+    acts = {}
+    inp = x
+    for l in range(nl):
+        a = _rb(np.maximum(R.conv3x3(inp, Wb[f"enc{l}a.w"], B[f"enc{l}a.b"]), 0))
+        b = _rb(np.maximum(R.conv3x3(a, Wb[f"enc{l}b.w"], B[f"enc{l}b.b"]), 0))
+        acts[f"enc{l}a"], acts[f"enc{l}b"] = a, b
+        acts[f"in{l}"] = inp
+        if l + 1 < nl:
+            inp = _rb(R.avgpool2(b))
+    low = acts[f"enc{nl - 1}b"]
+    for l in range(nl - 2, -1, -1):
+        up = R.upsample2(low)
+        cat = np.concatenate([up, acts[f"enc{l}b"]], axis=3)
+        a = _rb(np.maximum(R.conv3x3(cat, Wb[f"dec{l}a.w"], B[f"dec{l}a.b"]), 0))
+        b = _rb(np.maximum(R.conv3x3(a, Wb[f"dec{l}b.w"], B[f"dec{l}b.b"]), 0))
+        acts[f"cat{l}"], acts[f"dec{l}a"], acts[f"dec{l}b"] = cat, a, b
+        low = b
+    flat = low.reshape(-1, low.shape[3])
+    y = R.head(flat, Hw, B["head.b"])
+    L, dy = R.mse(y, target, wt)
+    grads = {}
+    dflat, grads["head.w"], grads["head.b"] = R.head_bwd(flat, dy, Hw)
+    g = _rb(dflat.reshape(low.shape) * (low > 0))
+    for l in range(0, nl - 1):
+        dw, db = R.conv3x3_wgrad(acts[f"dec{l}a"], g)
+        grads[f"dec{l}b.w"], grads[f"dec{l}b.b"] = dw, db
+        g = _rb(R.conv3x3_dgrad(g, Wb[f"dec{l}b.w"]) * (acts[f"dec{l}a"] > 0))
+        dw, db = R.conv3x3_wgrad(acts[f"cat{l}"], g)
+        grads[f"dec{l}a.w"], grads[f"dec{l}a.b"] = dw, db
+        gcat = _rb(R.conv3x3_dgrad(g, Wb[f"dec{l}a.w"]))
+        cu = model.levels[l + 1]
+        acts[f"gskip{l}"] = gcat[..., cu:]
+        below = acts[f"dec{l + 1}b"] if l + 1 < nl - 1 else acts[f"enc{nl - 1}b"]
+        g = _rb(_rb(R.upsample2_bwd(gcat[..., :cu])) * (below > 0))
+    for l in range(nl - 1, -1, -1):
+        if l < nl - 1:
+            g = _rb((_rb(R.avgpool2_bwd(gpool)) + acts[f"gskip{l}"]) * (acts[f"enc{l}b"] > 0))
+        dw, db = R.conv3x3_wgrad(acts[f"enc{l}a"], g)
+        grads[f"enc{l}b.w"], grads[f"enc{l}b.b"] = dw, db
+        g = _rb(R.conv3x3_dgrad(g, Wb[f"enc{l}b.w"]) * (acts[f"enc{l}a"] > 0))
+        dw, db = R.conv3x3_wgrad(acts[f"in{l}"], g)
+        grads[f"enc{l}a.w"], grads[f"enc{l}a.b"] = dw, db
+        if l > 0:
+            gpool = _rb(R.conv3x3_dgrad(g, Wb[f"enc{l}a.w"]))
+    return L, grads
+
+
+def test_unet_gradient_against_oracle_composition():
+    _say("[nn] unet gradient vs oracle composition")
+    model = nn.UNet(device=DEV, seed=3, levels=(32, 64, 128))
+    rng = np.random.default_rng(9)
+    Bn, H, W = 2, 16, 16
+    x, xd = _bf(np.concatenate([rng.normal(size=(Bn, H, W, 5)), np.zeros((Bn, H, W, nn.IN_CH - 5))], axis=3))
+    target = rng.normal(size=(Bn * H * W, nn.OUT_CH)).astype(np.float32)
+    wt = np.ones(Bn * H * W, np.float32)
+    model.forward(xd)
+    loss, g_out = model.loss_and_grad(torch.tensor(target, device=DEV), torch.tensor(wt, device=DEV))
+    model.backward(g_out)
+    torch.cuda.synchronize()
+    Lr, gr = _oracle_unet(model, x, target.astype(np.float64), wt.astype(np.float64))
+    assert abs(loss.item() / Lr - 1) < 1e-3
+    errs = {k: _rel(ref, model.view(k, "grad").cpu().numpy()) for k, ref in gr.items()}
+    _say("   max gradient error " + str(max(errs.values())))
+    # only accumulation order (and a ReLU or rounding tie it may flip) differs
+    assert all(e < 1e-2 for e in errs.values()), errs
