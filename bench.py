@@ -167,13 +167,19 @@ def summarize_traffic(fetch_db, write_db, copy_fetch_db, copy_write_db, kernel_p
 
 
 def parse_launch(text):
+    """'64x4g8v' -> (64, 4, 8, 1): tile of 64 x 4 threads, 8 XCD bands, vector
+    step kernel ('v') or one node per thread ('s', default)."""
     t = text.lower()
+    vec = 0
+    if t.endswith("v") or t.endswith("s"):
+        vec = 1 if t[-1] == "v" else 0
+        t = t[:-1]
     groups = 1
     if "g" in t:
         t, g = t.split("g")
         groups = int(g)
     bx, by = (int(v) for v in t.split("x"))
-    return bx, by, groups
+    return bx, by, groups, vec
 
 
 def time_launches(solver, stream, n, fields=0, out=None, reps=3):
@@ -211,7 +217,8 @@ def sweep(out_path):
     for N in (128, 256, 384):
         for st in ("f32", "f64", "f16dev", "bf16dev"):
             runs.append(("d3q7", N, st))
-    shapes = [(64, 4, 8), (64, 4, 1), (256, 1, 8), (128, 2, 8), (64, 2, 8), (64, 1, 8)]
+    shapes = [(64, 4, 8, 1), (128, 2, 8, 1), (256, 1, 8, 1), (64, 2, 8, 1), (64, 4, 8, 0), (128, 2, 8, 0),
+              (256, 1, 8, 0)]
     with open(out_path, "w") as fh:
         for lat, N, st in runs:
             if lat == "d2q5":
@@ -228,11 +235,11 @@ def sweep(out_path):
             nodes = spec.nodes
             alg = nodes * 2 * q * ns * sb[st]
             n = max(5, min(400, int(2e10 / alg)))
-            for bx, by, g in shapes:
-                solver.set_launch(bx, by, g)
+            for bx, by, g, vec in shapes:
+                solver.set_launch(bx, by, g, vec)
                 solver.step(2)
                 ms = time_launches(solver, stream, n)
-                rec = {"lattice": lat, "N": N, "storage": st, "launch": f"{bx}x{by}g{g}",
+                rec = {"lattice": lat, "N": N, "storage": st, "launch": f"{bx}x{by}g{g}{'v' if vec else 's'}",
                        "ms": round(ms, 5), "MLUPS": round(nodes / ms / 1e3, 1),
                        "GBps": round(alg / ms / 1e6, 1), "frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4),
                        "working_set_MB": round(2 * alg / 2 / 1e6, 1)}
@@ -419,7 +426,7 @@ def steady_study(out_path):
         json.dump(out, fh, indent=1)
 
 
-def warmstart_study(out_path, n_train=1024, n_test=32, N=128, epochs=30, batch=16):
+def warmstart_study(out_path, n_train=1024, n_test=32, N=128, epochs=30, batch=16, lr=2e-3, clip=None):
     """Learned warm start (cavities with obstacles, N^2): training data from
     the batched FP32 solver (residual 1e-7), training of the encoder-decoder
     with the project's kernels, then cold vs warm FP64 solves of held-out
@@ -439,17 +446,23 @@ def warmstart_study(out_path, n_train=1024, n_test=32, N=128, epochs=30, batch=1
     rec.update({"datagen_wall_s": round(wall, 1), "datagen_converged": len(good),
                 "datagen_nonfinite": int((st == 1).sum()), "datagen_steps_median": int(np.median(steps))})
     log(json.dumps({k: rec[k] for k in ("datagen_wall_s", "datagen_converged", "datagen_nonfinite")}))
-    data = WS.dataset([tr[k] for k in good], _Subset(solver, good))
+    data = WS.dataset([tr[k] for k in good], _Subset(solver, good), log=log)
     del solver
     torch.cuda.empty_cache()
+    # the last 64 converged cases are held out of training for the validation loss
+    nv = min(64, len(good) // 8)
+    val = {k: v[-nv:] for k, v in data.items()}
+    data = {k: v[:-nv] for k, v in data.items()}
     model = nn.UNet(device="cuda:0", seed=0)
     rec["params"] = model.nparams
+    rec.update({"lr": lr, "target_clip_sigma": clip, "n_val": nv})
     t0 = time.perf_counter()
-    hist = WS.train(model, data, epochs=epochs, batch=batch, lr=2e-3, log=log)
+    hist, vhist = WS.train(model, data, epochs=epochs, batch=batch, lr=lr, clip=clip, val=val, log=log)
     torch.cuda.synchronize()
     rec["train_wall_s"] = round(time.perf_counter() - t0, 1)
     rec["loss_history"] = [round(h, 6) for h in hist]
-    np.savez(os.path.join(os.path.dirname(out_path), "warmstart_model.npz"), **model.state_dict())
+    rec["val_loss_history"] = vhist
+    np.savez(os.path.join(os.path.dirname(out_path), f"warmstart_model_{N}.npz"), **model.state_dict())
     # held-out: cold vs warm, FP64
     cold, cst, csteps, cres, cwall = WS.solve(te, "f64", tol=1e-8, max_steps=600000, stream=stream, log=log)
     t0 = time.perf_counter()
@@ -458,6 +471,10 @@ def warmstart_study(out_path, n_train=1024, n_test=32, N=128, epochs=30, batch=1
     t_inf = time.perf_counter() - t0
     warm, wst, wsteps, wres, wwall = WS.solve(te, "f64", tol=1e-8, max_steps=600000, init=init, stream=stream,
                                               log=log)
+    # an exact predictor: restart from the cold solution's own fields
+    exact = [WS.solution_init(cold, k) for k in range(n_test)]
+    _, xst, xsteps, _, xwall = WS.solve(te, "f64", tol=1e-8, max_steps=600000, init=exact, stream=stream, log=log)
+    perr = [WS.prediction_error(init[k], exact[k], te[k]["mask"]) for k in range(n_test) if cst[k] == 0]
     init_eq = WS.predict(model, te, with_grad=False)
     weq, est, esteps, eres, ewall = WS.solve(te, "f64", tol=1e-8, max_steps=600000, init=init_eq, stream=stream,
                                              log=log)
@@ -468,6 +485,7 @@ def warmstart_study(out_path, n_train=1024, n_test=32, N=128, epochs=30, batch=1
         cases_out.append({"Re": round(te[k]["Re"], 1), "U": round(te[k]["U"], 4),
                           "obstacle_frac": round(float(te[k]["mask"].mean()), 4),
                           "cold_steps": int(csteps[k]), "warm_steps": int(wsteps[k]), "warm_feq_steps": int(esteps[k]),
+                          "exact_restart_steps": int(xsteps[k]),
                           "cold_status": int(cst[k]), "warm_status": int(wst[k])})
     rec.update({
         "cold_wall_s": round(cwall, 2), "warm_wall_s": round(wwall + t_inf, 2), "inference_s": round(t_inf, 3),
@@ -476,9 +494,12 @@ def warmstart_study(out_path, n_train=1024, n_test=32, N=128, epochs=30, batch=1
         "speedup_steps_total": round(float(csteps[ok].sum()) / max(1.0, float(wsteps[ok].sum())), 3),
         "speedup_steps_median_case": round(float(np.median(csteps[ok] / np.maximum(wsteps[ok], 1))), 3),
         "ablation_feq_only_speedup_steps_total": round(float(csteps[ok].sum()) / max(1.0, float(esteps[ok].sum())), 3),
+        "exact_fields_restart_speedup_steps_total": round(float(csteps[ok].sum()) / max(1.0, float(xsteps[ok].sum())), 3),
+        "prediction_rel_l2_median": {c: float(np.median([e[c] for e in perr])) for c in WS.CHANNELS},
         "field_rel_l2_warm_vs_cold_max": max(errs) if errs else None,
         "field_rel_l2_warm_vs_cold_median": float(np.median(errs)) if errs else None,
         "fallbacks_needed": int(sum(1 for k in range(n_test) if wst[k] != 0)),
+        "warm_within_1e-4_of_cold": int(sum(1 for e in errs if e <= 1e-4)),
         "cases": cases_out,
     })
     log(json.dumps({k: v for k, v in rec.items() if k not in ("cases", "loss_history")}))
@@ -502,7 +523,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--launch", default="64x4g8", help="threads per block and XCD groups, BXxBYgG")
+    ap.add_argument("--launch", default="128x2g8s",
+                    help="threads per block, XCD groups and kernel form, BXxBYgG[v|s] (v: vector, s: one node/thread)")
     ap.add_argument("--sweep", metavar="OUT_JSONL",
                     help="time the step kernel over grid sizes, storages and launch shapes")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -520,6 +542,8 @@ def main():
     ap.add_argument("--ws-train", type=int, default=1024)
     ap.add_argument("--ws-epochs", type=int, default=30)
     ap.add_argument("--ws-n", type=int, default=128)
+    ap.add_argument("--ws-lr", type=float, default=1e-3)
+    ap.add_argument("--ws-clip", type=float, default=0.0, help="target clip in standard deviations (0: none)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -537,7 +561,8 @@ def main():
         steady_study(args.steady_study)
         return
     if args.warmstart_study:
-        warmstart_study(args.warmstart_study, n_train=args.ws_train, N=args.ws_n, epochs=args.ws_epochs)
+        warmstart_study(args.warmstart_study, n_train=args.ws_train, N=args.ws_n, epochs=args.ws_epochs,
+                        lr=args.ws_lr, clip=args.ws_clip or None)
         return
     if args.summarize_trace:
         with open(args.summarize_trace[1], "w") as fh:
@@ -546,7 +571,7 @@ def main():
     if args.summarize_traffic:
         fdb, wdb, cfdb, cwdb, out_md = args.summarize_traffic
         nodes = 1024 * 1024
-        md, ent = summarize_traffic(fdb, wdb, cfdb, cwdb, "k_step<LatD2Q5, 1, true, false, false>", nodes * (2 * 15 * 4 + 4 * 4),
+        md, ent = summarize_traffic(fdb, wdb, cfdb, cwdb, "k_step<LatD2Q5, 1, true, false, false, 1>", nodes * (2 * 15 * 4 + 4 * 4),
                                     "k_step<D2Q5,F32,emit>_cavity1024", args.command.split(" ;; "))
         with open(out_md, "w") as fh:
             fh.write(md)
@@ -572,8 +597,8 @@ def main():
     fields = mdf.FIELD_VORT | mdf.FIELD_STRAIN
     stream = torch.cuda.Stream(device=dev)
     solver = mdf.Solver([spec], storage="f32", device=dev, stream=stream)
-    bx, by, groups = parse_launch(args.launch)
-    solver.set_launch(bx, by, groups)
+    bx, by, groups, vec = parse_launch(args.launch)
+    solver.set_launch(bx, by, groups, vec)
     out = solver.new_field_buffers(fields)
     K = 100
     nodes = spec.nodes
@@ -624,7 +649,8 @@ def main():
         "config": {
             "workload": "lid-driven cavity 1024x1024, D2Q5 x 3 sets, FP32 storage, Re=1000, lid 0.1, "
                         "per-step vorticity+strain emission, FP64 residual every 100 steps",
-            "nodes": nodes, "Re": 1000, "lid_u": 0.1, "storage": "f32", "launch": f"{bx}x{by}g{groups}",
+            "nodes": nodes, "Re": 1000, "lid_u": 0.1, "storage": "f32",
+            "launch": f"{bx}x{by}g{groups}{'v' if vec else 's'}",
         },
         "hbm_roofline_pct": round(100.0 * mlups * 1e6 * bytes_per_node / (HBM_PEAK_GBS * 1e9), 2),
         "roofline": {
@@ -638,10 +664,28 @@ def main():
             "bytes_per_launch": alg_bytes,
             "avg_launch_ms": round(avg_ms, 5),
             "launch_timing": f"HIP events around {nlaunch} back-to-back launches, best of {reps}",
-            "note": "working set 120 MiB + 16 MiB of emitted fields fits the 256 MB Infinity Cache",
+            "note": "working set 120 MiB + 16 MiB of emitted fields fits the 256 MB Infinity Cache; "
+                    "see roofline_hbm_resident for an 8 GiB working set",
         },
         "residual_after": float(res[0]),
     }
+    # the same kernel on a grid whose working set (8 GiB) is far beyond the
+    # Infinity Cache: the HBM-resident fraction of the roofline
+    del solver, out
+    torch.cuda.empty_cache()
+    big = C.cavity_case(N=8192, Re=1000.0, U=0.1)
+    bsolver = mdf.Solver([big], storage="f32", device=dev, stream=stream)
+    bsolver.set_launch(bx, by, groups, vec)
+    bout = bsolver.new_field_buffers(fields)
+    bsolver.step_emit(2, fields, bout)
+    big_ms = time_launches(bsolver, stream, 40, fields, bout, reps)
+    big_bytes = big.nodes * bytes_per_node
+    result["roofline_hbm_resident"] = {
+        "workload": "same kernel, cavity 8192x8192 (8 GiB of populations)",
+        "achieved": round(big_bytes / (big_ms / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(big_bytes / (big_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "avg_launch_ms": round(big_ms, 4)}
+    del bsolver, bout
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(spec)
     print(json.dumps(result), flush=True)

@@ -155,7 +155,7 @@ struct mdf_ctx {
     std::vector<int64_t> time;
     std::vector<int64_t> snap_time;    // time of the velocity snapshot, -1 = none
     std::vector<uint8_t> enabled;      // mdf_set_active
-    LaunchShape shape{64, 4, 8};
+    LaunchShape shape{64, 4, 8, 1};
     hipError_t latched = hipSuccess;
     std::string err;
     std::vector<double> host_red;
@@ -239,7 +239,7 @@ mdf_status finalize_and_fetch(mdf_ctx *ctx, int k, int nblocks, hipStream_t st, 
 mdf_status step_case(mdf_ctx *ctx, int k, bool check, uint32_t fields, void *out, hipStream_t st,
                      int *nblocks)
 {
-    if (check && mdf::grid_blocks(ctx->kc[k], ctx->shape) > ctx->bufs[k].max_blocks)
+    if (check && mdf::grid_blocks(ctx->kc[k], ctx->storage, ctx->shape) > ctx->bufs[k].max_blocks)
         return fail(ctx, MDF_EINVAL, "launch grid exceeds the reduction workspace");
     hipError_t e = mdf::launch_step(ctx->lattice, ctx->storage, ctx->kc[k], ctx->bufs[k], ctx->cur[k], check,
                                     fields, out, ctx->shape, nblocks, st);
@@ -301,7 +301,8 @@ mdf_status batch_upload(mdf_ctx *ctx, const std::vector<int> &active, uint32_t f
         e.partial = ctx->bufs[k].partial;
         e.result = ctx->bufs[k].result;
         e.out = (fields && out) ? out[k] : nullptr;
-        e.gx = (e.p.nx + ctx->shape.bx - 1) / ctx->shape.bx;
+        const int tile_x = ctx->shape.bx * mdf::step_vx(ctx->storage, ctx->shape);
+        e.gx = (e.p.nx + tile_x - 1) / tile_x;
         e.gy = (e.p.ny + ctx->shape.by - 1) / ctx->shape.by;
         e.ntiles = e.gx * e.gy * e.p.nz;
         e.cur = ctx->cur[k];
@@ -523,14 +524,15 @@ mdf_status mdf_init(mdf_ctx **out, mdf_lattice lattice, mdf_storage storage, con
     return MDF_OK;
 }
 
-mdf_status mdf_set_launch(mdf_ctx *ctx, int32_t bx, int32_t by, int32_t groups)
+mdf_status mdf_set_launch(mdf_ctx *ctx, int32_t bx, int32_t by, int32_t groups, int32_t vec)
 {
     if (!ctx) return fail(nullptr, MDF_EINVAL, "mdf_set_launch: ctx is NULL");
     if (bx < 32 || bx % 32 != 0 || by < 1 || bx * by > 256 || (bx * by) % 64 != 0)
         return fail(ctx, MDF_EINVAL,
                     "mdf_set_launch: need bx %% 32 == 0 and bx*by a multiple of 64 up to 256 (got %d x %d)", bx, by);
     if (groups < 0 || groups > 64) return fail(ctx, MDF_EINVAL, "mdf_set_launch: groups outside [0, 64]");
-    ctx->shape = LaunchShape{bx, by, groups};
+    if (vec != 0 && vec != 1) return fail(ctx, MDF_EINVAL, "mdf_set_launch: vec must be 0 or 1");
+    ctx->shape = LaunchShape{bx, by, groups, vec ? 2 : 1};
     drop_graphs(ctx);
     return MDF_OK;
 }
@@ -588,7 +590,7 @@ static mdf_status read_impl(const mdf_ctx *cctx, int32_t case_id, int mode, uint
         return fail(ctx, MDF_EINVAL, "bad field selection 0x%x", fields);
     const int k = case_id;
     if ((mode == mdf::kReadCheck || mode == mdf::kReadSums) &&
-        mdf::grid_blocks(ctx->kc[k], ctx->shape) > ctx->bufs[k].max_blocks)
+        mdf::read_blocks(ctx->kc[k], ctx->shape) > ctx->bufs[k].max_blocks)
         return fail(ctx, MDF_EINVAL, "launch grid exceeds the reduction workspace");
     const bool pull = ctx->time[k] > 0;
     hipError_t e = mdf::launch_read(ctx->lattice, ctx->storage, ctx->kc[k], ctx->bufs[k], ctx->cur[k] ^ 1, pull,
@@ -760,8 +762,9 @@ mdf_status mdf_autotune(mdf_ctx *ctx, int32_t trial_steps, int32_t *chosen, doub
 {
     if (!ctx) return fail(nullptr, MDF_EINVAL, "mdf_autotune: ctx is NULL");
     if (trial_steps < 1) return fail(ctx, MDF_EINVAL, "mdf_autotune: trial_steps < 1");
-    static const int cand[][3] = {{64, 4, 8}, {128, 2, 8}, {256, 1, 8}, {64, 2, 8},
-                                  {64, 1, 8}, {64, 4, 1}, {128, 1, 8}, {32, 8, 8}};
+    static const int cand[][4] = {{64, 4, 8, 1}, {128, 2, 8, 1}, {256, 1, 8, 1}, {64, 2, 8, 1},
+                                  {64, 1, 8, 1}, {64, 4, 1, 1}, {64, 4, 8, 0}, {128, 2, 8, 0},
+                                  {256, 1, 8, 0}, {64, 4, 1, 0}, {128, 1, 8, 0}, {32, 8, 8, 0}};
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
@@ -771,7 +774,7 @@ mdf_status mdf_autotune(mdf_ctx *ctx, int32_t trial_steps, int32_t *chosen, doub
     int bi = 0;
     mdf_status r = MDF_OK;
     for (int c = 0; c < int(sizeof cand / sizeof cand[0]) && r == MDF_OK; ++c) {
-        r = mdf_set_launch(ctx, cand[c][0], cand[c][1], cand[c][2]);
+        r = mdf_set_launch(ctx, cand[c][0], cand[c][1], cand[c][2], cand[c][3]);
         if (r != MDF_OK) break;
         r = step_impl(ctx, 1, 0, nullptr, stream);           // warm-up (and graph capture)
         if (r != MDF_OK) break;
@@ -790,8 +793,9 @@ mdf_status mdf_autotune(mdf_ctx *ctx, int32_t trial_steps, int32_t *chosen, doub
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (r != MDF_OK) return r;
-    r = mdf_set_launch(ctx, cand[bi][0], cand[bi][1], cand[bi][2]);
-    if (chosen) { chosen[0] = cand[bi][0]; chosen[1] = cand[bi][1]; chosen[2] = cand[bi][2]; }
+    r = mdf_set_launch(ctx, cand[bi][0], cand[bi][1], cand[bi][2], cand[bi][3]);
+    if (chosen)
+        for (int k = 0; k < 4; ++k) chosen[k] = cand[bi][k];
     if (best_ms) *best_ms = double(best) / trial_steps;
     return r;
 }

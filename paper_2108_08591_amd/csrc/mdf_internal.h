@@ -42,6 +42,7 @@ struct CaseBufs {
 struct LaunchShape {
     int bx, by;             // threads per block along x and y (bx * by <= 256)
     int groups;             // > 1: hand out tiles in `groups` contiguous bands, one per XCD
+    int vx;                 // > 1: step kernels give each thread the storage's vector width of x-nodes
 };
 
 // Tile grid of one launch: gx * gy * gz tiles of bx * by threads, launched
@@ -97,6 +98,10 @@ hipError_t batch_blocks_per_cu(int lattice, int storage, LaunchShape shape, bool
 hipError_t launch_finalize_batch(const BatchEntry *tab, const int *meta, const int *active, int nactive,
                                  hipStream_t stream);
 
-int grid_blocks(const KCase &p, LaunchShape shape);
+// Nodes per thread along x of the step kernels for a storage and shape.
+int step_vx(int storage, LaunchShape shape);
+// Blocks of one step launch / one read launch.
+int grid_blocks(const KCase &p, int storage, LaunchShape shape);
+int read_blocks(const KCase &p, LaunchShape shape);
 
 }  // namespace mdf

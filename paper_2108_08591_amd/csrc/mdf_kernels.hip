@@ -85,12 +85,18 @@ __device__ __forceinline__ int block_tile(const Tiling &t)
 
 // ----------------------------------------------------------------- storage
 
-// Storage codes follow mdf_storage.
+// Storage codes follow mdf_storage.  decode/encode convert one stored value;
+// load/store address it.  VX is the number of consecutive x-nodes one thread
+// owns in the vector step kernel: one 16-byte access per plane for FP64 and
+// FP32, 8 bytes for the 16-bit formats.
 template <int ST> struct Store;
 
 template <> struct Store<MDF_F64> {
     using T = double;
     using C = double;
+    static constexpr int VX = 2;
+    static __device__ __forceinline__ C decode(T v, C, float) { return v; }
+    static __device__ __forceinline__ T encode(C v, C, float) { return v; }
     static __device__ __forceinline__ C load(const T *p, long long k, C, float) { return p[k]; }
     static __device__ __forceinline__ void store(T *p, long long k, C v, C, float) { p[k] = v; }
 };
@@ -98,6 +104,9 @@ template <> struct Store<MDF_F64> {
 template <> struct Store<MDF_F32> {
     using T = float;
     using C = float;
+    static constexpr int VX = 4;
+    static __device__ __forceinline__ C decode(T v, C, float) { return v; }
+    static __device__ __forceinline__ T encode(C v, C, float) { return v; }
     static __device__ __forceinline__ C load(const T *p, long long k, C, float) { return p[k]; }
     static __device__ __forceinline__ void store(T *p, long long k, C v, C, float) { p[k] = v; }
 };
@@ -106,13 +115,22 @@ template <> struct Store<MDF_F32> {
 template <> struct Store<MDF_F16DEV> {
     using T = _Float16;
     using C = float;
+    static constexpr int VX = 4;
+    static __device__ __forceinline__ C decode(T v, C rest, float scale)
+    {
+        return rest + scale * static_cast<float>(v);
+    }
+    static __device__ __forceinline__ T encode(C v, C rest, float inv_scale)
+    {
+        return static_cast<_Float16>((v - rest) * inv_scale);
+    }
     static __device__ __forceinline__ C load(const T *p, long long k, C rest, float scale)
     {
-        return rest + scale * static_cast<float>(p[k]);
+        return decode(p[k], rest, scale);
     }
     static __device__ __forceinline__ void store(T *p, long long k, C v, C rest, float inv_scale)
     {
-        p[k] = static_cast<_Float16>((v - rest) * inv_scale);
+        p[k] = encode(v, rest, inv_scale);
     }
 };
 
@@ -127,15 +145,89 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float v)
 template <> struct Store<MDF_BF16DEV> {
     using T = uint16_t;
     using C = float;
+    static constexpr int VX = 4;
+    static __device__ __forceinline__ C decode(T v, C rest, float scale)
+    {
+        return rest + scale * __uint_as_float(((uint32_t)v) << 16);
+    }
+    static __device__ __forceinline__ T encode(C v, C rest, float inv_scale)
+    {
+        return f32_to_bf16_rne((v - rest) * inv_scale);
+    }
     static __device__ __forceinline__ C load(const T *p, long long k, C rest, float scale)
     {
-        return rest + scale * __uint_as_float(((uint32_t)p[k]) << 16);
+        return decode(p[k], rest, scale);
     }
     static __device__ __forceinline__ void store(T *p, long long k, C v, C rest, float inv_scale)
     {
-        p[k] = f32_to_bf16_rne((v - rest) * inv_scale);
+        p[k] = encode(v, rest, inv_scale);
     }
 };
+
+// VX consecutive stored values, accessed as one aligned vector.
+template <class T, int VX>
+struct alignas(sizeof(T) * VX) VecT {
+    T v[VX];
+};
+
+// Raw bits of a vector, as one 8- or 16-byte register tuple, so that a
+// vector is moved by exactly one load or store instruction.
+template <int B> struct RawVec;
+template <> struct RawVec<8> { typedef unsigned int type __attribute__((ext_vector_type(2))); };
+template <> struct RawVec<16> { typedef unsigned int type __attribute__((ext_vector_type(4))); };
+
+template <class T, int VX>
+__device__ __forceinline__ VecT<T, VX> vload(const T *p)
+{
+    using R = typename RawVec<sizeof(T) * VX>::type;
+    const R r = *reinterpret_cast<const R *>(p);
+    VecT<T, VX> v;
+    __builtin_memcpy(&v, &r, sizeof v);
+    return v;
+}
+
+template <class T, int VX>
+__device__ __forceinline__ void vstore(T *p, const VecT<T, VX> &v)
+{
+    using R = typename RawVec<sizeof(T) * VX>::type;
+    R r;
+    __builtin_memcpy(&r, &v, sizeof r);
+    *reinterpret_cast<R *>(p) = r;
+}
+
+// Value of the lane one below / one above in the wavefront (all lanes must
+// execute these; a lane at the wave's edge gets its own value back).
+template <class T>
+__device__ __forceinline__ T lane_up1(T v)
+{
+    if constexpr (sizeof(T) == 2) {
+        uint16_t b;
+        __builtin_memcpy(&b, &v, 2);
+        const int r = __shfl_up((int)b, 1, 64);
+        const uint16_t o = (uint16_t)r;
+        T out;
+        __builtin_memcpy(&out, &o, 2);
+        return out;
+    } else {
+        return __shfl_up(v, 1, 64);
+    }
+}
+
+template <class T>
+__device__ __forceinline__ T lane_down1(T v)
+{
+    if constexpr (sizeof(T) == 2) {
+        uint16_t b;
+        __builtin_memcpy(&b, &v, 2);
+        const int r = __shfl_down((int)b, 1, 64);
+        const uint16_t o = (uint16_t)r;
+        T out;
+        __builtin_memcpy(&out, &o, 2);
+        return out;
+    } else {
+        return __shfl_down(v, 1, 64);
+    }
+}
 
 // rest state of a population: w_i rho0 for the set a = 0, zero otherwise
 // (pressure gauge P = 0).
@@ -221,6 +313,101 @@ __device__ __forceinline__ bool gather(const KCase &p, const typename Store<ST>:
         }
     }
     return true;
+}
+
+// Vector form of gather(): the thread owns the VX consecutive nodes
+// x0 .. x0+VX-1 of row (y, z) (x0 a multiple of VX, rows padded to whole
+// 128-byte lines, so every vector lies inside its padded row).  Each plane
+// is read as one aligned vector per thread: for directions with c_x = 0 from
+// the upstream row, for c_x = +-1 from the own row, the one value the shift
+// pulls in from outside the vector coming from the neighbouring lane (or, at
+// the edge of a wavefront or a tile row, from one scalar load).  Periodic
+// wraps in x, walls and solid links are resolved per node with scalar loads
+// (the same values gather() reads).  Every lane must call this (it
+// exchanges values between lanes); `rowok` says whether the thread owns any
+// node, `fix_lo` / `fix_hi` whether its lower / upper neighbour in x lies
+// in another wavefront or tile row.
+template <class L, int ST, bool MASK, int VX>
+__device__ __forceinline__ void gather_vec(const KCase &p, const typename Store<ST>::T *__restrict__ src,
+                                           const uint8_t *__restrict__ links, int x0, int y, int z, bool rowok,
+                                           bool fix_lo, bool fix_hi, Node<L, typename Store<ST>::C> (&n)[VX],
+                                           bool (&fluid)[VX])
+{
+    using S = Store<ST>;
+    using T = typename S::T;
+    using C = typename S::C;
+    const long long own = ((long long)z * p.ny + y) * p.pitch + x0;
+    unsigned lb[VX];
+#pragma unroll
+    for (int v = 0; v < VX; ++v) {
+        const bool in = rowok && (x0 + v < p.nx);
+        lb[v] = (MASK && in) ? links[own + v] : 0u;
+        fluid[v] = in && !(lb[v] & 0x80u);
+    }
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const int cxi = L::cx[i];
+        int sy = y - L::cy[i], sz = z - L::cz[i];
+        int face = -1;
+        if (L::cy[i] != 0) {
+            if (sy < 0) { if (p.bc[2] == MDF_WALL) face = 2; else sy += p.ny; }
+            else if (sy >= p.ny) { if (p.bc[3] == MDF_WALL) face = 3; else sy -= p.ny; }
+        }
+        if (L::cz[i] != 0) {
+            if (sz < 0) { if (p.bc[4] == MDF_WALL) face = 4; else sz += p.nz; }
+            else if (sz >= p.nz) { if (p.bc[5] == MDF_WALL) face = 5; else sz -= p.nz; }
+        }
+        const C w = C(i == 0 ? L::w0 : L::w1);
+        const int j = L::opp[i];
+#pragma unroll
+        for (int a = 0; a < L::NS; ++a) {
+            const T *plane = src + (long long)(a * L::Q + i) * p.dstride;
+            const T *oplane = src + (long long)(a * L::Q + j) * p.dstride;
+            const C rest_i = rest_value<L, C>(p, a, i), rest_j = rest_value<L, C>(p, a, j);
+            VecT<T, VX> vec;
+#pragma unroll
+            for (int v = 0; v < VX; ++v) vec.v[v] = T(0);
+            if (rowok && face < 0) vec = vload<T, VX>(plane + ((long long)sz * p.ny + sy) * p.pitch + x0);
+            T lo = T(0), hi = T(0);
+            if (cxi > 0) {
+                lo = lane_up1(vec.v[VX - 1]);
+                if (rowok && fix_lo && x0 > 0) lo = plane[own - 1];
+            }
+            if (cxi < 0) {
+                hi = lane_down1(vec.v[0]);
+                if (rowok && fix_hi && x0 + VX < p.nx) hi = plane[own + VX];
+            }
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                if (!fluid[v]) continue;
+                int sx = x0 + v - cxi;
+                int f = face;
+                bool wrapped = false;
+                if (cxi != 0) {
+                    if (sx < 0) { if (p.bc[0] == MDF_WALL) f = 0; else { sx += p.nx; wrapped = true; } }
+                    else if (sx >= p.nx) { if (p.bc[1] == MDF_WALL) f = 1; else { sx -= p.nx; wrapped = true; } }
+                }
+                if (MASK && f < 0 && ((lb[v] >> i) & 1u)) f = 6;
+                if (f >= 0) {
+                    const C val = S::decode(oplane[own + v], rest_j, p.scale);
+                    if (a == 0) {
+                        n[v].f[a][i] = val;
+                    } else {
+                        const C uw = (f < 6) ? C(p.wallu[f][a - 1]) : C(0);
+                        n[v].f[a][i] = -val + C(2) * w * uw;
+                    }
+                } else {
+                    T raw;
+                    const int k = v - cxi;
+                    if (wrapped) raw = plane[own - x0 + sx];
+                    else if (k < 0) raw = lo;
+                    else if (k >= VX) raw = hi;
+                    else raw = vec.v[k < 0 ? 0 : (k >= VX ? VX - 1 : k)];
+                    n[v].f[a][i] = S::decode(raw, rest_i, p.scale);
+                }
+            }
+        }
+    }
 }
 
 // eq. 2-7 and eq. 3-15.
@@ -512,14 +699,108 @@ __device__ __forceinline__ void step_tile(const KCase &p, int gx, int gy, int ti
     }
 }
 
-template <class L, int ST, bool EMIT, bool CHECK, bool MASK>
+// Vector form of step_tile(): thread (tx, ty) of a tile owns the VX nodes
+// x0 = (tile_x * bx + tx) * VX .. x0 + VX - 1 of its row; the tile covers
+// bx * VX by by nodes.  Per node the arithmetic is exactly step_tile()'s, so
+// populations and fields are bitwise those of the scalar kernel.
+template <class L, int ST, bool EMIT, bool CHECK, bool MASK, int VX>
+__device__ __forceinline__ void step_tile_vec(const KCase &p, int gx, int gy, int tile,
+                                              const typename Store<ST>::T *__restrict__ src,
+                                              typename Store<ST>::T *__restrict__ dst,
+                                              const uint8_t *__restrict__ links, uint32_t fields,
+                                              typename Store<ST>::C *__restrict__ out,
+                                              typename Store<ST>::C *__restrict__ snap, double *__restrict__ partial)
+{
+    using S = Store<ST>;
+    using T = typename S::T;
+    using C = typename S::C;
+    const int tx = tile % gx, rest = tile / gx;
+    const int x0 = (tx * blockDim.x + threadIdx.x) * VX;
+    const int y = (rest % gy) * blockDim.y + threadIdx.y;
+    const int z = rest / gy;
+    const bool rowok = (x0 < p.nx) && (y < p.ny);
+    const int lane = (threadIdx.y * blockDim.x + threadIdx.x) & 63;
+    const bool fix_lo = (threadIdx.x == 0) || (lane == 0);
+    const bool fix_hi = (threadIdx.x == blockDim.x - 1) || (lane == 63);
+    Node<L, C> n[VX];
+    bool fluid[VX];
+    gather_vec<L, ST, MASK, VX>(p, src, links, x0, y, z, rowok, fix_lo, fix_hi, n, fluid);
+    const long long nodes = (long long)p.nx * p.ny * p.nz;
+    const long long own = ((long long)z * p.ny + y) * p.pitch + x0;
+    bool all_fluid = true;
+#pragma unroll
+    for (int v = 0; v < VX; ++v) all_fluid = all_fluid && fluid[v];
+    double acc[kNRed];
+#pragma unroll
+    for (int k = 0; k < kNRed; ++k) acc[k] = 0.0;
+    Moments<L, C> m[VX];
+#pragma unroll
+    for (int v = 0; v < VX; ++v) {
+        const long long node = ((long long)z * p.ny + y) * p.nx + x0 + v;
+        const bool inside = rowok && (x0 + v < p.nx);
+        if (fluid[v]) {
+            moments<L, C>(p, n[v], m[v]);
+            if (EMIT) write_fields<L, C>(p, n[v], m[v], fields, out, node, nodes);
+        } else if (EMIT && inside) {
+            int nch = 0;
+            if (fields & MDF_FIELD_MOMENTS) nch += L::NS + 1;
+            if (fields & MDF_FIELD_GRAD) nch += L::D * L::D;
+            if (fields & MDF_FIELD_DIV) nch += 1;
+            if (fields & MDF_FIELD_STRAIN) nch += L::D * (L::D + 1) / 2;
+            if (fields & MDF_FIELD_STRESS) nch += L::D * (L::D + 1) / 2;
+            if (fields & MDF_FIELD_VORT) nch += (L::D == 2 ? 1 : 3);
+            for (int ch = 0; ch < nch; ++ch) out[ch * nodes + node] = C(0);
+        }
+        if (CHECK) {
+            double vv[kNRed];
+            check_values<L, C, true>(m[v], fluid[v], snap, node, nodes, vv);
+#pragma unroll
+            for (int k = 0; k < kNRed; ++k) acc[k] += vv[k];
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < L::NS; ++a) {
+        // collide set a of every owned node in place, then store plane by plane
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            if (!fluid[v]) continue;
+            C ne[L::Q], fo[L::Q];
+            nonequilibrium<L, C>(n[v], m[v], a, ne);
+            collide_set<L, C>(p, n[v], a, ne, fo);
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) n[v].f[a][i] = fo[i];
+        }
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            T *plane = dst + (long long)(a * L::Q + i) * p.dstride;
+            const C rest_i = rest_value<L, C>(p, a, i);
+            VecT<T, VX> ov;
+#pragma unroll
+            for (int v = 0; v < VX; ++v) ov.v[v] = fluid[v] ? S::encode(n[v].f[a][i], rest_i, p.inv_scale) : T(0);
+            if (all_fluid) {
+                vstore<T, VX>(plane + own, ov);
+            } else {
+#pragma unroll
+                for (int v = 0; v < VX; ++v)
+                    if (fluid[v]) plane[own + v] = ov.v[v];
+            }
+        }
+    }
+    if (CHECK) block_reduce_store(acc, partial, tile);
+}
+
+template <class L, int ST, bool EMIT, bool CHECK, bool MASK, int VX>
 __global__ void __launch_bounds__(256)
 k_step(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, typename Store<ST>::T *__restrict__ dst,
        const uint8_t *__restrict__ links, uint32_t fields, typename Store<ST>::C *__restrict__ out,
        typename Store<ST>::C *__restrict__ snap, double *__restrict__ partial)
 {
-    step_tile<L, ST, EMIT, CHECK, MASK>(p, tl.gx, tl.gy, block_tile(tl), src, dst, links, fields, out, snap,
-                                        partial);
+    if constexpr (VX == 1)
+        step_tile<L, ST, EMIT, CHECK, MASK>(p, tl.gx, tl.gy, block_tile(tl), src, dst, links, fields, out, snap,
+                                            partial);
+    else
+        step_tile_vec<L, ST, EMIT, CHECK, MASK, VX>(p, tl.gx, tl.gy, block_tile(tl), src, dst, links, fields, out,
+                                                    snap, partial);
 }
 
 // Batched step: one persistent launch advances every active case of a
@@ -528,7 +809,7 @@ k_step(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, typena
 // to the resident capacity of the chip and each block walks the list.  Tiles
 // are dealt in XCD bands: blocks b with b % groups == g take the g-th
 // contiguous band of the list, so neighbouring tiles of a case share an L2.
-template <class L, int ST, bool EMIT, bool CHECK, bool MASK>
+template <class L, int ST, bool EMIT, bool CHECK, bool MASK, int VX>
 __global__ void __launch_bounds__(256)
 k_step_batch(const BatchEntry *__restrict__ tab, const int *__restrict__ meta, const int *__restrict__ tile_start,
              const int *__restrict__ active, int parity, uint32_t fields, int groups)
@@ -549,9 +830,16 @@ k_step_batch(const BatchEntry *__restrict__ tab, const int *__restrict__ meta, c
         const int sel = (e.cur + parity) & 1;
         using T = typename Store<ST>::T;
         using C = typename Store<ST>::C;
-        step_tile<L, ST, EMIT, CHECK, MASK>(e.p, e.gx, e.gy, t - tile_start[lo], static_cast<const T *>(e.pop[sel]),
-                                            static_cast<T *>(e.pop[sel ^ 1]), e.links, fields,
-                                            static_cast<C *>(e.out), static_cast<C *>(e.snap), e.partial);
+        if constexpr (VX == 1)
+            step_tile<L, ST, EMIT, CHECK, MASK>(e.p, e.gx, e.gy, t - tile_start[lo],
+                                                static_cast<const T *>(e.pop[sel]), static_cast<T *>(e.pop[sel ^ 1]),
+                                                e.links, fields, static_cast<C *>(e.out), static_cast<C *>(e.snap),
+                                                e.partial);
+        else
+            step_tile_vec<L, ST, EMIT, CHECK, MASK, VX>(e.p, e.gx, e.gy, t - tile_start[lo],
+                                                        static_cast<const T *>(e.pop[sel]),
+                                                        static_cast<T *>(e.pop[sel ^ 1]), e.links, fields,
+                                                        static_cast<C *>(e.out), static_cast<C *>(e.snap), e.partial);
         if (CHECK) __syncthreads();   // the block reduction's LDS is reused by the next tile
     }
 }
@@ -769,10 +1057,12 @@ dim3 grid_of(const KCase &p, LaunchShape s)
     return dim3((p.nx + s.bx - 1) / s.bx, (p.ny + s.by - 1) / s.by, p.nz);
 }
 
-Tiling tiling_of(const KCase &p, LaunchShape s)
+// Tiles of the step kernels (bx * vx by by nodes); the read kernels use
+// one node per thread (vx = 1).
+Tiling tiling_of(const KCase &p, LaunchShape s, int vx)
 {
     Tiling t;
-    t.gx = (p.nx + s.bx - 1) / s.bx;
+    t.gx = (p.nx + s.bx * vx - 1) / (s.bx * vx);
     t.gy = (p.ny + s.by - 1) / s.by;
     t.nb = t.gx * t.gy * p.nz;
     t.groups = s.groups > 1 ? s.groups : 1;
@@ -790,12 +1080,15 @@ hipError_t step_dispatch(const KCase &p, const CaseBufs &b, int src, bool check,
     T *o = static_cast<T *>(b.pop[src ^ 1]);
     C *emit = static_cast<C *>(out);
     C *snap = static_cast<C *>(b.snap);
-    const Tiling tl = tiling_of(p, s);
+    const int vx = s.vx > 1 ? S::VX : 1;
+    const Tiling tl = tiling_of(p, s, vx);
     const dim3 grid(tl.nb, 1, 1), block(s.bx, s.by, 1);
     const bool emit_on = (fields != 0) && out != nullptr;
     const bool mask = b.links != nullptr;
+#define MDF_STEP_LAUNCH1(E, K, M, V) \
+    hipLaunchKernelGGL((k_step<L, ST, E, K, M, V>), grid, block, 0, stream, p, tl, in, o, b.links, fields, emit, snap, b.partial)
 #define MDF_STEP_LAUNCH(E, K, M) \
-    hipLaunchKernelGGL((k_step<L, ST, E, K, M>), grid, block, 0, stream, p, tl, in, o, b.links, fields, emit, snap, b.partial)
+    do { if (vx > 1) MDF_STEP_LAUNCH1(E, K, M, S::VX); else MDF_STEP_LAUNCH1(E, K, M, 1); } while (0)
     if (mask) {
         if (emit_on) { if (check) MDF_STEP_LAUNCH(true, true, true); else MDF_STEP_LAUNCH(true, false, true); }
         else { if (check) MDF_STEP_LAUNCH(false, true, true); else MDF_STEP_LAUNCH(false, false, true); }
@@ -804,6 +1097,7 @@ hipError_t step_dispatch(const KCase &p, const CaseBufs &b, int src, bool check,
         else { if (check) MDF_STEP_LAUNCH(false, true, false); else MDF_STEP_LAUNCH(false, false, false); }
     }
 #undef MDF_STEP_LAUNCH
+#undef MDF_STEP_LAUNCH1
     return hipGetLastError();
 }
 
@@ -817,7 +1111,7 @@ hipError_t read_dispatch(const KCase &p, const CaseBufs &b, int src, bool pull, 
     const T *in = static_cast<const T *>(b.pop[src]);
     C *o = static_cast<C *>(out);
     C *snap = static_cast<C *>(b.snap);
-    const Tiling tl = tiling_of(p, s);
+    const Tiling tl = tiling_of(p, s, 1);
     const dim3 grid(tl.nb, 1, 1), block(s.bx, s.by, 1);
     const bool mask = b.links != nullptr;
 #define MDF_READ_LAUNCH(M, PL, MD) \
@@ -859,10 +1153,13 @@ hipError_t init_dispatch(const KCase &p, const CaseBufs &b, int cur, int kind, c
 template <class L, int ST>
 hipError_t batch_dispatch(const BatchLaunch &bl, bool check, bool emit, hipStream_t stream)
 {
+    using S = Store<ST>;
     const dim3 grid(bl.grid, 1, 1), block(bl.shape.bx, bl.shape.by, 1);
-#define MDF_BATCH_LAUNCH(E, K, M)                                                                      \
-    hipLaunchKernelGGL((k_step_batch<L, ST, E, K, M>), grid, block, 0, stream, bl.tab, bl.meta, bl.tile_start, \
+#define MDF_BATCH_LAUNCH1(E, K, M, V)                                                                      \
+    hipLaunchKernelGGL((k_step_batch<L, ST, E, K, M, V>), grid, block, 0, stream, bl.tab, bl.meta, bl.tile_start, \
                        bl.active, bl.parity, bl.fields, bl.shape.groups)
+#define MDF_BATCH_LAUNCH(E, K, M) \
+    do { if (bl.shape.vx > 1) MDF_BATCH_LAUNCH1(E, K, M, S::VX); else MDF_BATCH_LAUNCH1(E, K, M, 1); } while (0)
     if (bl.mask) {
         if (emit) { if (check) MDF_BATCH_LAUNCH(true, true, true); else MDF_BATCH_LAUNCH(true, false, true); }
         else { if (check) MDF_BATCH_LAUNCH(false, true, true); else MDF_BATCH_LAUNCH(false, false, true); }
@@ -871,6 +1168,7 @@ hipError_t batch_dispatch(const BatchLaunch &bl, bool check, bool emit, hipStrea
         else { if (check) MDF_BATCH_LAUNCH(false, true, false); else MDF_BATCH_LAUNCH(false, false, false); }
     }
 #undef MDF_BATCH_LAUNCH
+#undef MDF_BATCH_LAUNCH1
     return hipGetLastError();
 }
 
@@ -878,19 +1176,43 @@ template <class L, int ST>
 hipError_t batch_capacity(LaunchShape shape, bool mask, int *blocks_per_cu)
 {
     // resident blocks per CU of the heaviest variant (emit + check)
+    using S = Store<ST>;
     const int threads = shape.bx * shape.by;
+    if (shape.vx > 1) {
+        if (mask)
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                blocks_per_cu, k_step_batch<L, ST, true, true, true, S::VX>, threads, 0);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu,
+                                                            k_step_batch<L, ST, true, true, false, S::VX>, threads, 0);
+    }
     if (mask)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_step_batch<L, ST, true, true, true>,
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_step_batch<L, ST, true, true, true, 1>,
                                                             threads, 0);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_step_batch<L, ST, true, true, false>,
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_step_batch<L, ST, true, true, false, 1>,
                                                         threads, 0);
 }
 
 }  // namespace
 
-int grid_blocks(const KCase &p, LaunchShape s)
+int step_vx(int storage, LaunchShape s)
 {
-    return tiling_of(p, s).nb;
+    if (s.vx <= 1) return 1;
+    switch (storage) {
+    case MDF_F64: return Store<MDF_F64>::VX;
+    case MDF_F32: return Store<MDF_F32>::VX;
+    case MDF_F16DEV: return Store<MDF_F16DEV>::VX;
+    default: return Store<MDF_BF16DEV>::VX;
+    }
+}
+
+int grid_blocks(const KCase &p, int storage, LaunchShape s)
+{
+    return tiling_of(p, s, step_vx(storage, s)).nb;
+}
+
+int read_blocks(const KCase &p, LaunchShape s)
+{
+    return tiling_of(p, s, 1).nb;
 }
 
 #define MDF_DISPATCH(lattice, storage, FN, ...)                                              \
@@ -916,7 +1238,7 @@ int grid_blocks(const KCase &p, LaunchShape s)
 hipError_t launch_step(int lattice, int storage, const KCase &p, const CaseBufs &b, int src, bool check,
                        uint32_t fields, void *out, LaunchShape shape, int *nblocks_out, hipStream_t stream)
 {
-    if (nblocks_out) *nblocks_out = grid_blocks(p, shape);
+    if (nblocks_out) *nblocks_out = grid_blocks(p, storage, shape);
     MDF_DISPATCH(lattice, storage, step_dispatch, p, b, src, check, fields, out, shape, stream);
 }
 
@@ -924,7 +1246,7 @@ hipError_t launch_read(int lattice, int storage, const KCase &p, const CaseBufs 
                        int mode, uint32_t fields, void *out, LaunchShape shape, int *nblocks_out,
                        hipStream_t stream)
 {
-    if (nblocks_out) *nblocks_out = grid_blocks(p, shape);
+    if (nblocks_out) *nblocks_out = read_blocks(p, shape);
     MDF_DISPATCH(lattice, storage, read_dispatch, p, b, src, pull, mode, fields, out, shape, stream);
 }
 

@@ -80,7 +80,7 @@ def lib():
         L.mdf_run_steady.argtypes = [vp, dbl, i32, i64, ctypes.c_uint32, ctypes.POINTER(vp),
                                      ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(dbl), vp]
         L.mdf_invariants.argtypes = [vp, i32, ctypes.POINTER(dbl), vp]
-        L.mdf_set_launch.argtypes = [vp, i32, i32, i32]
+        L.mdf_set_launch.argtypes = [vp, i32, i32, i32, i32]
         L.mdf_autotune.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl), vp]
         L.mdf_set_active.argtypes = [vp, ctypes.POINTER(i32)]
         L.mdf_time.argtypes = [vp, i32]
@@ -265,8 +265,10 @@ class Solver:
             self._ctx = None
 
     # -------------------------------------------------------------- stepping
-    def set_launch(self, bx: int, by: int, groups: int = 8):
-        _check(lib().mdf_set_launch(self._ctx, bx, by, groups), self._ctx)
+    def set_launch(self, bx: int, by: int, groups: int = 8, vec: int = 0):
+        """Tile of bx x by threads, XCD bands, and vec = 1 for the vector step
+        kernels (several x-nodes per thread) or 0 for one node per thread."""
+        _check(lib().mdf_set_launch(self._ctx, bx, by, groups, int(vec)), self._ctx)
 
     def set_active(self, active):
         """Enable (non-zero) or disable (0) each case."""
@@ -275,7 +277,7 @@ class Solver:
 
     def autotune(self, trial_steps: int = 20):
         """Pick the fastest launch shape on real steps (advances time)."""
-        chosen = (ctypes.c_int32 * 3)()
+        chosen = (ctypes.c_int32 * 4)()
         best = ctypes.c_double()
         _check(lib().mdf_autotune(self._ctx, int(trial_steps), chosen, ctypes.byref(best),
                                   _stream_ptr(self.stream)), self._ctx)

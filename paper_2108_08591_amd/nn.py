@@ -22,7 +22,7 @@ import torch
 
 from . import mdf
 
-FEATURES = 5          # solid mask, Re feature, lid-speed feature, x, y
+FEATURES = 6          # solid mask, Re feature, lid-speed feature, x, y, wall distance
 IN_CH = 32            # features padded to the 32-channel granularity of the kernels
 OUT_CH = 7            # P, u, v, du/dx, du/dy, dv/dx, dv/dy
 LEVELS = (32, 64, 128, 256)
@@ -392,9 +392,11 @@ class UNet:
 # ---------------------------------------------------------------- data
 
 def input_features(N, mask, Re, U):
-    """Per-node features: solid flag, (log10 Re - 2), U / 0.1 - 0.75, and
-    the node coordinates in [-1, 1]; zero-padded to IN_CH channels.
-    Returns float32 [N, N, IN_CH] ([y, x, c])."""
+    """Per-node features: solid flag, (log10 Re - 2), U / 0.1 - 0.75, the
+    node coordinates in [-1, 1] and the distance to the nearest solid node or
+    cavity wall (in units of N; 0 inside solids); zero-padded to IN_CH
+    channels.  Returns float32 [N, N, IN_CH] ([y, x, c])."""
+    from scipy.ndimage import distance_transform_edt
     f = np.zeros((N, N, IN_CH), np.float32)
     f[..., 0] = mask.astype(np.float32)
     f[..., 1] = math.log10(Re) - 2.0
@@ -402,26 +404,34 @@ def input_features(N, mask, Re, U):
     c = (np.arange(N) + 0.5) / N * 2 - 1
     f[..., 3] = c[None, :]
     f[..., 4] = c[:, None]
+    # walls sit halfway outside the first and last nodes: a solid ring one
+    # node wide around the grid, distances shifted by the half node
+    fluid = np.zeros((N + 2, N + 2), bool)
+    fluid[1:-1, 1:-1] = mask == 0
+    d = distance_transform_edt(fluid)[1:-1, 1:-1]
+    f[..., 5] = np.where(mask == 0, (d - 0.5) / N, 0.0)
     return f
 
 
-def raw_targets(fields: Dict[str, torch.Tensor], N, U):
-    """Steady fields of one case scaled by the lid speed: P / U^2, u / U,
-    v / U and grad u * N / U, as float32 [N, N, OUT_CH]."""
+def raw_targets(fields: Dict[str, torch.Tensor], N, U, Re):
+    """Steady fields of one case in scales that keep every case O(1):
+    P Re / U^2 (the cavity pressure of this scheme follows the viscous
+    scaling P ~ U^2 / Re over the whole Re range), u / U, v / U and
+    grad u * N / U, as float32 [N, N, OUT_CH]."""
     P = fields["P"] - fields["P"].mean()
     g = fields["grad"]
-    out = torch.stack([P / (U * U), fields["u"][0] / U, fields["u"][1] / U,
+    out = torch.stack([P * (Re / (U * U)), fields["u"][0] / U, fields["u"][1] / U,
                        g[0, 0] * N / U, g[0, 1] * N / U, g[1, 0] * N / U, g[1, 1] * N / U], dim=-1)
     return out.float()
 
 
-def fields_from_prediction(pred: np.ndarray, N, U, mask, norm):
+def fields_from_prediction(pred: np.ndarray, N, U, Re, mask, norm):
     """Inverse of raw_targets for one case: [N, N, OUT_CH] normalised
     network output -> channel-major [P, u, v, grad(4)] init data (float64)
     with solid nodes zeroed."""
     y = pred * norm["std"] + norm["mean"]
     fl = np.zeros((7, N, N))
-    fl[0] = y[..., 0] * U * U
+    fl[0] = y[..., 0] * (U * U / Re)
     fl[1] = y[..., 1] * U
     fl[2] = y[..., 2] * U
     for k in range(4):

@@ -76,15 +76,17 @@ def solve(cases: List[dict], storage="f32", tol=1e-8, K=100, max_steps=400000, i
     return solver, st, steps, res, time.perf_counter() - t0
 
 
-def dataset(cases: List[dict], solver) -> Dict[str, torch.Tensor]:
+def dataset(cases: List[dict], solver, log: Optional[Callable[[str], None]] = None) -> Dict[str, torch.Tensor]:
     """Inputs (bf16 [n, N, N, IN_CH]), raw targets (f32 [n, N*N, OUT_CH])
     and fluid weights (f32 [n, N*N]) from solved cases."""
     X, T, Wt = [], [], []
     for k, c in enumerate(cases):
+        if log and k % 2048 == 0:
+            log(json.dumps({"dataset_cases": k, "of": len(cases)}))
         N = c["N"]
         X.append(torch.tensor(nn.input_features(N, c["mask"], c["Re"], c["U"])))
         f = solver.fields(FIELDS, k)
-        T.append(nn.raw_targets(f, N, c["U"]).reshape(N * N, nn.OUT_CH).cpu())
+        T.append(nn.raw_targets(f, N, c["U"], c["Re"]).reshape(N * N, nn.OUT_CH).cpu())
         Wt.append(torch.tensor((c["mask"] == 0).astype(np.float32).reshape(-1)))
     torch.cuda.synchronize()
     return {"X": torch.stack(X), "T": torch.stack(T), "W": torch.stack(Wt)}
@@ -99,20 +101,30 @@ def fit_normalisation(T, W):
     return {"mean": mean.numpy().astype(np.float32), "std": std.numpy().astype(np.float32)}
 
 
-def train(model: nn.UNet, data: Dict[str, torch.Tensor], epochs=30, batch=16, lr=2e-3, seed=0,
-          log: Optional[Callable[[str], None]] = None):
+def train(model: nn.UNet, data: Dict[str, torch.Tensor], epochs=30, batch=16, lr=2e-3, seed=0, clip=None,
+          val: Optional[Dict[str, torch.Tensor]] = None, log: Optional[Callable[[str], None]] = None):
     """Adam on the weighted MSE of the normalised targets; inputs and
-    targets are moved to the device once.  Returns the per-epoch losses."""
+    targets are moved to the device once.  clip (in standard deviations)
+    bounds the normalised targets, so that the few nodes at the singular lid
+    corners do not dominate the loss.  Returns the per-epoch losses (and
+    the held-out losses when `val` is given)."""
     dev = model.device
     model.norm = fit_normalisation(data["T"], data["W"])
     mean = torch.tensor(model.norm["mean"], device=dev)
     std = torch.tensor(model.norm["std"], device=dev)
-    X = nn.to_bf16(data["X"].to(dev))
-    T = ((data["T"].to(dev) - mean) / std).contiguous()
-    W = data["W"].to(dev).contiguous()
+
+    def prep(d):
+        X = nn.to_bf16(d["X"].to(dev))
+        T = (d["T"].to(dev) - mean) / std
+        if clip is not None:
+            T = T.clamp(-clip, clip)
+        return X, T.contiguous(), d["W"].to(dev).contiguous()
+
+    X, T, W = prep(data)
+    Xv, Tv, Wv = prep(val) if val is not None else (None, None, None)
     n = X.shape[0]
     rng = np.random.default_rng(seed)
-    history = []
+    history, val_hist = [], []
     steps_per_epoch = max(1, n // batch)
     total = epochs * steps_per_epoch
     it = 0
@@ -133,9 +145,19 @@ def train(model: nn.UNet, data: Dict[str, torch.Tensor], epochs=30, batch=16, lr
             it += 1
             acc += float(loss.item())
         history.append(acc / steps_per_epoch)
+        rec = {"epoch": ep + 1, "loss": round(history[-1], 6)}
+        if Xv is not None and ((ep + 1) % 10 == 0 or ep + 1 == epochs):
+            vl = 0.0
+            for b in range(0, Xv.shape[0], batch):
+                model.forward(Xv[b:b + batch].contiguous())
+                l, _ = model.loss_and_grad(Tv[b:b + batch].reshape(-1, nn.OUT_CH).contiguous(),
+                                           Wv[b:b + batch].reshape(-1).contiguous())
+                vl += float(l.item()) * min(batch, Xv.shape[0] - b)
+            rec["val_loss"] = round(vl / Xv.shape[0], 6)
+            val_hist.append((ep + 1, rec["val_loss"]))
         if log:
-            log(json.dumps({"epoch": ep + 1, "loss": round(history[-1], 6)}))
-    return history
+            log(json.dumps(rec))
+    return (history, val_hist) if Xv is not None else history
 
 
 def predict(model: nn.UNet, cases: List[dict], with_grad=True, batch=16) -> List[np.ndarray]:
@@ -150,8 +172,34 @@ def predict(model: nn.UNet, cases: List[dict], with_grad=True, batch=16) -> List
         y = model.forward(nn.to_bf16(X.to(dev)))
         y = y.reshape(len(part), N, N, nn.OUT_CH).cpu().numpy()
         for k, c in enumerate(part):
-            fl = nn.fields_from_prediction(y[k], N, c["U"], c["mask"], model.norm)
+            fl = nn.fields_from_prediction(y[k], N, c["U"], c["Re"], c["mask"], model.norm)
             out.append(fl if with_grad else fl[:3].copy())
+    return out
+
+
+def solution_init(solver, k) -> np.ndarray:
+    """The steady fields of case k as channel-major [P, u, v, grad(4)]
+    init data (float64): the warm start an exact predictor would give."""
+    f = solver.fields(FIELDS, k)
+    P = f["P"].double().cpu().numpy()
+    u = f["u"].double().cpu().numpy()
+    g = f["grad"].double().cpu().numpy()
+    return np.stack([P, u[0], u[1], g[0, 0], g[0, 1], g[1, 0], g[1, 1]])
+
+
+CHANNELS = ("P", "u", "v", "du/dx", "du/dy", "dv/dx", "dv/dy")
+
+
+def prediction_error(init: np.ndarray, exact: np.ndarray, mask) -> Dict[str, float]:
+    """Relative L2 error per channel of a predicted init over fluid nodes
+    (P with its mean removed from both, since only its gradient acts)."""
+    fl = mask == 0
+    out = {}
+    for c, name in enumerate(CHANNELS):
+        a, b = init[c][fl], exact[c][fl]
+        if c == 0:
+            a, b = a - a.mean(), b - b.mean()
+        out[name] = float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
     return out
 
 

@@ -258,18 +258,47 @@ def test_emit_equals_readonly_bitwise():
     assert torch.equal(mom, again[: 4])
 
 
-def test_launch_shapes_bitwise_identical():
-    spec = C.cavity_case(N=100, Re=100.0)
-    spec.shape = (100, 70)
-    pops = []
-    for bx, by, g in ((64, 4, 8), (64, 4, 1), (256, 1, 8), (128, 2, 3), (32, 2, 8), (64, 1, 1)):
-        _say(f"[gpu] launch shape {bx}x{by} groups {g}")
-        s = mdf.Solver([spec], storage="f32", device=DEV)
-        s.set_launch(bx, by, g)
-        s.step(50)
-        pops.append(s.populations())
-    for p in pops[1:]:
-        assert torch.equal(p, pops[0])
+def _shape_cases():
+    """Walls in x (cavity), periodic x with obstacles, and a 3D box with
+    periodic x and walls in y and z; every width is ragged for the vector
+    kernels (not a multiple of 4 nodes, and rows shorter and longer than one
+    tile)."""
+    cav = C.cavity_case(N=102, Re=100.0)
+    cav.shape = (102, 70)
+    per = C.tgv2d_case(N=70, u0=0.02, Re=20.0)
+    per.shape = (70, 46)
+    per.force = (2e-6, -1e-6, 0.0)
+    mask = np.zeros((46, 70), np.uint8)
+    mask[10:18, 20:27] = 1
+    mask[30:34, 0:3] = 1          # touches the periodic seam
+    mask[20:25, 66:70] = 1
+    box = C.CaseSpec(C.D3Q7, (38, 22, 14), 1.1, bc=(C.PERIODIC, C.PERIODIC, C.WALL, C.WALL, C.WALL, C.WALL),
+                     wall_u=((0, 0, 0), (0, 0, 0), (0, 0, 0), (0.05, 0, 0), (0, 0, 0), (0, 0.02, 0)))
+    return [("cavity", cav, None), ("periodic+mask", per, mask), ("box3d", box, None)]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev", "bf16dev"])
+def test_launch_shapes_bitwise_identical(storage):
+    """Scalar and vector step kernels, any tile shape and band count: the
+    same populations and emitted fields, bit for bit."""
+    for name, spec, mask in _shape_cases():
+        fields = mdf.FIELD_ALL
+        pops, outs = [], []
+        for bx, by, g, vec in ((64, 4, 8, 0), (64, 4, 8, 1), (64, 4, 1, 1), (256, 1, 8, 1), (128, 2, 3, 1),
+                               (32, 2, 8, 1), (64, 1, 1, 1), (32, 8, 8, 0)):
+            _say(f"[gpu] {storage} {name} launch {bx}x{by} groups {g} vec {vec}")
+            P, u = C.smooth_random_fields(spec, seed=5, amp=0.03)
+            init = ("fields", [_fields_tensor(P, u, storage=storage)])
+            s = mdf.Solver([spec], storage=storage, solid=None if mask is None else [mask], init=init,
+                           device=DEV, u_ref=0.05)
+            s.set_launch(bx, by, g, vec)
+            s.step(23)
+            out = s.step_emit(1, fields)
+            pops.append(s.populations())
+            outs.append(out[0].clone())
+        for p, o in zip(pops[1:], outs[1:]):
+            assert torch.equal(p, pops[0])
+            assert torch.equal(o, outs[0])
 
 
 def test_invariants_and_residual_match_oracle():
@@ -313,7 +342,7 @@ def test_full_size_cavity_sampled_parity():
     spec = C.cavity_case(N=1024, Re=1000.0)
     _say("[parity] full-size cavity 1024^2 sampled")
     s = mdf.Solver([spec], storage="f32", device=DEV)
-    s.set_launch(64, 4, 8)
+    s.set_launch(64, 4, 8, 1)
     s.step(300)
     f_t = _np(s.populations())
     s.step(1)
