@@ -108,27 +108,32 @@ def _short_kernel_name(name):
 
 
 def summarize_trace(db_path, command):
-    """Markdown summary of a rocprofv3 --kernel-trace --stats database."""
+    """Markdown summary of a rocprofv3 --kernel-trace --stats database, one
+    row per kernel and grid size."""
     import sqlite3
     cur = sqlite3.connect(db_path).cursor()
-    rows = list(cur.execute("select name, total_calls, total_duration, average, percentage "
-                            "from top_kernels order by total_duration desc"))
+    rows = list(cur.execute(
+        "select name, grid_x * grid_y * grid_z as g, count(*), sum(duration) / 1000.0, "
+        "avg(duration) / 1000.0 from kernels group by name, g order by sum(duration) desc"))
+    total = sum(r[3] for r in rows)
     out = ["# rocprofv3 kernel trace", "", "Command (run from the repository root on the GPU box):", "",
            "```", command, "```", "",
-           "| kernel | calls | total (us) | average (us) | % |", "|---|---|---|---|---|"]
-    for name, calls, tot, avg, pct in rows:
-        out.append(f"| `{_short_kernel_name(name)}` | {calls} | {tot:.1f} | {avg:.3f} | {pct:.2f} |")
+           "| kernel | grid (work-items) | calls | total (us) | average (us) | % |", "|---|---|---|---|---|---|"]
+    for name, g, calls, tot, avg in rows:
+        out.append(f"| `{_short_kernel_name(name)}` | {g} | {calls} | {tot:.1f} | {avg:.3f} | "
+                   f"{100.0 * tot / total:.2f} |")
     return "\n".join(out) + "\n"
 
 
 def counter_means(db_path, counter):
+    """Mean of a counter per (kernel, grid size): {(name, grid): (dispatches, mean)}."""
     import sqlite3
     import statistics
     cur = sqlite3.connect(db_path).cursor()
     acc = {}
-    for name, val in cur.execute("select kernel_name, value from counters_collection where counter_name=?",
-                                 (counter,)):
-        acc.setdefault(_short_kernel_name(name), []).append(val)
+    for name, g, val in cur.execute("select kernel_name, grid_size, value from counters_collection "
+                                    "where counter_name=?", (counter,)):
+        acc.setdefault((_short_kernel_name(name), g), []).append(val)
     return {k: (len(v), statistics.mean(v)) for k, v in acc.items()}
 
 
@@ -142,11 +147,12 @@ def summarize_traffic(fetch_db, write_db, copy_fetch_db, copy_write_db, kernel_p
     cf = counter_means(copy_fetch_db, "FETCH_SIZE")
     cw = counter_means(copy_write_db, "WRITE_SIZE")
     copy_kib = 256 * 1024
-    ck = [k for k in cf if "copyBuffer" in k][0]
+    ck = [k for k in cf if "copyBuffer" in k[0]][0]
     fetch_scale = copy_kib / cf[ck][1]
     write_scale = copy_kib / cw[ck][1]
-    kf = [k for k in f if k.startswith(kernel_prefix)][0]
-    kw = [k for k in w if k.startswith(kernel_prefix)][0]
+    # the step kernel on the benchmark grid: the most frequent dispatch shape
+    kf = max((k for k in f if k[0].startswith(kernel_prefix)), key=lambda k: f[k][0])
+    kw = max((k for k in w if k[0].startswith(kernel_prefix)), key=lambda k: w[k][0])
     fetch_b = f[kf][1] * 1024 * fetch_scale
     write_b = w[kw][1] * 1024 * write_scale
     total = fetch_b + write_b
