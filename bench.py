@@ -513,6 +513,65 @@ def warmstart_study(out_path, n_train=1024, n_test=32, N=128, epochs=30, batch=1
         json.dump(rec, fh, indent=1)
 
 
+def restart_study(out_path, n=16, N=128):
+    """What a warm start gains as a function of the accuracy of the fields it
+    starts from: held-out cavities are solved cold to residual 1e-8 (FP64),
+    refined to 1e-12, and restarted from the refined (P, u, grad u) exactly,
+    with f^eq only, with P zeroed, and with seeded smooth relative errors of
+    1e-4 .. 1e-1 on every channel or on the velocity alone."""
+    import numpy as np
+    import torch
+    from paper_2108_08591_amd import warmstart as WS
+    log = lambda m: print(m, flush=True)
+    stream = torch.cuda.Stream()
+    cases = [c for c in WS.warmstart_cases(24, N, seed=777) if c["Re"] < 600][:n]
+    cold_solver, st, cold, _, wall = WS.solve(cases, "f64", 1e-8, 100, 400000, stream=stream)
+    rec = {"N": N, "cases": len(cases), "cold_steps": cold.tolist(), "cold_status": st.tolist(),
+           "cold_wall_s": round(wall, 2), "variants": []}
+    first = [WS.solution_init(cold_solver, k) for k in range(len(cases))]
+    del cold_solver
+    ref_solver, st2, _, _, _ = WS.solve(cases, "f64", 1e-12, 100, 800000, init=first, stream=stream)
+    ref = [WS.solution_init(ref_solver, k) for k in range(len(cases))]
+    del ref_solver
+    rng = np.random.default_rng(1)
+
+    def smooth(n_):
+        k = np.fft.fftfreq(n_)[:, None] ** 2 + np.fft.fftfreq(n_)[None, :] ** 2
+        z = np.fft.ifft2(np.fft.fft2(rng.standard_normal((n_, n_))) * np.exp(-k * (n_ / 8) ** 2)).real
+        return z / np.abs(z).max()
+
+    def run(name, make, feq_only=False):
+        init = []
+        for k, c in enumerate(cases):
+            a = make(ref[k].copy())
+            a[:, c["mask"].astype(bool)] = 0.0
+            init.append(a[:3].copy() if feq_only else a)
+        _, wst, steps, _, w = WS.solve(cases, "f64", 1e-8, 100, 400000, init=init, stream=stream)
+        ent = {"variant": name, "steps": steps.tolist(), "status": wst.tolist(),
+               "speedup_steps_total": round(float(cold.sum()) / max(1.0, float(steps.sum())), 3)}
+        rec["variants"].append(ent)
+        log(json.dumps({k: ent[k] for k in ("variant", "speedup_steps_total")}))
+
+    run("exact", lambda a: a)
+    run("exact, f^eq only", lambda a: a, feq_only=True)
+    run("exact, P = 0", lambda a: np.concatenate([0 * a[:1], a[1:]]))
+    for eps in (1e-4, 1e-3, 1e-2, 1e-1):
+        def all_ch(a, eps=eps):
+            for ch in range(a.shape[0]):
+                a[ch] *= 1 + eps * smooth(N)
+            return a
+
+        def vel(a, eps=eps):
+            scale = np.abs(a[1:3]).max()
+            a[1] += eps * scale * smooth(N)
+            a[2] += eps * scale * smooth(N)
+            return a
+        run(f"every channel x (1 + {eps:g} s)", all_ch)
+        run(f"u, v + {eps:g} max|u| s", vel)
+    with open(out_path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+
+
 class _Subset:
     """Read-outs of selected cases of a solver, renumbered from 0."""
 
@@ -545,6 +604,7 @@ def main():
     ap.add_argument("--batch-study", metavar="OUT_JSON", help="512-case uneven batch to steady state")
     ap.add_argument("--steady-study", metavar="OUT_JSON", help="wall time to residual 1e-8")
     ap.add_argument("--warmstart-study", metavar="OUT_JSON", help="learned warm start vs cold start")
+    ap.add_argument("--restart-study", metavar="OUT_JSON", help="warm-start gain vs accuracy of the initial fields")
     ap.add_argument("--ws-train", type=int, default=1024)
     ap.add_argument("--ws-epochs", type=int, default=30)
     ap.add_argument("--ws-n", type=int, default=128)
@@ -565,6 +625,9 @@ def main():
         return
     if args.steady_study:
         steady_study(args.steady_study)
+        return
+    if args.restart_study:
+        restart_study(args.restart_study)
         return
     if args.warmstart_study:
         warmstart_study(args.warmstart_study, n_train=args.ws_train, N=args.ws_n, epochs=args.ws_epochs,
