@@ -173,19 +173,20 @@ def summarize_traffic(fetch_db, write_db, copy_fetch_db, copy_write_db, kernel_p
 
 
 def parse_launch(text):
-    """'64x4g8v' -> (64, 4, 8, 1): tile of 64 x 4 threads, 8 XCD bands, vector
-    step kernel ('v') or one node per thread ('s', default)."""
+    """'128x2g8t' -> (128, 2, 8, 2): tile of 128 x 2 threads, 8 XCD bands and
+    the step-kernel form: 's' one node per thread (default, 0), 'v' vector
+    (1), 't' two steps per launch (2)."""
     t = text.lower()
-    vec = 0
-    if t.endswith("v") or t.endswith("s"):
-        vec = 1 if t[-1] == "v" else 0
+    form = 0
+    if t[-1] in "svt":
+        form = "svt".index(t[-1])
         t = t[:-1]
     groups = 1
     if "g" in t:
         t, g = t.split("g")
         groups = int(g)
     bx, by = (int(v) for v in t.split("x"))
-    return bx, by, groups, vec
+    return bx, by, groups, form
 
 
 def time_launches(solver, stream, n, fields=0, out=None, reps=3):
@@ -224,7 +225,7 @@ def sweep(out_path):
         for st in ("f32", "f64", "f16dev", "bf16dev"):
             runs.append(("d3q7", N, st))
     shapes = [(64, 4, 8, 1), (128, 2, 8, 1), (256, 1, 8, 1), (64, 2, 8, 1), (64, 4, 8, 0), (128, 2, 8, 0),
-              (256, 1, 8, 0)]
+              (256, 1, 8, 0), (128, 2, 8, 2), (128, 2, 1, 2)]
     with open(out_path, "w") as fh:
         for lat, N, st in runs:
             if lat == "d2q5":
@@ -241,11 +242,13 @@ def sweep(out_path):
             nodes = spec.nodes
             alg = nodes * 2 * q * ns * sb[st]
             n = max(5, min(400, int(2e10 / alg)))
-            for bx, by, g, vec in shapes:
-                solver.set_launch(bx, by, g, vec)
+            for bx, by, g, form in shapes:
+                if form == 2 and lat != "d2q5":
+                    continue
+                solver.set_launch(bx, by, g, form)
                 solver.step(2)
                 ms = time_launches(solver, stream, n)
-                rec = {"lattice": lat, "N": N, "storage": st, "launch": f"{bx}x{by}g{g}{'v' if vec else 's'}",
+                rec = {"lattice": lat, "N": N, "storage": st, "launch": f"{bx}x{by}g{g}{'svt'[form]}",
                        "ms": round(ms, 5), "MLUPS": round(nodes / ms / 1e3, 1),
                        "GBps": round(alg / ms / 1e6, 1), "frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4),
                        "working_set_MB": round(2 * alg / 2 / 1e6, 1)}
@@ -588,8 +591,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--launch", default="128x2g8s",
-                    help="threads per block, XCD groups and kernel form, BXxBYgG[v|s] (v: vector, s: one node/thread)")
+    ap.add_argument("--launch", default="128x2g8t",
+                    help="threads per block, XCD groups and kernel form, BXxBYgG[s|v|t] (s: one node/thread, v: vector, t: two steps per launch)")
     ap.add_argument("--sweep", metavar="OUT_JSONL",
                     help="time the step kernel over grid sizes, storages and launch shapes")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -600,6 +603,8 @@ def main():
                     metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB", "OUT_MD"),
                     help="calibrated HBM traffic of the step kernel from rocprofv3 counter databases")
     ap.add_argument("--command", default="", help="command recorded in a summary")
+    ap.add_argument("--traffic-kernel", default="step", choices=["step", "step2"],
+                    help="kernel whose counters --summarize-traffic reads (one-step or two-step)")
     ap.add_argument("--precision-study", metavar="OUT_JSON", help="FP16/BF16/FP32 vs FP64 storage, 3D TGV")
     ap.add_argument("--batch-study", metavar="OUT_JSON", help="512-case uneven batch to steady state")
     ap.add_argument("--steady-study", metavar="OUT_JSON", help="wall time to residual 1e-8")
@@ -640,8 +645,14 @@ def main():
     if args.summarize_traffic:
         fdb, wdb, cfdb, cwdb, out_md = args.summarize_traffic
         nodes = 1024 * 1024
-        md, ent = summarize_traffic(fdb, wdb, cfdb, cwdb, "k_step<LatD2Q5, 1, true, false, false, 1>", nodes * (2 * 15 * 4 + 4 * 4),
-                                    "k_step<D2Q5,F32,emit>_cavity1024", args.command.split(" ;; "))
+        if args.traffic_kernel == "step2":
+            md, ent = summarize_traffic(fdb, wdb, cfdb, cwdb, "k_step2<LatD2Q5, 1, true, false>",
+                                        nodes * (2 * 15 * 4 + 2 * 4 * 4), "k_step2<D2Q5,F32,emit>_cavity1024",
+                                        args.command.split(" ;; "))
+        else:
+            md, ent = summarize_traffic(fdb, wdb, cfdb, cwdb, "k_step<LatD2Q5, 1, true, false, false, 1>",
+                                        nodes * (2 * 15 * 4 + 4 * 4), "k_step<D2Q5,F32,emit>_cavity1024",
+                                        args.command.split(" ;; "))
         with open(out_md, "w") as fh:
             fh.write(md)
         path = os.path.join(ROOT, "profiles", "traffic_counters.json")
@@ -666,8 +677,8 @@ def main():
     fields = mdf.FIELD_VORT | mdf.FIELD_STRAIN
     stream = torch.cuda.Stream(device=dev)
     solver = mdf.Solver([spec], storage="f32", device=dev, stream=stream)
-    bx, by, groups, vec = parse_launch(args.launch)
-    solver.set_launch(bx, by, groups, vec)
+    bx, by, groups, form = parse_launch(args.launch)
+    solver.set_launch(bx, by, groups, form)
     out = solver.new_field_buffers(fields)
     K = 100
     nodes = spec.nodes
@@ -693,13 +704,27 @@ def main():
 
     # average launch duration of the step kernel: HIP events on the stream
     # the kernel runs on, around batches of back-to-back launches (no other
-    # work in between)
-    nlaunch, reps = 500, 5
-    avg_ms = time_launches(solver, stream, nlaunch, fields, out, reps)
-    bytes_per_node = 2 * 15 * 4 + 4 * 4          # populations read+write, 4 emitted FP32 fields
-    alg_bytes = nodes * bytes_per_node
+    # work in between).  With two steps per launch a call of 2m + 1 steps is
+    # m two-step launches and one one-step launch.
+    reps = 5
+    state_bytes = 2 * 15 * 4                      # one read and one write of the FP32 state per node
+    field_bytes = 4 * 4                           # 4 emitted FP32 fields per node and step
+    step_bytes = state_bytes + field_bytes        # per node and step (one-step kernel)
+    if form == 2:
+        steps_per_launch, nsteps_timed = 2, 1001
+        launch_bytes = state_bytes + 2 * field_bytes
+        kernel_key = "k_step2<D2Q5,F32,emit>_cavity1024"
+        kernel_note = ("two steps per launch: the state crosses HBM once per two steps, so the algorithmic bytes "
+                       "of a launch are one read and one write of the state plus the fields of both steps")
+    else:
+        steps_per_launch, nsteps_timed = 1, 500
+        launch_bytes = step_bytes
+        kernel_key = "k_step<D2Q5,F32,emit>_cavity1024"
+        kernel_note = "one step per launch"
+    avg_step_ms = time_launches(solver, stream, nsteps_timed, fields, out, reps)
+    avg_ms = avg_step_ms * steps_per_launch
+    alg_bytes = nodes * launch_bytes
     achieved = alg_bytes / (avg_ms / 1e3) / 1e9
-    kernel_key = "k_step<D2Q5,F32,emit>_cavity1024"
     traffic = measured_traffic(kernel_key, alg_bytes)
 
     result = {
@@ -719,9 +744,12 @@ def main():
             "workload": "lid-driven cavity 1024x1024, D2Q5 x 3 sets, FP32 storage, Re=1000, lid 0.1, "
                         "per-step vorticity+strain emission, FP64 residual every 100 steps",
             "nodes": nodes, "Re": 1000, "lid_u": 0.1, "storage": "f32",
-            "launch": f"{bx}x{by}g{groups}{'v' if vec else 's'}",
+            "launch": f"{bx}x{by}g{groups}{'svt'[form]}",
         },
-        "hbm_roofline_pct": round(100.0 * mlups * 1e6 * bytes_per_node / (HBM_PEAK_GBS * 1e9), 2),
+        # per-step bytes of a one-step update (state read + write + fields) at
+        # the achieved MLUPS, against the HBM peak; above 100 % only when
+        # several steps share one pass over HBM
+        "hbm_roofline_pct": round(100.0 * mlups * 1e6 * step_bytes / (HBM_PEAK_GBS * 1e9), 2),
         "roofline": {
             "bound": "hbm",
             "achieved": round(achieved, 1),
@@ -731,10 +759,11 @@ def main():
             "traffic": traffic,
             "kernel": kernel_key,
             "bytes_per_launch": alg_bytes,
+            "steps_per_launch": steps_per_launch,
             "avg_launch_ms": round(avg_ms, 5),
-            "launch_timing": f"HIP events around {nlaunch} back-to-back launches, best of {reps}",
-            "note": "working set 120 MiB + 16 MiB of emitted fields fits the 256 MB Infinity Cache; "
-                    "see roofline_hbm_resident for an 8 GiB working set",
+            "launch_timing": f"HIP events around {nsteps_timed} back-to-back steps, best of {reps}",
+            "note": kernel_note + "; working set 120 MiB + 16 MiB of emitted fields fits the 256 MB Infinity "
+                    "Cache; see roofline_hbm_resident for an 8 GiB working set",
         },
         "residual_after": float(res[0]),
     }
@@ -744,15 +773,16 @@ def main():
     torch.cuda.empty_cache()
     big = C.cavity_case(N=8192, Re=1000.0, U=0.1)
     bsolver = mdf.Solver([big], storage="f32", device=dev, stream=stream)
-    bsolver.set_launch(bx, by, groups, vec)
+    bsolver.set_launch(bx, by, groups, form)
     bout = bsolver.new_field_buffers(fields)
     bsolver.step_emit(2, fields, bout)
-    big_ms = time_launches(bsolver, stream, 40, fields, bout, reps)
-    big_bytes = big.nodes * bytes_per_node
+    big_ms = time_launches(bsolver, stream, 41, fields, bout, reps) * steps_per_launch
+    big_bytes = big.nodes * launch_bytes
     result["roofline_hbm_resident"] = {
         "workload": "same kernel, cavity 8192x8192 (8 GiB of populations)",
         "achieved": round(big_bytes / (big_ms / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(big_bytes / (big_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "avg_launch_ms": round(big_ms, 4)}
+        "frac": round(big_bytes / (big_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "avg_launch_ms": round(big_ms, 4),
+        "MLUPS": round(big.nodes * steps_per_launch / (big_ms / 1e3) / 1e6, 1)}
     del bsolver, bout
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:

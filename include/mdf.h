@@ -199,15 +199,24 @@ mdf_status mdf_invariants(const mdf_ctx *ctx, int32_t case_id, double *out, void
  * by by threads, bx * by a multiple of 64 up to 256 (whole wavefronts), and
  * `groups` > 1 hands the tiles out in that many contiguous bands, one per
  * XCD (8 on MI355X), so neighbouring tiles share an L2; 0 or 1 keeps plain
- * order.  vec = 1 gives each thread of the step kernels a vector of
- * consecutive x-nodes (2 for MDF_STORAGE_F64, 4 for the other storages), read
- * and written as one 16-byte (8-byte for the 16-bit storages) access per
- * plane; vec = 0 gives one node per thread.  The read kernels always use one
- * node per thread.  Default 64 x 4, 8 groups, vec = 0.  MDF_EINVAL
- * otherwise.  Any shape gives bitwise identical populations and fields; only
- * the summation order of the FP64 sums of mdf_check, mdf_run_steady and
+ * order.  `form` selects the step kernel:
+ *   0  one node per thread;
+ *   1  vector: each thread of the step kernels owns consecutive x-nodes (2
+ *      for MDF_STORAGE_F64, 4 for the other storages), read and written as one
+ *      16-byte (8-byte for the 16-bit storages) access per plane;
+ *   2  two steps per launch (MDF_D2Q5 only): tiles of 64 x 4/8/16 nodes
+ *      (FP64/FP32/16-bit) take one step on the tile and a one-node halo into
+ *      LDS and the second from LDS, so the state crosses HBM once per two
+ *      steps.  Used by mdf_step, mdf_step_emit and mdf_run_steady of
+ *      single-case contexts for all but the last step of each call (and
+ *      chunk), which runs as form 0 with these bx, by; batched contexts run
+ *      form 0.
+ * The read kernels always use one node per thread.  Default 64 x 4, 8
+ * groups, form 0.  MDF_EINVAL otherwise (also form 2 on MDF_D3Q7).  Any shape
+ * and form give bitwise identical populations and fields; only the
+ * summation order of the FP64 sums of mdf_check, mdf_run_steady and
  * mdf_invariants follows it. */
-mdf_status mdf_set_launch(mdf_ctx *ctx, int32_t bx, int32_t by, int32_t groups, int32_t vec);
+mdf_status mdf_set_launch(mdf_ctx *ctx, int32_t bx, int32_t by, int32_t groups, int32_t form);
 
 /* Enable or disable cases.  Disabled cases are skipped by mdf_step,
  * mdf_step_emit, mdf_run_steady and mdf_autotune: their populations and
@@ -219,11 +228,12 @@ mdf_status mdf_set_active(mdf_ctx *ctx, const int32_t *active);
 /* Choose the launch shape of this context by timing candidate shapes
  * (vector tiles 64x4, 128x2, 256x1, 64x2, 64x1 with XCD bands and 64x4
  * without; one-node tiles 64x4, 128x2, 256x1, 128x1, 32x8 with bands and
- * 64x4 without) on `trial_steps` real steps each and keeping the fastest.
- * Every case advances by (trial_steps + 1) steps per candidate (results
- * are bitwise independent of the shape).  chosen: host int[4] (bx, by,
- * groups, vec) or NULL; best_ms: host double, time per step, or NULL.
- * Waits for the device. */
+ * 64x4 without; for single-case D2Q5 contexts also two steps per launch with
+ * and without bands) on `trial_steps` real steps each and keeping the
+ * fastest.  Every case advances by (trial_steps + 1) steps per candidate
+ * tried (results are bitwise independent of the shape).  chosen: host
+ * int[4] (bx, by, groups, form) or NULL; best_ms: host double, time per
+ * step, or NULL.  Waits for the device. */
 mdf_status mdf_autotune(mdf_ctx *ctx, int32_t trial_steps, int32_t *chosen, double *best_ms,
                         void *stream);
 

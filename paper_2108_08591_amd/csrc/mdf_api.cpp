@@ -155,7 +155,7 @@ struct mdf_ctx {
     std::vector<int64_t> time;
     std::vector<int64_t> snap_time;    // time of the velocity snapshot, -1 = none
     std::vector<uint8_t> enabled;      // mdf_set_active
-    LaunchShape shape{64, 4, 8, 1};
+    LaunchShape shape{64, 4, 8, 1, 0};
     hipError_t latched = hipSuccess;
     std::string err;
     std::vector<double> host_red;
@@ -246,6 +246,30 @@ mdf_status step_case(mdf_ctx *ctx, int k, bool check, uint32_t fields, void *out
     if (e != hipSuccess) return device_error(ctx, e, "step launch");
     ctx->cur[k] ^= 1;
     ctx->time[k] += 1;
+    return MDF_OK;
+}
+
+// Advance case k by nsteps.  With the two-step form, pairs of steps run as
+// one launch and the call always ends with at least one one-step launch, so
+// that the buffer the read kernels pull from holds f*(t - 1) again; the
+// check (if any) rides on the last step.
+mdf_status advance_case(mdf_ctx *ctx, int k, int64_t nsteps, bool check_last, uint32_t fields, void *out,
+                        hipStream_t st, int *nblocks)
+{
+    int64_t pairs = 0;
+    if (ctx->shape.fuse && ctx->lattice == MDF_D2Q5 && nsteps >= 3) pairs = (nsteps - 1) / 2;
+    for (int64_t s = 0; s < pairs; ++s) {
+        hipError_t e = mdf::launch_step2(ctx->lattice, ctx->storage, ctx->kc[k], ctx->bufs[k], ctx->cur[k], fields,
+                                         out, ctx->shape, st);
+        if (e != hipSuccess) return device_error(ctx, e, "two-step launch");
+        ctx->cur[k] ^= 1;
+        ctx->time[k] += 2;
+    }
+    const int64_t singles = nsteps - 2 * pairs;
+    for (int64_t s = 0; s < singles; ++s) {
+        mdf_status r = step_case(ctx, k, check_last && s == singles - 1, fields, out, st, nblocks);
+        if (r != MDF_OK) return r;
+    }
     return MDF_OK;
 }
 
@@ -524,15 +548,17 @@ mdf_status mdf_init(mdf_ctx **out, mdf_lattice lattice, mdf_storage storage, con
     return MDF_OK;
 }
 
-mdf_status mdf_set_launch(mdf_ctx *ctx, int32_t bx, int32_t by, int32_t groups, int32_t vec)
+mdf_status mdf_set_launch(mdf_ctx *ctx, int32_t bx, int32_t by, int32_t groups, int32_t form)
 {
     if (!ctx) return fail(nullptr, MDF_EINVAL, "mdf_set_launch: ctx is NULL");
     if (bx < 32 || bx % 32 != 0 || by < 1 || bx * by > 256 || (bx * by) % 64 != 0)
         return fail(ctx, MDF_EINVAL,
                     "mdf_set_launch: need bx %% 32 == 0 and bx*by a multiple of 64 up to 256 (got %d x %d)", bx, by);
     if (groups < 0 || groups > 64) return fail(ctx, MDF_EINVAL, "mdf_set_launch: groups outside [0, 64]");
-    if (vec != 0 && vec != 1) return fail(ctx, MDF_EINVAL, "mdf_set_launch: vec must be 0 or 1");
-    ctx->shape = LaunchShape{bx, by, groups, vec ? 2 : 1};
+    if (form < 0 || form > 2) return fail(ctx, MDF_EINVAL, "mdf_set_launch: form must be 0, 1 or 2");
+    if (form == 2 && ctx->lattice != MDF_D2Q5)
+        return fail(ctx, MDF_EINVAL, "mdf_set_launch: two steps per launch needs MDF_D2Q5");
+    ctx->shape = LaunchShape{bx, by, groups, form == 1 ? 2 : 1, form == 2 ? 1 : 0};
     drop_graphs(ctx);
     return MDF_OK;
 }
@@ -559,12 +585,11 @@ static mdf_status step_impl(mdf_ctx *ctx, int32_t nsteps, uint32_t fields, void 
         if (r != MDF_OK) return r;
         return batch_steps(ctx, nsteps, false, fields, st);
     }
-    for (int s = 0; s < nsteps; ++s)
-        for (int k = 0; k < ctx->ncases; ++k) {
-            if (!ctx->enabled[k]) continue;
-            mdf_status r = step_case(ctx, k, false, fields, fields ? out[k] : nullptr, st, nullptr);
-            if (r != MDF_OK) return r;
-        }
+    for (int k = 0; k < ctx->ncases; ++k) {
+        if (!ctx->enabled[k]) continue;
+        mdf_status r = advance_case(ctx, k, nsteps, false, fields, fields ? out[k] : nullptr, st, nullptr);
+        if (r != MDF_OK) return r;
+    }
     return MDF_OK;
 }
 
@@ -709,8 +734,8 @@ mdf_status mdf_run_steady(mdf_ctx *ctx, double tol, int32_t K, int64_t max_steps
             if (done >= max_steps) continue;
             const int64_t chunk = std::min<int64_t>(K, max_steps - done);
             int nb = 0;
-            for (int64_t s = 0; s < chunk; ++s) {
-                mdf_status r = step_case(ctx, k, s == chunk - 1, fields, fields ? out[k] : nullptr, st, &nb);
+            {
+                mdf_status r = advance_case(ctx, k, chunk, true, fields, fields ? out[k] : nullptr, st, &nb);
                 if (r != MDF_OK) return r;
             }
             mdf_status r = finalize_and_fetch(ctx, k, nb, st, ctx->host_red.data());
@@ -764,7 +789,8 @@ mdf_status mdf_autotune(mdf_ctx *ctx, int32_t trial_steps, int32_t *chosen, doub
     if (trial_steps < 1) return fail(ctx, MDF_EINVAL, "mdf_autotune: trial_steps < 1");
     static const int cand[][4] = {{64, 4, 8, 1}, {128, 2, 8, 1}, {256, 1, 8, 1}, {64, 2, 8, 1},
                                   {64, 1, 8, 1}, {64, 4, 1, 1}, {64, 4, 8, 0}, {128, 2, 8, 0},
-                                  {256, 1, 8, 0}, {64, 4, 1, 0}, {128, 1, 8, 0}, {32, 8, 8, 0}};
+                                  {256, 1, 8, 0}, {64, 4, 1, 0}, {128, 1, 8, 0}, {32, 8, 8, 0},
+                                  {128, 2, 8, 2}, {64, 4, 1, 2}};
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
@@ -774,6 +800,8 @@ mdf_status mdf_autotune(mdf_ctx *ctx, int32_t trial_steps, int32_t *chosen, doub
     int bi = 0;
     mdf_status r = MDF_OK;
     for (int c = 0; c < int(sizeof cand / sizeof cand[0]) && r == MDF_OK; ++c) {
+        // two steps per launch: 2D single-case contexts only
+        if (cand[c][3] == 2 && (ctx->lattice != MDF_D2Q5 || ctx->batched)) continue;
         r = mdf_set_launch(ctx, cand[c][0], cand[c][1], cand[c][2], cand[c][3]);
         if (r != MDF_OK) break;
         r = step_impl(ctx, 1, 0, nullptr, stream);           // warm-up (and graph capture)

@@ -43,6 +43,7 @@ struct LaunchShape {
     int bx, by;             // threads per block along x and y (bx * by <= 256)
     int groups;             // > 1: hand out tiles in `groups` contiguous bands, one per XCD
     int vx;                 // > 1: step kernels give each thread the storage's vector width of x-nodes
+    int fuse;               // 1: advance two steps per launch where possible (D2Q5, single-case contexts)
 };
 
 // Tile grid of one launch: gx * gy * gz tiles of bx * by threads, launched
@@ -86,6 +87,10 @@ hipError_t launch_links(int lattice, const KCase &p, const uint8_t *solid, uint8
                         hipStream_t stream);
 hipError_t launch_init(int lattice, int storage, const KCase &p, const CaseBufs &b, int cur,
                        int kind, const void *data, hipStream_t stream);
+// Two steps in one launch (D2Q5 only): f*(t) in pop[src] -> f*(t+2) in
+// pop[src ^ 1]; fields (if any) emitted at both steps.
+hipError_t launch_step2(int lattice, int storage, const KCase &p, const CaseBufs &b, int src, uint32_t fields,
+                        void *out, LaunchShape shape, hipStream_t stream);
 hipError_t launch_step(int lattice, int storage, const KCase &p, const CaseBufs &b, int src,
                        bool check, uint32_t fields, void *out, LaunchShape shape,
                        int *nblocks_out, hipStream_t stream);

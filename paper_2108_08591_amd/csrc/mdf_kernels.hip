@@ -803,6 +803,154 @@ k_step(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, typena
                                                     snap, partial);
 }
 
+// ----------------------------------------------------------------- two steps per pass (D2Q5)
+
+// Output rows of one tile of k_step2 per storage, so that the LDS copy of
+// the intermediate state (NS * Q planes of (64 + 2) x (rows + 2) stored
+// values) stays within 64 KB: 47.5 KB for FP64, 39.6 KB for FP32, 35.6 KB
+// for the 16-bit formats.
+template <int ST> struct Fuse2Rows { static constexpr int TY = 16; };
+template <> struct Fuse2Rows<MDF_F64> { static constexpr int TY = 4; };
+template <> struct Fuse2Rows<MDF_F32> { static constexpr int TY = 8; };
+
+constexpr int kF2X = 64;                 // output columns of a tile
+constexpr int kF2W = kF2X + 2;           // columns of the tile plus its one-node halo
+
+// Two time steps in one pass over HBM (temporal blocking, 2D only).  A block
+// owns a tile of 64 x TY nodes.  Step 1 runs on the tile and a one-node
+// halo with the one-step code (pull from the post-collision state f*(t) in
+// HBM, wall rule, moments, fields, collision); its result f*(t+1) goes to
+// LDS in the storage format (encoded exactly as a one-step launch would store
+// it).  Halo nodes across a periodic face are the wrapped nodes; halo nodes
+// behind a wall are not needed (step 2 takes the wall rule there).  Step 2
+// pulls f(t+2) from LDS, applies the same wall rule, emits the fields and
+// writes f*(t+2) to HBM.  Every population, field and emitted value is
+// bitwise that of two one-step launches; HBM traffic per step drops from one
+// read and one write of the state to about half of that plus the halo
+// re-reads ((64 + 2)(TY + 2) / (64 TY) of a read per two steps).
+// The caller keeps f*(t+1) out of HBM, so the buffer the read kernels pull
+// from is stale after this kernel until the next one-step launch.
+template <class L, int ST, bool EMIT, bool MASK>
+__global__ void __launch_bounds__(256)
+k_step2(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, typename Store<ST>::T *__restrict__ dst,
+        const uint8_t *__restrict__ links, uint32_t fields, typename Store<ST>::C *__restrict__ out)
+{
+    static_assert(L::D == 2, "two-step tiles are two-dimensional");
+    using S = Store<ST>;
+    using T = typename S::T;
+    using C = typename S::C;
+    constexpr int TY = Fuse2Rows<ST>::TY;
+    constexpr int W = kF2W, NE = kF2W * (TY + 2), NP = L::NS * L::Q;
+    __shared__ T lds[NP * NE];
+    const int tile = block_tile(tl);
+    const int x0 = (tile % tl.gx) * kF2X, y0 = (tile / tl.gx) * TY;
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    const long long nodes = (long long)p.nx * p.ny;
+
+    // step 1: t -> t+1 on the tile and its halo, into LDS
+    for (int e = tid; e < NE; e += nthr) {
+        const int ex = e % W, ey = e / W;
+        int x = x0 - 1 + ex, y = y0 - 1 + ey;
+        const bool interior = ex >= 1 && ex <= kF2X && ey >= 1 && ey <= TY && x < p.nx && y < p.ny;
+        if (x < 0 || x >= p.nx) {
+            if (p.bc[x < 0 ? 0 : 1] == MDF_WALL) continue;
+            x = ((x % p.nx) + p.nx) % p.nx;
+        }
+        if (y < 0 || y >= p.ny) {
+            if (p.bc[y < 0 ? 2 : 3] == MDF_WALL) continue;
+            y = ((y % p.ny) + p.ny) % p.ny;
+        }
+        Node<L, C> n;
+        if (!gather<L, ST, MASK, true>(p, src, links, x, y, 0, n)) continue;      // solid node
+        Moments<L, C> m;
+        moments<L, C>(p, n, m);
+        if (EMIT && interior) write_fields<L, C>(p, n, m, fields, out, (long long)y * p.nx + x, nodes);
+#pragma unroll
+        for (int a = 0; a < L::NS; ++a) {
+            C ne[L::Q], fo[L::Q];
+            nonequilibrium<L, C>(n, m, a, ne);
+            collide_set<L, C>(p, n, a, ne, fo);
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i)
+                lds[(a * L::Q + i) * NE + e] = S::encode(fo[i], rest_value<L, C>(p, a, i), p.inv_scale);
+        }
+    }
+    __syncthreads();
+
+    // step 2: t+1 -> t+2 on the tile, from LDS to HBM
+    for (int e = tid; e < kF2X * TY; e += nthr) {
+        const int ox = e % kF2X, oy = e / kF2X;
+        const int x = x0 + ox, y = y0 + oy;
+        if (x >= p.nx || y >= p.ny) continue;
+        const long long own = (long long)y * p.pitch + x;
+        const long long node = (long long)y * p.nx + x;
+        const int le = (oy + 1) * W + (ox + 1);
+        unsigned lb = 0;
+        if (MASK) lb = links[own];
+        if (MASK && (lb & 0x80u)) {
+            if (EMIT) {
+                int nch = 0;
+                if (fields & MDF_FIELD_MOMENTS) nch += L::NS + 1;
+                if (fields & MDF_FIELD_GRAD) nch += L::D * L::D;
+                if (fields & MDF_FIELD_DIV) nch += 1;
+                if (fields & MDF_FIELD_STRAIN) nch += L::D * (L::D + 1) / 2;
+                if (fields & MDF_FIELD_STRESS) nch += L::D * (L::D + 1) / 2;
+                if (fields & MDF_FIELD_VORT) nch += 1;
+                for (int ch = 0; ch < nch; ++ch) out[ch * nodes + node] = C(0);
+            }
+            continue;
+        }
+        Node<L, C> n;
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const int sx = x - L::cx[i], sy = y - L::cy[i];
+            int face = -1;
+            if (L::cx[i] != 0) {
+                if (sx < 0) { if (p.bc[0] == MDF_WALL) face = 0; }
+                else if (sx >= p.nx) { if (p.bc[1] == MDF_WALL) face = 1; }
+            }
+            if (L::cy[i] != 0) {
+                if (sy < 0) { if (p.bc[2] == MDF_WALL) face = 2; }
+                else if (sy >= p.ny) { if (p.bc[3] == MDF_WALL) face = 3; }
+            }
+            if (MASK && face < 0 && ((lb >> i) & 1u)) face = 6;
+            const C w = C(i == 0 ? L::w0 : L::w1);
+            if (face < 0) {
+                const int k = le - L::cx[i] - L::cy[i] * W;
+#pragma unroll
+                for (int a = 0; a < L::NS; ++a)
+                    n.f[a][i] = S::decode(lds[(a * L::Q + i) * NE + k], rest_value<L, C>(p, a, i), p.scale);
+            } else {
+                const int j = L::opp[i];
+#pragma unroll
+                for (int a = 0; a < L::NS; ++a) {
+                    const C v = S::decode(lds[(a * L::Q + j) * NE + le], rest_value<L, C>(p, a, j), p.scale);
+                    if (a == 0) {
+                        n.f[a][i] = v;
+                    } else {
+                        const C uw = (face < 6) ? C(p.wallu[face][a - 1]) : C(0);
+                        n.f[a][i] = -v + C(2) * w * uw;
+                    }
+                }
+            }
+        }
+        Moments<L, C> m;
+        moments<L, C>(p, n, m);
+        if (EMIT) write_fields<L, C>(p, n, m, fields, out, node, nodes);
+#pragma unroll
+        for (int a = 0; a < L::NS; ++a) {
+            C ne[L::Q], fo[L::Q];
+            nonequilibrium<L, C>(n, m, a, ne);
+            collide_set<L, C>(p, n, a, ne, fo);
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i)
+                S::store(dst + (long long)(a * L::Q + i) * p.dstride, own, fo[i], rest_value<L, C>(p, a, i),
+                         p.inv_scale);
+        }
+    }
+}
+
 // Batched step: one persistent launch advances every active case of a
 // context by one step.  The tiles of all active cases form one flat list
 // (case k owns tiles tile_start[k] .. tile_start[k+1]-1); the grid is sized
@@ -1102,6 +1250,35 @@ hipError_t step_dispatch(const KCase &p, const CaseBufs &b, int src, bool check,
 }
 
 template <class L, int ST>
+hipError_t step2_dispatch(const KCase &p, const CaseBufs &b, int src, uint32_t fields, void *out, LaunchShape s,
+                          hipStream_t stream)
+{
+    using S = Store<ST>;
+    using T = typename S::T;
+    using C = typename S::C;
+    if constexpr (L::D != 2) {
+        return hipErrorInvalidValue;
+    } else {
+        const T *in = static_cast<const T *>(b.pop[src]);
+        T *o = static_cast<T *>(b.pop[src ^ 1]);
+        C *emit = static_cast<C *>(out);
+        Tiling tl;
+        tl.gx = (p.nx + kF2X - 1) / kF2X;
+        tl.gy = (p.ny + Fuse2Rows<ST>::TY - 1) / Fuse2Rows<ST>::TY;
+        tl.nb = tl.gx * tl.gy;
+        tl.groups = s.groups > 1 ? s.groups : 1;
+        const bool emit_on = (fields != 0) && out != nullptr;
+        const bool mask = b.links != nullptr;
+#define MDF_STEP2_LAUNCH(E, M) \
+    hipLaunchKernelGGL((k_step2<L, ST, E, M>), dim3(tl.nb), dim3(256), 0, stream, p, tl, in, o, b.links, fields, emit)
+        if (mask) { if (emit_on) MDF_STEP2_LAUNCH(true, true); else MDF_STEP2_LAUNCH(false, true); }
+        else { if (emit_on) MDF_STEP2_LAUNCH(true, false); else MDF_STEP2_LAUNCH(false, false); }
+#undef MDF_STEP2_LAUNCH
+        return hipGetLastError();
+    }
+}
+
+template <class L, int ST>
 hipError_t read_dispatch(const KCase &p, const CaseBufs &b, int src, bool pull, int mode, uint32_t fields,
                          void *out, LaunchShape s, hipStream_t stream)
 {
@@ -1240,6 +1417,13 @@ hipError_t launch_step(int lattice, int storage, const KCase &p, const CaseBufs 
 {
     if (nblocks_out) *nblocks_out = grid_blocks(p, storage, shape);
     MDF_DISPATCH(lattice, storage, step_dispatch, p, b, src, check, fields, out, shape, stream);
+}
+
+hipError_t launch_step2(int lattice, int storage, const KCase &p, const CaseBufs &b, int src, uint32_t fields,
+                        void *out, LaunchShape shape, hipStream_t stream)
+{
+    if (lattice != MDF_D2Q5 || p.nz != 1) return hipErrorInvalidValue;
+    MDF_DISPATCH(lattice, storage, step2_dispatch, p, b, src, fields, out, shape, stream);
 }
 
 hipError_t launch_read(int lattice, int storage, const KCase &p, const CaseBufs &b, int src, bool pull,

@@ -265,10 +265,11 @@ class Solver:
             self._ctx = None
 
     # -------------------------------------------------------------- stepping
-    def set_launch(self, bx: int, by: int, groups: int = 8, vec: int = 0):
-        """Tile of bx x by threads, XCD bands, and vec = 1 for the vector step
-        kernels (several x-nodes per thread) or 0 for one node per thread."""
-        _check(lib().mdf_set_launch(self._ctx, bx, by, groups, int(vec)), self._ctx)
+    def set_launch(self, bx: int, by: int, groups: int = 8, form: int = 0):
+        """Tile of bx x by threads, XCD bands, and the step-kernel form: 0 one
+        node per thread, 1 vector (several x-nodes per thread), 2 two steps
+        per launch (D2Q5)."""
+        _check(lib().mdf_set_launch(self._ctx, bx, by, groups, int(form)), self._ctx)
 
     def set_active(self, active):
         """Enable (non-zero) or disable (0) each case."""

@@ -284,21 +284,56 @@ def test_launch_shapes_bitwise_identical(storage):
     for name, spec, mask in _shape_cases():
         fields = mdf.FIELD_ALL
         pops, outs = [], []
-        for bx, by, g, vec in ((64, 4, 8, 0), (64, 4, 8, 1), (64, 4, 1, 1), (256, 1, 8, 1), (128, 2, 3, 1),
-                               (32, 2, 8, 1), (64, 1, 1, 1), (32, 8, 8, 0)):
-            _say(f"[gpu] {storage} {name} launch {bx}x{by} groups {g} vec {vec}")
+        shapes = [(64, 4, 8, 0), (64, 4, 8, 1), (64, 4, 1, 1), (256, 1, 8, 1), (128, 2, 3, 1), (32, 2, 8, 1),
+                  (64, 1, 1, 1), (32, 8, 8, 0)]
+        if spec.lattice == C.D2Q5:
+            shapes += [(64, 4, 8, 2), (128, 2, 1, 2)]
+        for bx, by, g, form in shapes:
+            _say(f"[gpu] {storage} {name} launch {bx}x{by} groups {g} form {form}")
             P, u = C.smooth_random_fields(spec, seed=5, amp=0.03)
             init = ("fields", [_fields_tensor(P, u, storage=storage)])
             s = mdf.Solver([spec], storage=storage, solid=None if mask is None else [mask], init=init,
                            device=DEV, u_ref=0.05)
-            s.set_launch(bx, by, g, vec)
+            s.set_launch(bx, by, g, form)
             s.step(23)
-            out = s.step_emit(1, fields)
+            out = s.step_emit(5, fields)
             pops.append(s.populations())
             outs.append(out[0].clone())
         for p, o in zip(pops[1:], outs[1:]):
             assert torch.equal(p, pops[0])
             assert torch.equal(o, outs[0])
+
+
+def test_two_step_form_state_and_reads():
+    """Two steps per launch: after calls of every length (pairs plus a last
+    one-step launch), the time, the populations, every read-out and the
+    steady-state residual equal those of one-step launches bit for bit; the
+    form is refused on D3Q7."""
+    spec = C.cavity_case(N=70, Re=100.0)
+    spec.shape = (70, 37)
+    runs = []
+    for form in (0, 2):
+        _say(f"[gpu] two-step form {form}")
+        s = mdf.Solver([spec], storage="f32", device=DEV)
+        s.set_launch(64, 4, 8, form)
+        rec = []
+        for n in (1, 2, 3, 4, 7, 10):
+            s.step(n)
+            rec.append((s.time(), s.populations(), s.gradients(mdf.FIELD_ALL)))
+        st, steps, res = s.run_steady(1e-300, 9, 45)
+        rec.append((s.time(), s.populations(), float(res[0])))
+        runs.append(rec)
+    for a, b in zip(runs[0], runs[1]):
+        assert a[0] == b[0]
+        assert torch.equal(a[1], b[1])
+        if isinstance(a[2], torch.Tensor):
+            assert torch.equal(a[2], b[2])
+        else:
+            assert abs(a[2] - b[2]) <= 1e-12 * abs(a[2])
+    box = C.CaseSpec(C.D3Q7, (16, 8, 8), 1.1)
+    s3 = mdf.Solver([box], storage="f32", device=DEV)
+    with pytest.raises(mdf.MdfError):
+        s3.set_launch(64, 4, 8, 2)
 
 
 def test_invariants_and_residual_match_oracle():
@@ -335,51 +370,55 @@ def test_mass_conserved_in_closed_cavity():
 
 
 def test_full_size_cavity_sampled_parity():
-    """C2 cavity at full size (1024^2, FP32, Re = 1000, the benchmark's launch
-    shape): after 300 steps, one more step is checked node by node against
-    the oracle on sampled patches (corners, lid, walls, interior), using the
-    GPU's own pre-collision state as the oracle's input."""
+    """C2 cavity at full size (1024^2, FP32, Re = 1000) in the benchmark's
+    launch configuration (two steps per launch, 128 x 2 tiles, 8 XCD bands):
+    after 300 steps, one more step and then three more (one two-step launch
+    and one one-step launch) are checked node by node against the oracle on
+    sampled patches (corners, lid, walls, interior), using the GPU's own
+    state as the oracle's input."""
     spec = C.cavity_case(N=1024, Re=1000.0)
-    _say("[parity] full-size cavity 1024^2 sampled")
+    _say("[parity] full-size cavity 1024^2 sampled, two-step launches")
     s = mdf.Solver([spec], storage="f32", device=DEV)
-    s.set_launch(64, 4, 8, 1)
+    s.set_launch(128, 2, 8, 2)
     s.step(300)
-    f_t = _np(s.populations())
-    s.step(1)
-    f_t1 = _np(s.populations())
-    fl_t1 = gpu_fields_np(s, mdf.FIELD_ALL)
     N = 1024
     patches = [(0, 0), (N - 16, 0), (0, N - 16), (N - 16, N - 16), (500, N - 16), (0, 400), (N - 16, 700),
-               (300, 0), (512, 512)]
-    for (x0, y0) in patches:
-        x1, y1 = x0 + 16, y0 + 16
-        # extend by one node where the patch does not touch a wall
-        ex0, ex1 = max(x0 - 1, 0), min(x1 + 1, N)
-        ey0, ey1 = max(y0 - 1, 0), min(y1 + 1, N)
-        wall = spec.wall_velocity().copy()
-        bc = [C.WALL if ex0 == 0 else C.PERIODIC, C.WALL if ex1 == N else C.PERIODIC,
-              C.WALL if ey0 == 0 else C.PERIODIC, C.WALL if ey1 == N else C.PERIODIC, 0, 0]
-        # periodic faces come in pairs: a patch touching one wall uses a
-        # wall on the opposite (halo) side too; those halo nodes are not compared
-        for ax in range(2):
-            if bc[2 * ax] != bc[2 * ax + 1]:
-                bc[2 * ax] = bc[2 * ax + 1] = C.WALL
-        sub = C.CaseSpec(C.D2Q5, (ex1 - ex0, ey1 - ey0), spec.s1, bc=tuple(bc), wall_u=wall)
-        o = oracle_for(sub).set_populations(f_t[:, :, ey0:ey1, ex0:ex1].copy())
-        o.run(1)
-        ix = slice(x0 - ex0, x1 - ex0)
-        iy = slice(y0 - ey0, y1 - ey0)
-        po = o.populations()[:, :, iy, ix]
-        pg = f_t1[:, :, y0:y1, x0:x1]
-        assert rel_err(po, pg) < 1e-5, (x0, y0)
-        fo = o.fields()
-        # fields: max error against the global size of the field (the
-        # interior is still at rest at this time)
-        for key in ("u", "vort", "S", "P"):
-            ref = fo[key][..., iy, ix]
-            got = fl_t1[key][..., y0:y1, x0:x1]
-            big = np.abs(fl_t1[key]).max()
-            assert np.abs(ref - got).max() <= 1e-5 * big, (key, x0, y0)
+               (300, 0), (512, 512), (127, 250)]
+    for nsteps in (1, 3):
+        f_t = _np(s.populations())
+        s.step(nsteps)
+        f_t1 = _np(s.populations())
+        fl_t1 = gpu_fields_np(s, mdf.FIELD_ALL)
+        h = nsteps
+        for (x0, y0) in patches:
+            x1, y1 = x0 + 16, y0 + 16
+            # extend by the dependence radius where the patch does not touch a wall
+            ex0, ex1 = max(x0 - h, 0), min(x1 + h, N)
+            ey0, ey1 = max(y0 - h, 0), min(y1 + h, N)
+            wall = spec.wall_velocity().copy()
+            bc = [C.WALL if ex0 == 0 else C.PERIODIC, C.WALL if ex1 == N else C.PERIODIC,
+                  C.WALL if ey0 == 0 else C.PERIODIC, C.WALL if ey1 == N else C.PERIODIC, 0, 0]
+            # periodic faces come in pairs: a patch touching one wall uses a
+            # wall on the opposite (halo) side too; those halo nodes are not compared
+            for ax in range(2):
+                if bc[2 * ax] != bc[2 * ax + 1]:
+                    bc[2 * ax] = bc[2 * ax + 1] = C.WALL
+            sub = C.CaseSpec(C.D2Q5, (ex1 - ex0, ey1 - ey0), spec.s1, bc=tuple(bc), wall_u=wall)
+            o = oracle_for(sub).set_populations(f_t[:, :, ey0:ey1, ex0:ex1].copy())
+            o.run(nsteps)
+            ix = slice(x0 - ex0, x1 - ex0)
+            iy = slice(y0 - ey0, y1 - ey0)
+            po = o.populations()[:, :, iy, ix]
+            pg = f_t1[:, :, y0:y1, x0:x1]
+            assert rel_err(po, pg) < 1e-5, (nsteps, x0, y0)
+            fo = o.fields()
+            # fields: max error against the global size of the field (the
+            # interior is still at rest at this time)
+            for key in ("u", "vort", "S", "P"):
+                ref = fo[key][..., iy, ix]
+                got = fl_t1[key][..., y0:y1, x0:x1]
+                big = np.abs(fl_t1[key]).max()
+                assert np.abs(ref - got).max() <= 1e-5 * big, (nsteps, key, x0, y0)
 
 
 def test_fp32_zeroth_moment_does_not_drift():
