@@ -607,6 +607,8 @@ def main():
                     help="kernel whose counters --summarize-traffic reads (one-step or two-step)")
     ap.add_argument("--precision-study", metavar="OUT_JSON", help="FP16/BF16/FP32 vs FP64 storage, 3D TGV")
     ap.add_argument("--batch-study", metavar="OUT_JSON", help="512-case uneven batch to steady state")
+    ap.add_argument("--batch-max-steps", type=int, default=400000)
+    ap.add_argument("--batch-wall-s", type=float, default=420.0)
     ap.add_argument("--steady-study", metavar="OUT_JSON", help="wall time to residual 1e-8")
     ap.add_argument("--warmstart-study", metavar="OUT_JSON", help="learned warm start vs cold start")
     ap.add_argument("--restart-study", metavar="OUT_JSON", help="warm-start gain vs accuracy of the initial fields")
@@ -614,6 +616,7 @@ def main():
     ap.add_argument("--ws-epochs", type=int, default=30)
     ap.add_argument("--ws-n", type=int, default=128)
     ap.add_argument("--ws-lr", type=float, default=1e-3)
+    ap.add_argument("--ws-batch", type=int, default=16)
     ap.add_argument("--ws-clip", type=float, default=0.0, help="target clip in standard deviations (0: none)")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -626,7 +629,7 @@ def main():
         precision_study(args.precision_study)
         return
     if args.batch_study:
-        batch_study(args.batch_study)
+        batch_study(args.batch_study, max_steps=args.batch_max_steps, wall_budget_s=args.batch_wall_s)
         return
     if args.steady_study:
         steady_study(args.steady_study)
@@ -636,7 +639,7 @@ def main():
         return
     if args.warmstart_study:
         warmstart_study(args.warmstart_study, n_train=args.ws_train, N=args.ws_n, epochs=args.ws_epochs,
-                        lr=args.ws_lr, clip=args.ws_clip or None)
+                        lr=args.ws_lr, clip=args.ws_clip or None, batch=args.ws_batch)
         return
     if args.summarize_trace:
         with open(args.summarize_trace[1], "w") as fh:

@@ -207,12 +207,12 @@ mdf_status mdf_invariants(const mdf_ctx *ctx, int32_t case_id, double *out, void
  *   2  two steps per launch (MDF_D2Q5 only): tiles of 64 x 4/8/16 nodes
  *      (FP64/FP32/16-bit) take one step on the tile and a one-node halo into
  *      LDS and the second from LDS, so the state crosses HBM once per two
- *      steps.  Used by mdf_step, mdf_step_emit and mdf_run_steady of
- *      single-case contexts for all but the last step of each call (and
- *      chunk), which runs as form 0 with these bx, by; batched contexts run
- *      form 0.
+ *      steps.  mdf_step, mdf_step_emit and mdf_run_steady (single-case and
+ *      batched contexts) run pairs of steps this way and the last step of
+ *      each call (and of each K-step chunk) as form 0 with these bx, by.
  * The read kernels always use one node per thread.  Default 64 x 4, 8
- * groups, form 0.  MDF_EINVAL otherwise (also form 2 on MDF_D3Q7).  Any shape
+ * groups, form 2 for MDF_D2Q5 and form 0 for MDF_D3Q7.  MDF_EINVAL
+ * otherwise (also form 2 on MDF_D3Q7).  Any shape
  * and form give bitwise identical populations and fields; only the
  * summation order of the FP64 sums of mdf_check, mdf_run_steady and
  * mdf_invariants follows it. */
@@ -228,8 +228,8 @@ mdf_status mdf_set_active(mdf_ctx *ctx, const int32_t *active);
 /* Choose the launch shape of this context by timing candidate shapes
  * (vector tiles 64x4, 128x2, 256x1, 64x2, 64x1 with XCD bands and 64x4
  * without; one-node tiles 64x4, 128x2, 256x1, 128x1, 32x8 with bands and
- * 64x4 without; for single-case D2Q5 contexts also two steps per launch with
- * and without bands) on `trial_steps` real steps each and keeping the
+ * 64x4 without; for D2Q5 contexts also two steps per launch with and
+ * without bands) on `trial_steps` real steps each and keeping the
  * fastest.  Every case advances by (trial_steps + 1) steps per candidate
  * tried (results are bitwise independent of the shape).  chosen: host
  * int[4] (bx, by, groups, form) or NULL; best_ms: host double, time per

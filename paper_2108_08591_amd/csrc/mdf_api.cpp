@@ -53,7 +53,7 @@ struct CaseLayout {
 
 // Context-wide regions of the workspace (batched launches).
 struct SharedLayout {
-    size_t table, meta, tile_start, active;
+    size_t table, meta, tile_start, tile_start2, active;
 };
 
 // Blocks of the largest grid any allowed launch shape produces
@@ -113,6 +113,8 @@ size_t layout(int lattice, int storage, const mdf_case *cases, int ncases, bool 
     off = align256(off + 4 * sizeof(int));
     sh.tile_start = off;
     off = align256(off + size_t(ncases + 1) * sizeof(int));
+    sh.tile_start2 = off;
+    off = align256(off + size_t(ncases + 1) * sizeof(int));
     sh.active = off;
     off = align256(off + size_t(ncases) * sizeof(int));
     if (shared) *shared = sh;
@@ -140,10 +142,10 @@ size_t layout(int lattice, int storage, const mdf_case *cases, int ncases, bool 
 }  // namespace
 
 struct GraphKey {
-    int len, check, emit, parity;
+    int len, check, emit, parity, fuse;
     bool operator==(const GraphKey &o) const
     {
-        return len == o.len && check == o.check && emit == o.emit && parity == o.parity;
+        return len == o.len && check == o.check && emit == o.emit && parity == o.parity && fuse == o.fuse;
     }
 };
 
@@ -163,12 +165,12 @@ struct mdf_ctx {
     bool batched = false;
     bool any_mask = false;
     mdf::BatchEntry *d_tab = nullptr;
-    int *d_meta = nullptr, *d_tile_start = nullptr, *d_active = nullptr;
+    int *d_meta = nullptr, *d_tile_start = nullptr, *d_tile_start2 = nullptr, *d_active = nullptr;
     double *d_results = nullptr;
     std::vector<mdf::BatchEntry> h_tab;
-    std::vector<int> h_tile_start, h_active, h_meta;
+    std::vector<int> h_tile_start, h_tile_start2, h_active, h_meta;
     std::vector<double> h_results;
-    int steps_since_upload = 0;
+    int launches_since_upload = 0;       // buffer parity of the uploaded table
     int uploaded_fields = -1;
     int num_cu = 0;
     std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
@@ -329,6 +331,12 @@ mdf_status batch_upload(mdf_ctx *ctx, const std::vector<int> &active, uint32_t f
         e.gx = (e.p.nx + tile_x - 1) / tile_x;
         e.gy = (e.p.ny + ctx->shape.by - 1) / ctx->shape.by;
         e.ntiles = e.gx * e.gy * e.p.nz;
+        if (ctx->lattice == MDF_D2Q5) {
+            const int rows = mdf::step2_rows(ctx->storage);
+            e.gx2 = (e.p.nx + 63) / 64;
+            e.gy2 = (e.p.ny + rows - 1) / rows;
+            e.ntiles2 = e.gx2 * e.gy2;
+        }
         e.cur = ctx->cur[k];
         if (e.ntiles > ctx->bufs[k].max_blocks)
             return fail(ctx, MDF_EINVAL, "launch grid exceeds the reduction workspace");
@@ -342,7 +350,15 @@ mdf_status batch_upload(mdf_ctx *ctx, const std::vector<int> &active, uint32_t f
     }
     if (total > 0x7fffffffLL) return fail(ctx, MDF_EINVAL, "batch has too many tiles");
     ctx->h_tile_start[active.size()] = int(total);
-    ctx->h_meta = {int(active.size()), int(total), 0, 0};
+    ctx->h_tile_start2.assign(active.size() + 1, 0);
+    long long total2 = 0;
+    for (size_t i = 0; i < active.size(); ++i) {
+        ctx->h_tile_start2[i] = int(total2);
+        total2 += ctx->h_tab[active[i]].ntiles2;
+    }
+    if (total2 > 0x7fffffffLL) return fail(ctx, MDF_EINVAL, "batch has too many tiles");
+    ctx->h_tile_start2[active.size()] = int(total2);
+    ctx->h_meta = {int(active.size()), int(total), int(total2), 0};
     hipError_t e = hipMemcpyAsync(ctx->d_tab, ctx->h_tab.data(), sizeof(mdf::BatchEntry) * n, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(ctx->d_meta, ctx->h_meta.data(), sizeof(int) * 4, hipMemcpyHostToDevice, st);
@@ -350,11 +366,14 @@ mdf_status batch_upload(mdf_ctx *ctx, const std::vector<int> &active, uint32_t f
         e = hipMemcpyAsync(ctx->d_tile_start, ctx->h_tile_start.data(), sizeof(int) * (active.size() + 1),
                            hipMemcpyHostToDevice, st);
         if (e == hipSuccess)
+            e = hipMemcpyAsync(ctx->d_tile_start2, ctx->h_tile_start2.data(), sizeof(int) * (active.size() + 1),
+                               hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
             e = hipMemcpyAsync(ctx->d_active, active.data(), sizeof(int) * active.size(), hipMemcpyHostToDevice, st);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return device_error(ctx, e, "batch table upload");
-    ctx->steps_since_upload = 0;
+    ctx->launches_since_upload = 0;
     ctx->uploaded_fields = int(fields);
     return MDF_OK;
 }
@@ -365,6 +384,7 @@ mdf::BatchLaunch batch_args(mdf_ctx *ctx, uint32_t fields, int grid)
     bl.tab = ctx->d_tab;
     bl.meta = ctx->d_meta;
     bl.tile_start = ctx->d_tile_start;
+    bl.tile_start2 = ctx->d_tile_start2;
     bl.active = ctx->d_active;
     bl.parity = 0;
     bl.fields = fields;
@@ -375,17 +395,44 @@ mdf::BatchLaunch batch_args(mdf_ctx *ctx, uint32_t fields, int grid)
 }
 
 // nsteps batched steps of the uploaded active cases; the last one fused with
-// the check when `check`.  A chunk whose length, check flag, emission and
-// starting parity were seen before replays a captured graph.
+// the check when `check`.  With the two-step form (D2Q5), pairs of steps run
+// as one launch of k_step2_batch and the chunk ends with at least one
+// one-step launch (which carries the check and leaves f*(t - 1) in the other
+// buffer for the read kernels).  A chunk whose length, form, check flag,
+// emission and starting parity were seen before replays a captured graph.
 mdf_status batch_steps(mdf_ctx *ctx, int nsteps, bool check, uint32_t fields, hipStream_t st)
 {
     if (nsteps <= 0) return MDF_OK;
     int grid = 0;
     mdf_status r = batch_capacity_grid(ctx, &grid);
     if (r != MDF_OK) return r;
+    const bool fuse = ctx->shape.fuse && ctx->lattice == MDF_D2Q5 && nsteps >= 3;
+    const int pairs = fuse ? (nsteps - 1) / 2 : 0;
+    const int singles = nsteps - 2 * pairs;
+    int grid2 = 0;
+    if (pairs > 0) {
+        int per_cu = 0;
+        hipError_t e = mdf::batch2_blocks_per_cu(ctx->lattice, ctx->storage, ctx->any_mask, &per_cu);
+        if (e != hipSuccess) return device_error(ctx, e, "occupancy query");
+        grid2 = ctx->num_cu * (per_cu < 1 ? 1 : per_cu);
+    }
     mdf::BatchLaunch bl = batch_args(ctx, fields, grid);
-    const int p0 = ctx->steps_since_upload & 1;
-    const GraphKey key{nsteps, check ? 1 : 0, int(fields), p0};
+    mdf::BatchLaunch bl2 = batch_args(ctx, fields, grid2);
+    const int p0 = ctx->launches_since_upload & 1;
+    auto enqueue = [&]() -> hipError_t {
+        hipError_t e = hipSuccess;
+        int launch = 0;
+        for (int s = 0; s < pairs && e == hipSuccess; ++s, ++launch) {
+            bl2.parity = (p0 + launch) & 1;
+            e = mdf::launch_step2_batch(ctx->lattice, ctx->storage, bl2, st);
+        }
+        for (int s = 0; s < singles && e == hipSuccess; ++s, ++launch) {
+            bl.parity = (p0 + launch) & 1;
+            e = mdf::launch_step_batch(ctx->lattice, ctx->storage, bl, check && s == singles - 1, st);
+        }
+        return e;
+    };
+    const GraphKey key{nsteps, check ? 1 : 0, int(fields), p0, fuse ? 1 : 0};
     hipGraphExec_t exec = nullptr;
     for (auto &g : ctx->graphs)
         if (g.first == key) exec = g.second;
@@ -393,10 +440,7 @@ mdf_status batch_steps(mdf_ctx *ctx, int nsteps, bool check, uint32_t fields, hi
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
         if (e == hipSuccess) {
-            for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
-                bl.parity = (p0 + s) & 1;
-                e = mdf::launch_step_batch(ctx->lattice, ctx->storage, bl, check && s == nsteps - 1, st);
-            }
+            e = enqueue();
             hipError_t e2 = hipStreamEndCapture(st, &graph);
             if (e == hipSuccess) e = e2;
             if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -413,16 +457,14 @@ mdf_status batch_steps(mdf_ctx *ctx, int nsteps, bool check, uint32_t fields, hi
         hipError_t e = hipGraphLaunch(exec, st);
         if (e != hipSuccess) return device_error(ctx, e, "graph launch");
     } else {
-        for (int s = 0; s < nsteps; ++s) {
-            bl.parity = (p0 + s) & 1;
-            hipError_t e = mdf::launch_step_batch(ctx->lattice, ctx->storage, bl, check && s == nsteps - 1, st);
-            if (e != hipSuccess) return device_error(ctx, e, "batched step launch");
-        }
+        hipError_t e = enqueue();
+        if (e != hipSuccess) return device_error(ctx, e, "batched step launch");
     }
-    ctx->steps_since_upload += nsteps;
+    const int launches = pairs + singles;
+    ctx->launches_since_upload += launches;
     for (int k : ctx->h_active) {
         ctx->time[k] += nsteps;
-        if (nsteps & 1) ctx->cur[k] ^= 1;
+        if (launches & 1) ctx->cur[k] ^= 1;
     }
     return MDF_OK;
 }
@@ -494,6 +536,7 @@ mdf_status mdf_init(mdf_ctx **out, mdf_lattice lattice, mdf_storage storage, con
 
     mdf_ctx *ctx = new mdf_ctx;
     ctx->lattice = lattice;
+    ctx->shape.fuse = lattice == MDF_D2Q5 ? 1 : 0;     // two steps per launch by default in 2D
     ctx->storage = storage;
     ctx->d = lat_d(lattice);
     ctx->q = lat_q(lattice);
@@ -511,6 +554,7 @@ mdf_status mdf_init(mdf_ctx **out, mdf_lattice lattice, mdf_storage storage, con
     ctx->d_tab = reinterpret_cast<mdf::BatchEntry *>(ws + shl.table);
     ctx->d_meta = reinterpret_cast<int *>(ws + shl.meta);
     ctx->d_tile_start = reinterpret_cast<int *>(ws + shl.tile_start);
+    ctx->d_tile_start2 = reinterpret_cast<int *>(ws + shl.tile_start2);
     ctx->d_active = reinterpret_cast<int *>(ws + shl.active);
     ctx->d_results = reinterpret_cast<double *>(ws + lay[0].result);
     ctx->h_results.assign(size_t(ncases) * mdf::kNRed, 0.0);
@@ -800,8 +844,8 @@ mdf_status mdf_autotune(mdf_ctx *ctx, int32_t trial_steps, int32_t *chosen, doub
     int bi = 0;
     mdf_status r = MDF_OK;
     for (int c = 0; c < int(sizeof cand / sizeof cand[0]) && r == MDF_OK; ++c) {
-        // two steps per launch: 2D single-case contexts only
-        if (cand[c][3] == 2 && (ctx->lattice != MDF_D2Q5 || ctx->batched)) continue;
+        // two steps per launch: 2D contexts only
+        if (cand[c][3] == 2 && ctx->lattice != MDF_D2Q5) continue;
         r = mdf_set_launch(ctx, cand[c][0], cand[c][1], cand[c][2], cand[c][3]);
         if (r != MDF_OK) break;
         r = step_impl(ctx, 1, 0, nullptr, stream);           // warm-up (and graph capture)

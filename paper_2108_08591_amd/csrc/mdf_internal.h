@@ -65,6 +65,7 @@ struct BatchEntry {
     double *result;
     void *out;              // emitted fields of the current call, or null
     int gx, gy, ntiles;     // tile grid of the case for the batch launch shape
+    int gx2, gy2, ntiles2;  // tile grid of two-step launches (D2Q5), else 0
     int cur;                // buffer holding f*(t) when the table was uploaded
 };
 
@@ -73,8 +74,9 @@ struct BatchLaunch {
     const BatchEntry *tab;  // device table (all cases)
     const int *meta;        // device: {active cases, total tiles}
     const int *tile_start;  // device: prefix offsets of the active cases' tiles
+    const int *tile_start2; // device: the same for two-step tiles
     const int *active;      // device: case ids of the active cases
-    int parity;             // steps since the table upload, mod 2
+    int parity;             // launches since the table upload, mod 2
     uint32_t fields;        // emitted fields (0: none)
     int grid;               // blocks of the persistent launch
     bool mask;              // any case has obstacles
@@ -100,6 +102,11 @@ hipError_t launch_read(int lattice, int storage, const KCase &p, const CaseBufs 
 hipError_t launch_finalize(const CaseBufs &b, int nblocks, hipStream_t stream);
 hipError_t launch_step_batch(int lattice, int storage, const BatchLaunch &bl, bool check, hipStream_t stream);
 hipError_t batch_blocks_per_cu(int lattice, int storage, LaunchShape shape, bool mask, int *blocks_per_cu);
+// Batched two steps per launch (D2Q5) over the two-step tile list.
+hipError_t launch_step2_batch(int lattice, int storage, const BatchLaunch &bl, hipStream_t stream);
+hipError_t batch2_blocks_per_cu(int lattice, int storage, bool mask, int *blocks_per_cu);
+// Two-step tile grid of a case (D2Q5): tiles of 64 x rows nodes.
+int step2_rows(int storage);
 hipError_t launch_finalize_batch(const BatchEntry *tab, const int *meta, const int *active, int nactive,
                                  hipStream_t stream);
 

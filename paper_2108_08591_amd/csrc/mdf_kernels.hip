@@ -815,6 +815,7 @@ template <> struct Fuse2Rows<MDF_F32> { static constexpr int TY = 8; };
 
 constexpr int kF2X = 64;                 // output columns of a tile
 constexpr int kF2W = kF2X + 2;           // columns of the tile plus its one-node halo
+constexpr int kF2Threads = 256;          // threads of a k_step2 block
 
 // Two time steps in one pass over HBM (temporal blocking, 2D only).  A block
 // owns a tile of 64 x TY nodes.  Step 1 runs on the tile and a one-node
@@ -830,56 +831,82 @@ constexpr int kF2W = kF2X + 2;           // columns of the tile plus its one-nod
 // re-reads ((64 + 2)(TY + 2) / (64 TY) of a read per two steps).
 // The caller keeps f*(t+1) out of HBM, so the buffer the read kernels pull
 // from is stale after this kernel until the next one-step launch.
+template <class L, int ST>
+struct Step2Lds {
+    static constexpr int NE = kF2W * (Fuse2Rows<ST>::TY + 2);
+    typename Store<ST>::T v[L::NS * L::Q * NE];
+};
+
 template <class L, int ST, bool EMIT, bool MASK>
-__global__ void __launch_bounds__(256)
-k_step2(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, typename Store<ST>::T *__restrict__ dst,
-        const uint8_t *__restrict__ links, uint32_t fields, typename Store<ST>::C *__restrict__ out)
+__device__ __forceinline__ void step2_tile(const KCase &p, int gx, int tile, const typename Store<ST>::T *__restrict__ src,
+                                           typename Store<ST>::T *__restrict__ dst, const uint8_t *__restrict__ links,
+                                           uint32_t fields, typename Store<ST>::C *__restrict__ out,
+                                           typename Store<ST>::T *__restrict__ lds)
 {
     static_assert(L::D == 2, "two-step tiles are two-dimensional");
     using S = Store<ST>;
     using T = typename S::T;
     using C = typename S::C;
     constexpr int TY = Fuse2Rows<ST>::TY;
-    constexpr int W = kF2W, NE = kF2W * (TY + 2), NP = L::NS * L::Q;
-    __shared__ T lds[NP * NE];
-    const int tile = block_tile(tl);
-    const int x0 = (tile % tl.gx) * kF2X, y0 = (tile / tl.gx) * TY;
+    constexpr int W = kF2W, NE = kF2W * (TY + 2);
+    const int x0 = (tile % gx) * kF2X, y0 = (tile / gx) * TY;
     const int tid = threadIdx.x;
-    const int nthr = blockDim.x;
     const long long nodes = (long long)p.nx * p.ny;
 
-    // step 1: t -> t+1 on the tile and its halo, into LDS
-    for (int e = tid; e < NE; e += nthr) {
-        const int ex = e % W, ey = e / W;
-        int x = x0 - 1 + ex, y = y0 - 1 + ey;
-        const bool interior = ex >= 1 && ex <= kF2X && ey >= 1 && ey <= TY && x < p.nx && y < p.ny;
-        if (x < 0 || x >= p.nx) {
-            if (p.bc[x < 0 ? 0 : 1] == MDF_WALL) continue;
-            x = ((x % p.nx) + p.nx) % p.nx;
-        }
-        if (y < 0 || y >= p.ny) {
-            if (p.bc[y < 0 ? 2 : 3] == MDF_WALL) continue;
-            y = ((y % p.ny) + p.ny) % p.ny;
-        }
-        Node<L, C> n;
-        if (!gather<L, ST, MASK, true>(p, src, links, x, y, 0, n)) continue;      // solid node
-        Moments<L, C> m;
-        moments<L, C>(p, n, m);
-        if (EMIT && interior) write_fields<L, C>(p, n, m, fields, out, (long long)y * p.nx + x, nodes);
+    // step 1: t -> t+1 on the tile and its halo, into LDS.  A thread owns
+    // the halo-tile nodes tid, tid + 256, ...; their pulls are issued G at a
+    // time before any of them is used, so that G nodes' loads are in flight
+    // together (occupancy is bounded by LDS, not by registers).
+    constexpr int K1 = (NE + kF2Threads - 1) / kF2Threads;
+    constexpr int G = K1 < 3 ? K1 : 3;
 #pragma unroll
-        for (int a = 0; a < L::NS; ++a) {
-            C ne[L::Q], fo[L::Q];
-            nonequilibrium<L, C>(n, m, a, ne);
-            collide_set<L, C>(p, n, a, ne, fo);
+    for (int k0 = 0; k0 < K1; k0 += G) {
+        Node<L, C> n[G];
+        bool fluid[G], interior[G];
+        long long node[G];
 #pragma unroll
-            for (int i = 0; i < L::Q; ++i)
-                lds[(a * L::Q + i) * NE + e] = S::encode(fo[i], rest_value<L, C>(p, a, i), p.inv_scale);
+        for (int g = 0; g < G; ++g) {
+            const int e = tid + (k0 + g) * kF2Threads;
+            fluid[g] = false;
+            interior[g] = false;
+            node[g] = 0;
+            if (k0 + g >= K1 || e >= NE) continue;
+            const int ex = e % W, ey = e / W;
+            int x = x0 - 1 + ex, y = y0 - 1 + ey;
+            interior[g] = ex >= 1 && ex <= kF2X && ey >= 1 && ey <= TY && x < p.nx && y < p.ny;
+            if (x < 0 || x >= p.nx) {
+                if (p.bc[x < 0 ? 0 : 1] == MDF_WALL) continue;
+                x = ((x % p.nx) + p.nx) % p.nx;
+            }
+            if (y < 0 || y >= p.ny) {
+                if (p.bc[y < 0 ? 2 : 3] == MDF_WALL) continue;
+                y = ((y % p.ny) + p.ny) % p.ny;
+            }
+            node[g] = (long long)y * p.nx + x;
+            fluid[g] = gather<L, ST, MASK, true>(p, src, links, x, y, 0, n[g]);   // false: solid node
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (!fluid[g]) continue;
+            const int e = tid + (k0 + g) * kF2Threads;
+            Moments<L, C> m;
+            moments<L, C>(p, n[g], m);
+            if (EMIT && interior[g]) write_fields<L, C>(p, n[g], m, fields, out, node[g], nodes);
+#pragma unroll
+            for (int a = 0; a < L::NS; ++a) {
+                C ne[L::Q], fo[L::Q];
+                nonequilibrium<L, C>(n[g], m, a, ne);
+                collide_set<L, C>(p, n[g], a, ne, fo);
+#pragma unroll
+                for (int i = 0; i < L::Q; ++i)
+                    lds[(a * L::Q + i) * NE + e] = S::encode(fo[i], rest_value<L, C>(p, a, i), p.inv_scale);
+            }
         }
     }
     __syncthreads();
 
     // step 2: t+1 -> t+2 on the tile, from LDS to HBM
-    for (int e = tid; e < kF2X * TY; e += nthr) {
+    for (int e = tid; e < kF2X * TY; e += kF2Threads) {
         const int ox = e % kF2X, oy = e / kF2X;
         const int x = x0 + ox, y = y0 + oy;
         if (x >= p.nx || y >= p.ny) continue;
@@ -948,6 +975,48 @@ k_step2(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, typen
                 S::store(dst + (long long)(a * L::Q + i) * p.dstride, own, fo[i], rest_value<L, C>(p, a, i),
                          p.inv_scale);
         }
+    }
+}
+
+template <class L, int ST, bool EMIT, bool MASK>
+__global__ void __launch_bounds__(kF2Threads)
+k_step2(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, typename Store<ST>::T *__restrict__ dst,
+        const uint8_t *__restrict__ links, uint32_t fields, typename Store<ST>::C *__restrict__ out)
+{
+    __shared__ Step2Lds<L, ST> lds;
+    step2_tile<L, ST, EMIT, MASK>(p, tl.gx, block_tile(tl), src, dst, links, fields, out, lds.v);
+}
+
+// Batched two steps per launch: the persistent walk of k_step_batch over
+// the flat list of the active cases' two-step tiles (prefix offsets
+// tile_start2, total meta[2]).
+template <class L, int ST, bool EMIT, bool MASK>
+__global__ void __launch_bounds__(kF2Threads)
+k_step2_batch(const BatchEntry *__restrict__ tab, const int *__restrict__ meta,
+              const int *__restrict__ tile_start2, const int *__restrict__ active, int parity, uint32_t fields,
+              int groups)
+{
+    __shared__ Step2Lds<L, ST> lds;
+    const int nact = meta[0], total = meta[2];
+    const int G = gridDim.x;
+    const int ng = (groups > 1 && G % groups == 0) ? groups : 1;
+    const int g = blockIdx.x % ng, per = G / ng, slot = blockIdx.x / ng;
+    const int band_lo = (int)((long long)total * g / ng), band_hi = (int)((long long)total * (g + 1) / ng);
+    for (int t = band_lo + slot; t < band_hi; t += per) {
+        int lo = 0, hi = nact - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tile_start2[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchEntry &e = tab[active[lo]];
+        const int sel = (e.cur + parity) & 1;
+        using T = typename Store<ST>::T;
+        using C = typename Store<ST>::C;
+        step2_tile<L, ST, EMIT, MASK>(e.p, e.gx2, t - tile_start2[lo], static_cast<const T *>(e.pop[sel]),
+                                      static_cast<T *>(e.pop[sel ^ 1]), e.links, fields, static_cast<C *>(e.out),
+                                      lds.v);
+        __syncthreads();   // the next tile's step 1 overwrites the LDS this tile's step 2 reads
     }
 }
 
@@ -1270,7 +1339,7 @@ hipError_t step2_dispatch(const KCase &p, const CaseBufs &b, int src, uint32_t f
         const bool emit_on = (fields != 0) && out != nullptr;
         const bool mask = b.links != nullptr;
 #define MDF_STEP2_LAUNCH(E, M) \
-    hipLaunchKernelGGL((k_step2<L, ST, E, M>), dim3(tl.nb), dim3(256), 0, stream, p, tl, in, o, b.links, fields, emit)
+    hipLaunchKernelGGL((k_step2<L, ST, E, M>), dim3(tl.nb), dim3(kF2Threads), 0, stream, p, tl, in, o, b.links, fields, emit)
         if (mask) { if (emit_on) MDF_STEP2_LAUNCH(true, true); else MDF_STEP2_LAUNCH(false, true); }
         else { if (emit_on) MDF_STEP2_LAUNCH(true, false); else MDF_STEP2_LAUNCH(false, false); }
 #undef MDF_STEP2_LAUNCH
@@ -1347,6 +1416,37 @@ hipError_t batch_dispatch(const BatchLaunch &bl, bool check, bool emit, hipStrea
 #undef MDF_BATCH_LAUNCH
 #undef MDF_BATCH_LAUNCH1
     return hipGetLastError();
+}
+
+template <class L, int ST>
+hipError_t batch2_dispatch(const BatchLaunch &bl, bool emit, hipStream_t stream)
+{
+    if constexpr (L::D != 2) {
+        return hipErrorInvalidValue;
+    } else {
+        const dim3 grid(bl.grid, 1, 1), block(kF2Threads, 1, 1);
+#define MDF_BATCH2_LAUNCH(E, M)                                                                              \
+    hipLaunchKernelGGL((k_step2_batch<L, ST, E, M>), grid, block, 0, stream, bl.tab, bl.meta, bl.tile_start2, \
+                       bl.active, bl.parity, bl.fields, bl.shape.groups)
+        if (bl.mask) { if (emit) MDF_BATCH2_LAUNCH(true, true); else MDF_BATCH2_LAUNCH(false, true); }
+        else { if (emit) MDF_BATCH2_LAUNCH(true, false); else MDF_BATCH2_LAUNCH(false, false); }
+#undef MDF_BATCH2_LAUNCH
+        return hipGetLastError();
+    }
+}
+
+template <class L, int ST>
+hipError_t batch2_capacity(bool mask, int *blocks_per_cu)
+{
+    if constexpr (L::D != 2) {
+        return hipErrorInvalidValue;
+    } else {
+        if (mask)
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_step2_batch<L, ST, true, true>,
+                                                                kF2Threads, 0);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_step2_batch<L, ST, true, false>,
+                                                            kF2Threads, 0);
+    }
 }
 
 template <class L, int ST>
@@ -1460,6 +1560,29 @@ hipError_t launch_finalize(const CaseBufs &b, int nblocks, hipStream_t stream)
 }  // namespace mdf
 
 namespace mdf {
+
+hipError_t launch_step2_batch(int lattice, int storage, const BatchLaunch &bl, hipStream_t stream)
+{
+    if (lattice != MDF_D2Q5) return hipErrorInvalidValue;
+    const bool emit = bl.fields != 0;
+    MDF_DISPATCH(lattice, storage, batch2_dispatch, bl, emit, stream);
+}
+
+hipError_t batch2_blocks_per_cu(int lattice, int storage, bool mask, int *blocks_per_cu)
+{
+    if (lattice != MDF_D2Q5) return hipErrorInvalidValue;
+    MDF_DISPATCH(lattice, storage, batch2_capacity, mask, blocks_per_cu);
+}
+
+int step2_rows(int storage)
+{
+    switch (storage) {
+    case MDF_F64: return Fuse2Rows<MDF_F64>::TY;
+    case MDF_F32: return Fuse2Rows<MDF_F32>::TY;
+    case MDF_F16DEV: return Fuse2Rows<MDF_F16DEV>::TY;
+    default: return Fuse2Rows<MDF_BF16DEV>::TY;
+    }
+}
 
 hipError_t launch_step_batch(int lattice, int storage, const BatchLaunch &bl, bool check, hipStream_t stream)
 {

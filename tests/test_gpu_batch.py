@@ -44,13 +44,16 @@ def _masks(specs):
     return masks
 
 
-@pytest.mark.parametrize("with_mask", [False, True])
-def test_batch_bitwise_equals_single_cases(with_mask):
+@pytest.mark.parametrize("with_mask,form", [(False, 0), (True, 0), (False, 2), (True, 2)])
+def test_batch_bitwise_equals_single_cases(with_mask, form):
+    """Batched launches (one step, or two steps per launch) against
+    one-step single-case contexts: populations and fields bit for bit."""
     specs = _mixed_cases()
     masks = _masks(specs) if with_mask else None
     stream = torch.cuda.Stream()
-    _say(f"[batch] bitwise vs single, mask={with_mask}")
+    _say(f"[batch] bitwise vs single, mask={with_mask}, form={form}")
     b = mdf.Solver(specs, storage="f32", solid=masks, device=DEV, stream=stream)
+    b.set_launch(64, 4, 8, form)
     fields = mdf.FIELD_VORT | mdf.FIELD_STRAIN
     out_b = b.new_field_buffers(fields)
     b.step(7)                      # odd count: buffer parity flips per case
@@ -70,14 +73,16 @@ def test_batch_bitwise_equals_single_cases(with_mask):
         assert b.time(k) == 22
 
 
-def test_batch_run_steady_matches_single_cases():
+@pytest.mark.parametrize("form", [0, 2])
+def test_batch_run_steady_matches_single_cases(form):
     """Per-case convergence inside one batch: same stopping step, same FP64
     residual and same state as solving each case alone."""
     specs = [C.cavity_case(N=32, Re=20.0, U=0.08), C.poiseuille_case(40, 24, umax=0.03, s1=1.0),
              C.cavity_case(N=48, Re=60.0, U=0.1)]
     stream = torch.cuda.Stream()
-    _say("[batch] run_steady vs single")
+    _say(f"[batch] run_steady vs single, form={form}")
     b = mdf.Solver(specs, storage="f64", device=DEV, stream=stream)
+    b.set_launch(64, 4, 8, form)
     st_b, steps_b, res_b = b.run_steady(1e-7, 100, 60000)
     assert (st_b == 0).all(), (st_b, steps_b, res_b)
     assert len(set(steps_b.tolist())) > 1          # cases stopped at different times
