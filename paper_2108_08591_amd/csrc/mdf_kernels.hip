@@ -809,13 +809,12 @@ k_step(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, typena
 // the intermediate state (NS * Q planes of (64 + 2) x (rows + 2) stored
 // values) stays within 64 KB: 47.5 KB for FP64, 39.6 KB for FP32, 35.6 KB
 // for the 16-bit formats.
-template <int ST> struct Fuse2Rows { static constexpr int TY = 16; };
-template <> struct Fuse2Rows<MDF_F64> { static constexpr int TY = 4; };
-template <> struct Fuse2Rows<MDF_F32> { static constexpr int TY = 8; };
+template <int ST> struct Fuse2Rows { static constexpr int TY = 16, NT = 256; };
+template <> struct Fuse2Rows<MDF_F64> { static constexpr int TY = 4, NT = 256; };
+template <> struct Fuse2Rows<MDF_F32> { static constexpr int TY = 8, NT = 256; };
 
 constexpr int kF2X = 64;                 // output columns of a tile
 constexpr int kF2W = kF2X + 2;           // columns of the tile plus its one-node halo
-constexpr int kF2Threads = 256;          // threads of a k_step2 block
 
 // Two time steps in one pass over HBM (temporal blocking, 2D only).  A block
 // owns a tile of 64 x TY nodes.  Step 1 runs on the tile and a one-node
@@ -847,7 +846,7 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int tile, con
     using S = Store<ST>;
     using T = typename S::T;
     using C = typename S::C;
-    constexpr int TY = Fuse2Rows<ST>::TY;
+    constexpr int TY = Fuse2Rows<ST>::TY, NT = Fuse2Rows<ST>::NT;
     constexpr int W = kF2W, NE = kF2W * (TY + 2);
     const int x0 = (tile % gx) * kF2X, y0 = (tile / gx) * TY;
     const int tid = threadIdx.x;
@@ -857,7 +856,7 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int tile, con
     // the halo-tile nodes tid, tid + 256, ...; their pulls are issued G at a
     // time before any of them is used, so that G nodes' loads are in flight
     // together (occupancy is bounded by LDS, not by registers).
-    constexpr int K1 = (NE + kF2Threads - 1) / kF2Threads;
+    constexpr int K1 = (NE + NT - 1) / NT;
     constexpr int G = K1 < 3 ? K1 : 3;
 #pragma unroll
     for (int k0 = 0; k0 < K1; k0 += G) {
@@ -866,7 +865,7 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int tile, con
         long long node[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            const int e = tid + (k0 + g) * kF2Threads;
+            const int e = tid + (k0 + g) * NT;
             fluid[g] = false;
             interior[g] = false;
             node[g] = 0;
@@ -888,7 +887,7 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int tile, con
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             if (!fluid[g]) continue;
-            const int e = tid + (k0 + g) * kF2Threads;
+            const int e = tid + (k0 + g) * NT;
             Moments<L, C> m;
             moments<L, C>(p, n[g], m);
             if (EMIT && interior[g]) write_fields<L, C>(p, n[g], m, fields, out, node[g], nodes);
@@ -906,7 +905,7 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int tile, con
     __syncthreads();
 
     // step 2: t+1 -> t+2 on the tile, from LDS to HBM
-    for (int e = tid; e < kF2X * TY; e += kF2Threads) {
+    for (int e = tid; e < kF2X * TY; e += NT) {
         const int ox = e % kF2X, oy = e / kF2X;
         const int x = x0 + ox, y = y0 + oy;
         if (x >= p.nx || y >= p.ny) continue;
@@ -979,7 +978,7 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int tile, con
 }
 
 template <class L, int ST, bool EMIT, bool MASK>
-__global__ void __launch_bounds__(kF2Threads)
+__global__ void __launch_bounds__(Fuse2Rows<ST>::NT)
 k_step2(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, typename Store<ST>::T *__restrict__ dst,
         const uint8_t *__restrict__ links, uint32_t fields, typename Store<ST>::C *__restrict__ out)
 {
@@ -991,7 +990,7 @@ k_step2(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, typen
 // the flat list of the active cases' two-step tiles (prefix offsets
 // tile_start2, total meta[2]).
 template <class L, int ST, bool EMIT, bool MASK>
-__global__ void __launch_bounds__(kF2Threads)
+__global__ void __launch_bounds__(Fuse2Rows<ST>::NT)
 k_step2_batch(const BatchEntry *__restrict__ tab, const int *__restrict__ meta,
               const int *__restrict__ tile_start2, const int *__restrict__ active, int parity, uint32_t fields,
               int groups)
@@ -1339,7 +1338,8 @@ hipError_t step2_dispatch(const KCase &p, const CaseBufs &b, int src, uint32_t f
         const bool emit_on = (fields != 0) && out != nullptr;
         const bool mask = b.links != nullptr;
 #define MDF_STEP2_LAUNCH(E, M) \
-    hipLaunchKernelGGL((k_step2<L, ST, E, M>), dim3(tl.nb), dim3(kF2Threads), 0, stream, p, tl, in, o, b.links, fields, emit)
+    hipLaunchKernelGGL((k_step2<L, ST, E, M>), dim3(tl.nb), dim3(Fuse2Rows<ST>::NT), 0, stream, p, tl, in, o, b.links, \
+                       fields, emit)
         if (mask) { if (emit_on) MDF_STEP2_LAUNCH(true, true); else MDF_STEP2_LAUNCH(false, true); }
         else { if (emit_on) MDF_STEP2_LAUNCH(true, false); else MDF_STEP2_LAUNCH(false, false); }
 #undef MDF_STEP2_LAUNCH
@@ -1424,7 +1424,7 @@ hipError_t batch2_dispatch(const BatchLaunch &bl, bool emit, hipStream_t stream)
     if constexpr (L::D != 2) {
         return hipErrorInvalidValue;
     } else {
-        const dim3 grid(bl.grid, 1, 1), block(kF2Threads, 1, 1);
+        const dim3 grid(bl.grid, 1, 1), block(Fuse2Rows<ST>::NT, 1, 1);
 #define MDF_BATCH2_LAUNCH(E, M)                                                                              \
     hipLaunchKernelGGL((k_step2_batch<L, ST, E, M>), grid, block, 0, stream, bl.tab, bl.meta, bl.tile_start2, \
                        bl.active, bl.parity, bl.fields, bl.shape.groups)
@@ -1443,9 +1443,9 @@ hipError_t batch2_capacity(bool mask, int *blocks_per_cu)
     } else {
         if (mask)
             return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_step2_batch<L, ST, true, true>,
-                                                                kF2Threads, 0);
+                                                                Fuse2Rows<ST>::NT, 0);
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_step2_batch<L, ST, true, false>,
-                                                            kF2Threads, 0);
+                                                            Fuse2Rows<ST>::NT, 0);
     }
 }
 
