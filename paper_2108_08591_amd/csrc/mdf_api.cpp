@@ -222,6 +222,20 @@ KCase make_kcase(int lattice, int storage, const mdf_case &c)
     const double scale = (storage == MDF_F16DEV || storage == MDF_BF16DEV) && c.u_ref > 0.0 ? c.u_ref : 1.0;
     p.scale = float(scale);
     p.inv_scale = float(1.0 / scale);
+    p.s1f = float(p.s1);
+    p.s2f = float(p.s2);
+    p.rho0f = float(p.rho0);
+    p.Rf = float(p.R);
+    for (int a = 0; a < 4; ++a) p.fbarf[a] = float(p.fbar[a]);
+    for (int f = 0; f < 6; ++f)
+        for (int b = 0; b < 3; ++b) p.walluf[f][b] = float(p.wallu[f][b]);
+    // rest weights of the lattice (eq. d2q5 / d3q7) times rho0
+    const double w0 = lattice == MDF_D2Q5 ? 1.0 / 3.0 : 1.0 / 4.0;
+    const double w1 = lattice == MDF_D2Q5 ? 1.0 / 6.0 : 1.0 / 8.0;
+    p.restd[0] = w0 * p.rho0;
+    p.restd[1] = w1 * p.rho0;
+    p.restf[0] = float(p.restd[0]);
+    p.restf[1] = float(p.restd[1]);
     return p;
 }
 

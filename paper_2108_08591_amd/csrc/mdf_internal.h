@@ -27,6 +27,14 @@ struct KCase {
     double wallu[6][3];
     int bc[6];
     float scale, inv_scale; // 16-bit deviation storage: f = rest + scale * stored
+    // the same parameters rounded to FP32 once on the host (the FP32 and
+    // 16-bit kernels compute in FP32), and the rest populations w_i rho0 of
+    // the set a = 0 (index 0: i = 0, index 1: i > 0)
+    float s1f, s2f, rho0f, Rf;
+    float fbarf[4];
+    float walluf[6][3];
+    double restd[2];
+    float restf[2];
 };
 
 // Device pointers of one case inside the workspace.

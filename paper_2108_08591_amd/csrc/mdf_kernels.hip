@@ -195,6 +195,12 @@ __device__ __forceinline__ void vstore(T *p, const VecT<T, VX> &v)
     *reinterpret_cast<R *>(p) = r;
 }
 
+// A case parameter in the compute type: the FP32 copy rounded on the host
+// for the FP32 and 16-bit kernels, the FP64 value for the FP64 kernels.
+template <class C> __device__ __forceinline__ C kpar(double d, float f);
+template <> __device__ __forceinline__ float kpar<float>(double, float f) { return f; }
+template <> __device__ __forceinline__ double kpar<double>(double d, float) { return d; }
+
 // Value of the lane one below / one above in the wavefront (all lanes must
 // execute these; a lane at the wave's edge gets its own value back).
 template <class T>
@@ -235,7 +241,7 @@ template <class L, class C>
 __device__ __forceinline__ C rest_value(const KCase &p, int a, int i)
 {
     if (a != 0) return C(0);
-    return C((i == 0 ? L::w0 : L::w1) * p.rho0);
+    return kpar<C>(p.restd[i != 0], p.restf[i != 0]);
 }
 
 // ----------------------------------------------------------------- node state
@@ -295,18 +301,18 @@ __device__ __forceinline__ bool gather(const KCase &p, const typename Store<ST>:
             const long long k = ((long long)sz * p.ny + sy) * p.pitch + sx;
 #pragma unroll
             for (int a = 0; a < L::NS; ++a)
-                n.f[a][i] = S::load(src + (long long)(a * L::Q + i) * p.dstride, k,
-                                    rest_value<L, C>(p, a, i), p.scale);
+                n.f[a][i] = S::load(src + (long long)(a * L::Q + i) * p.dstride, k, rest_value<L, C>(p, a, i),
+                                    p.scale);
         } else {
             const int j = L::opp[i];
 #pragma unroll
             for (int a = 0; a < L::NS; ++a) {
-                C v = S::load(src + (long long)(a * L::Q + j) * p.dstride, own,
-                              rest_value<L, C>(p, a, j), p.scale);
+                C v = S::load(src + (long long)(a * L::Q + j) * p.dstride, own, rest_value<L, C>(p, a, j),
+                              p.scale);
                 if (a == 0) {
                     n.f[a][i] = v;
                 } else {
-                    C uw = (face < 6) ? C(p.wallu[face][a - 1]) : C(0);
+                    C uw = (face < 6) ? kpar<C>(p.wallu[face][a - 1], p.walluf[face][a - 1]) : C(0);
                     n.f[a][i] = -v + C(2) * w * uw;
                 }
             }
@@ -393,7 +399,7 @@ __device__ __forceinline__ void gather_vec(const KCase &p, const typename Store<
                     if (a == 0) {
                         n[v].f[a][i] = val;
                     } else {
-                        const C uw = (f < 6) ? C(p.wallu[f][a - 1]) : C(0);
+                        const C uw = (f < 6) ? kpar<C>(p.wallu[f][a - 1], p.walluf[f][a - 1]) : C(0);
                         n[v].f[a][i] = -val + C(2) * w * uw;
                     }
                 } else {
@@ -436,7 +442,7 @@ __device__ __forceinline__ void moments(const KCase &p, const Node<L, C> &n, Mom
         u2 += m.u[a - 1] * m.u[a - 1];
     }
     m.trJ = trJ;
-    m.P = (trJ + C(L::cs2) * C(p.R) / C(p.s1) - u2) * C(1.0 / L::D);
+    m.P = (trJ + C(L::cs2) * kpar<C>(p.R, p.Rf) / kpar<C>(p.s1, p.s1f) - u2) * C(1.0 / L::D);
 }
 
 // Equilibrium of one set (eq. 2-4), f^eq_i = w_i [ubar + c_i . flux / cs^2]
@@ -494,8 +500,8 @@ template <class L, class C>
 __device__ __forceinline__ void collide_set(const KCase &p, const Node<L, C> &n, int a,
                                             const C (&ne)[L::Q], C (&out)[L::Q])
 {
-    const C s1 = C(p.s1), s2 = C(p.s2);
-    const C fb = C(p.fbar[a]);
+    const C s1 = kpar<C>(p.s1, p.s1f), s2 = kpar<C>(p.s2, p.s2f);
+    const C fb = kpar<C>(p.fbar[a], p.fbarf[a]);
     const C wf = C(L::w1) * fb;
     C dsum = C(0);
 #pragma unroll
@@ -535,7 +541,7 @@ __device__ __forceinline__ void write_fields(const KCase &p, const Node<L, C> &n
             mne[a - 1][b] = s;
         }
     }
-    const C gscale = -C(p.s1) * C(L::inv_cs2);           // eq. 3-16
+    const C gscale = -kpar<C>(p.s1, p.s1f) * C(L::inv_cs2);           // eq. 3-16
     C G[D][D];
 #pragma unroll
     for (int a = 0; a < D; ++a)
@@ -567,7 +573,7 @@ __device__ __forceinline__ void write_fields(const KCase &p, const Node<L, C> &n
                 out[(ch++) * nodes + node] = C(0.5) * (G[a][b] + G[b][a]);   // eq. 3-17
     }
     if (fields & MDF_FIELD_STRESS) {
-        const C sc = -C(p.rho0) * (C(1) - C(0.5) * C(p.s1));                // eq. 3-17a
+        const C sc = -kpar<C>(p.rho0, p.rho0f) * (C(1) - C(0.5) * kpar<C>(p.s1, p.s1f));   // eq. 3-17a
 #pragma unroll
         for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -678,8 +684,8 @@ __device__ __forceinline__ void step_tile(const KCase &p, int gx, int gy, int ti
             collide_set<L, C>(p, n, a, ne, fo);
 #pragma unroll
             for (int i = 0; i < L::Q; ++i)
-                S::store(dst + (long long)(a * L::Q + i) * p.dstride, own, fo[i],
-                         rest_value<L, C>(p, a, i), p.inv_scale);
+                S::store(dst + (long long)(a * L::Q + i) * p.dstride, own, fo[i], rest_value<L, C>(p, a, i),
+                         p.inv_scale);
         }
     } else if (EMIT && inside) {
         // solid node: every emitted channel is zero
@@ -955,7 +961,7 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int tile, con
                     if (a == 0) {
                         n.f[a][i] = v;
                     } else {
-                        const C uw = (face < 6) ? C(p.wallu[face][a - 1]) : C(0);
+                        const C uw = (face < 6) ? kpar<C>(p.wallu[face][a - 1], p.walluf[face][a - 1]) : C(0);
                         n.f[a][i] = -v + C(2) * w * uw;
                     }
                 }
