@@ -516,6 +516,93 @@ def warmstart_study(out_path, n_train=1024, n_test=32, N=128, epochs=30, batch=1
         json.dump(rec, fh, indent=1)
 
 
+def coarse_warmstart_study(out_path, n_train=4096, n_test=32, N=128, epochs=36, batch=16, lr=1e-3):
+    """Warm start informed by a coarse solve (an extension of the learned
+    warm start): each case is first solved on a grid twice as coarse (FP32,
+    residual 1e-6), its steady fields are interpolated to the fine grid, and
+    the encoder-decoder, given them as extra inputs, predicts the correction
+    to them.  Compared on held-out cases (FP64, residual 1e-8): cold start,
+    the interpolated coarse solution alone (nested iteration, the method
+    without the network), and coarse solution + network.  Warm wall times
+    include the coarse solve and the inference."""
+    import numpy as np
+    import torch
+    from paper_2108_08591_amd import nn
+    from paper_2108_08591_amd import warmstart as WS
+    log = lambda m: print(m, flush=True)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    rec = {"N": N, "n_train": n_train, "n_test": n_test, "epochs": epochs, "batch": batch, "lr": lr,
+           "coarse_factor": 2, "coarse_solve": "FP32, residual 1e-6"}
+    tr = WS.warmstart_cases(n_train, N, seed=20210819)
+    te = WS.warmstart_cases(n_test, N, seed=20210820)
+    solver, st, steps, _, wall = WS.solve(tr, "f32", tol=1e-7, max_steps=300000, stream=stream, log=log)
+    trc = WS.coarse_cases(tr)
+    csolver, cst, _, _, cwall_tr = WS.solve(trc, "f32", tol=1e-6, max_steps=300000, stream=stream, log=log)
+    up_tr = WS.upsampled_init(tr, trc, csolver, cst)
+    del csolver
+    good = [k for k in range(n_train) if st[k] == 0 and cst[k] == 0]
+    rec.update({"datagen_wall_s": round(wall, 1), "coarse_datagen_wall_s": round(cwall_tr, 1),
+                "train_cases_used": len(good)})
+    log(json.dumps({k: rec[k] for k in ("datagen_wall_s", "coarse_datagen_wall_s", "train_cases_used")}))
+    data = WS.dataset([tr[k] for k in good], _Subset(solver, good), log=log, coarse=[up_tr[k] for k in good])
+    del solver, up_tr
+    torch.cuda.empty_cache()
+    nv = min(64, len(good) // 8)
+    val = {k: v[-nv:] for k, v in data.items()}
+    data = {k: v[:-nv] for k, v in data.items()}
+    model = nn.UNet(device="cuda:0", seed=0)
+    t0 = time.perf_counter()
+    hist, vhist = WS.train(model, data, epochs=epochs, batch=batch, lr=lr, val=val, log=log)
+    torch.cuda.synchronize()
+    rec.update({"train_wall_s": round(time.perf_counter() - t0, 1), "loss_history": [round(h, 6) for h in hist],
+                "val_loss_history": vhist})
+    del data, val
+    # held-out cases
+    cold, cst_te, csteps, _, cwall = WS.solve(te, "f64", tol=1e-8, max_steps=600000, stream=stream, log=log)
+    t0 = time.perf_counter()
+    tec = WS.coarse_cases(te)
+    cs_te, cst2, csteps2, _, _ = WS.solve(tec, "f32", tol=1e-6, max_steps=300000, stream=stream)
+    up_te = WS.upsampled_init(te, tec, cs_te, cst2)
+    torch.cuda.synchronize()
+    t_coarse = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    pred = WS.predict(model, te, with_grad=True, coarse=up_te)
+    torch.cuda.synchronize()
+    t_inf = time.perf_counter() - t0
+    rest = np.zeros((7, N, N))
+    # a case whose coarse solve failed starts from rest
+    init_nested = [u if u is not None else rest for u in up_te]
+    init_net = [pred[k] if up_te[k] is not None else rest for k in range(n_test)]
+    nst_s, nst, nsteps, _, nwall = WS.solve(te, "f64", tol=1e-8, max_steps=600000, init=init_nested, stream=stream)
+    net_s, wst, wsteps, _, wwall = WS.solve(te, "f64", tol=1e-8, max_steps=600000, init=init_net, stream=stream)
+    exact = [WS.solution_init(cold, k) for k in range(n_test)]
+    ok = [k for k in range(n_test) if cst_te[k] == 0 and wst[k] == 0 and nst[k] == 0]
+    coarse_equiv = float(csteps2.sum()) / 4.0          # coarse node-steps in fine node-steps
+    perr_net = [WS.prediction_error(init_net[k], exact[k], te[k]["mask"]) for k in ok]
+    perr_nest = [WS.prediction_error(init_nested[k], exact[k], te[k]["mask"]) for k in ok]
+    errs = [WS.field_error(cold, net_s, k) for k in ok]
+    cs_ok = float(csteps[ok].sum())
+    rec.update({
+        "cold_wall_s": round(cwall, 2), "coarse_wall_s": round(t_coarse, 2), "inference_s": round(t_inf, 3),
+        "nested_fine_wall_s": round(nwall, 2), "network_fine_wall_s": round(wwall, 2),
+        "speedup_wall_nested": round(cwall / (t_coarse + nwall), 3),
+        "speedup_wall_network": round(cwall / (t_coarse + t_inf + wwall), 3),
+        "speedup_fine_steps_nested": round(cs_ok / max(1.0, float(nsteps[ok].sum())), 3),
+        "speedup_fine_steps_network": round(cs_ok / max(1.0, float(wsteps[ok].sum())), 3),
+        "speedup_steps_incl_coarse_network": round(float(csteps.sum()) / (float(wsteps.sum()) + coarse_equiv), 3),
+        "prediction_rel_l2_median_nested": {c: float(np.median([e[c] for e in perr_nest])) for c in WS.CHANNELS},
+        "prediction_rel_l2_median_network": {c: float(np.median([e[c] for e in perr_net])) for c in WS.CHANNELS},
+        "coarse_failed": int(sum(1 for u in up_te if u is None)),
+        "warm_not_converged": int(sum(1 for k in range(n_test) if wst[k] != 0)),
+        "field_rel_l2_warm_vs_cold_max": max(errs) if errs else None,
+        "warm_within_1e-4_of_cold": int(sum(1 for e in errs if e <= 1e-4)), "compared_cases": len(ok),
+    })
+    log(json.dumps({k: v for k, v in rec.items() if k not in ("loss_history",)}))
+    with open(out_path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+
+
 def restart_study(out_path, n=16, N=128):
     """What a warm start gains as a function of the accuracy of the fields it
     starts from: held-out cavities are solved cold to residual 1e-8 (FP64),
@@ -612,6 +699,8 @@ def main():
     ap.add_argument("--steady-study", metavar="OUT_JSON", help="wall time to residual 1e-8")
     ap.add_argument("--warmstart-study", metavar="OUT_JSON", help="learned warm start vs cold start")
     ap.add_argument("--restart-study", metavar="OUT_JSON", help="warm-start gain vs accuracy of the initial fields")
+    ap.add_argument("--coarse-warmstart-study", metavar="OUT_JSON",
+                    help="warm start from a coarse solve, with and without the network's correction")
     ap.add_argument("--ws-train", type=int, default=1024)
     ap.add_argument("--ws-epochs", type=int, default=30)
     ap.add_argument("--ws-n", type=int, default=128)
@@ -633,6 +722,10 @@ def main():
         return
     if args.steady_study:
         steady_study(args.steady_study)
+        return
+    if args.coarse_warmstart_study:
+        coarse_warmstart_study(args.coarse_warmstart_study, n_train=args.ws_train, epochs=args.ws_epochs,
+                               lr=args.ws_lr, batch=args.ws_batch)
         return
     if args.restart_study:
         restart_study(args.restart_study)

@@ -23,6 +23,7 @@ import torch
 from . import mdf
 
 FEATURES = 6          # solid mask, Re feature, lid-speed feature, x, y, wall distance
+COARSE_FEATURES = 8   # optional: a coarse-grid solution in target scales (7) and its validity flag
 IN_CH = 32            # features padded to the 32-channel granularity of the kernels
 OUT_CH = 7            # P, u, v, du/dx, du/dy, dv/dx, dv/dy
 LEVELS = (32, 64, 128, 256)
@@ -391,7 +392,7 @@ class UNet:
 
 # ---------------------------------------------------------------- data
 
-def input_features(N, mask, Re, U):
+def input_features(N, mask, Re, U, coarse=None):
     """Per-node features: solid flag, (log10 Re - 2), U / 0.1 - 0.75, the
     node coordinates in [-1, 1] and the distance to the nearest solid node or
     cavity wall (in units of N; 0 inside solids); zero-padded to IN_CH
@@ -410,6 +411,11 @@ def input_features(N, mask, Re, U):
     fluid[1:-1, 1:-1] = mask == 0
     d = distance_transform_edt(fluid)[1:-1, 1:-1]
     f[..., 5] = np.where(mask == 0, (d - 0.5) / N, 0.0)
+    if coarse is not None:
+        # an interpolated coarse-grid steady solution in the scales of
+        # raw_targets ([N, N, OUT_CH]) and a flag saying it exists
+        f[..., FEATURES:FEATURES + OUT_CH] = coarse
+        f[..., FEATURES + OUT_CH] = 1.0
     return f
 
 
@@ -425,11 +431,28 @@ def raw_targets(fields: Dict[str, torch.Tensor], N, U, Re):
     return out.float()
 
 
-def fields_from_prediction(pred: np.ndarray, N, U, Re, mask, norm):
+def scaled_fields(fl: np.ndarray, N, U, Re, mask) -> np.ndarray:
+    """Channel-major [P, u, v, grad(4)] fields in lattice units -> the scales
+    of raw_targets, [N, N, OUT_CH] float32 (P with its fluid mean removed)."""
+    fluid = mask == 0
+    out = np.zeros((N, N, OUT_CH), np.float32)
+    P = fl[0] - (fl[0][fluid].mean() if fluid.any() else 0.0)
+    out[..., 0] = P * (Re / (U * U))
+    out[..., 1] = fl[1] / U
+    out[..., 2] = fl[2] / U
+    for k in range(4):
+        out[..., 3 + k] = fl[3 + k] * N / U
+    return out
+
+
+def fields_from_prediction(pred: np.ndarray, N, U, Re, mask, norm, base=None):
     """Inverse of raw_targets for one case: [N, N, OUT_CH] normalised
-    network output -> channel-major [P, u, v, grad(4)] init data (float64)
-    with solid nodes zeroed."""
+    network output (plus `base`, a field in target scales, when the network
+    predicts a correction to it) -> channel-major [P, u, v, grad(4)] init
+    data (float64) with solid nodes zeroed."""
     y = pred * norm["std"] + norm["mean"]
+    if base is not None:
+        y = y + base
     fl = np.zeros((7, N, N))
     fl[0] = y[..., 0] * (U * U / Re)
     fl[1] = y[..., 1] * U

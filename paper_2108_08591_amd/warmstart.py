@@ -76,17 +76,66 @@ def solve(cases: List[dict], storage="f32", tol=1e-8, K=100, max_steps=400000, i
     return solver, st, steps, res, time.perf_counter() - t0
 
 
-def dataset(cases: List[dict], solver, log: Optional[Callable[[str], None]] = None) -> Dict[str, torch.Tensor]:
+def coarse_cases(cases: List[dict], factor: int = 2) -> List[dict]:
+    """The same cavities on a grid `factor` times coarser: same Re and lid
+    speed (so the same flow in lattice velocity units), a node solid when
+    any of the fine nodes it covers is solid, one fluid ring at the walls."""
+    out = []
+    for c in cases:
+        N = c["N"]
+        n = N // factor
+        m = c["mask"].reshape(n, factor, n, factor).max(axis=(1, 3)).astype(np.uint8)
+        m[:1, :] = 0
+        m[-1:, :] = 0
+        m[:, :1] = 0
+        m[:, -1:] = 0
+        out.append({"spec": C.cavity_case(N=n, Re=c["Re"], U=c["U"]), "mask": m, "Re": c["Re"], "U": c["U"], "N": n})
+    return out
+
+
+def upsampled_init(cases: List[dict], coarse: List[dict], solver, status, factor: int = 2):
+    """Steady fields of the coarse solves, interpolated (bilinear, cell
+    centred) to the fine grids as channel-major [P, u, v, grad(4)] init data;
+    gradients rescaled to the fine node spacing, solid nodes zeroed, the
+    divergence of the gradient removed.  None for a coarse solve that did not
+    converge."""
+    from scipy.ndimage import zoom
+    out = []
+    for k, c in enumerate(cases):
+        if status[k] != 0:
+            out.append(None)
+            continue
+        a = solution_init(solver, k)
+        up = np.stack([zoom(a[ch], factor, order=1, grid_mode=True, mode="nearest") for ch in range(7)])
+        up[3:] /= factor
+        div = up[3] + up[6]
+        up[3] -= 0.5 * div
+        up[6] -= 0.5 * div
+        up[:, c["mask"].astype(bool)] = 0.0
+        out.append(up.astype(np.float32))
+    return out
+
+
+def dataset(cases: List[dict], solver, log: Optional[Callable[[str], None]] = None,
+            coarse: Optional[List[Optional[np.ndarray]]] = None) -> Dict[str, torch.Tensor]:
     """Inputs (bf16 [n, N, N, IN_CH]), raw targets (f32 [n, N*N, OUT_CH])
-    and fluid weights (f32 [n, N*N]) from solved cases."""
+    and fluid weights (f32 [n, N*N]) from solved cases.  With `coarse`
+    (upsampled coarse solutions, or None per case) the inputs carry them and
+    the targets are the corrections to them."""
     X, T, Wt = [], [], []
     for k, c in enumerate(cases):
         if log and k % 2048 == 0:
             log(json.dumps({"dataset_cases": k, "of": len(cases)}))
         N = c["N"]
-        X.append(torch.tensor(nn.input_features(N, c["mask"], c["Re"], c["U"])))
+        base = None
+        if coarse is not None and coarse[k] is not None:
+            base = nn.scaled_fields(coarse[k], N, c["U"], c["Re"], c["mask"])
+        X.append(torch.tensor(nn.input_features(N, c["mask"], c["Re"], c["U"], base)))
         f = solver.fields(FIELDS, k)
-        T.append(nn.raw_targets(f, N, c["U"], c["Re"]).reshape(N * N, nn.OUT_CH).cpu())
+        t = nn.raw_targets(f, N, c["U"], c["Re"]).cpu()
+        if base is not None:
+            t = t - torch.tensor(base)
+        T.append(t.reshape(N * N, nn.OUT_CH))
         Wt.append(torch.tensor((c["mask"] == 0).astype(np.float32).reshape(-1)))
     torch.cuda.synchronize()
     return {"X": torch.stack(X), "T": torch.stack(T), "W": torch.stack(Wt)}
@@ -160,19 +209,26 @@ def train(model: nn.UNet, data: Dict[str, torch.Tensor], epochs=30, batch=16, lr
     return (history, val_hist) if Xv is not None else history
 
 
-def predict(model: nn.UNet, cases: List[dict], with_grad=True, batch=16) -> List[np.ndarray]:
+def predict(model: nn.UNet, cases: List[dict], with_grad=True, batch=16,
+            coarse: Optional[List[Optional[np.ndarray]]] = None) -> List[np.ndarray]:
     """Initial fields per case from the network ([P, u, v] or
-    [P, u, v, grad(4)], channel-major float64)."""
+    [P, u, v, grad(4)], channel-major float64); with `coarse`, the network
+    corrects the upsampled coarse solutions it is given."""
     out = []
     dev = model.device
     for s in range(0, len(cases), batch):
         part = cases[s:s + batch]
         N = part[0]["N"]
-        X = torch.stack([torch.tensor(nn.input_features(N, c["mask"], c["Re"], c["U"])) for c in part])
+        bases = []
+        for k, c in enumerate(part):
+            cf = coarse[s + k] if coarse is not None else None
+            bases.append(None if cf is None else nn.scaled_fields(cf, N, c["U"], c["Re"], c["mask"]))
+        X = torch.stack([torch.tensor(nn.input_features(N, c["mask"], c["Re"], c["U"], bases[k]))
+                         for k, c in enumerate(part)])
         y = model.forward(nn.to_bf16(X.to(dev)))
         y = y.reshape(len(part), N, N, nn.OUT_CH).cpu().numpy()
         for k, c in enumerate(part):
-            fl = nn.fields_from_prediction(y[k], N, c["U"], c["Re"], c["mask"], model.norm)
+            fl = nn.fields_from_prediction(y[k], N, c["U"], c["Re"], c["mask"], model.norm, bases[k])
             out.append(fl if with_grad else fl[:3].copy())
     return out
 
