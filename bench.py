@@ -583,6 +583,12 @@ def coarse_warmstart_study(out_path, n_train=4096, n_test=32, N=128, epochs=36, 
     perr_nest = [WS.prediction_error(init_nested[k], exact[k], te[k]["mask"]) for k in ok]
     errs = [WS.field_error(cold, net_s, k) for k in ok]
     cs_ok = float(csteps[ok].sum())
+    rec["cases"] = [{"Re": round(te[k]["Re"], 1), "Re_coarse": round(tec[k]["Re"], 1), "U": round(te[k]["U"], 4),
+                     "cold_steps": int(csteps[k]), "coarse_steps": int(csteps2[k]), "coarse_status": int(cst2[k]),
+                     "nested_steps": int(nsteps[k]), "network_steps": int(wsteps[k]),
+                     "cold_status": int(cst_te[k]), "network_status": int(wst[k])} for k in range(n_test)]
+    rec["speedup_fine_steps_network_median_case"] = round(float(np.median(csteps[ok] / np.maximum(wsteps[ok], 1))), 3)
+    rec["speedup_fine_steps_nested_median_case"] = round(float(np.median(csteps[ok] / np.maximum(nsteps[ok], 1))), 3)
     rec.update({
         "cold_wall_s": round(cwall, 2), "coarse_wall_s": round(t_coarse, 2), "inference_s": round(t_inf, 3),
         "nested_fine_wall_s": round(nwall, 2), "network_fine_wall_s": round(wwall, 2),
@@ -598,7 +604,7 @@ def coarse_warmstart_study(out_path, n_train=4096, n_test=32, N=128, epochs=36, 
         "field_rel_l2_warm_vs_cold_max": max(errs) if errs else None,
         "warm_within_1e-4_of_cold": int(sum(1 for e in errs if e <= 1e-4)), "compared_cases": len(ok),
     })
-    log(json.dumps({k: v for k, v in rec.items() if k not in ("loss_history",)}))
+    log(json.dumps({k: v for k, v in rec.items() if k not in ("loss_history", "cases")}))
     with open(out_path, "w") as fh:
         json.dump(rec, fh, indent=1)
 

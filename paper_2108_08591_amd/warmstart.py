@@ -76,10 +76,15 @@ def solve(cases: List[dict], storage="f32", tol=1e-8, K=100, max_steps=400000, i
     return solver, st, steps, res, time.perf_counter() - t0
 
 
-def coarse_cases(cases: List[dict], factor: int = 2) -> List[dict]:
-    """The same cavities on a grid `factor` times coarser: same Re and lid
-    speed (so the same flow in lattice velocity units), a node solid when
-    any of the fine nodes it covers is solid, one fluid ring at the walls."""
+def coarse_cases(cases: List[dict], factor: int = 2, s1_max: float = 1.85) -> List[dict]:
+    """The same cavities on a grid `factor` times coarser: same lid speed
+    (the same flow in lattice velocity units) and Re, a node solid when any of
+    the fine nodes it covers is solid, one fluid ring at the walls.  Where the
+    coarse grid cannot resolve the flow stably (s1 above s1_max, the cell
+    Reynolds number too high), the coarse case takes the lowest viscosity
+    with s1 = s1_max instead: a lower-Re flow that still serves as a first
+    guess (its Re is recorded as "Re")."""
+    nu_min = (1.0 / s1_max - 0.5) / 3.0
     out = []
     for c in cases:
         N = c["N"]
@@ -89,7 +94,9 @@ def coarse_cases(cases: List[dict], factor: int = 2) -> List[dict]:
         m[-1:, :] = 0
         m[:, :1] = 0
         m[:, -1:] = 0
-        out.append({"spec": C.cavity_case(N=n, Re=c["Re"], U=c["U"]), "mask": m, "Re": c["Re"], "U": c["U"], "N": n})
+        nu = max(c["U"] * n / c["Re"], nu_min)
+        re_c = c["U"] * n / nu
+        out.append({"spec": C.cavity_case(N=n, Re=re_c, U=c["U"]), "mask": m, "Re": re_c, "U": c["U"], "N": n})
     return out
 
 

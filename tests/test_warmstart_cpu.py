@@ -9,19 +9,27 @@ from paper_2108_08591_amd import warmstart as WS
 
 
 def test_coarse_cases_keep_flow_parameters_and_pool_the_mask():
-    cases = WS.warmstart_cases(3, N=64, seed=3)
-    coarse = WS.coarse_cases(cases)
+    cases = WS.warmstart_cases(24, N=64, seed=3)
+    coarse = WS.coarse_cases(cases, s1_max=1.85)
+    capped = 0
     for c, k in zip(cases, coarse):
         assert k["N"] == 32 and k["spec"].shape == (32, 32)
-        assert k["Re"] == c["Re"] and k["U"] == c["U"]
-        # same lid speed and Reynolds number: the viscosity scales with N
+        assert k["U"] == c["U"]
         nu_f = 1.0 / 3.0 * (1.0 / c["spec"].s1 - 0.5)
         nu_c = 1.0 / 3.0 * (1.0 / k["spec"].s1 - 0.5)
-        assert abs(nu_f / nu_c - 2.0) < 1e-12
+        if abs(k["Re"] - c["Re"]) < 1e-9 * c["Re"]:
+            # same lid speed and Reynolds number: the viscosity scales with N
+            assert abs(nu_f / nu_c - 2.0) < 1e-9
+            assert k["spec"].s1 <= 1.85 + 1e-12
+        else:
+            # too fine a viscosity for the coarse grid: capped at s1 = 1.85
+            capped += 1
+            assert k["Re"] < c["Re"] and abs(k["spec"].s1 - 1.85) < 1e-9
         pooled = c["mask"].reshape(32, 2, 32, 2).max(axis=(1, 3))
         inner = (slice(1, -1), slice(1, -1))
         assert np.array_equal(k["mask"][inner], pooled[inner])
         assert k["mask"][0].sum() == 0 and k["mask"][:, -1].sum() == 0
+    assert 0 < capped < len(cases)
 
 
 def test_scaled_fields_round_trip():
