@@ -274,7 +274,12 @@ def _shape_cases():
     mask[20:25, 66:70] = 1
     box = C.CaseSpec(C.D3Q7, (38, 22, 14), 1.1, bc=(C.PERIODIC, C.PERIODIC, C.WALL, C.WALL, C.WALL, C.WALL),
                      wall_u=((0, 0, 0), (0, 0, 0), (0, 0, 0), (0.05, 0, 0), (0, 0, 0), (0, 0.02, 0)))
-    return [("cavity", cav, None), ("periodic+mask", per, mask), ("box3d", box, None)]
+    # large enough for interior tiles (no face within reach) in every form
+    wide = C.cavity_case(N=300, Re=300.0)
+    wide.shape = (302, 90)
+    box2 = C.CaseSpec(C.D3Q7, (140, 12, 9), 1.2, bc=(C.PERIODIC,) * 6, force=(2e-6, 1e-6, 0.0))
+    return [("cavity", cav, None), ("periodic+mask", per, mask), ("box3d", box, None), ("wide cavity", wide, None),
+            ("periodic box3d", box2, None)]
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16dev", "bf16dev"])
@@ -358,6 +363,25 @@ def test_invariants_and_residual_match_oracle():
     assert np.allclose(inv, o.invariants(), rtol=1e-13, atol=1e-12)
     N = spec.nodes
     assert abs(inv[1] - (inv0[1] + 40 * N * 1e-5)) < 1e-12 * N
+
+
+@pytest.mark.parametrize("form", [0, 2])
+def test_interior_tiles_match_oracle(form):
+    """A grid large enough for tiles whose upstream nodes all lie inside the
+    domain (the kernels skip the face tests there), with walls in y and a
+    periodic x: FP64 GPU vs the FP64 oracle after 31 steps."""
+    spec = C.CaseSpec(C.D2Q5, (196, 132), 1.3, bc=(C.PERIODIC, C.PERIODIC, C.WALL, C.WALL, C.PERIODIC, C.PERIODIC),
+                      wall_u=((0, 0, 0), (0, 0, 0), (0, 0, 0), (0.04, 0.0, 0), (0, 0, 0), (0, 0, 0)),
+                      force=(3e-6, 0.0, 0.0))
+    P, u = C.smooth_random_fields(spec, seed=17, amp=0.02)
+    _say(f"[parity] interior tiles 196x132 FP64 form {form}")
+    s = mdf.Solver([spec], storage="f64", init=("fields", [_fields_tensor(P, u)]), device=DEV)
+    s.set_launch(64, 4, 8, form)
+    s.step(31)
+    o = oracle_for(spec).init(P, u)
+    o.run(31)
+    assert rel_err(o.populations(), _np(s.populations())) < 1e-12
+    compare_fields(o.fields(), gpu_fields_np(s, mdf.FIELD_ALL), 1e-12)
 
 
 def test_mass_conserved_in_closed_cavity():
