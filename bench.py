@@ -684,6 +684,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sets", default="all", choices=["all", "velocity"],
+                    help="distribution sets stored: all d+1 (the configuration) or the d velocity sets (Remark IV)")
     ap.add_argument("--launch", default="128x2g8t",
                     help="threads per block, XCD groups and kernel form, BXxBYgG[s|v|t] (s: one node/thread, v: vector, t: two steps per launch)")
     ap.add_argument("--sweep", metavar="OUT_JSONL",
@@ -778,7 +780,8 @@ def main():
     spec = C.cavity_case(N=1024, Re=1000.0, U=0.1)
     fields = mdf.FIELD_VORT | mdf.FIELD_STRAIN
     stream = torch.cuda.Stream(device=dev)
-    solver = mdf.Solver([spec], storage="f32", device=dev, stream=stream)
+    solver = mdf.Solver([spec], storage="f32", device=dev, stream=stream, sets=args.sets)
+    nsets = solver.nsets
     bx, by, groups, form = parse_launch(args.launch)
     solver.set_launch(bx, by, groups, form)
     out = solver.new_field_buffers(fields)
@@ -809,19 +812,20 @@ def main():
     # work in between).  With two steps per launch a call of 2m + 1 steps is
     # m two-step launches and one one-step launch.
     reps = 5
-    state_bytes = 2 * 15 * 4                      # one read and one write of the FP32 state per node
+    state_bytes = 2 * 5 * nsets * 4               # one read and one write of the FP32 state per node
     field_bytes = 4 * 4                           # 4 emitted FP32 fields per node and step
     step_bytes = state_bytes + field_bytes        # per node and step (one-step kernel)
+    lat_tag = "D2Q5" if nsets == 3 else "D2Q5V"
     if form == 2:
         steps_per_launch, nsteps_timed = 2, 1001
         launch_bytes = state_bytes + 2 * field_bytes
-        kernel_key = "k_step2<D2Q5,F32,emit>_cavity1024"
+        kernel_key = f"k_step2<{lat_tag},F32,emit>_cavity1024"
         kernel_note = ("two steps per launch: the state crosses HBM once per two steps, so the algorithmic bytes "
                        "of a launch are one read and one write of the state plus the fields of both steps")
     else:
         steps_per_launch, nsteps_timed = 1, 500
         launch_bytes = step_bytes
-        kernel_key = "k_step<D2Q5,F32,emit>_cavity1024"
+        kernel_key = f"k_step<{lat_tag},F32,emit>_cavity1024"
         kernel_note = "one step per launch"
     avg_step_ms = time_launches(solver, stream, nsteps_timed, fields, out, reps)
     avg_ms = avg_step_ms * steps_per_launch
@@ -843,8 +847,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "lid-driven cavity 1024x1024, D2Q5 x 3 sets, FP32 storage, Re=1000, lid 0.1, "
+            "workload": f"lid-driven cavity 1024x1024, D2Q5 x {nsets} sets, FP32 storage, Re=1000, lid 0.1, "
                         "per-step vorticity+strain emission, FP64 residual every 100 steps",
+            "sets": args.sets,
             "nodes": nodes, "Re": 1000, "lid_u": 0.1, "storage": "f32",
             "launch": f"{bx}x{by}g{groups}{'svt'[form]}",
         },
@@ -864,8 +869,9 @@ def main():
             "steps_per_launch": steps_per_launch,
             "avg_launch_ms": round(avg_ms, 5),
             "launch_timing": f"HIP events around {nsteps_timed} back-to-back steps, best of {reps}",
-            "note": kernel_note + "; working set 120 MiB + 16 MiB of emitted fields fits the 256 MB Infinity "
-                    "Cache; see roofline_hbm_resident for an 8 GiB working set",
+            "note": kernel_note + f"; working set {state_bytes * nodes >> 20} MiB of populations (both buffers) + "
+                    f"{field_bytes * nodes >> 20} MiB of emitted fields fits the 256 MB Infinity Cache; see "
+                    "roofline_hbm_resident for a working set far beyond it",
         },
         "residual_after": float(res[0]),
     }
@@ -874,14 +880,14 @@ def main():
     del solver, out
     torch.cuda.empty_cache()
     big = C.cavity_case(N=8192, Re=1000.0, U=0.1)
-    bsolver = mdf.Solver([big], storage="f32", device=dev, stream=stream)
+    bsolver = mdf.Solver([big], storage="f32", device=dev, stream=stream, sets=args.sets)
     bsolver.set_launch(bx, by, groups, form)
     bout = bsolver.new_field_buffers(fields)
     bsolver.step_emit(2, fields, bout)
     big_ms = time_launches(bsolver, stream, 41, fields, bout, reps) * steps_per_launch
     big_bytes = big.nodes * launch_bytes
     result["roofline_hbm_resident"] = {
-        "workload": "same kernel, cavity 8192x8192 (8 GiB of populations)",
+        "workload": f"same kernel, cavity 8192x8192 ({state_bytes * big.nodes / 2**30:.1f} GiB of populations)",
         "achieved": round(big_bytes / (big_ms / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(big_bytes / (big_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "avg_launch_ms": round(big_ms, 4),
         "MLUPS": round(big.nodes * steps_per_launch / (big_ms / 1e3) / 1e6, 1)}

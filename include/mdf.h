@@ -56,7 +56,15 @@ typedef enum {
     MDF_ESTATE = -5      /* call not valid in the context's current state  */
 } mdf_status;
 
-typedef enum { MDF_D2Q5 = 0, MDF_D3Q7 = 1 } mdf_lattice;
+/* Lattices (eq. d2q5, eq. d3q7).  MDF_D2Q5 / MDF_D3Q7 store all d + 1
+ * distribution sets a = 0..d of eq. 2-2 (ubar_0 = rho0, ubar_a = u_a).  The
+ * *_V variants store only the d velocity sets a = 1..d (Remark IV: the set
+ * a = 0 advects rho0 passively and no other quantity reads it), moving
+ * d/(d+1) of the bytes per step; their velocity sets, P and every derived
+ * field are identical to the full form's, and ubar_0 reads as the constant
+ * rho0.  Populations (mdf_populations, MDF_INIT_POPULATIONS) then have d
+ * sets, a = 1..d. */
+typedef enum { MDF_D2Q5 = 0, MDF_D3Q7 = 1, MDF_D2Q5_V = 2, MDF_D3Q7_V = 3 } mdf_lattice;
 
 /* Storage of the populations.  MDF_F16DEV / MDF_BF16DEV keep
  * (f - f_rest) / u_ref in 16 bits (round to nearest even on store), with
@@ -217,6 +225,16 @@ mdf_status mdf_invariants(const mdf_ctx *ctx, int32_t case_id, double *out, void
  * summation order of the FP64 sums of mdf_check, mdf_run_steady and
  * mdf_invariants follows it. */
 mdf_status mdf_set_launch(mdf_ctx *ctx, int32_t bx, int32_t by, int32_t groups, int32_t form);
+
+/* Per-node force (eq. 2-6 with a space-dependent F, as in the four-roll
+ * mill of Section 4.2) for case `case_id`: F_b(x) at force[b * nodes + node]
+ * for b = 0..d-1, node = (z * ny + y) * nx + x, in the compute dtype (double
+ * for MDF_STORAGE_F64, float otherwise), added to the case's uniform force
+ * in the collision of every later step.  `force` is caller-owned device
+ * memory that must stay valid while the context steps; NULL removes it.  The
+ * pointer is read by the kernels, not copied.  MDF_EINVAL on a bad case or a
+ * misaligned pointer. */
+mdf_status mdf_set_force_field(mdf_ctx *ctx, int32_t case_id, const void *force);
 
 /* Enable or disable cases.  Disabled cases are skipped by mdf_step,
  * mdf_step_emit, mdf_run_steady and mdf_autotune: their populations and

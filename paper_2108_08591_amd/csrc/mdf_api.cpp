@@ -26,9 +26,13 @@ thread_local std::string g_last_error;
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-int lat_d(int lattice) { return lattice == MDF_D2Q5 ? 2 : 3; }
-int lat_q(int lattice) { return lattice == MDF_D2Q5 ? 5 : 7; }
-double lat_cs2(int lattice) { return lattice == MDF_D2Q5 ? 1.0 / 3.0 : 1.0 / 4.0; }
+bool lat_2d(int lattice) { return lattice == MDF_D2Q5 || lattice == MDF_D2Q5_V; }
+bool lat_ok(int lattice) { return lattice >= MDF_D2Q5 && lattice <= MDF_D3Q7_V; }
+int lat_d(int lattice) { return lat_2d(lattice) ? 2 : 3; }
+int lat_q(int lattice) { return lat_2d(lattice) ? 5 : 7; }
+// stored distribution sets: all d + 1, or the d velocity sets (the *_V lattices)
+int lat_ns(int lattice) { return (lattice == MDF_D2Q5_V || lattice == MDF_D3Q7_V) ? lat_d(lattice) : lat_d(lattice) + 1; }
+double lat_cs2(int lattice) { return lat_2d(lattice) ? 1.0 / 3.0 : 1.0 / 4.0; }
 size_t storage_bytes(int storage)
 {
     switch (storage) {
@@ -67,7 +71,7 @@ bool validate_case(int lattice, const mdf_case &c, std::string &why)
     if (c.nx < 1 || c.ny < 1 || c.nz < 1) { why = "grid sizes must be >= 1"; return false; }
     if (d == 2 && c.nz != 1) { why = "D2Q5 needs nz = 1"; return false; }
     const double nodes = double(c.nx) * c.ny * c.nz;
-    if (nodes * lat_q(lattice) * (d + 1) > 2.0e9) { why = "case too large (>2e9 populations)"; return false; }
+    if (nodes * lat_q(lattice) * lat_ns(lattice) > 2.0e9) { why = "case too large (>2e9 populations)"; return false; }
     if (!(c.s1 > 0.0 && c.s1 < 2.0)) {
         snprintf(buf, sizeof buf, "s1 = %g outside (0, 2)", c.s1);
         why = buf;
@@ -123,7 +127,7 @@ size_t layout(int lattice, int storage, const mdf_case *cases, int ncases, bool 
         CaseLayout L;
         const size_t pitch = row_pitch(c.nx, storage);
         const size_t plane = pitch * c.ny * c.nz;
-        const size_t popb = size_t(d + 1) * q * plane * storage_bytes(storage);
+        const size_t popb = size_t(lat_ns(lattice)) * q * plane * storage_bytes(storage);
         const size_t nodes = size_t(c.nx) * c.ny * c.nz;
         for (int b = 0; b < 2; ++b) { L.pop[b] = off; off = align256(off + popb); }
         L.links = off;
@@ -230,8 +234,8 @@ KCase make_kcase(int lattice, int storage, const mdf_case &c)
     for (int f = 0; f < 6; ++f)
         for (int b = 0; b < 3; ++b) p.walluf[f][b] = float(p.wallu[f][b]);
     // rest weights of the lattice (eq. d2q5 / d3q7) times rho0
-    const double w0 = lattice == MDF_D2Q5 ? 1.0 / 3.0 : 1.0 / 4.0;
-    const double w1 = lattice == MDF_D2Q5 ? 1.0 / 6.0 : 1.0 / 8.0;
+    const double w0 = lat_2d(lattice) ? 1.0 / 3.0 : 1.0 / 4.0;
+    const double w1 = lat_2d(lattice) ? 1.0 / 6.0 : 1.0 / 8.0;
     p.restd[0] = w0 * p.rho0;
     p.restd[1] = w1 * p.rho0;
     p.restf[0] = float(p.restd[0]);
@@ -273,7 +277,7 @@ mdf_status advance_case(mdf_ctx *ctx, int k, int64_t nsteps, bool check_last, ui
                         hipStream_t st, int *nblocks)
 {
     int64_t pairs = 0;
-    if (ctx->shape.fuse && ctx->lattice == MDF_D2Q5 && nsteps >= 3) pairs = (nsteps - 1) / 2;
+    if (ctx->shape.fuse && lat_2d(ctx->lattice) && nsteps >= 3) pairs = (nsteps - 1) / 2;
     for (int64_t s = 0; s < pairs; ++s) {
         hipError_t e = mdf::launch_step2(ctx->lattice, ctx->storage, ctx->kc[k], ctx->bufs[k], ctx->cur[k], fields,
                                          out, ctx->shape, st);
@@ -345,7 +349,7 @@ mdf_status batch_upload(mdf_ctx *ctx, const std::vector<int> &active, uint32_t f
         e.gx = (e.p.nx + tile_x - 1) / tile_x;
         e.gy = (e.p.ny + ctx->shape.by - 1) / ctx->shape.by;
         e.ntiles = e.gx * e.gy * e.p.nz;
-        if (ctx->lattice == MDF_D2Q5) {
+        if (lat_2d(ctx->lattice)) {
             const int rows = mdf::step2_rows(ctx->storage);
             e.gx2 = (e.p.nx + 63) / 64;
             e.gy2 = (e.p.ny + rows - 1) / rows;
@@ -420,7 +424,7 @@ mdf_status batch_steps(mdf_ctx *ctx, int nsteps, bool check, uint32_t fields, hi
     int grid = 0;
     mdf_status r = batch_capacity_grid(ctx, &grid);
     if (r != MDF_OK) return r;
-    const bool fuse = ctx->shape.fuse && ctx->lattice == MDF_D2Q5 && nsteps >= 3;
+    const bool fuse = ctx->shape.fuse && lat_2d(ctx->lattice) && nsteps >= 3;
     const int pairs = fuse ? (nsteps - 1) / 2 : 0;
     const int singles = nsteps - 2 * pairs;
     int grid2 = 0;
@@ -502,7 +506,7 @@ extern "C" {
 size_t mdf_workspace_size(mdf_lattice lattice, mdf_storage storage, const mdf_case *cases, int32_t ncases,
                           int32_t has_solid)
 {
-    if ((lattice != MDF_D2Q5 && lattice != MDF_D3Q7) || storage < MDF_F64 || storage > MDF_BF16DEV ||
+    if (!lat_ok(lattice) || storage < MDF_F64 || storage > MDF_BF16DEV ||
         !cases || ncases < 1) {
         fail(nullptr, MDF_EINVAL, "mdf_workspace_size: invalid lattice, storage or cases");
         return 0;
@@ -522,7 +526,7 @@ mdf_status mdf_init(mdf_ctx **out, mdf_lattice lattice, mdf_storage storage, con
 {
     if (!out) return fail(nullptr, MDF_EINVAL, "mdf_init: out is NULL");
     *out = nullptr;
-    if (lattice != MDF_D2Q5 && lattice != MDF_D3Q7) return fail(nullptr, MDF_EINVAL, "mdf_init: bad lattice");
+    if (!lat_ok(lattice)) return fail(nullptr, MDF_EINVAL, "mdf_init: bad lattice");
     if (storage < MDF_F64 || storage > MDF_BF16DEV) return fail(nullptr, MDF_EINVAL, "mdf_init: bad storage");
     if (!cases || ncases < 1) return fail(nullptr, MDF_EINVAL, "mdf_init: no cases");
     if (init_kind < MDF_INIT_REST || init_kind > MDF_INIT_POPULATIONS)
@@ -550,7 +554,7 @@ mdf_status mdf_init(mdf_ctx **out, mdf_lattice lattice, mdf_storage storage, con
 
     mdf_ctx *ctx = new mdf_ctx;
     ctx->lattice = lattice;
-    ctx->shape.fuse = lattice == MDF_D2Q5 ? 1 : 0;     // two steps per launch by default in 2D
+    ctx->shape.fuse = lat_2d(lattice) ? 1 : 0;     // two steps per launch by default in 2D
     ctx->storage = storage;
     ctx->d = lat_d(lattice);
     ctx->q = lat_q(lattice);
@@ -614,8 +618,8 @@ mdf_status mdf_set_launch(mdf_ctx *ctx, int32_t bx, int32_t by, int32_t groups, 
                     "mdf_set_launch: need bx %% 32 == 0 and bx*by a multiple of 64 up to 256 (got %d x %d)", bx, by);
     if (groups < 0 || groups > 64) return fail(ctx, MDF_EINVAL, "mdf_set_launch: groups outside [0, 64]");
     if (form < 0 || form > 2) return fail(ctx, MDF_EINVAL, "mdf_set_launch: form must be 0, 1 or 2");
-    if (form == 2 && ctx->lattice != MDF_D2Q5)
-        return fail(ctx, MDF_EINVAL, "mdf_set_launch: two steps per launch needs MDF_D2Q5");
+    if (form == 2 && !lat_2d(ctx->lattice))
+        return fail(ctx, MDF_EINVAL, "mdf_set_launch: two steps per launch needs a 2D lattice");
     ctx->shape = LaunchShape{bx, by, groups, form == 1 ? 2 : 1, form == 2 ? 1 : 0};
     drop_graphs(ctx);
     return MDF_OK;
@@ -833,6 +837,18 @@ mdf_status mdf_invariants(const mdf_ctx *cctx, int32_t case_id, double *out, voi
     return MDF_OK;
 }
 
+mdf_status mdf_set_force_field(mdf_ctx *ctx, int32_t case_id, const void *force)
+{
+    if (!ctx) return fail(nullptr, MDF_EINVAL, "mdf_set_force_field: ctx is NULL");
+    if (!case_ok(ctx, case_id)) return fail(ctx, MDF_EINVAL, "case_id %d out of range", case_id);
+    const size_t align = ctx->storage == MDF_F64 ? 8 : 4;
+    if (reinterpret_cast<uintptr_t>(force) % align != 0)
+        return fail(ctx, MDF_EINVAL, "mdf_set_force_field: force not aligned to its element size");
+    ctx->kc[case_id].ffield = force;
+    drop_graphs(ctx);          // captured launches hold the old case parameters
+    return MDF_OK;
+}
+
 mdf_status mdf_set_active(mdf_ctx *ctx, const int32_t *active)
 {
     if (!ctx) return fail(nullptr, MDF_EINVAL, "mdf_set_active: ctx is NULL");
@@ -859,7 +875,7 @@ mdf_status mdf_autotune(mdf_ctx *ctx, int32_t trial_steps, int32_t *chosen, doub
     mdf_status r = MDF_OK;
     for (int c = 0; c < int(sizeof cand / sizeof cand[0]) && r == MDF_OK; ++c) {
         // two steps per launch: 2D contexts only
-        if (cand[c][3] == 2 && ctx->lattice != MDF_D2Q5) continue;
+        if (cand[c][3] == 2 && !lat_2d(ctx->lattice)) continue;
         r = mdf_set_launch(ctx, cand[c][0], cand[c][1], cand[c][2], cand[c][3]);
         if (r != MDF_OK) break;
         r = step_impl(ctx, 1, 0, nullptr, stream);           // warm-up (and graph capture)

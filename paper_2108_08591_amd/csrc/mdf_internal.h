@@ -35,6 +35,9 @@ struct KCase {
     float walluf[6][3];
     double restd[2];
     float restf[2];
+    // optional per-node force, d x nodes values component-major in the
+    // compute dtype (caller-owned device memory), added to fbar[1..d]
+    const void *ffield;
 };
 
 // Device pointers of one case inside the workspace.

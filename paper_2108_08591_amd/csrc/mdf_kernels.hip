@@ -39,9 +39,13 @@ namespace {
 
 // ----------------------------------------------------------------- lattices
 
-// D2Q5 (eq. d2q5) with w_0 = 1/3 as used in Section 4.
+// D2Q5 (eq. d2q5) with w_0 = 1/3 as used in Section 4.  NS is the number of
+// stored distribution sets and A0 the set index a of the first stored one:
+// all d + 1 sets (a = 0..d), or, in the *V variants, only the d velocity
+// sets a = 1..d (Remark IV: the set a = 0 only advects rho0 and no other
+// quantity reads it).
 struct LatD2Q5 {
-    static constexpr int D = 2, Q = 5, NS = 3;
+    static constexpr int D = 2, Q = 5, NS = 3, A0 = 0;
     static constexpr int cx[5] = {0, 1, 0, -1, 0};
     static constexpr int cy[5] = {0, 0, 1, 0, -1};
     static constexpr int cz[5] = {0, 0, 0, 0, 0};
@@ -52,13 +56,21 @@ struct LatD2Q5 {
 
 // D3Q7 (eq. d3q7).
 struct LatD3Q7 {
-    static constexpr int D = 3, Q = 7, NS = 4;
+    static constexpr int D = 3, Q = 7, NS = 4, A0 = 0;
     static constexpr int cx[7] = {0, 1, -1, 0, 0, 0, 0};
     static constexpr int cy[7] = {0, 0, 0, 1, -1, 0, 0};
     static constexpr int cz[7] = {0, 0, 0, 0, 0, 1, -1};
     static constexpr int opp[7] = {0, 2, 1, 4, 3, 6, 5};
     static constexpr double w0 = 1.0 / 4.0, w1 = 1.0 / 8.0;
     static constexpr double cs2 = 1.0 / 4.0, inv_cs2 = 4.0;
+};
+
+// The same lattices storing only the velocity sets a = 1..d.
+struct LatD2Q5V : LatD2Q5 {
+    static constexpr int NS = 2, A0 = 1;
+};
+struct LatD3Q7V : LatD3Q7 {
+    static constexpr int NS = 3, A0 = 1;
 };
 
 template <class L>
@@ -240,7 +252,7 @@ __device__ __forceinline__ T lane_down1(T v)
 template <class L, class C>
 __device__ __forceinline__ C rest_value(const KCase &p, int a, int i)
 {
-    if (a != 0) return C(0);
+    if (a + L::A0 != 0) return C(0);
     return kpar<C>(p.restd[i != 0], p.restf[i != 0]);
 }
 
@@ -253,7 +265,7 @@ struct Node {
 
 template <class L, class C>
 struct Moments {
-    C ubar[L::NS];          // eq. 2-7
+    C ubar[L::D + 1];       // eq. 2-7, sets a = 0..d (a = 0: rho0 when that set is not stored)
     C u[L::D];
     C P;                    // eq. 3-15
     C trJ;                  // sum_{a>=1} J_{a,a}
@@ -309,10 +321,11 @@ __device__ __forceinline__ bool gather(const KCase &p, const typename Store<ST>:
             for (int a = 0; a < L::NS; ++a) {
                 C v = S::load(src + (long long)(a * L::Q + j) * p.dstride, own, rest_value<L, C>(p, a, j),
                               p.scale);
-                if (a == 0) {
+                if (a + L::A0 == 0) {
                     n.f[a][i] = v;
                 } else {
-                    C uw = (face < 6) ? kpar<C>(p.wallu[face][a - 1], p.walluf[face][a - 1]) : C(0);
+                    const int b = a + L::A0 - 1;
+                    C uw = (face < 6) ? kpar<C>(p.wallu[face][b], p.walluf[face][b]) : C(0);
                     n.f[a][i] = -v + C(2) * w * uw;
                 }
             }
@@ -396,10 +409,11 @@ __device__ __forceinline__ void gather_vec(const KCase &p, const typename Store<
                 if (MASK && f < 0 && ((lb[v] >> i) & 1u)) f = 6;
                 if (f >= 0) {
                     const C val = S::decode(oplane[own + v], rest_j, p.scale);
-                    if (a == 0) {
+                    if (a + L::A0 == 0) {
                         n[v].f[a][i] = val;
                     } else {
-                        const C uw = (f < 6) ? kpar<C>(p.wallu[f][a - 1], p.walluf[f][a - 1]) : C(0);
+                        const int b = a + L::A0 - 1;
+                        const C uw = (f < 6) ? kpar<C>(p.wallu[f][b], p.walluf[f][b]) : C(0);
                         n[v].f[a][i] = -val + C(2) * w * uw;
                     }
                 } else {
@@ -425,21 +439,23 @@ __device__ __forceinline__ void moments(const KCase &p, const Node<L, C> &n, Mom
         C s = n.f[a][0];
 #pragma unroll
         for (int i = 1; i < L::Q; ++i) s += n.f[a][i];
-        m.ubar[a] = s;
+        m.ubar[a + L::A0] = s;
     }
+    if (L::A0 == 1) m.ubar[0] = kpar<C>(p.rho0, p.rho0f);
 #pragma unroll
     for (int b = 0; b < L::D; ++b) m.u[b] = m.ubar[b + 1];
     C trJ = C(0), u2 = C(0);
 #pragma unroll
-    for (int a = 1; a < L::NS; ++a) {
+    for (int pa = 1; pa <= L::D; ++pa) {     // velocity sets
+        const int a = pa - L::A0;
         C j = C(0);
 #pragma unroll
         for (int i = 1; i < L::Q; ++i) {
-            if (cdir<L>(i, a - 1) > 0) j += n.f[a][i];
-            else if (cdir<L>(i, a - 1) < 0) j -= n.f[a][i];
+            if (cdir<L>(i, pa - 1) > 0) j += n.f[a][i];
+            else if (cdir<L>(i, pa - 1) < 0) j -= n.f[a][i];
         }
         trJ += j;
-        u2 += m.u[a - 1] * m.u[a - 1];
+        u2 += m.u[pa - 1] * m.u[pa - 1];
     }
     m.trJ = trJ;
     m.P = (trJ + C(L::cs2) * kpar<C>(p.R, p.Rf) / kpar<C>(p.s1, p.s1f) - u2) * C(1.0 / L::D);
@@ -476,10 +492,11 @@ template <class L, class C>
 __device__ __forceinline__ void nonequilibrium(const Node<L, C> &n, const Moments<L, C> &m, int a,
                                                C (&ne)[L::Q])
 {
-    const C ub = m.ubar[a];
+    const int pa = a + L::A0;              // set index a of the stored set
+    const C ub = m.ubar[pa];
     C flux[L::D];
 #pragma unroll
-    for (int b = 0; b < L::D; ++b) flux[b] = ub * m.u[b] + ((a >= 1 && b == a - 1) ? m.P : C(0));
+    for (int b = 0; b < L::D; ++b) flux[b] = ub * m.u[b] + ((pa >= 1 && b == pa - 1) ? m.P : C(0));
     C feq[L::Q];
     equilibrium<L, C>(ub, flux, feq);
 #pragma unroll
@@ -498,10 +515,14 @@ __device__ __forceinline__ void nonequilibrium(const Node<L, C> &n, const Moment
 // rounds the same way every step and drifts by ~1e-5 in a few thousand).
 template <class L, class C>
 __device__ __forceinline__ void collide_set(const KCase &p, const Node<L, C> &n, int a,
-                                            const C (&ne)[L::Q], C (&out)[L::Q])
+                                            const C (&ne)[L::Q], C (&out)[L::Q], long long node)
 {
     const C s1 = kpar<C>(p.s1, p.s1f), s2 = kpar<C>(p.s2, p.s2f);
-    const C fb = kpar<C>(p.fbar[a], p.fbarf[a]);
+    const int pa = a + L::A0;
+    C fb = kpar<C>(p.fbar[pa], p.fbarf[pa]);
+    // a per-node force field (eq. 2-6 with F = F(x)) adds to the uniform force
+    if (pa >= 1 && p.ffield)
+        fb += static_cast<const C *>(p.ffield)[(long long)(pa - 1) * ((long long)p.nx * p.ny * p.nz) + node];
     const C wf = C(L::w1) * fb;
     C dsum = C(0);
 #pragma unroll
@@ -527,9 +548,9 @@ __device__ __forceinline__ void write_fields(const KCase &p, const Node<L, C> &n
     // first moment of the non-equilibrium part, mne[a][b] = sum_i c_{i,b} n_{i,a}
     C mne[D][D];
 #pragma unroll
-    for (int a = 1; a < L::NS; ++a) {
+    for (int pa = 1; pa <= D; ++pa) {       // velocity sets
         C ne[L::Q];
-        nonequilibrium<L, C>(n, m, a, ne);
+        nonequilibrium<L, C>(n, m, pa - L::A0, ne);
 #pragma unroll
         for (int b = 0; b < D; ++b) {
             C s = C(0);
@@ -538,7 +559,7 @@ __device__ __forceinline__ void write_fields(const KCase &p, const Node<L, C> &n
                 if (cdir<L>(i, b) > 0) s += ne[i];
                 else if (cdir<L>(i, b) < 0) s -= ne[i];
             }
-            mne[a - 1][b] = s;
+            mne[pa - 1][b] = s;
         }
     }
     const C gscale = -kpar<C>(p.s1, p.s1f) * C(L::inv_cs2);           // eq. 3-16
@@ -550,7 +571,7 @@ __device__ __forceinline__ void write_fields(const KCase &p, const Node<L, C> &n
     long long ch = 0;
     if (fields & MDF_FIELD_MOMENTS) {
 #pragma unroll
-        for (int a = 0; a < L::NS; ++a) out[(ch++) * nodes + node] = m.ubar[a];
+        for (int a = 0; a <= L::D; ++a) out[(ch++) * nodes + node] = m.ubar[a];
         out[(ch++) * nodes + node] = m.P;
     }
     if (fields & MDF_FIELD_GRAD) {
@@ -640,7 +661,7 @@ __device__ __forceinline__ void check_values(const Moments<L, C> &m, bool valid,
         }
     }
 #pragma unroll
-    for (int a = 0; a < L::NS; ++a) {
+    for (int a = 0; a <= L::D; ++a) {
         v[2 + a] = (double)m.ubar[a];
         finite = finite && isfinite((double)m.ubar[a]);
     }
@@ -681,7 +702,7 @@ __device__ __forceinline__ void step_tile(const KCase &p, int gx, int gy, int ti
         for (int a = 0; a < L::NS; ++a) {
             C ne[L::Q], fo[L::Q];
             nonequilibrium<L, C>(n, m, a, ne);
-            collide_set<L, C>(p, n, a, ne, fo);
+            collide_set<L, C>(p, n, a, ne, fo, node);
 #pragma unroll
             for (int i = 0; i < L::Q; ++i)
                 S::store(dst + (long long)(a * L::Q + i) * p.dstride, own, fo[i], rest_value<L, C>(p, a, i),
@@ -690,7 +711,7 @@ __device__ __forceinline__ void step_tile(const KCase &p, int gx, int gy, int ti
     } else if (EMIT && inside) {
         // solid node: every emitted channel is zero
         int nch = 0;
-        if (fields & MDF_FIELD_MOMENTS) nch += L::NS + 1;
+        if (fields & MDF_FIELD_MOMENTS) nch += L::D + 2;
         if (fields & MDF_FIELD_GRAD) nch += L::D * L::D;
         if (fields & MDF_FIELD_DIV) nch += 1;
         if (fields & MDF_FIELD_STRAIN) nch += L::D * (L::D + 1) / 2;
@@ -749,7 +770,7 @@ __device__ __forceinline__ void step_tile_vec(const KCase &p, int gx, int gy, in
             if (EMIT) write_fields<L, C>(p, n[v], m[v], fields, out, node, nodes);
         } else if (EMIT && inside) {
             int nch = 0;
-            if (fields & MDF_FIELD_MOMENTS) nch += L::NS + 1;
+            if (fields & MDF_FIELD_MOMENTS) nch += L::D + 2;
             if (fields & MDF_FIELD_GRAD) nch += L::D * L::D;
             if (fields & MDF_FIELD_DIV) nch += 1;
             if (fields & MDF_FIELD_STRAIN) nch += L::D * (L::D + 1) / 2;
@@ -772,7 +793,7 @@ __device__ __forceinline__ void step_tile_vec(const KCase &p, int gx, int gy, in
             if (!fluid[v]) continue;
             C ne[L::Q], fo[L::Q];
             nonequilibrium<L, C>(n[v], m[v], a, ne);
-            collide_set<L, C>(p, n[v], a, ne, fo);
+            collide_set<L, C>(p, n[v], a, ne, fo, ((long long)z * p.ny + y) * p.nx + x0 + v);
 #pragma unroll
             for (int i = 0; i < L::Q; ++i) n[v].f[a][i] = fo[i];
         }
@@ -901,7 +922,7 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int tile, con
             for (int a = 0; a < L::NS; ++a) {
                 C ne[L::Q], fo[L::Q];
                 nonequilibrium<L, C>(n[g], m, a, ne);
-                collide_set<L, C>(p, n[g], a, ne, fo);
+                collide_set<L, C>(p, n[g], a, ne, fo, node[g]);
 #pragma unroll
                 for (int i = 0; i < L::Q; ++i)
                     lds[(a * L::Q + i) * NE + e] = S::encode(fo[i], rest_value<L, C>(p, a, i), p.inv_scale);
@@ -923,7 +944,7 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int tile, con
         if (MASK && (lb & 0x80u)) {
             if (EMIT) {
                 int nch = 0;
-                if (fields & MDF_FIELD_MOMENTS) nch += L::NS + 1;
+                if (fields & MDF_FIELD_MOMENTS) nch += L::D + 2;
                 if (fields & MDF_FIELD_GRAD) nch += L::D * L::D;
                 if (fields & MDF_FIELD_DIV) nch += 1;
                 if (fields & MDF_FIELD_STRAIN) nch += L::D * (L::D + 1) / 2;
@@ -958,10 +979,11 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int tile, con
 #pragma unroll
                 for (int a = 0; a < L::NS; ++a) {
                     const C v = S::decode(lds[(a * L::Q + j) * NE + le], rest_value<L, C>(p, a, j), p.scale);
-                    if (a == 0) {
+                    if (a + L::A0 == 0) {
                         n.f[a][i] = v;
                     } else {
-                        const C uw = (face < 6) ? kpar<C>(p.wallu[face][a - 1], p.walluf[face][a - 1]) : C(0);
+                        const int b = a + L::A0 - 1;
+                        const C uw = (face < 6) ? kpar<C>(p.wallu[face][b], p.walluf[face][b]) : C(0);
                         n.f[a][i] = -v + C(2) * w * uw;
                     }
                 }
@@ -974,7 +996,7 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int tile, con
         for (int a = 0; a < L::NS; ++a) {
             C ne[L::Q], fo[L::Q];
             nonequilibrium<L, C>(n, m, a, ne);
-            collide_set<L, C>(p, n, a, ne, fo);
+            collide_set<L, C>(p, n, a, ne, fo, node);
 #pragma unroll
             for (int i = 0; i < L::Q; ++i)
                 S::store(dst + (long long)(a * L::Q + i) * p.dstride, own, fo[i], rest_value<L, C>(p, a, i),
@@ -1119,7 +1141,7 @@ k_read(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, const 
             write_fields<L, C>(p, n, m, fields, out, node, nodes);
         } else {
             int nch = 0;
-            if (fields & MDF_FIELD_MOMENTS) nch += L::NS + 1;
+            if (fields & MDF_FIELD_MOMENTS) nch += L::D + 2;
             if (fields & MDF_FIELD_GRAD) nch += L::D * L::D;
             if (fields & MDF_FIELD_DIV) nch += 1;
             if (fields & MDF_FIELD_STRAIN) nch += L::D * (L::D + 1) / 2;
@@ -1186,10 +1208,11 @@ k_init(KCase p, typename Store<ST>::T *__restrict__ pre, typename Store<ST>::T *
         }
 #pragma unroll
         for (int a = 0; a < L::NS; ++a) {
-            const C ub = (a == 0) ? C(p.rho0) : u[a - 1];
+            const int pa = a + L::A0;
+            const C ub = (pa == 0) ? C(p.rho0) : u[pa - 1];
             C flux[L::D], feq[L::Q];
 #pragma unroll
-            for (int b = 0; b < L::D; ++b) flux[b] = ub * u[b] + ((a >= 1 && b == a - 1) ? P : C(0));
+            for (int b = 0; b < L::D; ++b) flux[b] = ub * u[b] + ((pa >= 1 && b == pa - 1) ? P : C(0));
             equilibrium<L, C>(ub, flux, feq);
             n.f[a][0] = feq[0];
 #pragma unroll
@@ -1198,8 +1221,8 @@ k_init(KCase p, typename Store<ST>::T *__restrict__ pre, typename Store<ST>::T *
 #pragma unroll
                 for (int b = 0; b < L::D; ++b) {
                     C g = C(0);
-                    if (kind == MDF_INIT_FIELDS_GRAD && a >= 1)
-                        g = data[(1 + L::D + (a - 1) * L::D + b) * nodes + node];
+                    if (kind == MDF_INIT_FIELDS_GRAD && pa >= 1)
+                        g = data[(1 + L::D + (pa - 1) * L::D + b) * nodes + node];
                     if (cdir<L>(i, b) > 0) cg += g;
                     else if (cdir<L>(i, b) < 0) cg -= g;
                 }
@@ -1214,7 +1237,7 @@ k_init(KCase p, typename Store<ST>::T *__restrict__ pre, typename Store<ST>::T *
     for (int a = 0; a < L::NS; ++a) {
         C ne[L::Q], fo[L::Q];
         nonequilibrium<L, C>(n, m, a, ne);
-        collide_set<L, C>(p, n, a, ne, fo);
+        collide_set<L, C>(p, n, a, ne, fo, node);
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
             const long long k = (long long)(a * L::Q + i) * p.dstride + own;
@@ -1498,22 +1521,21 @@ int read_blocks(const KCase &p, LaunchShape s)
     return tiling_of(p, s, 1).nb;
 }
 
+#define MDF_DISPATCH_LAT(LAT, storage, FN, ...)                                              \
+    switch (storage) {                                                                       \
+    case MDF_F64: return FN<LAT, MDF_F64>(__VA_ARGS__);                                      \
+    case MDF_F32: return FN<LAT, MDF_F32>(__VA_ARGS__);                                      \
+    case MDF_F16DEV: return FN<LAT, MDF_F16DEV>(__VA_ARGS__);                                \
+    case MDF_BF16DEV: return FN<LAT, MDF_BF16DEV>(__VA_ARGS__);                              \
+    }
+
 #define MDF_DISPATCH(lattice, storage, FN, ...)                                              \
     do {                                                                                     \
-        if (lattice == MDF_D2Q5) {                                                           \
-            switch (storage) {                                                               \
-            case MDF_F64: return FN<LatD2Q5, MDF_F64>(__VA_ARGS__);                          \
-            case MDF_F32: return FN<LatD2Q5, MDF_F32>(__VA_ARGS__);                          \
-            case MDF_F16DEV: return FN<LatD2Q5, MDF_F16DEV>(__VA_ARGS__);                    \
-            case MDF_BF16DEV: return FN<LatD2Q5, MDF_BF16DEV>(__VA_ARGS__);                  \
-            }                                                                                \
-        } else {                                                                             \
-            switch (storage) {                                                               \
-            case MDF_F64: return FN<LatD3Q7, MDF_F64>(__VA_ARGS__);                          \
-            case MDF_F32: return FN<LatD3Q7, MDF_F32>(__VA_ARGS__);                          \
-            case MDF_F16DEV: return FN<LatD3Q7, MDF_F16DEV>(__VA_ARGS__);                    \
-            case MDF_BF16DEV: return FN<LatD3Q7, MDF_BF16DEV>(__VA_ARGS__);                  \
-            }                                                                                \
+        switch (lattice) {                                                                   \
+        case MDF_D2Q5: MDF_DISPATCH_LAT(LatD2Q5, storage, FN, __VA_ARGS__) break;             \
+        case MDF_D3Q7: MDF_DISPATCH_LAT(LatD3Q7, storage, FN, __VA_ARGS__) break;             \
+        case MDF_D2Q5_V: MDF_DISPATCH_LAT(LatD2Q5V, storage, FN, __VA_ARGS__) break;          \
+        case MDF_D3Q7_V: MDF_DISPATCH_LAT(LatD3Q7V, storage, FN, __VA_ARGS__) break;          \
         }                                                                                    \
         return hipErrorInvalidValue;                                                         \
     } while (0)
@@ -1528,7 +1550,7 @@ hipError_t launch_step(int lattice, int storage, const KCase &p, const CaseBufs 
 hipError_t launch_step2(int lattice, int storage, const KCase &p, const CaseBufs &b, int src, uint32_t fields,
                         void *out, LaunchShape shape, hipStream_t stream)
 {
-    if (lattice != MDF_D2Q5 || p.nz != 1) return hipErrorInvalidValue;
+    if ((lattice != MDF_D2Q5 && lattice != MDF_D2Q5_V) || p.nz != 1) return hipErrorInvalidValue;
     MDF_DISPATCH(lattice, storage, step2_dispatch, p, b, src, fields, out, shape, stream);
 }
 
@@ -1550,7 +1572,7 @@ hipError_t launch_links(int lattice, const KCase &p, const uint8_t *solid, uint8
 {
     const LaunchShape s{64, 4, 1};
     const dim3 grid = grid_of(p, s), block(s.bx, s.by, 1);
-    if (lattice == MDF_D2Q5)
+    if (lattice == MDF_D2Q5 || lattice == MDF_D2Q5_V)
         hipLaunchKernelGGL((k_links<LatD2Q5>), grid, block, 0, stream, p, solid, links);
     else
         hipLaunchKernelGGL((k_links<LatD3Q7>), grid, block, 0, stream, p, solid, links);
@@ -1569,14 +1591,14 @@ namespace mdf {
 
 hipError_t launch_step2_batch(int lattice, int storage, const BatchLaunch &bl, hipStream_t stream)
 {
-    if (lattice != MDF_D2Q5) return hipErrorInvalidValue;
+    if (lattice != MDF_D2Q5 && lattice != MDF_D2Q5_V) return hipErrorInvalidValue;
     const bool emit = bl.fields != 0;
     MDF_DISPATCH(lattice, storage, batch2_dispatch, bl, emit, stream);
 }
 
 hipError_t batch2_blocks_per_cu(int lattice, int storage, bool mask, int *blocks_per_cu)
 {
-    if (lattice != MDF_D2Q5) return hipErrorInvalidValue;
+    if (lattice != MDF_D2Q5 && lattice != MDF_D2Q5_V) return hipErrorInvalidValue;
     MDF_DISPATCH(lattice, storage, batch2_capacity, mask, blocks_per_cu);
 }
 

@@ -31,7 +31,8 @@ STORAGE_NAMES = {"f64": F64, "f32": F32, "f16dev": F16DEV, "bf16dev": BF16DEV}
 
 EXPORTED = ["mdf_workspace_size", "mdf_init", "mdf_step", "mdf_step_emit", "mdf_moments",
             "mdf_gradients", "mdf_populations", "mdf_check", "mdf_run_steady", "mdf_invariants",
-            "mdf_set_launch", "mdf_set_active", "mdf_autotune", "mdf_time", "mdf_last_error",
+            "mdf_set_launch", "mdf_set_active", "mdf_set_force_field", "mdf_autotune", "mdf_time",
+            "mdf_last_error",
             "mdf_destroy"]
 
 
@@ -83,6 +84,7 @@ def lib():
         L.mdf_set_launch.argtypes = [vp, i32, i32, i32, i32]
         L.mdf_autotune.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl), vp]
         L.mdf_set_active.argtypes = [vp, ctypes.POINTER(i32)]
+        L.mdf_set_force_field.argtypes = [vp, i32, vp]
         L.mdf_time.argtypes = [vp, i32]
         L.mdf_time.restype = i64
         L.mdf_last_error.argtypes = [vp]
@@ -90,7 +92,7 @@ def lib():
         L.mdf_destroy.argtypes = [vp]
         for name in ("mdf_init", "mdf_step", "mdf_step_emit", "mdf_moments", "mdf_gradients",
                      "mdf_populations", "mdf_check", "mdf_run_steady", "mdf_invariants",
-                     "mdf_set_launch", "mdf_set_active", "mdf_autotune", "mdf_destroy"):
+                     "mdf_set_launch", "mdf_set_active", "mdf_set_force_field", "mdf_autotune", "mdf_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -171,10 +173,12 @@ class Solver:
 
     ``init`` is ``"rest"`` or a tuple ``(kind, [tensor per case])`` with kind
     in {"fields", "fields_grad", "populations"}; tensors are channel-major in
-    the compute dtype (FP64 for f64 storage, FP32 otherwise)."""
+    the compute dtype (FP64 for f64 storage, FP32 otherwise).  ``sets`` is
+    "all" (the d + 1 sets a = 0..d) or "velocity" (only a = 1..d, the *_V
+    lattices: same velocity, pressure and derived fields, fewer bytes)."""
 
     def __init__(self, specs: Sequence[CaseSpec], storage="f32", solid=None, init="rest",
-                 u_ref: float = 0.0, device="cuda:0", stream=None):
+                 u_ref: float = 0.0, device="cuda:0", stream=None, sets: str = "all"):
         if isinstance(specs, CaseSpec):
             specs = [specs]
         self.specs = list(specs)
@@ -184,6 +188,11 @@ class Solver:
         self.storage = STORAGE_NAMES[storage] if isinstance(storage, str) else int(storage)
         self.d = self.specs[0].d
         self.q = 5 if self.lattice == D2Q5 else 7
+        if sets not in ("all", "velocity"):
+            raise ValueError("sets must be 'all' or 'velocity'")
+        self.nsets = self.d + 1 if sets == "all" else self.d
+        if sets == "velocity":
+            self.lattice += 2          # MDF_D2Q5_V / MDF_D3Q7_V
         self.device = torch.device(device)
         self.dtype = torch.float64 if self.storage == F64 else torch.float32
         self.stream = stream
@@ -239,7 +248,7 @@ class Solver:
             return 1 + d
         if kind == INIT_FIELDS_GRAD:
             return 1 + d + d * d
-        return (d + 1) * self.q
+        return self.nsets * self.q
 
     def _sync(self):
         (self.stream or torch.cuda.current_stream()).synchronize()
@@ -270,6 +279,22 @@ class Solver:
         node per thread, 1 vector (several x-nodes per thread), 2 two steps
         per launch (D2Q5)."""
         _check(lib().mdf_set_launch(self._ctx, bx, by, groups, int(form)), self._ctx)
+
+    def set_force_field(self, force, case: int = 0):
+        """Per-node force F_b(x), array [d, *fshape] (or None to remove it);
+        kept on the device by the solver for as long as it is set."""
+        if force is None:
+            self._force = getattr(self, "_force", {})
+            self._force.pop(case, None)
+            _check(lib().mdf_set_force_field(self._ctx, case, None), self._ctx)
+            return
+        t = torch.as_tensor(force).to(device=self.device, dtype=self.dtype).contiguous()
+        if t.numel() != self.d * self.specs[case].nodes:
+            raise ValueError(f"force field of case {case}: {t.numel()} values, {self.d * self.specs[case].nodes} expected")
+        self._force = getattr(self, "_force", {})
+        self._force[case] = t
+        torch.cuda.current_stream().synchronize()
+        _check(lib().mdf_set_force_field(self._ctx, case, ctypes.c_void_p(t.data_ptr())), self._ctx)
 
     def set_active(self, active):
         """Enable (non-zero) or disable (0) each case."""
@@ -324,7 +349,7 @@ class Solver:
         return split_fields(self.d, fields, self.gradients(fields, case))
 
     def populations(self, case: int = 0) -> torch.Tensor:
-        out = torch.empty((self.d + 1, self.q) + self.specs[case].fshape, dtype=self.dtype,
+        out = torch.empty((self.nsets, self.q) + self.specs[case].fshape, dtype=self.dtype,
                           device=self.device)
         _check(lib().mdf_populations(self._ctx, case, ctypes.c_void_p(out.data_ptr()),
                                      _stream_ptr(self.stream)), self._ctx)

@@ -46,6 +46,20 @@ def test_workspace_size_scales_with_storage_and_grid():
     assert _ws(big) > 3.5 * w32
 
 
+def test_velocity_set_lattices_store_d_of_d_plus_one_sets():
+    """MDF_D2Q5_V / MDF_D3Q7_V keep only the d velocity sets (Remark IV):
+    the population part of the workspace shrinks by d/(d+1)."""
+    for spec, d in ((C.cavity_case(N=256, Re=100), 2), (C.tgv3d_case(N=64, u0=0.05, Re=100.0), 3)):
+        c = (mdf.MdfCase * 1)(mdf._case_struct(spec))
+        full = mdf.lib().mdf_workspace_size(spec.lattice, mdf.F32, c, 1, 0)
+        vel = mdf.lib().mdf_workspace_size(spec.lattice + 2, mdf.F32, c, 1, 0)
+        q = 5 if d == 2 else 7
+        one_set = 2 * q * spec.nodes * 4          # both ping-pong buffers, FP32
+        assert full - vel == pytest.approx(one_set, rel=0.02)
+        assert full > (d + 1) * one_set
+    assert mdf.lib().mdf_workspace_size(4, mdf.F32, c, 1, 0) == 0
+
+
 @pytest.mark.parametrize("mutate,msg", [
     (lambda s: setattr(s, "s1", 2.0), "s1"),
     (lambda s: setattr(s, "s1", 0.0), "s1"),
