@@ -23,6 +23,13 @@
  *   L = M^{-1} S_d M                                         (eq. 4-1..4-3)
  * and the local post-processing of Section 3.3 (eq. 3-16 .. 3-19).
  *
+ * With forcing = ORC_SCHEME2 the update is Scheme II (eq. 2-3c) instead:
+ *   fbar_{i,a}(x + c_i, t + 1) = fbar - sum_k L_{ik} [fbar_{k,a} - f^eq_{k,a}]
+ *                                + sum_k (delta_{ik} - L_{ik}/2) w_k Fbar_a
+ * on the shifted populations fbar = f - F/2, with
+ *   ubar_a = sum_i fbar_{i,a} + Fbar_a / 2                   (eq. 2-7a)
+ * and eq. 3-15 evaluated with fbar in place of f.
+ *
  * Lattice units throughout: dx = dt = c = 1.
  *
  * Readings where the paper gives no formula (each is listed with its reason
@@ -52,6 +59,8 @@
 #define ORC_D3Q7 1
 #define ORC_PERIODIC 0
 #define ORC_WALL 1
+#define ORC_PLAIN 0
+#define ORC_SCHEME2 1
 #define QMAX 7
 
 typedef struct {
@@ -63,6 +72,7 @@ typedef struct {
     double force[3];        /* uniform body force F_a, a = 1..d (eq. 2-1b) */
     double R;               /* uniform mass source R (eq. 2-1a) */
     double rho0;            /* constant density rho0 (eq. 2-2, eq. 3-17a) */
+    int32_t forcing;        /* ORC_PLAIN (eq. 3-21) or ORC_SCHEME2 (eq. 2-3c) */
 } orc_case;
 
 typedef struct {
@@ -213,14 +223,29 @@ typedef struct {
     double P;           /* eq. 3-15 */
 } moments_t;
 
+/* Fbar_a at node n, a = 0..d (eq. 2-2): Fbar_0 = R, Fbar_a = F_a plus the
+ * per-node force field (component-major, d*N values) when one is given. */
+static void node_source(const orc_case *cs, int d, const double *force_field, long N, long n,
+                        double *Fbar)
+{
+    Fbar[0] = cs->R;
+    for (int a = 1; a <= d; ++a) {
+        Fbar[a] = cs->force[a - 1];
+        if (force_field) Fbar[a] += force_field[(a - 1) * N + n];
+    }
+}
+
+/* Moments of the stored populations fn of one node.  Fbar is used only by
+ * Scheme II, whose ubar is eq. 2-7a. */
 static void node_moments(const lattice_t *L, const orc_case *cs,
-                         const double *fn /* [set][dir] */, moments_t *m)
+                         const double *fn /* [set][dir] */, const double *Fbar, moments_t *m)
 {
     int d = L->d, q = L->q;
     memset(m, 0, sizeof(*m));
     for (int a = 0; a <= d; ++a) {
         double s = 0.0;
         for (int i = 0; i < q; ++i) s += fn[a * q + i];
+        if (cs->forcing == ORC_SCHEME2) s += 0.5 * Fbar[a];      /* eq. 2-7a */
         m->ubar[a] = s;
         for (int b = 0; b < d; ++b) {
             double j = 0.0;
@@ -261,6 +286,7 @@ static int check_case(const orc_case *cs, lattice_t *L)
     if (cs->nx < 1 || cs->ny < 1 || cs->nz < 1) return -1;
     if (L->d == 2 && cs->nz != 1) return -1;
     if (!(cs->s1 > 0.0 && cs->s1 < 2.0)) return -1;
+    if (cs->forcing != ORC_PLAIN && cs->forcing != ORC_SCHEME2) return -1;
     return 0;
 }
 
@@ -303,9 +329,11 @@ int orc_collision_matrix(int lattice, double s0, double s1, double s2, double *o
  * f = f^eq(rho0, u, P) (eq. 2-4) plus, when grad is given, the
  * non-equilibrium part f^ne_{i,a} = -(1/s1) w_i c_i . grad u_a (inverse of
  * eq. 3-16; the set a = 0 carries the constant rho0 and gets none).
+ * Scheme II stores fbar = f - F/2, F_{i,a} = w_i Fbar_a (force_field as in
+ * orc_collide), so that eq. 2-7a returns the given ubar.
  * solid may be NULL; solid nodes are set to zero. */
-int orc_init(const orc_case *cs, const uint8_t *solid, const double *P,
-             const double *u, const double *grad, double *f)
+int orc_init(const orc_case *cs, const uint8_t *solid, const double *force_field,
+             const double *P, const double *u, const double *grad, double *f)
 {
     lattice_t L;
     if (check_case(cs, &L) != 0) return -1;
@@ -334,12 +362,21 @@ int orc_init(const orc_case *cs, const uint8_t *solid, const double *P,
                 fn[a * q + i] = feq[i] + fne;
             }
         }
+        if (cs->forcing == ORC_SCHEME2) {
+            double Fbar[4];
+            node_source(cs, d, force_field, N, n, Fbar);
+            for (int a = 0; a <= d; ++a)
+                for (int i = 0; i < q; ++i) fn[a * q + i] -= 0.5 * L.w[i] * Fbar[a];
+        }
     }
     return 0;
 }
 
 /* Collision at every fluid node (right-hand side of eq. 3-21):
- *   fpost_{i,a} = f_{i,a} - sum_k L_{ik} (f_{k,a} - f^eq_{k,a}) + w_i Fbar_a.
+ *   fpost_{i,a} = f_{i,a} - sum_k L_{ik} (f_{k,a} - f^eq_{k,a}) + w_i Fbar_a,
+ * or under Scheme II (right-hand side of eq. 2-3c, f standing for fbar):
+ *   fpost_{i,a} = f_{i,a} - sum_k L_{ik} (f_{k,a} - f^eq_{k,a})
+ *                 + sum_k (delta_{ik} - L_{ik}/2) w_k Fbar_a.
  * force_field: d*N values (component-major) added to the uniform force, or
  * NULL. */
 int orc_collide(const orc_case *cs, const uint8_t *solid, const double *force_field,
@@ -359,18 +396,25 @@ int orc_collide(const orc_case *cs, const uint8_t *solid, const double *force_fi
             for (int k = 0; k < ns * q; ++k) fo[k] = 0.0;
             continue;
         }
+        double Fbar[4];
+        node_source(cs, d, force_field, N, n, Fbar);
         moments_t m;
-        node_moments(&L, cs, fn, &m);
+        node_moments(&L, cs, fn, Fbar, &m);
         for (int a = 0; a <= d; ++a) {
             double feq[QMAX], fne[QMAX];
             equilibrium(&L, a, m.ubar[a], m.u, m.P, feq);
             for (int i = 0; i < q; ++i) fne[i] = fn[a * q + i] - feq[i];
-            double Fbar = (a == 0) ? cs->R : cs->force[a - 1];
-            if (a >= 1 && force_field) Fbar += force_field[(a - 1) * N + n];
             for (int i = 0; i < q; ++i) {
                 double coll = 0.0;
                 for (int k = 0; k < q; ++k) coll += Lam[i][k] * fne[k];
-                fo[a * q + i] = fn[a * q + i] - coll + L.w[i] * Fbar;
+                double src = L.w[i] * Fbar[a];
+                if (cs->forcing == ORC_SCHEME2) {
+                    /* (I - L/2) applied to F_{k,a} = w_k Fbar_a */
+                    double lf = 0.0;
+                    for (int k = 0; k < q; ++k) lf += Lam[i][k] * L.w[k] * Fbar[a];
+                    src -= 0.5 * lf;
+                }
+                fo[a * q + i] = fn[a * q + i] - coll + src;
             }
         }
     }
@@ -468,8 +512,11 @@ int orc_num_fields(int lattice)
  *   sigma: same order            eq. 3-17a
  *   vorticity: omega (2D) or (omega_x, omega_y, omega_z) (3D), from the
  *   antisymmetric tensor Omega (eq. 3-18) through eq. 3-19.
+ * Under Scheme II, f holds fbar; the non-equilibrium part is taken of the
+ * unshifted f = fbar + F/2 (force_field as in orc_collide).
  * Solid nodes get zeros. */
-int orc_fields(const orc_case *cs, const uint8_t *solid, const double *f, double *out)
+int orc_fields(const orc_case *cs, const uint8_t *solid, const double *force_field,
+               const double *f, double *out)
 {
     lattice_t L;
     if (check_case(cs, &L) != 0) return -1;
@@ -483,8 +530,10 @@ int orc_fields(const orc_case *cs, const uint8_t *solid, const double *f, double
             continue;
         }
         const double *fn = f + n * ns * q;
+        double Fbar[4];
+        node_source(cs, d, force_field, N, n, Fbar);
         moments_t m;
-        node_moments(&L, cs, fn, &m);
+        node_moments(&L, cs, fn, Fbar, &m);
         /* first moment of the non-equilibrium part, mne[a][b] =
          * sum_i c_{i,b} f^ne_{i,a}, a = 1..d */
         double mne[4][3];
@@ -493,7 +542,11 @@ int orc_fields(const orc_case *cs, const uint8_t *solid, const double *f, double
             equilibrium(&L, a, m.ubar[a], m.u, m.P, feq);
             for (int b = 0; b < d; ++b) {
                 double acc = 0.0;
-                for (int i = 0; i < q; ++i) acc += L.c[i][b] * (fn[a * q + i] - feq[i]);
+                for (int i = 0; i < q; ++i) {
+                    double fi = fn[a * q + i];
+                    if (cs->forcing == ORC_SCHEME2) fi += 0.5 * L.w[i] * Fbar[a];
+                    acc += L.c[i][b] * (fi - feq[i]);
+                }
                 mne[a][b] = acc;
             }
         }
@@ -573,8 +626,10 @@ int orc_run(const orc_case *cs, const uint8_t *solid, const double *force_field,
 
 /* Global sums over fluid nodes of pre-collision f(., t):
  *   out[a] = sum_x ubar_a for a = 0..d,
- *   out[d+1] = sum_x sum_{a>=1} J_{a,a}. */
-int orc_invariants(const orc_case *cs, const uint8_t *solid, const double *f, double *out)
+ *   out[d+1] = sum_x sum_{a>=1} J_{a,a}.
+ * force_field as in orc_collide (it enters ubar under Scheme II). */
+int orc_invariants(const orc_case *cs, const uint8_t *solid, const double *force_field,
+                   const double *f, double *out)
 {
     lattice_t L;
     if (check_case(cs, &L) != 0) return -1;
@@ -583,8 +638,10 @@ int orc_invariants(const orc_case *cs, const uint8_t *solid, const double *f, do
     for (int k = 0; k < d + 2; ++k) out[k] = 0.0;
     for (long n = 0; n < N; ++n) {
         if (solid && solid[n]) continue;
+        double Fbar[4];
+        node_source(cs, d, force_field, N, n, Fbar);
         moments_t m;
-        node_moments(&L, cs, f + n * ns * q, &m);
+        node_moments(&L, cs, f + n * ns * q, Fbar, &m);
         for (int a = 0; a <= d; ++a) out[a] += m.ubar[a];
         for (int a = 1; a <= d; ++a) out[d + 1] += m.J[a][a - 1];
     }

@@ -20,6 +20,8 @@ D2Q5 = 0
 D3Q7 = 1
 PERIODIC = 0
 WALL = 1
+PLAIN = 0        # forcing of eq. 3-21
+SCHEME2 = 1      # forcing of Scheme II, eq. 2-3c / 2-7a
 
 _LIB = None
 
@@ -38,6 +40,7 @@ class OrcCase(ctypes.Structure):
         ("force", ctypes.c_double * 3),
         ("R", ctypes.c_double),
         ("rho0", ctypes.c_double),
+        ("forcing", ctypes.c_int32),
     ]
 
 
@@ -54,14 +57,14 @@ def lib():
                                        ctypes.POINTER(ctypes.c_int), dp, dp, dp]
         L.orc_collision_matrix.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double, dp]
-        L.orc_init.argtypes = [cp, u8p, dp, dp, dp, dp]
+        L.orc_init.argtypes = [cp, u8p, dp, dp, dp, dp, dp]
         L.orc_collide.argtypes = [cp, u8p, dp, dp, dp]
         L.orc_stream.argtypes = [cp, u8p, dp, dp]
-        L.orc_fields.argtypes = [cp, u8p, dp, dp]
+        L.orc_fields.argtypes = [cp, u8p, dp, dp, dp]
         L.orc_num_fields.argtypes = [ctypes.c_int]
         L.orc_step.argtypes = [cp, u8p, dp, dp, dp]
         L.orc_run.argtypes = [cp, u8p, dp, dp, dp, ctypes.c_long]
-        L.orc_invariants.argtypes = [cp, u8p, dp, dp]
+        L.orc_invariants.argtypes = [cp, u8p, dp, dp, dp]
         for name in ("orc_lattice_info", "orc_collision_matrix", "orc_init", "orc_collide",
                      "orc_stream", "orc_fields", "orc_num_fields", "orc_step", "orc_run",
                      "orc_invariants"):
@@ -119,7 +122,7 @@ class Case:
     """One simulation case for the oracle (lattice units)."""
 
     def __init__(self, lattice, shape, s1, s0=1.0, s2=0.0, bc=None, wall_u=None, force=None,
-                 R=0.0, rho0=1.0):
+                 R=0.0, rho0=1.0, forcing=0):
         self.lattice = lattice
         self.d = 2 if lattice == D2Q5 else 3
         self.q = 5 if lattice == D2Q5 else 7
@@ -139,6 +142,7 @@ class Case:
             self.force[: len(force)] = force
         self.R = float(R)
         self.rho0 = float(rho0)
+        self.forcing = int(forcing)      # PLAIN: eq. 3-21; SCHEME2: eq. 2-3c / 2-7a
 
     @property
     def fshape(self):
@@ -157,6 +161,7 @@ class Case:
             s.force[b] = float(self.force[b])
         s.R = self.R
         s.rho0 = self.rho0
+        s.forcing = self.forcing
         return s
 
 
@@ -184,7 +189,7 @@ class Oracle:
         g = None
         if grad is not None:
             g = np.ascontiguousarray(np.asarray(grad, float).reshape(c.d * c.d, -1))
-        _ok(lib().orc_init(ctypes.byref(self._cs), _u8(self.solid), _dp(P), _dp(u), _dp(g),
+        _ok(lib().orc_init(ctypes.byref(self._cs), _u8(self.solid), _dp(self.force_field), _dp(P), _dp(u), _dp(g),
                            _dp(self.f)), "init")
         self.t = 0
         return self
@@ -222,7 +227,7 @@ class Oracle:
         c = self.case
         nch = lib().orc_num_fields(c.lattice)
         out = np.zeros(nch * c.N)
-        _ok(lib().orc_fields(ctypes.byref(self._cs), _u8(self.solid), _dp(self.f), _dp(out)),
+        _ok(lib().orc_fields(ctypes.byref(self._cs), _u8(self.solid), _dp(self.force_field), _dp(self.f), _dp(out)),
             "fields")
         out = out.reshape((nch,) + c.fshape)
         d = c.d
@@ -247,7 +252,7 @@ class Oracle:
     def invariants(self):
         c = self.case
         out = np.zeros(c.d + 2)
-        _ok(lib().orc_invariants(ctypes.byref(self._cs), _u8(self.solid), _dp(self.f), _dp(out)),
+        _ok(lib().orc_invariants(ctypes.byref(self._cs), _u8(self.solid), _dp(self.force_field), _dp(self.f), _dp(out)),
             "invariants")
         return out
 

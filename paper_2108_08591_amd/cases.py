@@ -26,6 +26,10 @@ CS2 = {D2Q5: 1.0 / 3.0, D3Q7: 1.0 / 4.0}
 PERIODIC = 0
 WALL = 1
 
+# forcing schemes (same numbering as the C ABI)
+PLAIN = 0        # eq. 3-21: F_i = w_i Fbar added once, ubar = sum_i f
+SCHEME2 = 1      # Scheme II, eq. 2-3c / 2-7a
+
 
 def s1_for_nu(nu: float, lattice: int = D2Q5) -> float:
     """Relaxation rate giving kinematic viscosity nu (eq. 3-13a solved for s1)."""
@@ -46,6 +50,7 @@ class CaseSpec:
     R: float = 0.0
     rho0: float = 1.0
     name: str = ""
+    forcing: int = PLAIN
 
     @property
     def d(self) -> int:

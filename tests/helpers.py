@@ -7,7 +7,8 @@ from oracle import oracle as O
 
 def oracle_for(spec, solid=None, force_field=None):
     case = O.Case(spec.lattice, spec.shape, spec.s1, s0=spec.s0, s2=spec.s2, bc=spec.bc,
-                  wall_u=spec.wall_velocity(), force=spec.force, R=spec.R, rho0=spec.rho0)
+                  wall_u=spec.wall_velocity(), force=spec.force, R=spec.R, rho0=spec.rho0,
+                  forcing=spec.forcing)
     return O.Oracle(case, solid=solid, force_field=force_field)
 
 

@@ -22,7 +22,8 @@ GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper
 
 def _oracle(spec, solid=None, force_field=None):
     case = O.Case(spec.lattice, spec.shape, spec.s1, s0=spec.s0, s2=spec.s2, bc=spec.bc,
-                  wall_u=spec.wall_velocity(), force=spec.force, R=spec.R, rho0=spec.rho0)
+                  wall_u=spec.wall_velocity(), force=spec.force, R=spec.R, rho0=spec.rho0,
+                  forcing=spec.forcing)
     return O.Oracle(case, solid=solid, force_field=force_field)
 
 
@@ -144,19 +145,24 @@ def test_equilibrium_moments(lat):
                 assert np.allclose(m2, (ubar * cs2 if b == g else 0.0), atol=1e-15)
 
 
+@pytest.mark.parametrize("forcing", [C.PLAIN, C.SCHEME2])
 @pytest.mark.parametrize("lat", [O.D2Q5, O.D3Q7])
-def test_init_gradient_round_trip(lat):
+def test_init_gradient_round_trip(lat, forcing):
     """Initial state with a velocity gradient (inverse of eq. 3-16): the
     gradient evaluated by eq. 3-16 returns the input exactly (to rounding),
-    and u and P are unchanged for a divergence-free input."""
-    spec = C.CaseSpec(lat, (6, 5) if lat == O.D2Q5 else (4, 3, 5), 1.37)
+    and u and P are unchanged for a divergence-free input.  Under Scheme II
+    (with a force, a per-node force field and a source) eq. 2-7a must give
+    back the same u from the shifted populations."""
+    spec = C.CaseSpec(lat, (6, 5) if lat == O.D2Q5 else (4, 3, 5), 1.37, forcing=forcing,
+                      force=(2e-3, -1e-3, 5e-4))
     rng = np.random.default_rng(11)
     d = spec.d
     u = rng.uniform(-0.05, 0.05, (d,) + spec.fshape)
     P = rng.uniform(-0.01, 0.01, spec.fshape)
     g = rng.uniform(-0.01, 0.01, (d, d) + spec.fshape)
     g[d - 1, d - 1] = -sum(g[b, b] for b in range(d - 1))      # trace-free
-    o = _oracle(spec).init(P, u, grad=g)
+    FF = rng.uniform(-3e-3, 3e-3, (d,) + spec.fshape)
+    o = _oracle(spec, force_field=FF).init(P, u, grad=g)
     fl = o.fields()
     assert np.allclose(fl["grad"], g, atol=1e-15)
     assert np.allclose(fl["u"], u, atol=1e-16)
@@ -185,12 +191,15 @@ def test_collision_zeroth_moment_and_trace(lat):
     assert np.allclose(trJs, trJ + cs2 * spec.R, atol=1e-15)
 
 
+@pytest.mark.parametrize("forcing", [C.PLAIN, C.SCHEME2])
 @pytest.mark.parametrize("lat", [O.D2Q5, O.D3Q7])
 @pytest.mark.parametrize("R", [0.0, 3e-3])
-def test_divergence_equals_source(lat, R):
+def test_divergence_equals_source(lat, R, forcing):
     """eq. 3-16a combined with the pressure of eq. 3-15 returns div u = R
-    identically, for any populations."""
-    spec = C.CaseSpec(lat, (5, 3) if lat == O.D2Q5 else (3, 3, 2), 1.4, R=R)
+    identically, for any populations (under Scheme II with fbar in eq. 3-15
+    and a force present)."""
+    spec = C.CaseSpec(lat, (5, 3) if lat == O.D2Q5 else (3, 3, 2), 1.4, R=R, forcing=forcing,
+                      force=(4e-3, 1e-3, -2e-3))
     f = C.random_populations(spec, seed=9, scale=0.1)
     fl = _oracle(spec).set_populations(f).fields()
     assert np.allclose(fl["div"], R, atol=1e-14)
@@ -362,6 +371,99 @@ def test_four_roll_mill_table_1(k):
     }
     for key, val in got.items():
         assert abs(val / g[key][k] - 1) < 1e-4, (key, val, g[key][k])
+
+
+# ------------------------------------------------------------------ Scheme II forcing
+
+@pytest.mark.parametrize("lat", [O.D2Q5, O.D3Q7])
+def test_scheme2_collision_moments(lat):
+    """eq. 2-3c at every node, for arbitrary populations fbar, a per-node
+    force field and a source: the zeroth moment gains exactly Fbar_a
+    (sum_i (delta_ik - L_ik/2) w_k Fbar = (1 - s0/2) Fbar, plus s0 Fbar/2 from
+    sum_i (fbar - f^eq) = -Fbar/2 by eq. 2-7a), and the first moments relax as
+    J* = (1 - s1) J + s1 J^eq with J^eq_{ab} = ubar_a u_b + P delta (first
+    moment of eq. 2-4, the forcing term having none), ubar from eq. 2-7a and
+    P from eq. 3-15 with fbar."""
+    spec = C.CaseSpec(lat, (4, 3) if lat == O.D2Q5 else (3, 2, 2), 1.23, s0=0.8,
+                      force=(1e-3, -2e-3, 3e-3), R=2e-3, forcing=C.SCHEME2)
+    d = spec.d
+    f = C.random_populations(spec, seed=5, scale=0.1)
+    FF = np.random.default_rng(3).uniform(-5e-3, 5e-3, (d,) + spec.fshape)
+    fs = _oracle(spec, force_field=FF).set_populations(f).collide()
+    info = O.lattice_info(lat)
+    c, cs2 = info["c"].astype(float), info["cs2"]
+    Fbar = [spec.R] + [spec.force[a - 1] + FF[a - 1] for a in range(1, d + 1)]
+    ubar = [f[a].sum(0) + 0.5 * Fbar[a] for a in range(d + 1)]
+    J = [[np.tensordot(c[:, b], f[a], axes=(0, 0)) for b in range(d)] for a in range(d + 1)]
+    trJ = sum(J[a][a - 1] for a in range(1, d + 1))
+    u2 = sum(ubar[b] ** 2 for b in range(1, d + 1))
+    P = (trJ + cs2 * spec.R / spec.s1 - u2) / d
+    for a in range(d + 1):
+        assert np.allclose(fs[a].sum(0), f[a].sum(0) + Fbar[a], atol=1e-15)
+        for b in range(d):
+            Jeq = ubar[a] * ubar[b + 1] + (P if a == b + 1 else 0.0)
+            Js = np.tensordot(c[:, b], fs[a], axes=(0, 0))
+            assert np.allclose(Js, (1 - spec.s1) * J[a][b] + spec.s1 * Jeq, atol=1e-15)
+
+
+def test_scheme2_without_force_is_the_plain_update():
+    """With Fbar = 0 (no force, no source) eq. 2-3c is eq. 3-21."""
+    spec = C.CaseSpec(C.D2Q5, (5, 4), 1.1, s0=0.9)
+    f = C.random_populations(spec, seed=2, scale=0.1)
+    plain = _oracle(spec).set_populations(f).collide()
+    spec.forcing = C.SCHEME2
+    assert np.array_equal(_oracle(spec).set_populations(f).collide(), plain)
+
+
+@pytest.mark.parametrize("s1", [0.7, 1.2, 1.7])
+def test_scheme2_poiseuille_exact(s1):
+    """Section 4.1 geometry (32 x 32, walls at y = 0 and y = 32, the printed
+    force and viscosity scaling) with Scheme II: the steady profile is the
+    parabola u1 = F/(2 nu) y (H - y) to the rounding floor for every s1 with
+    the section's s2 = 8(2 - s1)/(8 - s1).  Under eq. 3-21 the same runs sit
+    a uniform Fbar/2 below it (the source of the printed E_L2(u1) =
+    5.9427e-4 at s1 = 1.2)."""
+    H = 32
+    base = C.poiseuille_paper_case()
+    nu = (1 / s1 - 0.5) / 3
+    F = base.force[0] * nu / ((1 / base.s1 - 0.5) / 3)      # same peak velocity
+    y = (np.arange(H) + 0.5)[:, None] * np.ones((1, base.shape[0]))
+    ex = A.poiseuille(F, nu, H, y)
+    us = {}
+    for forcing in (C.PLAIN, C.SCHEME2):
+        spec = C.CaseSpec(C.D2Q5, base.shape, s1, bc=base.bc, force=(F, 0.0), forcing=forcing)
+        o = _oracle(spec).init(0.0, np.zeros((2,) + spec.fshape))
+        assert _run_to_steady(o, 2000, 1e-15, 200000)
+        us[forcing] = o.fields()["u"][0]
+    assert A.rel_l2(ex["u1"], us[C.SCHEME2]) < 1e-10
+    off = us[C.PLAIN] - ex["u1"]
+    assert np.allclose(off, -F / 2, rtol=1e-6, atol=0)
+
+
+def test_scheme2_four_roll_mill_removes_force_offset():
+    """Section 4.2, Table 1 under Scheme II.  The viscous part of the
+    four-roll force, lattice size nu_lat (k dx)^2 relative to u, is what a
+    Fbar/2 velocity offset contributes to E(u1) under eq. 3-21; Scheme II
+    has no such offset, so its E(u1) must equal the printed E(u1) minus
+    nu_lat (k dx)^2 for every s1 (to the table's 5 digits), and its S and
+    vorticity errors must not depend on s1."""
+    g = GOLDEN["four_roll_mill_table_1"]
+    kdx = 2 * math.pi / 64
+    e_u, e_s = [], []
+    for k, s1 in enumerate(g["s1"]):
+        spec, FF, dt, dx = C.four_roll_mill(64, s1)
+        spec.forcing = C.SCHEME2
+        o = _oracle(spec, force_field=FF).init(0.0, np.zeros((2,) + spec.fshape))
+        assert _run_to_steady(o, 2000, 1e-12, 100000)
+        fl = o.fields()
+        ex = A.four_roll_mill(64, 1e-4)
+        e1 = A.rel_l2(ex["u1"] * dt / dx, fl["u"][0])
+        nu_lat = (1 / s1 - 0.5) / 3
+        assert abs(e1 / (g["E_u1"][k] - nu_lat * kdx ** 2) - 1) < 1e-4, (s1, e1)
+        e_u.append(e1)
+        e_s.append(A.rel_l2(ex["Sxx"] * dt, fl["S"][0]))
+    assert max(e_u) / min(e_u) - 1 < 1e-5
+    assert max(e_s) / min(e_s) - 1 < 1e-5
 
 
 @pytest.mark.parametrize("lat", [O.D2Q5, O.D3Q7])
