@@ -208,6 +208,53 @@ def time_launches(solver, stream, n, fields=0, out=None, reps=3):
     return min(res)
 
 
+def variants_study(out_path):
+    """Cost of each variant of the update against the plain one on the same
+    grid, storage and default launch shape (two steps per launch in 2D),
+    stepping without field emission: the d velocity sets only (Remark IV),
+    Scheme II forcing (eq. 2-3c), and a per-node force field (d more reads
+    per node and step).  Algorithmic bytes per step: one read and one write
+    of every stored population, plus the force field when one is set."""
+    import torch
+    from paper_2108_08591_amd import cases as C
+    from paper_2108_08591_amd import mdf
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    sb = {"f64": 8, "f32": 4, "f16dev": 2, "bf16dev": 2}
+    cb = {"f64": 8, "f32": 4, "f16dev": 4, "bf16dev": 4}       # compute dtype of the force field
+    runs = [("d2q5", 1024, "f32"), ("d2q5", 8192, "f32"), ("d2q5", 8192, "f16dev"), ("d2q5", 8192, "f64"),
+            ("d3q7", 256, "f32"), ("d3q7", 256, "f16dev"), ("d3q7", 256, "f64")]
+    variants = [("all", C.PLAIN, False), ("velocity", C.PLAIN, False), ("all", C.SCHEME2, False),
+                ("all", C.PLAIN, True), ("velocity", C.SCHEME2, True)]
+    with open(out_path, "w") as fh:
+        for lat, N, st in runs:
+            spec = C.cavity_case(N=N, Re=1000.0) if lat == "d2q5" else C.tgv3d_case(N=N, u0=0.05, Re=100.0)
+            q = 5 if lat == "d2q5" else 7
+            base = None
+            for sets, forcing, field in variants:
+                spec.forcing = forcing
+                solver = mdf.Solver([spec], storage=st, device=dev, stream=stream, u_ref=0.1, sets=sets)
+                if field:
+                    ff = torch.full((spec.d,) + spec.fshape, 1e-7, dtype=solver.dtype, device=dev)
+                    solver.set_force_field(ff)
+                solver.step(3)
+                ms = time_launches(solver, stream, 41)
+                step_bytes = spec.nodes * (2 * q * solver.nsets * sb[st] + (spec.d * cb[st] if field else 0))
+                rec = {"lattice": lat, "N": N, "storage": st, "sets": sets,
+                       "forcing": "scheme2" if forcing == C.SCHEME2 else "plain", "force_field": field,
+                       "ms_per_step": round(ms, 5), "MLUPS": round(spec.nodes / ms / 1e3, 1),
+                       "step_bytes_MB": round(step_bytes / 1e6, 1),
+                       "GBps_per_step": round(step_bytes / ms / 1e6, 1)}
+                if base is None:
+                    base = ms
+                else:
+                    rec["speedup_vs_plain_all_sets"] = round(base / ms, 3)
+                print(json.dumps(rec), file=fh, flush=True)
+                print(json.dumps(rec), flush=True)
+                del solver
+                torch.cuda.empty_cache()
+
+
 def sweep(out_path):
     """Step-kernel timing over grid sizes (incl. working sets far beyond the
     256 MB Infinity Cache), storages, lattices and launch shapes."""
@@ -688,6 +735,8 @@ def main():
                     help="distribution sets stored: all d+1 (the configuration) or the d velocity sets (Remark IV)")
     ap.add_argument("--launch", default="128x2g8t",
                     help="threads per block, XCD groups and kernel form, BXxBYgG[s|v|t] (s: one node/thread, v: vector, t: two steps per launch)")
+    ap.add_argument("--variants-study", metavar="OUT_JSONL",
+                    help="velocity sets / Scheme II / force field against the plain update")
     ap.add_argument("--sweep", metavar="OUT_JSONL",
                     help="time the step kernel over grid sizes, storages and launch shapes")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -718,6 +767,9 @@ def main():
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.variants_study:
+        variants_study(args.variants_study)
         return
     if args.sweep:
         sweep(args.sweep)

@@ -108,6 +108,19 @@ typedef enum {
 /* One case (lattice units).  Velocity directions are ordered
  *   D2Q5: 0, +x, +y, -x, -y          (eq. d2q5)
  *   D3Q7: 0, +x, -x, +y, -y, +z, -z  (eq. d3q7)                        */
+/* Forcing scheme of a case.
+ *   MDF_FORCING_PLAIN: the diffusive-scaling update of Remark I (eq. 3-21),
+ *     F_{i,a} = w_i Fbar_a added once, ubar_a = sum_i f_{i,a} (eq. 2-7).
+ *     Used for all of the paper's numerics.  (Scheme I, eq. 2-3b, is the
+ *     same update for forces that do not change in time.)
+ *   MDF_FORCING_SCHEME2: Scheme II (eq. 2-3c): the stored populations are
+ *     fbar = f - F/2, updated with (I - L/2) F, and ubar_a = sum_i fbar_{i,a}
+ *     + Fbar_a / 2 (eq. 2-7a); P by eq. 3-15 with fbar in place of f.  The
+ *     velocity gradient (eq. 3-16) is unchanged: F_{i,a} has no first moment.
+ *     Initial states from fields are shifted by -F/2 so that eq. 2-7a gives
+ *     back the given velocity. */
+typedef enum { MDF_FORCING_PLAIN = 0, MDF_FORCING_SCHEME2 = 1 } mdf_forcing;
+
 typedef struct {
     int32_t nx, ny, nz;     /* nodes per axis; nz = 1 for D2Q5             */
     double s0, s1, s2;      /* S_d = diag(s0, s1.., s2..) (eq. 4-3); 0 < s1 < 2;
@@ -120,6 +133,7 @@ typedef struct {
     double R;               /* uniform mass source R (eq. 2-1a); Fbar_0 = R */
     double rho0;            /* constant density (eq. 2-2, eq. 3-17a); > 0  */
     double u_ref;           /* 16-bit storage scale; <= 0 selects 1        */
+    int32_t forcing;        /* mdf_forcing: how F and R enter the update    */
 } mdf_case;
 
 typedef struct mdf_ctx mdf_ctx;

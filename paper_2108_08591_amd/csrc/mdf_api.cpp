@@ -81,6 +81,10 @@ bool validate_case(int lattice, const mdf_case &c, std::string &why)
     const double s2 = c.s2 > 0.0 ? c.s2 : 8.0 * (2.0 - c.s1) / (8.0 - c.s1);
     if (!(s2 > 0.0 && s2 < 2.0)) { why = "s2 outside (0, 2)"; return false; }
     if (!(c.rho0 > 0.0) || !std::isfinite(c.rho0)) { why = "rho0 must be > 0"; return false; }
+    if (c.forcing != MDF_FORCING_PLAIN && c.forcing != MDF_FORCING_SCHEME2) {
+        why = "forcing must be MDF_FORCING_PLAIN or MDF_FORCING_SCHEME2";
+        return false;
+    }
     for (int f = 0; f < 6; ++f) {
         if (c.bc[f] != MDF_PERIODIC && c.bc[f] != MDF_WALL) { why = "bc must be PERIODIC or WALL"; return false; }
         for (int b = 0; b < 3; ++b)
@@ -231,6 +235,9 @@ KCase make_kcase(int lattice, int storage, const mdf_case &c)
     p.rho0f = float(p.rho0);
     p.Rf = float(p.R);
     for (int a = 0; a < 4; ++a) p.fbarf[a] = float(p.fbar[a]);
+    p.forcing = c.forcing;
+    p.fmove = c.forcing == MDF_FORCING_SCHEME2 ? 1.0 - 0.5 * p.s2 : 1.0;
+    p.fmovef = float(p.fmove);
     for (int f = 0; f < 6; ++f)
         for (int b = 0; b < 3; ++b) p.walluf[f][b] = float(p.wallu[f][b]);
     // rest weights of the lattice (eq. d2q5 / d3q7) times rho0

@@ -38,6 +38,11 @@ struct KCase {
     // optional per-node force, d x nodes values component-major in the
     // compute dtype (caller-owned device memory), added to fbar[1..d]
     const void *ffield;
+    // forcing scheme: 0 = eq. 3-21, 1 = Scheme II (eq. 2-3c, 2-7a); fmove is
+    // the factor of w_i Fbar on the moving populations (1, or 1 - s2/2)
+    int forcing;
+    double fmove;
+    float fmovef;
 };
 
 // Device pointers of one case inside the workspace.

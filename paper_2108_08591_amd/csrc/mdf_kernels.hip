@@ -269,6 +269,7 @@ struct Moments {
     C u[L::D];
     C P;                    // eq. 3-15
     C trJ;                  // sum_{a>=1} J_{a,a}
+    C fb[L::D + 1];         // Fbar_a at the node: uniform part + force field
 };
 
 // Pull the populations of node (x, y, z) at time t+1 out of the
@@ -430,15 +431,30 @@ __device__ __forceinline__ void gather_vec(const KCase &p, const typename Store<
     }
 }
 
-// eq. 2-7 and eq. 3-15.
-template <class L, class C>
-__device__ __forceinline__ void moments(const KCase &p, const Node<L, C> &n, Moments<L, C> &m)
+// Source Fbar_a of set a at a node (eq. 2-2, eq. 2-6): Fbar_0 = R, Fbar_a =
+// the uniform force plus the per-node force field when one is set.
+template <class C>
+__device__ __forceinline__ C source_of(const KCase &p, int pa, long long node)
 {
+    C fb = kpar<C>(p.fbar[pa], p.fbarf[pa]);
+    if (pa >= 1 && p.ffield)
+        fb += static_cast<const C *>(p.ffield)[(long long)(pa - 1) * ((long long)p.nx * p.ny * p.nz) + node];
+    return fb;
+}
+
+// eq. 2-7 (Scheme II: eq. 2-7a) and eq. 3-15, and the source of every set.
+template <class L, class C>
+__device__ __forceinline__ void moments(const KCase &p, const Node<L, C> &n, Moments<L, C> &m, long long node)
+{
+#pragma unroll
+    for (int pa = 0; pa <= L::D; ++pa) m.fb[pa] = source_of<C>(p, pa, node);
 #pragma unroll
     for (int a = 0; a < L::NS; ++a) {
         C s = n.f[a][0];
 #pragma unroll
         for (int i = 1; i < L::Q; ++i) s += n.f[a][i];
+        // Scheme II stores fbar = f - F/2: half the source is added back
+        if (p.forcing == MDF_FORCING_SCHEME2) s += C(0.5) * m.fb[a + L::A0];
         m.ubar[a + L::A0] = s;
     }
     if (L::A0 == 1) m.ubar[0] = kpar<C>(p.rho0, p.rho0f);
@@ -503,7 +519,8 @@ __device__ __forceinline__ void nonequilibrium(const Node<L, C> &n, const Moment
     for (int i = 0; i < L::Q; ++i) ne[i] = n.f[a][i] - feq[i];
 }
 
-// Post-collision populations of one set (right-hand side of eq. 3-21).
+// Post-collision populations of one set (right-hand side of eq. 3-21, or of
+// eq. 2-3c under Scheme II).
 // The s0 part of L n multiplies sum_i n_i, which vanishes identically
 // (eq. 3-8); the moving populations take s1 on the odd and s2 on the even part
 // of n.  Each population is advanced by a small increment d_i computed first,
@@ -513,17 +530,17 @@ __device__ __forceinline__ void nonequilibrium(const Node<L, C> &n, const Moment
 // stored value is rounded once, and the zeroth moment is conserved up to
 // unbiased rounding (forming s0 sum_i n_i, or subtracting large partial sums,
 // rounds the same way every step and drifts by ~1e-5 in a few thousand).
+// Scheme II: with n = fbar - f^eq (ubar from eq. 2-7a), the update is
+// fbar + F - L (n + F/2), and sum_i (n + F/2)_i = 0, so the same projection
+// applies; F/2 is even, which turns the force on the moving populations
+// into (1 - s2/2) w_i Fbar while sum_i fbar*_i = ubar - Fbar/2 + Fbar still
+// fixes the rest population.
 template <class L, class C>
 __device__ __forceinline__ void collide_set(const KCase &p, const Node<L, C> &n, int a,
-                                            const C (&ne)[L::Q], C (&out)[L::Q], long long node)
+                                            const C (&ne)[L::Q], C (&out)[L::Q], C fb)
 {
     const C s1 = kpar<C>(p.s1, p.s1f), s2 = kpar<C>(p.s2, p.s2f);
-    const int pa = a + L::A0;
-    C fb = kpar<C>(p.fbar[pa], p.fbarf[pa]);
-    // a per-node force field (eq. 2-6 with F = F(x)) adds to the uniform force
-    if (pa >= 1 && p.ffield)
-        fb += static_cast<const C *>(p.ffield)[(long long)(pa - 1) * ((long long)p.nx * p.ny * p.nz) + node];
-    const C wf = C(L::w1) * fb;
+    const C wf = C(L::w1) * fb * kpar<C>(p.fmove, p.fmovef);
     C dsum = C(0);
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
@@ -695,14 +712,14 @@ __device__ __forceinline__ void step_tile(const KCase &p, int gx, int gy, int ti
     const long long nodes = (long long)p.nx * p.ny * p.nz;
     const long long node = ((long long)z * p.ny + y) * p.nx + x;
     if (fluid) {
-        moments<L, C>(p, n, m);
+        moments<L, C>(p, n, m, node);
         if (EMIT) write_fields<L, C>(p, n, m, fields, out, node, nodes);
         const long long own = ((long long)z * p.ny + y) * p.pitch + x;
 #pragma unroll
         for (int a = 0; a < L::NS; ++a) {
             C ne[L::Q], fo[L::Q];
             nonequilibrium<L, C>(n, m, a, ne);
-            collide_set<L, C>(p, n, a, ne, fo, node);
+            collide_set<L, C>(p, n, a, ne, fo, m.fb[a + L::A0]);
 #pragma unroll
             for (int i = 0; i < L::Q; ++i)
                 S::store(dst + (long long)(a * L::Q + i) * p.dstride, own, fo[i], rest_value<L, C>(p, a, i),
@@ -766,7 +783,7 @@ __device__ __forceinline__ void step_tile_vec(const KCase &p, int gx, int gy, in
         const long long node = ((long long)z * p.ny + y) * p.nx + x0 + v;
         const bool inside = rowok && (x0 + v < p.nx);
         if (fluid[v]) {
-            moments<L, C>(p, n[v], m[v]);
+            moments<L, C>(p, n[v], m[v], node);
             if (EMIT) write_fields<L, C>(p, n[v], m[v], fields, out, node, nodes);
         } else if (EMIT && inside) {
             int nch = 0;
@@ -793,7 +810,7 @@ __device__ __forceinline__ void step_tile_vec(const KCase &p, int gx, int gy, in
             if (!fluid[v]) continue;
             C ne[L::Q], fo[L::Q];
             nonequilibrium<L, C>(n[v], m[v], a, ne);
-            collide_set<L, C>(p, n[v], a, ne, fo, ((long long)z * p.ny + y) * p.nx + x0 + v);
+            collide_set<L, C>(p, n[v], a, ne, fo, m[v].fb[a + L::A0]);
 #pragma unroll
             for (int i = 0; i < L::Q; ++i) n[v].f[a][i] = fo[i];
         }
@@ -916,13 +933,13 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int tile, con
             if (!fluid[g]) continue;
             const int e = tid + (k0 + g) * NT;
             Moments<L, C> m;
-            moments<L, C>(p, n[g], m);
+            moments<L, C>(p, n[g], m, node[g]);
             if (EMIT && interior[g]) write_fields<L, C>(p, n[g], m, fields, out, node[g], nodes);
 #pragma unroll
             for (int a = 0; a < L::NS; ++a) {
                 C ne[L::Q], fo[L::Q];
                 nonequilibrium<L, C>(n[g], m, a, ne);
-                collide_set<L, C>(p, n[g], a, ne, fo, node[g]);
+                collide_set<L, C>(p, n[g], a, ne, fo, m.fb[a + L::A0]);
 #pragma unroll
                 for (int i = 0; i < L::Q; ++i)
                     lds[(a * L::Q + i) * NE + e] = S::encode(fo[i], rest_value<L, C>(p, a, i), p.inv_scale);
@@ -990,13 +1007,13 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int tile, con
             }
         }
         Moments<L, C> m;
-        moments<L, C>(p, n, m);
+        moments<L, C>(p, n, m, node);
         if (EMIT) write_fields<L, C>(p, n, m, fields, out, node, nodes);
 #pragma unroll
         for (int a = 0; a < L::NS; ++a) {
             C ne[L::Q], fo[L::Q];
             nonequilibrium<L, C>(n, m, a, ne);
-            collide_set<L, C>(p, n, a, ne, fo, node);
+            collide_set<L, C>(p, n, a, ne, fo, m.fb[a + L::A0]);
 #pragma unroll
             for (int i = 0; i < L::Q; ++i)
                 S::store(dst + (long long)(a * L::Q + i) * p.dstride, own, fo[i], rest_value<L, C>(p, a, i),
@@ -1135,7 +1152,7 @@ k_read(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, const 
     if (inside) fluid = gather<L, ST, MASK, PULL>(p, src, links, x, y, z, n);
     const long long nodes = (long long)p.nx * p.ny * p.nz;
     const long long node = ((long long)z * p.ny + y) * p.nx + x;
-    if (fluid) moments<L, C>(p, n, m);
+    if (fluid) moments<L, C>(p, n, m, node);
     if (MODE == kReadFields && inside) {
         if (fluid) {
             write_fields<L, C>(p, n, m, fields, out, node, nodes);
@@ -1229,15 +1246,28 @@ k_init(KCase p, typename Store<ST>::T *__restrict__ pre, typename Store<ST>::T *
                 // f^eq (eq. 2-4) + f^ne with f^ne = -(1/s1) w_i c_i . grad u_a
                 n.f[a][i] = feq[i] - (C(1) / C(p.s1)) * C(L::w1) * cg;
             }
+            if (p.forcing == MDF_FORCING_SCHEME2) {
+                // stored state fbar = f - w_i Fbar_a / 2, so that eq. 2-7a
+                // gives back the initial ubar_a
+                const C hf = C(0.5) * source_of<C>(p, pa, node);
+                const C whf = C(L::w1) * hf;
+                C moved = C(0);
+#pragma unroll
+                for (int i = 1; i < L::Q; ++i) {
+                    n.f[a][i] -= whf;
+                    moved += whf;
+                }
+                n.f[a][0] -= hf - moved;
+            }
         }
     }
     Moments<L, C> m;
-    moments<L, C>(p, n, m);
+    moments<L, C>(p, n, m, node);
 #pragma unroll
     for (int a = 0; a < L::NS; ++a) {
         C ne[L::Q], fo[L::Q];
         nonequilibrium<L, C>(n, m, a, ne);
-        collide_set<L, C>(p, n, a, ne, fo, node);
+        collide_set<L, C>(p, n, a, ne, fo, m.fb[a + L::A0]);
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
             const long long k = (long long)(a * L::Q + i) * p.dstride + own;

@@ -52,6 +52,7 @@ class MdfCase(ctypes.Structure):
         ("R", ctypes.c_double),
         ("rho0", ctypes.c_double),
         ("u_ref", ctypes.c_double),
+        ("forcing", ctypes.c_int32),
     ]
 
 
@@ -153,6 +154,7 @@ def _case_struct(spec: CaseSpec, u_ref: float = 0.0) -> MdfCase:
     c.R = float(spec.R)
     c.rho0 = float(spec.rho0)
     c.u_ref = float(u_ref)
+    c.forcing = int(spec.forcing)
     return c
 
 

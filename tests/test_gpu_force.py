@@ -1,6 +1,8 @@
-"""Per-node force fields (eq. 2-6 with a space-dependent F) on the HIP path,
-through mdf_set_force_field: parity with the FP64 oracle at fixed step
-counts, and the four-roll mill of Section 4.2 (Table 1) solved on the GPU.
+"""Forces on the HIP path: per-node force fields (eq. 2-6 with a
+space-dependent F) through mdf_set_force_field, and the Scheme II forcing of
+eq. 2-3c / 2-7a.  Parity with the FP64 oracle at fixed step counts, the
+four-roll mill of Section 4.2 (Table 1) solved on the GPU, and the exact
+Poiseuille profile of Scheme II.
 
 A force field set on a context enters every later collision; the state
 already held by the context (the collision done by mdf_init) keeps the force
@@ -160,3 +162,111 @@ def test_four_roll_mill_table_1_on_gpu(k):
     }
     for key, val in got.items():
         assert abs(val / g[key][k] - 1) < 1e-4, (key, val, g[key][k])
+
+
+# ---------------------------------------------------------------- Scheme II
+
+@pytest.mark.parametrize("form", [0, 2])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_scheme2_parity_2d(storage, form):
+    """Scheme II on the walled 2D case with an obstacle, a uniform force, a
+    mass source and a per-node force field."""
+    spec, mask = _walled_2d()
+    spec.forcing = C.SCHEME2
+    spec.R = 1e-4
+    FF = _cast(_force(spec, 12), storage)
+    _say(f"[scheme2] 2d 70x45 {storage} form {form}")
+    s = mdf.Solver([spec], storage=storage, solid=[mask], device=DEV)
+    s.set_launch(64, 4, 8, form)
+    s.set_force_field(FF)
+    s.step(57)
+    o = _oracle_run(spec, mask, FF, 57)
+    assert rel_err(o.populations(), _np(s.populations())) < TOL[storage]
+    compare_fields(o.fields(), gpu_fields_np(s, mdf.FIELD_ALL), TOL[storage])
+    inv = s.invariants()
+    ref = o.invariants()
+    assert np.allclose(inv, ref, rtol=TOL[storage], atol=TOL[storage] * np.abs(ref).max())
+
+
+def test_scheme2_parity_3d():
+    spec = C.CaseSpec(C.D3Q7, (21, 14, 11), 1.1, bc=(C.PERIODIC, C.PERIODIC, C.WALL, C.WALL, C.WALL, C.WALL),
+                      force=(1e-5, 0.0, 2e-5), R=5e-5, forcing=C.SCHEME2)
+    FF = _force(spec, 6)
+    _say("[scheme2] 3d 21x14x11 f64")
+    s = mdf.Solver([spec], storage="f64", device=DEV)
+    s.set_force_field(FF)
+    s.step(33)
+    o = _oracle_run(spec, None, FF, 33)
+    assert rel_err(o.populations(), _np(s.populations())) < 1e-12
+    compare_fields(o.fields(), gpu_fields_np(s, mdf.FIELD_ALL), 1e-12)
+
+
+def test_scheme2_and_plain_cases_in_one_batch():
+    """One batched context holding both forcing schemes; each case matches
+    its own oracle."""
+    specs = [C.CaseSpec(C.D2Q5, (40, 33), 1.2, force=(2e-5, 1e-5), forcing=C.SCHEME2),
+             C.CaseSpec(C.D2Q5, (65, 20), 0.9, bc=(C.PERIODIC, C.PERIODIC, C.WALL, C.WALL, 0, 0),
+                        force=(3e-5, 0.0)),
+             C.CaseSpec(C.D2Q5, (31, 47), 1.5, force=(0.0, -2e-5), R=1e-4, forcing=C.SCHEME2)]
+    _say("[scheme2] batch of 3, f64")
+    s = mdf.Solver(specs, storage="f64", device=DEV)
+    s.step(25)
+    for k, spec in enumerate(specs):
+        o = _oracle_run(spec, None, None, 25)
+        assert rel_err(o.populations(), _np(s.populations(k))) < 1e-12, k
+
+
+def test_scheme2_velocity_sets_equal_full_form():
+    """Scheme II with only the d velocity sets (Remark IV) agrees bit for bit
+    with all d + 1 sets (the source R of the set a = 0 reaches nothing)."""
+    spec, mask = _walled_2d()
+    spec.forcing = C.SCHEME2
+    spec.R = 1e-4
+    _say("[scheme2] velocity sets vs full, f32")
+    full = mdf.Solver([spec], storage="f32", solid=[mask], device=DEV)
+    vel = mdf.Solver([spec], storage="f32", solid=[mask], device=DEV, sets="velocity")
+    FF = _force(spec, 13)
+    for x in (full, vel):
+        x.set_force_field(FF)
+        x.step(41)
+    assert torch.equal(full.populations()[1:], vel.populations())
+    assert torch.equal(full.gradients(mdf.FIELD_ALL)[1:], vel.gradients(mdf.FIELD_ALL)[1:])
+
+
+def test_scheme2_poiseuille_exact_on_gpu():
+    """Section 4.1 geometry under Scheme II on the GPU in FP64: the steady
+    profile is the parabola to the rounding floor (eq. 3-21 leaves Fbar/2)."""
+    spec = C.poiseuille_paper_case()
+    spec.forcing = C.SCHEME2
+    _say("[scheme2] poiseuille 32x32 f64")
+    s = mdf.Solver([spec], storage="f64", device=DEV)
+    st, steps, res = s.run_steady(1e-15, 1000, 200000)
+    assert st[0] == 0, (st, steps, res)
+    got = gpu_fields_np(s, mdf.FIELD_ALL)
+    F, H = spec.force[0], 32
+    nu = (1 / spec.s1 - 0.5) / 3
+    y = (np.arange(H) + 0.5)[:, None] * np.ones((1, 32))
+    ex = A.poiseuille(F, nu, H, y)
+    assert A.rel_l2(ex["u1"], got["u"][0]) < 1e-10
+    assert A.rel_l2(ex["du1dy"], got["grad"][0, 1]) < 1e-12
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_scheme2_four_roll_mill_on_gpu(k):
+    """Table 1 under Scheme II on the GPU in FP64: E(u1) equals the printed
+    E(u1) minus nu_lat (k dx)^2, the part a Fbar/2 offset contributes under
+    eq. 3-21, to the table's 5 digits."""
+    g = _table_1()
+    s1 = g["s1"][k]
+    spec, FF, dt, dx = C.four_roll_mill(64, s1)
+    spec.forcing = C.SCHEME2
+    _say(f"[scheme2] four-roll mill 64^2 s1={s1} f64")
+    s = mdf.Solver([spec], storage="f64", device=DEV)
+    s.set_force_field(FF)
+    st, steps, res = s.run_steady(1e-12, 100, 400000)
+    assert st[0] == 0 and res[0] < 1e-12, (st, steps, res)
+    fl = gpu_fields_np(s, mdf.FIELD_ALL)
+    ex = A.four_roll_mill(64, 1e-4)
+    e1 = A.rel_l2(ex["u1"] * dt / dx, fl["u"][0])
+    nu_lat = (1 / s1 - 0.5) / 3
+    assert abs(e1 / (g["E_u1"][k] - nu_lat * (2 * np.pi / 64) ** 2) - 1) < 1e-4, e1
