@@ -57,6 +57,8 @@
 
 #define ORC_D2Q5 0
 #define ORC_D3Q7 1
+#define ORC_D2Q4 4
+#define ORC_D3Q6 5
 #define ORC_PERIODIC 0
 #define ORC_WALL 1
 #define ORC_PLAIN 0
@@ -64,7 +66,7 @@
 #define QMAX 7
 
 typedef struct {
-    int32_t lattice;        /* ORC_D2Q5 or ORC_D3Q7 */
+    int32_t lattice;        /* ORC_D2Q5, ORC_D3Q7, ORC_D2Q4 or ORC_D3Q6 */
     int32_t nx, ny, nz;     /* nz = 1 in 2D */
     double s0, s1, s2;      /* relaxation rates of S_d (eq. 4-3) */
     int32_t bc[6];          /* faces -x,+x,-y,+y,-z,+z: ORC_PERIODIC / ORC_WALL */
@@ -137,10 +139,67 @@ static void make_d3q7(lattice_t *L)
     L->cs2 = 1.0 / 4.0;
 }
 
+/* D2Q4 (eq. d2q4), no rest population, cs^2 = 1/2.  The paper prints no M
+ * for it; rows: e, c_x, c_y and the remaining even moment c_x^2 - c_y^2,
+ * with S_d = diag(s0, s1, s1, s2). */
+static void make_d2q4(lattice_t *L)
+{
+    static const int cx[4] = {1, 0, -1, 0};
+    static const int cy[4] = {0, 1, 0, -1};
+    static const double M[4][4] = {
+        { 1,  1,  1,  1},
+        { 1,  0, -1,  0},
+        { 0,  1,  0, -1},
+        { 1, -1,  1, -1},
+    };
+    memset(L, 0, sizeof(*L));
+    L->d = 2;
+    L->q = 4;
+    for (int i = 0; i < 4; ++i) {
+        L->c[i][0] = cx[i];
+        L->c[i][1] = cy[i];
+        L->c[i][2] = 0;
+        L->w[i] = 1.0 / 4.0;
+        for (int k = 0; k < 4; ++k) L->M[i][k] = M[i][k];
+    }
+    L->cs2 = 1.0 / 2.0;
+}
+
+/* D3Q6 (eq. d3q6), no rest population, cs^2 = 1/3.  No M in the paper;
+ * rows: e, c_x, c_y, c_z, 2c_x^2 - c_y^2 - c_z^2 and c_y^2 - c_z^2, with
+ * S_d = diag(s0, s1, s1, s1, s2, s2). */
+static void make_d3q6(lattice_t *L)
+{
+    static const int cx[6] = {1, -1, 0, 0, 0, 0};
+    static const int cy[6] = {0, 0, 1, -1, 0, 0};
+    static const int cz[6] = {0, 0, 0, 0, 1, -1};
+    static const double M[6][6] = {
+        { 1,  1,  1,  1,  1,  1},
+        { 1, -1,  0,  0,  0,  0},
+        { 0,  0,  1, -1,  0,  0},
+        { 0,  0,  0,  0,  1, -1},
+        { 2,  2, -1, -1, -1, -1},
+        { 0,  0,  1,  1, -1, -1},
+    };
+    memset(L, 0, sizeof(*L));
+    L->d = 3;
+    L->q = 6;
+    for (int i = 0; i < 6; ++i) {
+        L->c[i][0] = cx[i];
+        L->c[i][1] = cy[i];
+        L->c[i][2] = cz[i];
+        L->w[i] = 1.0 / 6.0;
+        for (int k = 0; k < 6; ++k) L->M[i][k] = M[i][k];
+    }
+    L->cs2 = 1.0 / 3.0;
+}
+
 static int make_lattice(int lattice, lattice_t *L)
 {
     if (lattice == ORC_D2Q5) { make_d2q5(L); return 0; }
     if (lattice == ORC_D3Q7) { make_d3q7(L); return 0; }
+    if (lattice == ORC_D2Q4) { make_d2q4(L); return 0; }
+    if (lattice == ORC_D3Q6) { make_d3q6(L); return 0; }
     return -1;
 }
 

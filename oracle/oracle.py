@@ -18,6 +18,9 @@ from . import build as _build
 
 D2Q5 = 0
 D3Q7 = 1
+D2Q4 = 4
+D3Q6 = 5
+_DQ = {D2Q5: (2, 5), D3Q7: (3, 7), D2Q4: (2, 4), D3Q6: (3, 6)}
 PERIODIC = 0
 WALL = 1
 PLAIN = 0        # forcing of eq. 3-21
@@ -124,8 +127,7 @@ class Case:
     def __init__(self, lattice, shape, s1, s0=1.0, s2=0.0, bc=None, wall_u=None, force=None,
                  R=0.0, rho0=1.0, forcing=0):
         self.lattice = lattice
-        self.d = 2 if lattice == D2Q5 else 3
-        self.q = 5 if lattice == D2Q5 else 7
+        self.d, self.q = _DQ[lattice]
         shape = tuple(int(s) for s in shape)
         if self.d == 2:
             nx, ny = shape

@@ -19,6 +19,9 @@ import analytic as A
 
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
 
+# eq. d2q5 and d3q7 (the paper's numerics), eq. d2q4 and d3q6 (no rest population)
+LATTICES = [O.D2Q5, O.D3Q7, O.D2Q4, O.D3Q6]
+
 
 def _oracle(spec, solid=None, force_field=None):
     case = O.Case(spec.lattice, spec.shape, spec.s1, s0=spec.s0, s2=spec.s2, bc=spec.bc,
@@ -40,16 +43,20 @@ def _run_to_steady(o, chunk, tol, max_steps):
 
 # ------------------------------------------------------------------ lattice tables
 
-@pytest.mark.parametrize("lat", [O.D2Q5, O.D3Q7])
+@pytest.mark.parametrize("lat", LATTICES)
 def test_lattice_moment_constraints_exact(lat):
     """eq. DdQq: sum w = 1, sum w c = 0, sum w c c = cs^2 I, in exact rationals,
     with the printed weights and sound speeds (eq. d2q5: 1/3, 1/6, cs^2 = 1/3;
-    eq. d3q7: 1/4, 1/8, cs^2 = 1/4)."""
+    eq. d3q7: 1/4, 1/8, cs^2 = 1/4; eq. d2q4: 1/4, cs^2 = 1/2; eq. d3q6: 1/6,
+    cs^2 = 1/3)."""
     info = O.lattice_info(lat)
     d, q = info["d"], info["q"]
     w = [Fraction(x).limit_denominator(64) for x in info["w"]]
     cs2 = Fraction(info["cs2"]).limit_denominator(64)
-    assert cs2 == (Fraction(1, 3) if lat == O.D2Q5 else Fraction(1, 4))
+    printed = {O.D2Q5: (Fraction(1, 3), Fraction(1, 6)), O.D3Q7: (Fraction(1, 4), Fraction(1, 8)),
+               O.D2Q4: (Fraction(1, 2), Fraction(1, 4)), O.D3Q6: (Fraction(1, 3), Fraction(1, 6))}
+    assert cs2 == printed[lat][0]
+    assert all(w[i] == printed[lat][1] for i in range(q) if any(info["c"][i]))
     assert sum(w) == 1
     c = info["c"]
     for b in range(d):
@@ -59,12 +66,13 @@ def test_lattice_moment_constraints_exact(lat):
             assert s == (cs2 if b == g else 0)
     # the tables are the printed ones, as sets of velocities
     vel = sorted(tuple(int(v) for v in row) for row in c)
-    expect = sorted([(0,) * d] + [tuple(s * (1 if k == b else 0) for k in range(d))
-                                  for b in range(d) for s in (1, -1)])
+    rest = [(0,) * d] if lat in (O.D2Q5, O.D3Q7) else []
+    expect = sorted(rest + [tuple(s * (1 if k == b else 0) for k in range(d))
+                            for b in range(d) for s in (1, -1)])
     assert vel == expect
 
 
-@pytest.mark.parametrize("lat", [O.D2Q5, O.D3Q7])
+@pytest.mark.parametrize("lat", LATTICES)
 def test_transformation_rows_orthogonal(lat):
     """The D2Q5 M of eq. 4-2 (and the D3Q7 reading) has mutually orthogonal
     rows whose first d+1 rows are e and the velocity components."""
@@ -77,7 +85,7 @@ def test_transformation_rows_orthogonal(lat):
         assert np.array_equal(M[1 + b], c[:, b])
 
 
-@pytest.mark.parametrize("lat", [O.D2Q5, O.D3Q7])
+@pytest.mark.parametrize("lat", LATTICES)
 @pytest.mark.parametrize("s1", [0.7, 1.2, 1.7, 1.98])
 def test_collision_matrix_eigen_conditions(lat, s1):
     """eq. 3-6: e^T L = s0 e^T and c^T L = s1 c^T, for L = M^{-1} S_d M."""
@@ -91,7 +99,7 @@ def test_collision_matrix_eigen_conditions(lat, s1):
         assert np.allclose(cb @ L, s1 * cb, atol=1e-14)
 
 
-@pytest.mark.parametrize("lat", [O.D2Q5, O.D3Q7])
+@pytest.mark.parametrize("lat", LATTICES)
 def test_collision_matrix_projection_form(lat):
     """Independent closed form of L: since M has orthogonal rows and S_d
     assigns s0 to e, s1 to the odd (velocity) rows and s2 to all remaining
@@ -125,10 +133,10 @@ def test_default_s2_magic_combination():
 
 # ------------------------------------------------------------------ equilibrium / init
 
-@pytest.mark.parametrize("lat", [O.D2Q5, O.D3Q7])
+@pytest.mark.parametrize("lat", LATTICES)
 def test_equilibrium_moments(lat):
     """eq. 3-7a: sum f^eq = ubar, sum c f^eq = ubar u + P E, sum c c f^eq = ubar cs^2 I."""
-    spec = C.CaseSpec(lat, (5, 4) if lat == O.D2Q5 else (3, 4, 2), 1.1)
+    spec = C.CaseSpec(lat, (5, 4) if C.DIM[lat] == 2 else (3, 4, 2), 1.1)
     P, u = C.smooth_random_fields(spec, seed=3, amp=0.1)
     o = _oracle(spec).init(P, u)
     info = O.lattice_info(lat)
@@ -146,14 +154,14 @@ def test_equilibrium_moments(lat):
 
 
 @pytest.mark.parametrize("forcing", [C.PLAIN, C.SCHEME2])
-@pytest.mark.parametrize("lat", [O.D2Q5, O.D3Q7])
+@pytest.mark.parametrize("lat", LATTICES)
 def test_init_gradient_round_trip(lat, forcing):
     """Initial state with a velocity gradient (inverse of eq. 3-16): the
     gradient evaluated by eq. 3-16 returns the input exactly (to rounding),
     and u and P are unchanged for a divergence-free input.  Under Scheme II
     (with a force, a per-node force field and a source) eq. 2-7a must give
     back the same u from the shifted populations."""
-    spec = C.CaseSpec(lat, (6, 5) if lat == O.D2Q5 else (4, 3, 5), 1.37, forcing=forcing,
+    spec = C.CaseSpec(lat, (6, 5) if C.DIM[lat] == 2 else (4, 3, 5), 1.37, forcing=forcing,
                       force=(2e-3, -1e-3, 5e-4))
     rng = np.random.default_rng(11)
     d = spec.d
@@ -171,12 +179,12 @@ def test_init_gradient_round_trip(lat, forcing):
 
 # ------------------------------------------------------------------ collision identities
 
-@pytest.mark.parametrize("lat", [O.D2Q5, O.D3Q7])
+@pytest.mark.parametrize("lat", LATTICES)
 def test_collision_zeroth_moment_and_trace(lat):
     """Per node, from eq. 3-6 and eq. 3-7: sum_i f*_{i,a} = ubar_a + Fbar_a,
     and the first-moment trace sum_{a>=1} J*_{aa} = sum J_{aa} + cs^2 R, for
     arbitrary (far from equilibrium) populations."""
-    spec = C.CaseSpec(lat, (4, 3) if lat == O.D2Q5 else (3, 2, 2), 1.23, s0=0.8,
+    spec = C.CaseSpec(lat, (4, 3) if C.DIM[lat] == 2 else (3, 2, 2), 1.23, s0=0.8,
                       force=(1e-3, -2e-3, 3e-3), R=2e-3)
     f = C.random_populations(spec, seed=5, scale=0.1)
     o = _oracle(spec).set_populations(f)
@@ -192,13 +200,13 @@ def test_collision_zeroth_moment_and_trace(lat):
 
 
 @pytest.mark.parametrize("forcing", [C.PLAIN, C.SCHEME2])
-@pytest.mark.parametrize("lat", [O.D2Q5, O.D3Q7])
+@pytest.mark.parametrize("lat", LATTICES)
 @pytest.mark.parametrize("R", [0.0, 3e-3])
 def test_divergence_equals_source(lat, R, forcing):
     """eq. 3-16a combined with the pressure of eq. 3-15 returns div u = R
     identically, for any populations (under Scheme II with fbar in eq. 3-15
     and a force present)."""
-    spec = C.CaseSpec(lat, (5, 3) if lat == O.D2Q5 else (3, 3, 2), 1.4, R=R, forcing=forcing,
+    spec = C.CaseSpec(lat, (5, 3) if C.DIM[lat] == 2 else (3, 3, 2), 1.4, R=R, forcing=forcing,
                       force=(4e-3, 1e-3, -2e-3))
     f = C.random_populations(spec, seed=9, scale=0.1)
     fl = _oracle(spec).set_populations(f).fields()
@@ -216,12 +224,12 @@ def test_stress_is_two_nu_strain():
 
 # ------------------------------------------------------------------ conservation
 
-@pytest.mark.parametrize("lat", [O.D2Q5, O.D3Q7])
+@pytest.mark.parametrize("lat", LATTICES)
 def test_periodic_global_invariants(lat):
     """Periodic streaming permutes values, so sum_x ubar_a is exact up to
     rounding; with a uniform force it grows by N Fbar_a per step; sum_x sum_a
     J_aa is invariant when R = 0."""
-    shape = (24, 20) if lat == O.D2Q5 else (10, 8, 6)
+    shape = (24, 20) if C.DIM[lat] == 2 else (10, 8, 6)
     force = (2e-6, -1e-6, 5e-7)
     spec = C.CaseSpec(lat, shape, 1.6, force=force)
     P, u = C.smooth_random_fields(spec, seed=4, amp=0.05)
@@ -304,12 +312,14 @@ def test_tgv2d_c1_against_closed_form():
     assert A.rel_l2(ex["P"], Pn) < 2e-2
 
 
-def test_tgv2d_second_order_convergence():
+@pytest.mark.parametrize("lat", [O.D2Q5, O.D2Q4])
+def test_tgv2d_second_order_convergence(lat):
     """Second-order convergence in space (Section 4.2) on the 2D Taylor-Green
-    vortex under diffusive scaling: N = 32, 64, 128 with fixed Re and s1."""
+    vortex under diffusive scaling: N = 32, 64, 128 with fixed Re and s1.  On
+    D2Q4 the viscosity follows from its own cs^2 = 1/2 (eq. 3-13a)."""
     errs = {"u": [], "grad": [], "vort": [], "S": []}
     for N, u0, nu, steps in C.tgv2d_convergence_set():
-        spec = C.CaseSpec(C.D2Q5, (N, N), C.s1_for_nu(nu))
+        spec = C.CaseSpec(lat, (N, N), C.s1_for_nu(nu, lat))
         P, u, g = C.taylor_green_2d_initial(N, u0, nu)
         o = _oracle(spec).init(P, u, grad=g)
         o.run(steps)
@@ -375,7 +385,7 @@ def test_four_roll_mill_table_1(k):
 
 # ------------------------------------------------------------------ Scheme II forcing
 
-@pytest.mark.parametrize("lat", [O.D2Q5, O.D3Q7])
+@pytest.mark.parametrize("lat", LATTICES)
 def test_scheme2_collision_moments(lat):
     """eq. 2-3c at every node, for arbitrary populations fbar, a per-node
     force field and a source: the zeroth moment gains exactly Fbar_a
@@ -384,7 +394,7 @@ def test_scheme2_collision_moments(lat):
     J* = (1 - s1) J + s1 J^eq with J^eq_{ab} = ubar_a u_b + P delta (first
     moment of eq. 2-4, the forcing term having none), ubar from eq. 2-7a and
     P from eq. 3-15 with fbar."""
-    spec = C.CaseSpec(lat, (4, 3) if lat == O.D2Q5 else (3, 2, 2), 1.23, s0=0.8,
+    spec = C.CaseSpec(lat, (4, 3) if C.DIM[lat] == 2 else (3, 2, 2), 1.23, s0=0.8,
                       force=(1e-3, -2e-3, 3e-3), R=2e-3, forcing=C.SCHEME2)
     d = spec.d
     f = C.random_populations(spec, seed=5, scale=0.1)
@@ -466,7 +476,7 @@ def test_scheme2_four_roll_mill_removes_force_offset():
     assert max(e_s) / min(e_s) - 1 < 1e-5
 
 
-@pytest.mark.parametrize("lat", [O.D2Q5, O.D3Q7])
+@pytest.mark.parametrize("lat", LATTICES)
 def test_couette_linear_profile_exact(lat):
     """Plane Couette flow: the halfway anti-bounce-back walls reproduce the
     linear profile u1 = U y / H exactly (to rounding) for any s1 — a wrong
@@ -480,7 +490,7 @@ def test_couette_linear_profile_exact(lat):
         y = np.arange(H) + 0.5
         ex = A.couette(0.04, H, y)
         u1 = fl["u"][0]
-        if lat == O.D2Q5:
+        if C.DIM[lat] == 2:
             prof = u1[:, 0]
         else:
             prof = u1[0, :, 0]
@@ -516,12 +526,14 @@ def test_mask_walls_match_face_walls():
 
 # ------------------------------------------------------------------ 3D
 
-def test_tgv3d_linear_regime_decay():
-    """D3Q7 (eq. d3q7; no paper pin for 3D): in the Stokes regime the 3D
-    Taylor-Green field decays as e^{-3 nu k^2 t}; the oracle follows it to
-    O(dx^2) and its vorticity matches the curl of the closed form."""
+@pytest.mark.parametrize("lat", [O.D3Q7, O.D3Q6])
+def test_tgv3d_linear_regime_decay(lat):
+    """D3Q7 and D3Q6 (eq. d3q7, d3q6; no paper pin for 3D): in the Stokes
+    regime the 3D Taylor-Green field decays as e^{-3 nu k^2 t} with nu from
+    the lattice's own cs^2 (eq. 3-13a); the oracle follows it to O(dx^2) and
+    its vorticity matches the curl of the closed form."""
     N, u0, nu = 24, 1e-5, 0.05
-    spec = C.CaseSpec(C.D3Q7, (N, N, N), C.s1_for_nu(nu, C.D3Q7))
+    spec = C.CaseSpec(lat, (N, N, N), C.s1_for_nu(nu, lat))
     P, u = C.taylor_green_3d_initial(N, u0)
     o = _oracle(spec).init(P * 0, u)
     steps = 300
