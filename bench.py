@@ -28,8 +28,9 @@ HBM_PEAK_GBS = 8000.0
 
 
 def kernel_source_hash():
+    from paper_2108_08591_amd import build as B
     h = hashlib.sha256()
-    for name in ("mdf_kernels.hip", "mdf_internal.h"):
+    for name in B.KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2108_08591_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -222,14 +223,20 @@ def variants_study(out_path):
     stream = torch.cuda.Stream(device=dev)
     sb = {"f64": 8, "f32": 4, "f16dev": 2, "bf16dev": 2}
     cb = {"f64": 8, "f32": 4, "f16dev": 4, "bf16dev": 4}       # compute dtype of the force field
-    runs = [("d2q5", 1024, "f32"), ("d2q5", 8192, "f32"), ("d2q5", 8192, "f16dev"), ("d2q5", 8192, "f64"),
-            ("d3q7", 256, "f32"), ("d3q7", 256, "f16dev"), ("d3q7", 256, "f64")]
+    names = {C.D2Q5: "d2q5", C.D3Q7: "d3q7", C.D2Q4: "d2q4", C.D3Q6: "d3q6"}
+    runs = [(C.D2Q5, 1024, "f32"), (C.D2Q5, 8192, "f32"), (C.D2Q5, 8192, "f16dev"), (C.D2Q5, 8192, "f64"),
+            (C.D3Q7, 256, "f32"), (C.D3Q7, 256, "f16dev"), (C.D3Q7, 256, "f64"),
+            (C.D2Q4, 8192, "f32"), (C.D2Q4, 8192, "f16dev"), (C.D3Q6, 256, "f32"), (C.D3Q6, 256, "f16dev")]
     variants = [("all", C.PLAIN, False), ("velocity", C.PLAIN, False), ("all", C.SCHEME2, False),
                 ("all", C.PLAIN, True), ("velocity", C.SCHEME2, True)]
     with open(out_path, "w") as fh:
-        for lat, N, st in runs:
-            spec = C.cavity_case(N=N, Re=1000.0) if lat == "d2q5" else C.tgv3d_case(N=N, u0=0.05, Re=100.0)
-            q = 5 if lat == "d2q5" else 7
+        for lid, N, st in runs:
+            lat = names[lid]
+            if C.DIM[lid] == 2:
+                spec = C.cavity_case(N=N, Re=1000.0, lattice=lid)
+            else:
+                spec = C.tgv3d_case(N=N, u0=0.05, Re=100.0, lattice=lid)
+            q = spec.q
             base = None
             for sets, forcing, field in variants:
                 spec.forcing = forcing

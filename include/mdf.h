@@ -56,15 +56,26 @@ typedef enum {
     MDF_ESTATE = -5      /* call not valid in the context's current state  */
 } mdf_status;
 
-/* Lattices (eq. d2q5, eq. d3q7).  MDF_D2Q5 / MDF_D3Q7 store all d + 1
- * distribution sets a = 0..d of eq. 2-2 (ubar_0 = rho0, ubar_a = u_a).  The
- * *_V variants store only the d velocity sets a = 1..d (Remark IV: the set
- * a = 0 advects rho0 passively and no other quantity reads it), moving
- * d/(d+1) of the bytes per step; their velocity sets, P and every derived
- * field are identical to the full form's, and ubar_0 reads as the constant
- * rho0.  Populations (mdf_populations, MDF_INIT_POPULATIONS) then have d
- * sets, a = 1..d. */
-typedef enum { MDF_D2Q5 = 0, MDF_D3Q7 = 1, MDF_D2Q5_V = 2, MDF_D3Q7_V = 3 } mdf_lattice;
+/* Lattices (eq. d2q5, eq. d3q7, eq. d2q4, eq. d3q6).  MDF_D2Q5 / MDF_D3Q7
+ * store all d + 1 distribution sets a = 0..d of eq. 2-2 (ubar_0 = rho0,
+ * ubar_a = u_a).  The *_V variants store only the d velocity sets a = 1..d
+ * (Remark IV: the set a = 0 advects rho0 passively and no other quantity
+ * reads it), moving d/(d+1) of the bytes per step; their velocity sets, P
+ * and every derived field are identical to the full form's, and ubar_0 reads
+ * as the constant rho0.  Populations (mdf_populations, MDF_INIT_POPULATIONS)
+ * then have d sets, a = 1..d.
+ * MDF_D2Q4 (cs^2 = 1/2) and MDF_D3Q6 (cs^2 = 1/3) have no rest population
+ * (4/5 and 6/7 of the bytes of D2Q5 and D3Q7); their populations are
+ * ordered as the columns of eq. d2q4 (+x, +y, -x, -y) and eq. d3q6 (+x, -x,
+ * +y, -y, +z, -z).  The paper prints no collision matrix for them; the one
+ * used keeps the structure of eq. 4-1..4-3: s0 on the conserved moment, s1
+ * on the d first moments and s2 on every other moment (xx - yy on D2Q4;
+ * 2xx - yy - zz and yy - zz on D3Q6), so the viscosity is
+ * nu = (1/s1 - 1/2) cs^2 with the lattice's own cs^2. */
+typedef enum {
+    MDF_D2Q5 = 0, MDF_D3Q7 = 1, MDF_D2Q5_V = 2, MDF_D3Q7_V = 3,
+    MDF_D2Q4 = 4, MDF_D3Q6 = 5, MDF_D2Q4_V = 6, MDF_D3Q6_V = 7
+} mdf_lattice;
 
 /* Storage of the populations.  MDF_F16DEV / MDF_BF16DEV keep
  * (f - f_rest) / u_ref in 16 bits (round to nearest even on store), with
@@ -226,15 +237,15 @@ mdf_status mdf_invariants(const mdf_ctx *ctx, int32_t case_id, double *out, void
  *   1  vector: each thread of the step kernels owns consecutive x-nodes (2
  *      for MDF_STORAGE_F64, 4 for the other storages), read and written as one
  *      16-byte (8-byte for the 16-bit storages) access per plane;
- *   2  two steps per launch (MDF_D2Q5 only): tiles of 64 x 4/8/16 nodes
+ *   2  two steps per launch (2D lattices only): tiles of 64 x 4/8/16 nodes
  *      (FP64/FP32/16-bit) take one step on the tile and a one-node halo into
  *      LDS and the second from LDS, so the state crosses HBM once per two
  *      steps.  mdf_step, mdf_step_emit and mdf_run_steady (single-case and
  *      batched contexts) run pairs of steps this way and the last step of
  *      each call (and of each K-step chunk) as form 0 with these bx, by.
  * The read kernels always use one node per thread.  Default 64 x 4, 8
- * groups, form 2 for MDF_D2Q5 and form 0 for MDF_D3Q7.  MDF_EINVAL
- * otherwise (also form 2 on MDF_D3Q7).  Any shape
+ * groups, form 2 for the 2D lattices and form 0 for the 3D ones.  MDF_EINVAL
+ * otherwise (also form 2 on a 3D lattice).  Any shape
  * and form give bitwise identical populations and fields; only the
  * summation order of the FP64 sums of mdf_check, mdf_run_steady and
  * mdf_invariants follows it. */

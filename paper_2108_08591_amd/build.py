@@ -11,7 +11,14 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmdf.so")
 
-SOURCES = ["mdf_kernels.hip", "mdf_api.cpp", "nn_kernels.hip"]
+# One translation unit per lattice (its kernels for every storage), the
+# lattice-independent launch code, the C ABI and the network kernels; they
+# compile in parallel.
+LATTICE_UNITS = ["lat_d2q5.hip", "lat_d3q7.hip", "lat_d2q5v.hip", "lat_d3q7v.hip",
+                 "lat_d2q4.hip", "lat_d3q6.hip", "lat_d2q4v.hip", "lat_d3q6v.hip"]
+SOURCES = LATTICE_UNITS + ["mdf_launch.hip", "mdf_api.cpp", "nn_kernels.hip"]
+# sources whose text determines the step kernels' machine code
+KERNEL_SOURCES = ["mdf_kernels.h", "mdf_internal.h"] + LATTICE_UNITS
 
 # Packed-FP32 instructions are disabled for every HIP source of the project.
 # No floating-point contraction: every kernel that evaluates the same
@@ -29,18 +36,28 @@ def hipcc():
     return exe
 
 
-def build(verbose: bool = False) -> str:
-    objs = []
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    jobs = jobs or min(len(SOURCES), os.cpu_count() or 1, 16)
+    objs, cmds = [], []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(CSRC, "_build", src + ".o")
         os.makedirs(os.path.dirname(obj), exist_ok=True)
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [hipcc()] + HIP_FLAGS + ["-I", INCLUDE, "-I", CSRC] + lang + ["-c", path, "-o", obj]
-        if verbose:
-            print(" ".join(cmd), file=sys.stderr)
-        subprocess.run(cmd, check=True)
+        cmds.append([hipcc()] + HIP_FLAGS + ["-I", INCLUDE, "-I", CSRC] + lang + ["-c", path, "-o", obj])
         objs.append(obj)
+    pending, running, failed = list(cmds), [], []
+    while pending or running:
+        while pending and len(running) < jobs:
+            cmd = pending.pop(0)
+            if verbose:
+                print(" ".join(cmd), file=sys.stderr)
+            running.append((cmd, subprocess.Popen(cmd)))
+        cmd, proc = running.pop(0)
+        if proc.wait() != 0:
+            failed.append(cmd[-3])
+    if failed:
+        raise RuntimeError("hipcc failed for " + ", ".join(failed))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     subprocess.run(cmd, check=True)

@@ -21,7 +21,13 @@ import numpy as np
 # lattice identifiers (same numbering as the C ABI)
 D2Q5 = 0
 D3Q7 = 1
-CS2 = {D2Q5: 1.0 / 3.0, D3Q7: 1.0 / 4.0}
+D2Q4 = 4        # no rest population
+D3Q6 = 5        # no rest population
+CS2 = {D2Q5: 1.0 / 3.0, D3Q7: 1.0 / 4.0, D2Q4: 1.0 / 2.0, D3Q6: 1.0 / 3.0}
+DIM = {D2Q5: 2, D3Q7: 3, D2Q4: 2, D3Q6: 3}
+NQ = {D2Q5: 5, D3Q7: 7, D2Q4: 4, D3Q6: 6}
+# weights in the population order of the C ABI (eq. d2q5, d3q7, d2q4, d3q6)
+WEIGHTS = {D2Q5: [1 / 3] + [1 / 6] * 4, D3Q7: [1 / 4] + [1 / 8] * 6, D2Q4: [1 / 4] * 4, D3Q6: [1 / 6] * 6}
 
 PERIODIC = 0
 WALL = 1
@@ -54,7 +60,11 @@ class CaseSpec:
 
     @property
     def d(self) -> int:
-        return 2 if self.lattice == D2Q5 else 3
+        return DIM[self.lattice]
+
+    @property
+    def q(self) -> int:
+        return NQ[self.lattice]
 
     @property
     def fshape(self) -> tuple:
@@ -91,10 +101,10 @@ def taylor_green_2d_initial(N: int, u0: float, nu: float):
     return P, np.stack([u, v]), grad
 
 
-def tgv2d_case(N: int = 64, u0: float = 0.01, Re: float = 10.0) -> CaseSpec:
+def tgv2d_case(N: int = 64, u0: float = 0.01, Re: float = 10.0, lattice: int = D2Q5) -> CaseSpec:
     """2D Taylor-Green on a periodic N x N box with Re = u0 N / nu."""
     nu = u0 * N / Re
-    return CaseSpec(D2Q5, (N, N), s1_for_nu(nu), name=f"tgv2d_{N}")
+    return CaseSpec(lattice, (N, N), s1_for_nu(nu, lattice), name=f"tgv2d_{N}")
 
 
 def tgv2d_convergence_set():
@@ -125,22 +135,23 @@ def taylor_green_3d_initial(N: int, u0: float):
     return P, np.stack([u, v, w])
 
 
-def tgv3d_case(N: int = 256, u0: float = 0.05, Re: float = 100.0) -> CaseSpec:
+def tgv3d_case(N: int = 256, u0: float = 0.05, Re: float = 100.0, lattice: int = D3Q7) -> CaseSpec:
     """3D Taylor-Green, Re = u0 N / (2 pi nu) (the usual convention of this
     benchmark: length scale N / 2 pi)."""
     nu = u0 * N / (2.0 * math.pi * Re)
-    return CaseSpec(D3Q7, (N, N, N), s1_for_nu(nu, D3Q7), name=f"tgv3d_{N}_Re{Re:g}")
+    return CaseSpec(lattice, (N, N, N), s1_for_nu(nu, lattice), name=f"tgv3d_{N}_Re{Re:g}")
 
 
 # ---------------------------------------------------------------- channel / cavity
 
-def poiseuille_case(nx: int = 256, ny: int = 64, umax: float = 0.05, s1: float = 1.2) -> CaseSpec:
+def poiseuille_case(nx: int = 256, ny: int = 64, umax: float = 0.05, s1: float = 1.2,
+                    lattice: int = D2Q5) -> CaseSpec:
     """Force-driven channel, periodic in x, walls at -y/+y (halfway between
     nodes, so the channel height is H = ny).  Force chosen so that the
     parabolic centreline velocity is umax: F = 8 nu umax / H^2."""
-    nu = (1.0 / s1 - 0.5) * CS2[D2Q5]
+    nu = (1.0 / s1 - 0.5) * CS2[lattice]
     F = 8.0 * nu * umax / (ny * ny)
-    return CaseSpec(D2Q5, (nx, ny), s1, bc=(PERIODIC, PERIODIC, WALL, WALL, PERIODIC, PERIODIC),
+    return CaseSpec(lattice, (nx, ny), s1, bc=(PERIODIC, PERIODIC, WALL, WALL, PERIODIC, PERIODIC),
                     force=(F, 0.0, 0.0), name=f"poiseuille_{nx}x{ny}")
 
 
@@ -158,13 +169,13 @@ def poiseuille_paper_case() -> CaseSpec:
                     force=(F, 0.0, 0.0), name="poiseuille_paper_32")
 
 
-def cavity_case(N: int = 1024, Re: float = 1000.0, U: float = 0.1) -> CaseSpec:
+def cavity_case(N: int = 1024, Re: float = 1000.0, U: float = 0.1, lattice: int = D2Q5) -> CaseSpec:
     """Lid-driven square cavity, walls on every face, lid = +y face moving
     with (U, 0).  nu = U N / Re."""
     nu = U * N / Re
     wall = np.zeros((6, 3))
     wall[3, 0] = U
-    return CaseSpec(D2Q5, (N, N), s1_for_nu(nu), bc=(WALL,) * 4 + (PERIODIC, PERIODIC),
+    return CaseSpec(lattice, (N, N), s1_for_nu(nu, lattice), bc=(WALL,) * 4 + (PERIODIC, PERIODIC),
                     wall_u=wall, name=f"cavity_{N}_Re{Re:g}")
 
 
@@ -174,26 +185,26 @@ def couette_case(nx: int = 16, ny: int = 24, U: float = 0.05, s1: float = 1.0,
     moving with (U, 0, 0)."""
     wall = np.zeros((6, 3))
     wall[3, 0] = U
-    shape = (nx, ny) if lattice == D2Q5 else (nx, ny, 4)
+    shape = (nx, ny) if DIM[lattice] == 2 else (nx, ny, 4)
     return CaseSpec(lattice, shape, s1, bc=(PERIODIC, PERIODIC, WALL, WALL, PERIODIC, PERIODIC),
                     wall_u=wall, name="couette")
 
 
 def four_roll_mill(N: int = 64, s1: float = 1.2, nu: float = 0.01, U0: float = 1e-4,
-                   shift: float = 0.5):
+                   shift: float = 0.5, lattice: int = D2Q5):
     """The simplified four-roll mill of Section 4.2 on [0, 2 pi]^2 (periodic)
     in lattice units.  Returns (case, force_field[2, y, x], dt, dx): the
     physical force of the section scaled by dt^2/dx with
     dt = nu_lat dx^2 / nu."""
     dx = 2.0 * math.pi / N
-    nu_lat = (1.0 / s1 - 0.5) * CS2[D2Q5]
+    nu_lat = (1.0 / s1 - 0.5) * CS2[lattice]
     dt = nu_lat * dx * dx / nu
     x = (np.arange(N) + shift) * dx
     X, Y = np.meshgrid(x, x, indexing="xy")
     F1 = U0 * U0 * np.sin(X) * np.cos(X) + 2.0 * nu * U0 * np.sin(X) * np.cos(Y)
     F2 = U0 * U0 * np.sin(Y) * np.cos(Y) - 2.0 * nu * U0 * np.sin(Y) * np.cos(X)
     FF = np.stack([F1, F2]) * dt * dt / dx
-    return CaseSpec(D2Q5, (N, N), s1, name=f"fourroll_{N}_s{s1:g}"), FF, dt, dx
+    return CaseSpec(lattice, (N, N), s1, name=f"fourroll_{N}_s{s1:g}"), FF, dt, dx
 
 
 # ---------------------------------------------------------------- random states
@@ -204,10 +215,10 @@ def random_populations(spec: CaseSpec, seed: int, scale: float = 0.05, rest: flo
     size ``scale`` everywhere (states far from equilibrium, to exercise every
     term of the collision)."""
     rng = np.random.default_rng(seed)
-    q = 5 if spec.lattice == D2Q5 else 7
+    q = spec.q
     ns = spec.d + 1
     f = rng.uniform(-scale, scale, size=(ns, q) + spec.fshape)
-    w = np.array([1 / 3] + [1 / 6] * 4) if q == 5 else np.array([1 / 4] + [1 / 8] * 6)
+    w = np.array(WEIGHTS[spec.lattice])
     f[0] += (rest * w).reshape((q,) + (1,) * spec.d)
     return f
 

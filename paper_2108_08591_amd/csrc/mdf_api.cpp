@@ -26,13 +26,19 @@ thread_local std::string g_last_error;
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-bool lat_2d(int lattice) { return lattice == MDF_D2Q5 || lattice == MDF_D2Q5_V; }
-bool lat_ok(int lattice) { return lattice >= MDF_D2Q5 && lattice <= MDF_D3Q7_V; }
+// Lattice ids: bit 0 selects 3D, bit 1 the velocity sets only (*_V), bit 2
+// the lattices without a rest population (D2Q4, D3Q6).
+bool lat_ok(int lattice) { return lattice >= MDF_D2Q5 && lattice <= MDF_D3Q6_V; }
+bool lat_2d(int lattice) { return (lattice & 1) == 0; }
+bool lat_restfree(int lattice) { return (lattice & 4) != 0; }
 int lat_d(int lattice) { return lat_2d(lattice) ? 2 : 3; }
-int lat_q(int lattice) { return lat_2d(lattice) ? 5 : 7; }
+int lat_q(int lattice) { return lat_2d(lattice) ? (lat_restfree(lattice) ? 4 : 5) : (lat_restfree(lattice) ? 6 : 7); }
 // stored distribution sets: all d + 1, or the d velocity sets (the *_V lattices)
-int lat_ns(int lattice) { return (lattice == MDF_D2Q5_V || lattice == MDF_D3Q7_V) ? lat_d(lattice) : lat_d(lattice) + 1; }
-double lat_cs2(int lattice) { return lat_2d(lattice) ? 1.0 / 3.0 : 1.0 / 4.0; }
+int lat_ns(int lattice) { return (lattice & 2) ? lat_d(lattice) : lat_d(lattice) + 1; }
+// weights of the rest and of the moving populations (eq. d2q5, d3q7, d2q4,
+// d3q6; without a rest population both are the moving weight)
+double lat_w0(int lattice) { return lat_restfree(lattice) ? 1.0 / lat_q(lattice) : (lat_2d(lattice) ? 1.0 / 3.0 : 1.0 / 4.0); }
+double lat_w1(int lattice) { return lat_restfree(lattice) ? 1.0 / lat_q(lattice) : (lat_2d(lattice) ? 1.0 / 6.0 : 1.0 / 8.0); }
 size_t storage_bytes(int storage)
 {
     switch (storage) {
@@ -241,8 +247,7 @@ KCase make_kcase(int lattice, int storage, const mdf_case &c)
     for (int f = 0; f < 6; ++f)
         for (int b = 0; b < 3; ++b) p.walluf[f][b] = float(p.wallu[f][b]);
     // rest weights of the lattice (eq. d2q5 / d3q7) times rho0
-    const double w0 = lat_2d(lattice) ? 1.0 / 3.0 : 1.0 / 4.0;
-    const double w1 = lat_2d(lattice) ? 1.0 / 6.0 : 1.0 / 8.0;
+    const double w0 = lat_w0(lattice), w1 = lat_w1(lattice);
     p.restd[0] = w0 * p.rho0;
     p.restd[1] = w1 * p.rho0;
     p.restf[0] = float(p.restd[0]);

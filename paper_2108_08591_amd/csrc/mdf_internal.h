@@ -1,5 +1,5 @@
 // mdf_internal.h -- declarations shared by the host API (mdf_api.cpp) and the
-// HIP kernels (mdf_kernels.hip).  Not part of the public ABI.
+// HIP kernels (mdf_kernels.h and the lat_*.hip units).  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime_api.h>
@@ -99,7 +99,33 @@ struct BatchLaunch {
     LaunchShape shape;
 };
 
-// Launchers (implemented in mdf_kernels.hip).  All enqueue on `stream` and
+// Entry points of one lattice for every storage.  Each lattice's kernels are
+// instantiated in a translation unit of their own (lat_*.hip).
+struct LatOps {
+    hipError_t (*step)(int storage, const KCase &p, const CaseBufs &b, int src, bool check, uint32_t fields,
+                       void *out, LaunchShape s, hipStream_t stream);
+    hipError_t (*step2)(int storage, const KCase &p, const CaseBufs &b, int src, uint32_t fields, void *out,
+                        LaunchShape s, hipStream_t stream);
+    hipError_t (*read)(int storage, const KCase &p, const CaseBufs &b, int src, bool pull, int mode,
+                       uint32_t fields, void *out, LaunchShape s, hipStream_t stream);
+    hipError_t (*init)(int storage, const KCase &p, const CaseBufs &b, int cur, int kind, const void *data,
+                       hipStream_t stream);
+    hipError_t (*batch)(int storage, const BatchLaunch &bl, bool check, bool emit, hipStream_t stream);
+    hipError_t (*batch2)(int storage, const BatchLaunch &bl, bool emit, hipStream_t stream);
+    hipError_t (*batch_cap)(int storage, LaunchShape shape, bool mask, int *blocks_per_cu);
+    hipError_t (*batch2_cap)(int storage, bool mask, int *blocks_per_cu);
+    hipError_t (*links)(const KCase &p, const uint8_t *solid, uint8_t *links, hipStream_t stream);
+};
+const LatOps &lat_ops_d2q5();
+const LatOps &lat_ops_d3q7();
+const LatOps &lat_ops_d2q5v();
+const LatOps &lat_ops_d3q7v();
+const LatOps &lat_ops_d2q4();
+const LatOps &lat_ops_d3q6();
+const LatOps &lat_ops_d2q4v();
+const LatOps &lat_ops_d3q6v();
+
+// Launchers (implemented in mdf_launch.hip).  All enqueue on `stream` and
 // return the hipError_t of the launch.
 hipError_t launch_links(int lattice, const KCase &p, const uint8_t *solid, uint8_t *links,
                         hipStream_t stream);

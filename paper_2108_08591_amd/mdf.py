@@ -21,6 +21,8 @@ LIB_PATH = os.path.join(HERE, "libmdf.so")
 # enums of mdf.h
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
 D2Q5, D3Q7 = 0, 1
+D2Q4, D3Q6 = 4, 5      # lattices without a rest population
+_NQ = {D2Q5: 5, D3Q7: 7, D2Q4: 4, D3Q6: 6}
 F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
 PERIODIC, WALL = 0, 1
 FIELD_MOMENTS, FIELD_GRAD, FIELD_DIV, FIELD_STRAIN, FIELD_STRESS, FIELD_VORT = 1, 2, 4, 8, 16, 32
@@ -189,12 +191,12 @@ class Solver:
             raise ValueError("all cases of a context share one lattice")
         self.storage = STORAGE_NAMES[storage] if isinstance(storage, str) else int(storage)
         self.d = self.specs[0].d
-        self.q = 5 if self.lattice == D2Q5 else 7
+        self.q = _NQ[self.lattice]
         if sets not in ("all", "velocity"):
             raise ValueError("sets must be 'all' or 'velocity'")
         self.nsets = self.d + 1 if sets == "all" else self.d
         if sets == "velocity":
-            self.lattice += 2          # MDF_D2Q5_V / MDF_D3Q7_V
+            self.lattice += 2          # the *_V lattice ids
         self.device = torch.device(device)
         self.dtype = torch.float64 if self.storage == F64 else torch.float32
         self.stream = stream

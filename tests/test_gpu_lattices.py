@@ -1,0 +1,196 @@
+"""The lattices without a rest population, D2Q4 and D3Q6 (eq. d2q4, eq. d3q6),
+on the HIP path: parity with the FP64 oracle, identity of every launch form,
+the velocity-set variant, batches, and FP32 conservation of the zeroth
+moment (the population that closes it is a moving one on these lattices).
+
+Bar: FP64 storage within 1e-12 relative L2, FP32 within 1e-5; sizes ragged.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2108_08591_amd import cases as C
+from paper_2108_08591_amd import mdf
+from helpers import compare_fields, gpu_fields_np, oracle_for, rel_err
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _cast(a, storage):
+    a = np.asarray(a, np.float64)
+    return a if storage == "f64" else a.astype(np.float32).astype(np.float64)
+
+
+def _setups():
+    out = []
+    out.append(("d2q4_periodic", C.CaseSpec(C.D2Q4, (37, 29), 1.31, force=(1e-3, -5e-4), R=2e-4), None))
+    wall = np.zeros((6, 3))
+    wall[3] = (0.08, 0.01, 0)
+    wall[2] = (-0.02, 0.0, 0)
+    spec = C.CaseSpec(C.D2Q4, (70, 45), 0.77, bc=(1, 1, 1, 1, 0, 0), wall_u=wall, force=(1e-4, 0.0),
+                      forcing=C.SCHEME2)
+    mask = np.zeros(spec.fshape, np.uint8)
+    mask[10:18, 20:31] = 1
+    out.append(("d2q4_walls_mask_scheme2", spec, mask))
+    out.append(("d3q6_periodic", C.CaseSpec(C.D3Q6, (21, 13, 9), 1.45, force=(1e-4, 2e-4, -3e-4), R=1e-4),
+                None))
+    wall = np.zeros((6, 3))
+    wall[3] = (0.05, 0, 0.02)
+    spec = C.CaseSpec(C.D3Q6, (19, 11, 7), 0.9, bc=(0, 0, 1, 1, 1, 1), wall_u=wall)
+    mask = np.zeros(spec.fshape, np.uint8)
+    mask[2:5, 3:7, 8:12] = 1
+    out.append(("d3q6_walls_mask", spec, mask))
+    return out
+
+
+SETUPS = _setups()
+
+
+@pytest.mark.parametrize("form", [0, 2])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("idx", range(len(SETUPS)), ids=[s[0] for s in SETUPS])
+def test_rest_free_steps_from_random_populations(idx, storage, form):
+    """Arbitrary populations, then 1 and 3 more steps (one and two steps per
+    launch in 2D): every population and field matches the oracle."""
+    name, spec, mask = SETUPS[idx]
+    if form == 2 and spec.d == 3:
+        pytest.skip("two steps per launch is a 2D form")
+    _say(f"[lattices] random populations {name} {storage} form {form} shape={spec.shape}")
+    f0 = _cast(C.random_populations(spec, seed=200 + idx, scale=0.05), storage)
+    s = mdf.Solver([spec], storage=storage, solid=None if mask is None else [mask],
+                   init=("populations", [torch.tensor(f0)]), device=DEV)
+    s.set_launch(64, 4, 8, form)
+    o = oracle_for(spec, solid=mask).set_populations(f0)
+    fluid = np.ones(spec.fshape, bool) if mask is None else (mask == 0)
+    compare_fields(o.fields(), gpu_fields_np(s, mdf.FIELD_ALL), TOL[storage])
+    for steps in (1, 3):
+        s.step(steps)
+        o.run(steps)
+        assert rel_err(o.populations()[..., fluid], _np(s.populations())[..., fluid]) < TOL[storage]
+        compare_fields(o.fields(), gpu_fields_np(s, mdf.FIELD_ALL), TOL[storage])
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("lat", [C.D2Q4, C.D3Q6])
+def test_rest_free_cavity_from_rest(lat, storage):
+    """A lid-driven box from rest, 600 steps, against the oracle."""
+    if lat == C.D2Q4:
+        spec = C.cavity_case(N=80, Re=100.0, U=0.1, lattice=C.D2Q4)
+        spec.shape = (80, 66)
+    else:
+        wall = np.zeros((6, 3))
+        wall[3] = (0.05, 0, 0)
+        spec = C.CaseSpec(C.D3Q6, (22, 18, 13), 1.2, bc=(C.WALL,) * 6, wall_u=wall)
+    _say(f"[lattices] cavity from rest {spec.shape} {storage}")
+    s = mdf.Solver([spec], storage=storage, device=DEV)
+    o = oracle_for(spec).init(0.0, np.zeros((spec.d,) + spec.fshape))
+    s.step(600)
+    o.run(600)
+    compare_fields(o.fields(), gpu_fields_np(s, mdf.FIELD_ALL), TOL[storage])
+
+
+def _shape_cases():
+    cav = C.cavity_case(N=102, Re=100.0, lattice=C.D2Q4)
+    cav.shape = (102, 70)
+    per = C.tgv2d_case(N=70, u0=0.02, Re=20.0, lattice=C.D2Q4)
+    per.shape = (70, 46)
+    per.force = (2e-6, -1e-6, 0.0)
+    mask = np.zeros((46, 70), np.uint8)
+    mask[10:18, 20:27] = 1
+    mask[30:34, 0:3] = 1
+    box = C.CaseSpec(C.D3Q6, (38, 22, 14), 1.1, bc=(C.PERIODIC, C.PERIODIC, C.WALL, C.WALL, C.WALL, C.WALL),
+                     wall_u=((0, 0, 0), (0, 0, 0), (0, 0, 0), (0.05, 0, 0), (0, 0, 0), (0, 0.02, 0)))
+    wide = C.cavity_case(N=300, Re=300.0, lattice=C.D2Q4)
+    wide.shape = (302, 90)
+    return [("cavity", cav, None), ("periodic+mask", per, mask), ("box3d", box, None), ("wide cavity", wide, None)]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev", "bf16dev"])
+def test_rest_free_launch_shapes_bitwise_identical(storage):
+    """Scalar, vector and two-step kernels and any tile shape give the same
+    populations and emitted fields bit for bit."""
+    for name, spec, mask in _shape_cases():
+        shapes = [(64, 4, 8, 0), (64, 4, 8, 1), (256, 1, 8, 1), (128, 2, 3, 1), (32, 8, 8, 0)]
+        if spec.d == 2:
+            shapes += [(64, 4, 8, 2), (128, 2, 1, 2)]
+        pops, outs = [], []
+        for bx, by, g, form in shapes:
+            _say(f"[lattices] {storage} {name} launch {bx}x{by} groups {g} form {form}")
+            P, u = C.smooth_random_fields(spec, seed=5, amp=0.03)
+            arr = np.concatenate([np.asarray(P)[None], np.asarray(u)], axis=0)
+            init = ("fields", [torch.tensor(_cast(arr, "f64" if storage == "f64" else "f32"))])
+            s = mdf.Solver([spec], storage=storage, solid=None if mask is None else [mask], init=init,
+                           device=DEV, u_ref=0.05)
+            s.set_launch(bx, by, g, form)
+            s.step(23)
+            out = s.step_emit(5, mdf.FIELD_ALL)
+            pops.append(s.populations())
+            outs.append(out[0].clone())
+        for p, o in zip(pops[1:], outs[1:]):
+            assert torch.equal(p, pops[0])
+            assert torch.equal(o, outs[0])
+
+
+@pytest.mark.parametrize("lat", [C.D2Q4, C.D3Q6])
+def test_rest_free_velocity_sets_equal_full_form(lat):
+    """Only the d velocity sets (Remark IV) on the rest-free lattices: the
+    same velocity-set populations and fields as all d + 1 sets, bit for bit."""
+    if lat == C.D2Q4:
+        spec = C.cavity_case(N=96, Re=150.0, lattice=C.D2Q4)
+        spec.shape = (98, 71)
+    else:
+        spec = C.CaseSpec(C.D3Q6, (30, 20, 12), 1.2, bc=(C.PERIODIC, C.PERIODIC, C.WALL, C.WALL, C.WALL, C.WALL),
+                          wall_u=((0, 0, 0), (0, 0, 0), (0, 0, 0), (0.04, 0, 0), (0, 0, 0), (0, 0, 0)))
+    _say(f"[lattices] velocity sets vs full, lattice {lat}")
+    full = mdf.Solver([spec], storage="f32", device=DEV)
+    vel = mdf.Solver([spec], storage="f32", device=DEV, sets="velocity")
+    for x in (full, vel):
+        x.step(41)
+    assert torch.equal(full.populations()[1:], vel.populations())
+    assert torch.equal(full.gradients(mdf.FIELD_ALL)[1:], vel.gradients(mdf.FIELD_ALL)[1:])
+
+
+def test_rest_free_batch_matches_oracle():
+    """Three uneven D2Q4 cases in one batched context (persistent launches)."""
+    specs = [C.CaseSpec(C.D2Q4, (40, 33), 1.2, force=(2e-5, 0.0)),
+             C.cavity_case(N=65, Re=80.0, lattice=C.D2Q4),
+             C.CaseSpec(C.D2Q4, (31, 47), 1.5, bc=(C.PERIODIC, C.PERIODIC, C.WALL, C.WALL, 0, 0))]
+    _say("[lattices] D2Q4 batch of 3, f64")
+    s = mdf.Solver(specs, storage="f64", device=DEV)
+    s.step(37)
+    for k, spec in enumerate(specs):
+        o = oracle_for(spec).init(0.0, np.zeros((2,) + spec.fshape))
+        o.run(37)
+        assert rel_err(o.populations(), _np(s.populations(k))) < 1e-12, k
+
+
+@pytest.mark.parametrize("lat", [C.D2Q4, C.D3Q6])
+def test_rest_free_fp32_zeroth_moment_does_not_drift(lat):
+    """FP32 on lattices whose weight 1/6 (D3Q6) does not round to a sum of
+    one: the total of ubar_0 in a closed box stays within unbiased rounding,
+    because a moving population closes the zeroth moment of the collision."""
+    if lat == C.D2Q4:
+        spec = C.cavity_case(N=256, Re=400.0, lattice=C.D2Q4)
+    else:
+        wall = np.zeros((6, 3))
+        wall[3] = (0.05, 0, 0)
+        spec = C.CaseSpec(C.D3Q6, (48, 48, 48), 1.3, bc=(C.WALL,) * 6, wall_u=wall)
+    _say(f"[lattices] fp32 mass drift, lattice {lat}")
+    s = mdf.Solver([spec], storage="f32", device=DEV)
+    m0 = s.invariants()[0]
+    s.step(5000)
+    assert abs(s.invariants()[0] / m0 - 1) < 2e-6
