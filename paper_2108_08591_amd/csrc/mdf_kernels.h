@@ -901,6 +901,32 @@ template <> struct Fuse2Rows<MDF_F32> { static constexpr int TY = 8, NT = 256; }
 
 constexpr int kF2X = 64;                 // output columns of a tile
 constexpr int kF2W = kF2X + 2;           // columns of the tile plus its one-node halo
+constexpr int kF2Strip = 16;             // tiles per strip of the two-step tile walk
+
+// Two-step tile t of a gx x gy grid, walked in vertical strips kF2Strip
+// tiles wide (the last strip takes the remaining columns): the tiles of one
+// strip row are consecutive and the strip's rows follow each other, so a
+// tile's neighbours in y run shortly before and after it, in the same XCD
+// band, while the halo rows they share are still in that XCD's L2.  Row by
+// row over a wide grid, one row of tiles (8192 x 10 rows x 15 FP32 planes,
+// 4.9 MB) would exceed the L2 before the next row reused its halo.  A
+// bijection on [0, gx * gy); with gx <= kF2Strip it is the row-major order.
+__device__ __forceinline__ void strip_tile(int t, int gx, int gy, int &tx, int &ty)
+{
+    const int full = gx / kF2Strip;        // strips of full width
+    const int per = kF2Strip * gy;         // tiles in one full strip
+    const int s = t / per;
+    if (s < full) {
+        const int r = t - s * per;
+        ty = r / kF2Strip;
+        tx = s * kF2Strip + r % kF2Strip;
+    } else {
+        const int w = gx - full * kF2Strip;
+        const int r = t - full * per;
+        ty = r / w;
+        tx = full * kF2Strip + r % w;
+    }
+}
 
 // Two time steps in one pass over HBM (temporal blocking, 2D only).  A block
 // owns a tile of 64 x TY nodes.  Step 1 runs on the tile and a one-node
@@ -923,7 +949,7 @@ struct Step2Lds {
 };
 
 template <class L, int ST, bool EMIT, bool MASK>
-__device__ __forceinline__ void step2_tile(const KCase &p, int gx, int tile, const typename Store<ST>::T *__restrict__ src,
+__device__ __forceinline__ void step2_tile(const KCase &p, int gx, int gy, int tile, const typename Store<ST>::T *__restrict__ src,
                                            typename Store<ST>::T *__restrict__ dst, const uint8_t *__restrict__ links,
                                            uint32_t fields, typename Store<ST>::C *__restrict__ out,
                                            typename Store<ST>::T *__restrict__ lds)
@@ -934,7 +960,9 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int tile, con
     using C = typename S::C;
     constexpr int TY = Fuse2Rows<ST>::TY, NT = Fuse2Rows<ST>::NT;
     constexpr int W = kF2W, NE = kF2W * (TY + 2);
-    const int x0 = (tile % gx) * kF2X, y0 = (tile / gx) * TY;
+    int tx, ty;
+    strip_tile(tile, gx, gy, tx, ty);
+    const int x0 = tx * kF2X, y0 = ty * TY;
     const int tid = threadIdx.x;
     const long long nodes = (long long)p.nx * p.ny;
 
@@ -1070,7 +1098,7 @@ k_step2(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, typen
         const uint8_t *__restrict__ links, uint32_t fields, typename Store<ST>::C *__restrict__ out)
 {
     __shared__ Step2Lds<L, ST> lds;
-    step2_tile<L, ST, EMIT, MASK>(p, tl.gx, block_tile(tl), src, dst, links, fields, out, lds.v);
+    step2_tile<L, ST, EMIT, MASK>(p, tl.gx, tl.gy, block_tile(tl), src, dst, links, fields, out, lds.v);
 }
 
 // Batched two steps per launch: the persistent walk of k_step_batch over
@@ -1099,7 +1127,7 @@ k_step2_batch(const BatchEntry *__restrict__ tab, const int *__restrict__ meta,
         const int sel = (e.cur + parity) & 1;
         using T = typename Store<ST>::T;
         using C = typename Store<ST>::C;
-        step2_tile<L, ST, EMIT, MASK>(e.p, e.gx2, t - tile_start2[lo], static_cast<const T *>(e.pop[sel]),
+        step2_tile<L, ST, EMIT, MASK>(e.p, e.gx2, e.gy2, t - tile_start2[lo], static_cast<const T *>(e.pop[sel]),
                                       static_cast<T *>(e.pop[sel ^ 1]), e.links, fields, static_cast<C *>(e.out),
                                       lds.v);
         __syncthreads();   // the next tile's step 1 overwrites the LDS this tile's step 2 reads
