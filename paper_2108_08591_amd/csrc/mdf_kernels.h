@@ -298,6 +298,7 @@ __device__ __forceinline__ C rest_value(const KCase &p, int a, int i)
 template <class L, class C>
 struct Node {
     C f[L::NS][L::Q];       // pre-collision populations f(x, t)
+    C fb[L::D + 1];         // source Fbar_a of every set at the node (read with the populations)
 };
 
 template <class L, class C>
@@ -308,6 +309,26 @@ struct Moments {
     C trJ;                  // sum_{a>=1} J_{a,a}
     C fb[L::D + 1];         // Fbar_a at the node: uniform part + force field
 };
+
+// Source Fbar_a of set a at a node (eq. 2-2, eq. 2-6): Fbar_0 = R, Fbar_a =
+// the uniform force plus the per-node force field when one is set.
+template <class C>
+__device__ __forceinline__ C source_of(const KCase &p, int pa, long long node)
+{
+    C fb = kpar<C>(p.fbar[pa], p.fbarf[pa]);
+    if (pa >= 1 && p.ffield)
+        fb += static_cast<const C *>(p.ffield)[(long long)(pa - 1) * ((long long)p.nx * p.ny * p.nz) + node];
+    return fb;
+}
+
+// The sources of every set at a node.  Issued together with the node's
+// population loads, so that a force field's loads do not wait behind them.
+template <class L, class C>
+__device__ __forceinline__ void load_sources(const KCase &p, long long node, Node<L, C> &n)
+{
+#pragma unroll
+    for (int pa = 0; pa <= L::D; ++pa) n.fb[pa] = source_of<C>(p, pa, node);
+}
 
 // Pull the populations of node (x, y, z) at time t+1 out of the
 // post-collision planes of time t (or, with PULL = false, read the node's
@@ -325,6 +346,7 @@ __device__ __forceinline__ bool gather(const KCase &p, const typename Store<ST>:
         lb = links[own];
         if (lb & 0x80u) return false;
     }
+    load_sources<L, C>(p, ((long long)z * p.ny + y) * p.nx + x, n);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         int sx = x - L::cx[i], sy = y - L::cy[i], sz = z - L::cz[i];
@@ -400,6 +422,7 @@ __device__ __forceinline__ void gather_vec(const KCase &p, const typename Store<
         const bool in = rowok && (x0 + v < p.nx);
         lb[v] = (MASK && in) ? links[own + v] : 0u;
         fluid[v] = in && !(lb[v] & 0x80u);
+        if (in) load_sources<L, C>(p, ((long long)z * p.ny + y) * p.nx + x0 + v, n[v]);
     }
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
@@ -468,23 +491,12 @@ __device__ __forceinline__ void gather_vec(const KCase &p, const typename Store<
     }
 }
 
-// Source Fbar_a of set a at a node (eq. 2-2, eq. 2-6): Fbar_0 = R, Fbar_a =
-// the uniform force plus the per-node force field when one is set.
-template <class C>
-__device__ __forceinline__ C source_of(const KCase &p, int pa, long long node)
-{
-    C fb = kpar<C>(p.fbar[pa], p.fbarf[pa]);
-    if (pa >= 1 && p.ffield)
-        fb += static_cast<const C *>(p.ffield)[(long long)(pa - 1) * ((long long)p.nx * p.ny * p.nz) + node];
-    return fb;
-}
-
 // eq. 2-7 (Scheme II: eq. 2-7a) and eq. 3-15, and the source of every set.
 template <class L, class C>
-__device__ __forceinline__ void moments(const KCase &p, const Node<L, C> &n, Moments<L, C> &m, long long node)
+__device__ __forceinline__ void moments(const KCase &p, const Node<L, C> &n, Moments<L, C> &m)
 {
 #pragma unroll
-    for (int pa = 0; pa <= L::D; ++pa) m.fb[pa] = source_of<C>(p, pa, node);
+    for (int pa = 0; pa <= L::D; ++pa) m.fb[pa] = n.fb[pa];
 #pragma unroll
     for (int a = 0; a < L::NS; ++a) {
         C s = n.f[a][0];
@@ -754,7 +766,7 @@ __device__ __forceinline__ void step_tile(const KCase &p, int gx, int gy, int ti
     const long long nodes = (long long)p.nx * p.ny * p.nz;
     const long long node = ((long long)z * p.ny + y) * p.nx + x;
     if (fluid) {
-        moments<L, C>(p, n, m, node);
+        moments<L, C>(p, n, m);
         if (EMIT) write_fields<L, C>(p, n, m, fields, out, node, nodes);
         const long long own = ((long long)z * p.ny + y) * p.pitch + x;
 #pragma unroll
@@ -825,7 +837,7 @@ __device__ __forceinline__ void step_tile_vec(const KCase &p, int gx, int gy, in
         const long long node = ((long long)z * p.ny + y) * p.nx + x0 + v;
         const bool inside = rowok && (x0 + v < p.nx);
         if (fluid[v]) {
-            moments<L, C>(p, n[v], m[v], node);
+            moments<L, C>(p, n[v], m[v]);
             if (EMIT) write_fields<L, C>(p, n[v], m[v], fields, out, node, nodes);
         } else if (EMIT && inside) {
             int nch = 0;
@@ -1003,7 +1015,7 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int gy, int t
             if (!fluid[g]) continue;
             const int e = tid + (k0 + g) * NT;
             Moments<L, C> m;
-            moments<L, C>(p, n[g], m, node[g]);
+            moments<L, C>(p, n[g], m);
             if (EMIT && interior[g]) write_fields<L, C>(p, n[g], m, fields, out, node[g], nodes);
 #pragma unroll
             for (int a = 0; a < L::NS; ++a) {
@@ -1042,6 +1054,7 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int gy, int t
             continue;
         }
         Node<L, C> n;
+        load_sources<L, C>(p, node, n);
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
             const int sx = x - L::cx[i], sy = y - L::cy[i];
@@ -1077,7 +1090,7 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int gy, int t
             }
         }
         Moments<L, C> m;
-        moments<L, C>(p, n, m, node);
+        moments<L, C>(p, n, m);
         if (EMIT) write_fields<L, C>(p, n, m, fields, out, node, nodes);
 #pragma unroll
         for (int a = 0; a < L::NS; ++a) {
@@ -1196,7 +1209,7 @@ k_read(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, const 
     if (inside) fluid = gather<L, ST, MASK, PULL>(p, src, links, x, y, z, n);
     const long long nodes = (long long)p.nx * p.ny * p.nz;
     const long long node = ((long long)z * p.ny + y) * p.nx + x;
-    if (fluid) moments<L, C>(p, n, m, node);
+    if (fluid) moments<L, C>(p, n, m);
     if (MODE == kReadFields && inside) {
         if (fluid) {
             write_fields<L, C>(p, n, m, fields, out, node, nodes);
@@ -1306,8 +1319,9 @@ k_init(KCase p, typename Store<ST>::T *__restrict__ pre, typename Store<ST>::T *
             }
         }
     }
+    load_sources<L, C>(p, node, n);
     Moments<L, C> m;
-    moments<L, C>(p, n, m, node);
+    moments<L, C>(p, n, m);
 #pragma unroll
     for (int a = 0; a < L::NS; ++a) {
         C ne[L::Q], fo[L::Q];
