@@ -40,7 +40,9 @@
  *         f_{i,a}(x, t+1) = -f*_{ibar,a}(x, t) + 2 w_i U_{w,a}   (a >= 1)
  *         f_{i,0}(x, t+1) =  f*_{ibar,0}(x, t)                   (a = 0)
  *     where f* is the post-collision value, ibar the opposite direction and
- *     U_w the wall velocity.  Walls sit halfway between nodes.
+ *     U_w the wall velocity.  Walls sit halfway between nodes.  A diagonal
+ *     link (D2Q9, D3Q15) whose upstream point lies behind two or three wall
+ *     faces takes the first of them in the order x, y, z.
  *   - D3Q7 transformation matrix: the paper prints none; rows e, c_x, c_y,
  *     c_z, (-6,1,1,1,1,1,1), (0,2,2,-1,-1,-1,-1), (0,0,0,1,1,-1,-1) with
  *     S_d = diag(s0, s1, s1, s1, s2, s2, s2).
@@ -59,14 +61,16 @@
 #define ORC_D3Q7 1
 #define ORC_D2Q4 4
 #define ORC_D3Q6 5
+#define ORC_D2Q9 8
+#define ORC_D3Q15 9
 #define ORC_PERIODIC 0
 #define ORC_WALL 1
 #define ORC_PLAIN 0
 #define ORC_SCHEME2 1
-#define QMAX 7
+#define QMAX 15
 
 typedef struct {
-    int32_t lattice;        /* ORC_D2Q5, ORC_D3Q7, ORC_D2Q4 or ORC_D3Q6 */
+    int32_t lattice;        /* ORC_D2Q5, ORC_D3Q7, ORC_D2Q4, ORC_D3Q6, ORC_D2Q9 or ORC_D3Q15 */
     int32_t nx, ny, nz;     /* nz = 1 in 2D */
     double s0, s1, s2;      /* relaxation rates of S_d (eq. 4-3) */
     int32_t bc[6];          /* faces -x,+x,-y,+y,-z,+z: ORC_PERIODIC / ORC_WALL */
@@ -83,6 +87,7 @@ typedef struct {
     double w[QMAX];
     double cs2;
     double M[QMAX][QMAX];
+    int nodd;           /* rows 1..nodd of M are odd under c -> -c and relax with s1 */
 } lattice_t;
 
 /* D2Q5 (eq. d2q5) with w_0 = 1/3 as chosen in Section 4; the transformation
@@ -109,6 +114,7 @@ static void make_d2q5(lattice_t *L)
         for (int k = 0; k < 5; ++k) L->M[i][k] = M[i][k];
     }
     L->cs2 = 1.0 / 3.0;
+    L->nodd = 2;
 }
 
 /* D3Q7 (eq. d3q7); M as read above (the paper gives none for D3Q7). */
@@ -137,6 +143,7 @@ static void make_d3q7(lattice_t *L)
         for (int k = 0; k < 7; ++k) L->M[i][k] = M[i][k];
     }
     L->cs2 = 1.0 / 4.0;
+    L->nodd = 3;
 }
 
 /* D2Q4 (eq. d2q4), no rest population, cs^2 = 1/2.  The paper prints no M
@@ -163,6 +170,7 @@ static void make_d2q4(lattice_t *L)
         for (int k = 0; k < 4; ++k) L->M[i][k] = M[i][k];
     }
     L->cs2 = 1.0 / 2.0;
+    L->nodd = 2;
 }
 
 /* D3Q6 (eq. d3q6), no rest population, cs^2 = 1/3.  No M in the paper;
@@ -192,6 +200,84 @@ static void make_d3q6(lattice_t *L)
         for (int k = 0; k < 6; ++k) L->M[i][k] = M[i][k];
     }
     L->cs2 = 1.0 / 3.0;
+    L->nodd = 3;
+}
+
+/* Fill L from velocities and weights; M from a list of row functions. */
+static void fill_lattice(lattice_t *L, int d, int q, const int (*c)[3], const double *w, double cs2,
+                         int nodd, const double (*M)[QMAX])
+{
+    memset(L, 0, sizeof(*L));
+    L->d = d;
+    L->q = q;
+    L->cs2 = cs2;
+    L->nodd = nodd;
+    for (int i = 0; i < q; ++i) {
+        for (int b = 0; b < 3; ++b) L->c[i][b] = c[i][b];
+        L->w[i] = w[i];
+        for (int r = 0; r < q; ++r) L->M[r][i] = M[r][i];
+    }
+}
+
+/* D2Q9 (eq. d2q9), cs^2 = 1/3.  The paper prints no M for it.  Rows, in
+ * the usual moment basis: e; the odd moments c_x, c_y and the energy fluxes
+ * (3|c|^2 - 5) c_x, (3|c|^2 - 5) c_y; the even moments 3|c|^2 - 4,
+ * (9|c|^4 - 21|c|^2 + 8)/2, c_x^2 - c_y^2 and c_x c_y.  S_d keeps the
+ * structure of eq. 4-3: s0 on e, s1 on every odd row, s2 on every even one. */
+static void make_d2q9(lattice_t *L)
+{
+    static const int c[9][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0},
+                                {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+    double w[9], M[QMAX][QMAX];
+    memset(M, 0, sizeof M);
+    for (int i = 0; i < 9; ++i) {
+        const int cx = c[i][0], cy = c[i][1], c2 = cx * cx + cy * cy;
+        w[i] = c2 == 0 ? 4.0 / 9.0 : (c2 == 1 ? 1.0 / 9.0 : 1.0 / 36.0);
+        M[0][i] = 1;
+        M[1][i] = cx;
+        M[2][i] = cy;
+        M[3][i] = (3 * c2 - 5) * cx;
+        M[4][i] = (3 * c2 - 5) * cy;
+        M[5][i] = 3 * c2 - 4;
+        M[6][i] = (9.0 * c2 * c2 - 21.0 * c2 + 8.0) / 2.0;
+        M[7][i] = cx * cx - cy * cy;
+        M[8][i] = cx * cy;
+    }
+    fill_lattice(L, 2, 9, c, w, 1.0 / 3.0, 4, (const double (*)[QMAX])M);
+}
+
+/* D3Q15 (eq. d3q15), cs^2 = 1/3, velocities in the column order printed.
+ * No M in the paper.  Rows: e; odd: c_x, c_y, c_z, (5|c|^2 - 13) c_b for
+ * each b, and c_x c_y c_z; even: |c|^2 - 2, (15|c|^4 - 55|c|^2 + 32)/2,
+ * 3c_x^2 - |c|^2, c_y^2 - c_z^2, c_x c_y, c_y c_z, c_z c_x.  s1 on every odd
+ * row, s2 on every even one. */
+static void make_d3q15(lattice_t *L)
+{
+    static const int c[15][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+                                 {1, 1, 1}, {1, 1, -1}, {1, -1, 1}, {-1, 1, 1}, {-1, -1, 1}, {-1, 1, -1},
+                                 {1, -1, -1}, {-1, -1, -1}};
+    double w[15], M[QMAX][QMAX];
+    memset(M, 0, sizeof M);
+    for (int i = 0; i < 15; ++i) {
+        const int cx = c[i][0], cy = c[i][1], cz = c[i][2], c2 = cx * cx + cy * cy + cz * cz;
+        w[i] = c2 == 0 ? 2.0 / 9.0 : (c2 == 1 ? 1.0 / 9.0 : 1.0 / 72.0);
+        M[0][i] = 1;
+        M[1][i] = cx;
+        M[2][i] = cy;
+        M[3][i] = cz;
+        M[4][i] = (5 * c2 - 13) * cx;
+        M[5][i] = (5 * c2 - 13) * cy;
+        M[6][i] = (5 * c2 - 13) * cz;
+        M[7][i] = cx * cy * cz;
+        M[8][i] = c2 - 2;
+        M[9][i] = (15.0 * c2 * c2 - 55.0 * c2 + 32.0) / 2.0;
+        M[10][i] = 3 * cx * cx - c2;
+        M[11][i] = cy * cy - cz * cz;
+        M[12][i] = cx * cy;
+        M[13][i] = cy * cz;
+        M[14][i] = cz * cx;
+    }
+    fill_lattice(L, 3, 15, c, w, 1.0 / 3.0, 7, (const double (*)[QMAX])M);
 }
 
 static int make_lattice(int lattice, lattice_t *L)
@@ -200,6 +286,8 @@ static int make_lattice(int lattice, lattice_t *L)
     if (lattice == ORC_D3Q7) { make_d3q7(L); return 0; }
     if (lattice == ORC_D2Q4) { make_d2q4(L); return 0; }
     if (lattice == ORC_D3Q6) { make_d3q6(L); return 0; }
+    if (lattice == ORC_D2Q9) { make_d2q9(L); return 0; }
+    if (lattice == ORC_D3Q15) { make_d3q15(L); return 0; }
     return -1;
 }
 
@@ -252,7 +340,8 @@ static int collision_matrix(const lattice_t *L, double s0, double s1, double s2,
     double Minv[QMAX][QMAX], S[QMAX];
     int q = L->q, d = L->d;
     if (invert(q, L->M, Minv) != 0) return -1;
-    for (int r = 0; r < q; ++r) S[r] = (r == 0) ? s0 : (r <= d ? s1 : s2);
+    (void)d;
+    for (int r = 0; r < q; ++r) S[r] = (r == 0) ? s0 : (r <= L->nodd ? s1 : s2);
     for (int i = 0; i < q; ++i)
         for (int k = 0; k < q; ++k) {
             double acc = 0.0;

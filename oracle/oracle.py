@@ -20,7 +20,9 @@ D2Q5 = 0
 D3Q7 = 1
 D2Q4 = 4
 D3Q6 = 5
-_DQ = {D2Q5: (2, 5), D3Q7: (3, 7), D2Q4: (2, 4), D3Q6: (3, 6)}
+D2Q9 = 8
+D3Q15 = 9
+_DQ = {D2Q5: (2, 5), D3Q7: (3, 7), D2Q4: (2, 4), D3Q6: (3, 6), D2Q9: (2, 9), D3Q15: (3, 15)}
 PERIODIC = 0
 WALL = 1
 PLAIN = 0        # forcing of eq. 3-21
@@ -97,10 +99,10 @@ def _ok(rc, what):
 
 def lattice_info(lattice):
     d, q = ctypes.c_int(), ctypes.c_int()
-    c = (ctypes.c_int * 21)()
-    w = np.zeros(7)
+    c = (ctypes.c_int * 45)()
+    w = np.zeros(15)
     cs2 = np.zeros(1)
-    M = np.zeros(49)
+    M = np.zeros(225)
     _ok(lib().orc_lattice_info(lattice, ctypes.byref(d), ctypes.byref(q), c, _dp(w), _dp(cs2),
                                _dp(M)), "lattice_info")
     qn = q.value

@@ -23,11 +23,15 @@ D2Q5 = 0
 D3Q7 = 1
 D2Q4 = 4        # no rest population
 D3Q6 = 5        # no rest population
-CS2 = {D2Q5: 1.0 / 3.0, D3Q7: 1.0 / 4.0, D2Q4: 1.0 / 2.0, D3Q6: 1.0 / 3.0}
-DIM = {D2Q5: 2, D3Q7: 3, D2Q4: 2, D3Q6: 3}
-NQ = {D2Q5: 5, D3Q7: 7, D2Q4: 4, D3Q6: 6}
-# weights in the population order of the C ABI (eq. d2q5, d3q7, d2q4, d3q6)
-WEIGHTS = {D2Q5: [1 / 3] + [1 / 6] * 4, D3Q7: [1 / 4] + [1 / 8] * 6, D2Q4: [1 / 4] * 4, D3Q6: [1 / 6] * 6}
+D2Q9 = 8        # diagonal links
+D3Q15 = 9       # diagonal links
+CS2 = {D2Q5: 1.0 / 3.0, D3Q7: 1.0 / 4.0, D2Q4: 1.0 / 2.0, D3Q6: 1.0 / 3.0, D2Q9: 1.0 / 3.0, D3Q15: 1.0 / 3.0}
+DIM = {D2Q5: 2, D3Q7: 3, D2Q4: 2, D3Q6: 3, D2Q9: 2, D3Q15: 3}
+NQ = {D2Q5: 5, D3Q7: 7, D2Q4: 4, D3Q6: 6, D2Q9: 9, D3Q15: 15}
+# weights in the population order of the C ABI (eq. d2q5, d3q7, d2q4, d3q6,
+# d2q9, d3q15: the printed column order)
+WEIGHTS = {D2Q5: [1 / 3] + [1 / 6] * 4, D3Q7: [1 / 4] + [1 / 8] * 6, D2Q4: [1 / 4] * 4, D3Q6: [1 / 6] * 6,
+           D2Q9: [4 / 9] + [1 / 9] * 4 + [1 / 36] * 4, D3Q15: [2 / 9] + [1 / 9] * 6 + [1 / 72] * 8}
 
 PERIODIC = 0
 WALL = 1

@@ -19,8 +19,9 @@ import analytic as A
 
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
 
-# eq. d2q5 and d3q7 (the paper's numerics), eq. d2q4 and d3q6 (no rest population)
-LATTICES = [O.D2Q5, O.D3Q7, O.D2Q4, O.D3Q6]
+# eq. d2q5 and d3q7 (the paper's numerics), eq. d2q4 and d3q6 (no rest
+# population), eq. d2q9 and d3q15 (diagonal links)
+LATTICES = [O.D2Q5, O.D3Q7, O.D2Q4, O.D3Q6, O.D2Q9, O.D3Q15]
 
 
 def _oracle(spec, solid=None, force_field=None):
@@ -46,17 +47,22 @@ def _run_to_steady(o, chunk, tol, max_steps):
 @pytest.mark.parametrize("lat", LATTICES)
 def test_lattice_moment_constraints_exact(lat):
     """eq. DdQq: sum w = 1, sum w c = 0, sum w c c = cs^2 I, in exact rationals,
-    with the printed weights and sound speeds (eq. d2q5: 1/3, 1/6, cs^2 = 1/3;
-    eq. d3q7: 1/4, 1/8, cs^2 = 1/4; eq. d2q4: 1/4, cs^2 = 1/2; eq. d3q6: 1/6,
-    cs^2 = 1/3)."""
+    with the printed weights (by |c|^2 = 0, 1, 2, 3) and sound speeds: eq.
+    d2q5 (1/3, 1/6; cs^2 = 1/3), d3q7 (1/4, 1/8; 1/4), d2q4 (-, 1/4; 1/2),
+    d3q6 (-, 1/6; 1/3), d2q9 (4/9, 1/9, 1/36; 1/3), d3q15 (2/9, 1/9, -,
+    1/72; 1/3)."""
     info = O.lattice_info(lat)
     d, q = info["d"], info["q"]
-    w = [Fraction(x).limit_denominator(64) for x in info["w"]]
+    w = [Fraction(x).limit_denominator(128) for x in info["w"]]
     cs2 = Fraction(info["cs2"]).limit_denominator(64)
-    printed = {O.D2Q5: (Fraction(1, 3), Fraction(1, 6)), O.D3Q7: (Fraction(1, 4), Fraction(1, 8)),
-               O.D2Q4: (Fraction(1, 2), Fraction(1, 4)), O.D3Q6: (Fraction(1, 3), Fraction(1, 6))}
+    F = Fraction
+    printed = {O.D2Q5: (F(1, 3), {0: F(1, 3), 1: F(1, 6)}), O.D3Q7: (F(1, 4), {0: F(1, 4), 1: F(1, 8)}),
+               O.D2Q4: (F(1, 2), {1: F(1, 4)}), O.D3Q6: (F(1, 3), {1: F(1, 6)}),
+               O.D2Q9: (F(1, 3), {0: F(4, 9), 1: F(1, 9), 2: F(1, 36)}),
+               O.D3Q15: (F(1, 3), {0: F(2, 9), 1: F(1, 9), 3: F(1, 72)})}
     assert cs2 == printed[lat][0]
-    assert all(w[i] == printed[lat][1] for i in range(q) if any(info["c"][i]))
+    for i in range(q):
+        assert w[i] == printed[lat][1][int(np.sum(info["c"][i] ** 2))], i
     assert sum(w) == 1
     c = info["c"]
     for b in range(d):
@@ -66,16 +72,21 @@ def test_lattice_moment_constraints_exact(lat):
             assert s == (cs2 if b == g else 0)
     # the tables are the printed ones, as sets of velocities
     vel = sorted(tuple(int(v) for v in row) for row in c)
-    rest = [(0,) * d] if lat in (O.D2Q5, O.D3Q7) else []
-    expect = sorted(rest + [tuple(s * (1 if k == b else 0) for k in range(d))
-                            for b in range(d) for s in (1, -1)])
-    assert vel == expect
+    rest = [(0,) * d] if lat in (O.D2Q5, O.D3Q7, O.D2Q9, O.D3Q15) else []
+    axis = [tuple(s * (1 if k == b else 0) for k in range(d)) for b in range(d) for s in (1, -1)]
+    diag = []
+    if lat == O.D2Q9:
+        diag = [(sx, sy) for sx in (1, -1) for sy in (1, -1)]
+    if lat == O.D3Q15:
+        diag = [(sx, sy, sz) for sx in (1, -1) for sy in (1, -1) for sz in (1, -1)]
+    assert vel == sorted(rest + axis + diag)
 
 
 @pytest.mark.parametrize("lat", LATTICES)
 def test_transformation_rows_orthogonal(lat):
-    """The D2Q5 M of eq. 4-2 (and the D3Q7 reading) has mutually orthogonal
-    rows whose first d+1 rows are e and the velocity components."""
+    """The D2Q5 M of eq. 4-2 (and the readings for the other lattices) has
+    mutually orthogonal rows whose first d+1 rows are e and the velocity
+    components, and full rank."""
     info = O.lattice_info(lat)
     M, c, d = info["M"], info["c"], info["d"]
     G = M @ M.T
@@ -83,6 +94,7 @@ def test_transformation_rows_orthogonal(lat):
     assert np.all(M[0] == 1)
     for b in range(d):
         assert np.array_equal(M[1 + b], c[:, b])
+    assert np.all(np.diag(G) > 0)
 
 
 @pytest.mark.parametrize("lat", LATTICES)
@@ -312,7 +324,7 @@ def test_tgv2d_c1_against_closed_form():
     assert A.rel_l2(ex["P"], Pn) < 2e-2
 
 
-@pytest.mark.parametrize("lat", [O.D2Q5, O.D2Q4])
+@pytest.mark.parametrize("lat", [O.D2Q5, O.D2Q4, O.D2Q9])
 def test_tgv2d_second_order_convergence(lat):
     """Second-order convergence in space (Section 4.2) on the 2D Taylor-Green
     vortex under diffusive scaling: N = 32, 64, 128 with fixed Re and s1.  On
@@ -480,7 +492,25 @@ def test_scheme2_four_roll_mill_removes_force_offset():
 def test_couette_linear_profile_exact(lat):
     """Plane Couette flow: the halfway anti-bounce-back walls reproduce the
     linear profile u1 = U y / H exactly (to rounding) for any s1 — a wrong
-    wall-velocity term (factor, weight or sign) breaks it."""
+    wall-velocity term (factor, weight or sign) breaks it.  With diagonal
+    links (D2Q9, D3Q15) the linear equilibrium has a third moment
+    sum_i w_i c_x c_y^2 (c_x flux_x) / cs^2 = flux_x / 3, so the x-flux
+    u^2 + P, which varies across the channel, leaves a residue nonlinear in
+    U: there the relative error must fall 4x each time U halves (a wrong
+    wall term would leave it independent of U)."""
+    diag = lat in (O.D2Q9, O.D3Q15)
+    if diag:
+        for s1 in (0.8, 1.5):
+            errs = []
+            for U in (0.04, 0.02):
+                spec = C.couette_case(8, 16, U=U, s1=s1, lattice=lat)
+                o = _oracle(spec).init(0.0, np.zeros((spec.d,) + spec.fshape))
+                assert _run_to_steady(o, 1000, 1e-15, 100000)
+                u1 = o.fields()["u"][0]
+                prof = u1[:, 0] if C.DIM[lat] == 2 else u1[0, :, 0]
+                errs.append(A.rel_l2(A.couette(U, 16, np.arange(16) + 0.5), prof))
+            assert errs[1] < 3e-3 and 3.9 < errs[0] / errs[1] < 4.2, errs
+        return
     for s1 in (0.8, 1.5):
         spec = C.couette_case(8, 16, U=0.04, s1=s1, lattice=lat)
         o = _oracle(spec).init(0.0, np.zeros((spec.d,) + spec.fshape))
@@ -526,7 +556,7 @@ def test_mask_walls_match_face_walls():
 
 # ------------------------------------------------------------------ 3D
 
-@pytest.mark.parametrize("lat", [O.D3Q7, O.D3Q6])
+@pytest.mark.parametrize("lat", [O.D3Q7, O.D3Q6, O.D3Q15])
 def test_tgv3d_linear_regime_decay(lat):
     """D3Q7 and D3Q6 (eq. d3q7, d3q6; no paper pin for 3D): in the Stokes
     regime the 3D Taylor-Green field decays as e^{-3 nu k^2 t} with nu from
@@ -540,7 +570,9 @@ def test_tgv3d_linear_regime_decay(lat):
     o.run(steps)
     fl = o.fields()
     ex = A.taylor_green_3d_linear(N, u0, nu, steps)
-    assert A.rel_l2(ex, fl["u"]) < 5e-3
+    # O(dx^2) at N = 24; D3Q15's truncation constant is larger (6.9e-3).  A
+    # wrong cs^2 would put the decay rate off by 25 % (an error of order 1)
+    assert A.rel_l2(ex, fl["u"]) < (1e-2 if lat == O.D3Q15 else 5e-3)
     k = 2 * math.pi / N
     c = (np.arange(N) + 0.5) * k
     Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
