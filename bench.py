@@ -211,7 +211,8 @@ def time_launches(solver, stream, n, fields=0, out=None, reps=3):
 
 def variants_study(out_path):
     """Cost of each variant of the update against the plain one on the same
-    grid, storage and default launch shape (two steps per launch in 2D),
+    grid, storage and default launch shape (two steps per launch on the 2D
+    axis-link lattices, one node per thread elsewhere),
     stepping without field emission: the d velocity sets only (Remark IV),
     Scheme II forcing (eq. 2-3c), and a per-node force field (d more reads
     per node and step).  Algorithmic bytes per step: one read and one write
@@ -223,10 +224,11 @@ def variants_study(out_path):
     stream = torch.cuda.Stream(device=dev)
     sb = {"f64": 8, "f32": 4, "f16dev": 2, "bf16dev": 2}
     cb = {"f64": 8, "f32": 4, "f16dev": 4, "bf16dev": 4}       # compute dtype of the force field
-    names = {C.D2Q5: "d2q5", C.D3Q7: "d3q7", C.D2Q4: "d2q4", C.D3Q6: "d3q6"}
+    names = {C.D2Q5: "d2q5", C.D3Q7: "d3q7", C.D2Q4: "d2q4", C.D3Q6: "d3q6", C.D2Q9: "d2q9", C.D3Q15: "d3q15"}
     runs = [(C.D2Q5, 1024, "f32"), (C.D2Q5, 8192, "f32"), (C.D2Q5, 8192, "f16dev"), (C.D2Q5, 8192, "f64"),
             (C.D3Q7, 256, "f32"), (C.D3Q7, 256, "f16dev"), (C.D3Q7, 256, "f64"),
-            (C.D2Q4, 8192, "f32"), (C.D2Q4, 8192, "f16dev"), (C.D3Q6, 256, "f32"), (C.D3Q6, 256, "f16dev")]
+            (C.D2Q4, 8192, "f32"), (C.D2Q4, 8192, "f16dev"), (C.D3Q6, 256, "f32"), (C.D3Q6, 256, "f16dev"),
+            (C.D2Q9, 8192, "f32"), (C.D3Q15, 256, "f32")]
     variants = [("all", C.PLAIN, False), ("velocity", C.PLAIN, False), ("all", C.SCHEME2, False),
                 ("all", C.PLAIN, True), ("velocity", C.SCHEME2, True)]
     with open(out_path, "w") as fh:

@@ -71,10 +71,17 @@ typedef enum {
  * used keeps the structure of eq. 4-1..4-3: s0 on the conserved moment, s1
  * on the d first moments and s2 on every other moment (xx - yy on D2Q4;
  * 2xx - yy - zz and yy - zz on D3Q6), so the viscosity is
- * nu = (1/s1 - 1/2) cs^2 with the lattice's own cs^2. */
+ * nu = (1/s1 - 1/2) cs^2 with the lattice's own cs^2.
+ * MDF_D2Q9 and MDF_D3Q15 (cs^2 = 1/3) add diagonal links, in the column
+ * order of eq. d2q9 and eq. d3q15.  Their collision relaxes every moment
+ * odd under c -> -c with s1 and every even one with s2 (the structure of
+ * eq. 4-3 carried to the larger moment sets).  A diagonal link whose
+ * upstream point lies behind two or three wall faces takes the first of them
+ * in the order x, y, z.  They run one node per thread (form 0) only. */
 typedef enum {
     MDF_D2Q5 = 0, MDF_D3Q7 = 1, MDF_D2Q5_V = 2, MDF_D3Q7_V = 3,
-    MDF_D2Q4 = 4, MDF_D3Q6 = 5, MDF_D2Q4_V = 6, MDF_D3Q6_V = 7
+    MDF_D2Q4 = 4, MDF_D3Q6 = 5, MDF_D2Q4_V = 6, MDF_D3Q6_V = 7,
+    MDF_D2Q9 = 8, MDF_D3Q15 = 9, MDF_D2Q9_V = 10, MDF_D3Q15_V = 11
 } mdf_lattice;
 
 /* Storage of the populations.  MDF_F16DEV / MDF_BF16DEV keep
@@ -237,15 +244,15 @@ mdf_status mdf_invariants(const mdf_ctx *ctx, int32_t case_id, double *out, void
  *   1  vector: each thread of the step kernels owns consecutive x-nodes (2
  *      for MDF_STORAGE_F64, 4 for the other storages), read and written as one
  *      16-byte (8-byte for the 16-bit storages) access per plane;
- *   2  two steps per launch (2D lattices only): tiles of 64 x 4/8/16 nodes
+ *   2  two steps per launch (D2Q5, D2Q4 and their *_V forms): tiles of 64 x 4/8/16 nodes
  *      (FP64/FP32/16-bit) take one step on the tile and a one-node halo into
  *      LDS and the second from LDS, so the state crosses HBM once per two
  *      steps.  mdf_step, mdf_step_emit and mdf_run_steady (single-case and
  *      batched contexts) run pairs of steps this way and the last step of
  *      each call (and of each K-step chunk) as form 0 with these bx, by.
  * The read kernels always use one node per thread.  Default 64 x 4, 8
- * groups, form 2 for the 2D lattices and form 0 for the 3D ones.  MDF_EINVAL
- * otherwise (also form 2 on a 3D lattice).  Any shape
+ * groups, form 2 where it exists and form 0 elsewhere.  MDF_EINVAL otherwise
+ * (also form 2 on a 3D lattice, forms 1 and 2 on D2Q9 / D3Q15).  Any shape
  * and form give bitwise identical populations and fields; only the
  * summation order of the FP64 sums of mdf_check, mdf_run_steady and
  * mdf_invariants follows it. */

@@ -27,18 +27,35 @@ thread_local std::string g_last_error;
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 // Lattice ids: bit 0 selects 3D, bit 1 the velocity sets only (*_V), bit 2
-// the lattices without a rest population (D2Q4, D3Q6).
-bool lat_ok(int lattice) { return lattice >= MDF_D2Q5 && lattice <= MDF_D3Q6_V; }
+// the lattices without a rest population (D2Q4, D3Q6), bit 3 those with
+// diagonal links (D2Q9, D3Q15).
+bool lat_ok(int lattice) { return lattice >= MDF_D2Q5 && lattice <= MDF_D3Q15_V; }
 bool lat_2d(int lattice) { return (lattice & 1) == 0; }
 bool lat_restfree(int lattice) { return (lattice & 4) != 0; }
+bool lat_diag(int lattice) { return (lattice & 8) != 0; }
+// two steps per launch: 2D lattices with axis links
+bool lat_fusable(int lattice) { return lat_2d(lattice) && !lat_diag(lattice); }
 int lat_d(int lattice) { return lat_2d(lattice) ? 2 : 3; }
-int lat_q(int lattice) { return lat_2d(lattice) ? (lat_restfree(lattice) ? 4 : 5) : (lat_restfree(lattice) ? 6 : 7); }
+int lat_q(int lattice)
+{
+    if (lat_diag(lattice)) return lat_2d(lattice) ? 9 : 15;
+    return lat_2d(lattice) ? (lat_restfree(lattice) ? 4 : 5) : (lat_restfree(lattice) ? 6 : 7);
+}
 // stored distribution sets: all d + 1, or the d velocity sets (the *_V lattices)
 int lat_ns(int lattice) { return (lattice & 2) ? lat_d(lattice) : lat_d(lattice) + 1; }
-// weights of the rest and of the moving populations (eq. d2q5, d3q7, d2q4,
-// d3q6; without a rest population both are the moving weight)
-double lat_w0(int lattice) { return lat_restfree(lattice) ? 1.0 / lat_q(lattice) : (lat_2d(lattice) ? 1.0 / 3.0 : 1.0 / 4.0); }
-double lat_w1(int lattice) { return lat_restfree(lattice) ? 1.0 / lat_q(lattice) : (lat_2d(lattice) ? 1.0 / 6.0 : 1.0 / 8.0); }
+// weight of the rest (k = 0), axis (1) and diagonal (2) directions (eq.
+// d2q5, d3q7, d2q4, d3q6, d2q9, d3q15; without a rest population the rest
+// entry repeats the moving weight)
+double lat_wclass(int lattice, int k)
+{
+    if (lat_restfree(lattice)) return 1.0 / lat_q(lattice);
+    if (lat_diag(lattice)) {
+        static const double w2[3] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 36.0}, w3[3] = {2.0 / 9.0, 1.0 / 9.0, 1.0 / 72.0};
+        return lat_2d(lattice) ? w2[k] : w3[k];
+    }
+    static const double w2[3] = {1.0 / 3.0, 1.0 / 6.0, 0.0}, w3[3] = {1.0 / 4.0, 1.0 / 8.0, 0.0};
+    return lat_2d(lattice) ? w2[k] : w3[k];
+}
 size_t storage_bytes(int storage)
 {
     switch (storage) {
@@ -247,11 +264,10 @@ KCase make_kcase(int lattice, int storage, const mdf_case &c)
     for (int f = 0; f < 6; ++f)
         for (int b = 0; b < 3; ++b) p.walluf[f][b] = float(p.wallu[f][b]);
     // rest weights of the lattice (eq. d2q5 / d3q7) times rho0
-    const double w0 = lat_w0(lattice), w1 = lat_w1(lattice);
-    p.restd[0] = w0 * p.rho0;
-    p.restd[1] = w1 * p.rho0;
-    p.restf[0] = float(p.restd[0]);
-    p.restf[1] = float(p.restd[1]);
+    for (int k = 0; k < 3; ++k) {
+        p.restd[k] = lat_wclass(lattice, k) * p.rho0;
+        p.restf[k] = float(p.restd[k]);
+    }
     return p;
 }
 
@@ -566,7 +582,7 @@ mdf_status mdf_init(mdf_ctx **out, mdf_lattice lattice, mdf_storage storage, con
 
     mdf_ctx *ctx = new mdf_ctx;
     ctx->lattice = lattice;
-    ctx->shape.fuse = lat_2d(lattice) ? 1 : 0;     // two steps per launch by default in 2D
+    ctx->shape.fuse = lat_fusable(lattice) ? 1 : 0;     // two steps per launch by default in 2D
     ctx->storage = storage;
     ctx->d = lat_d(lattice);
     ctx->q = lat_q(lattice);
@@ -630,8 +646,10 @@ mdf_status mdf_set_launch(mdf_ctx *ctx, int32_t bx, int32_t by, int32_t groups, 
                     "mdf_set_launch: need bx %% 32 == 0 and bx*by a multiple of 64 up to 256 (got %d x %d)", bx, by);
     if (groups < 0 || groups > 64) return fail(ctx, MDF_EINVAL, "mdf_set_launch: groups outside [0, 64]");
     if (form < 0 || form > 2) return fail(ctx, MDF_EINVAL, "mdf_set_launch: form must be 0, 1 or 2");
-    if (form == 2 && !lat_2d(ctx->lattice))
-        return fail(ctx, MDF_EINVAL, "mdf_set_launch: two steps per launch needs a 2D lattice");
+    if (form == 2 && !lat_fusable(ctx->lattice))
+        return fail(ctx, MDF_EINVAL, "mdf_set_launch: two steps per launch needs a 2D lattice with axis links");
+    if (form == 1 && lat_diag(ctx->lattice))
+        return fail(ctx, MDF_EINVAL, "mdf_set_launch: the vector form needs a lattice with axis links");
     ctx->shape = LaunchShape{bx, by, groups, form == 1 ? 2 : 1, form == 2 ? 1 : 0};
     drop_graphs(ctx);
     return MDF_OK;
@@ -887,7 +905,8 @@ mdf_status mdf_autotune(mdf_ctx *ctx, int32_t trial_steps, int32_t *chosen, doub
     mdf_status r = MDF_OK;
     for (int c = 0; c < int(sizeof cand / sizeof cand[0]) && r == MDF_OK; ++c) {
         // two steps per launch: 2D contexts only
-        if (cand[c][3] == 2 && !lat_2d(ctx->lattice)) continue;
+        if (cand[c][3] == 2 && !lat_fusable(ctx->lattice)) continue;
+        if (cand[c][3] == 1 && lat_diag(ctx->lattice)) continue;
         r = mdf_set_launch(ctx, cand[c][0], cand[c][1], cand[c][2], cand[c][3]);
         if (r != MDF_OK) break;
         r = step_impl(ctx, 1, 0, nullptr, stream);           // warm-up (and graph capture)

@@ -33,8 +33,8 @@ struct KCase {
     float s1f, s2f, rho0f, Rf;
     float fbarf[4];
     float walluf[6][3];
-    double restd[2];
-    float restf[2];
+    double restd[3];        // w * rho0 by weight class: rest, axis, diagonal
+    float restf[3];
     // optional per-node force, d x nodes values component-major in the
     // compute dtype (caller-owned device memory), added to fbar[1..d]
     const void *ffield;
@@ -124,6 +124,10 @@ const LatOps &lat_ops_d2q4();
 const LatOps &lat_ops_d3q6();
 const LatOps &lat_ops_d2q4v();
 const LatOps &lat_ops_d3q6v();
+const LatOps &lat_ops_d2q9();
+const LatOps &lat_ops_d3q15();
+const LatOps &lat_ops_d2q9v();
+const LatOps &lat_ops_d3q15v();
 
 // Launchers (implemented in mdf_launch.hip).  All enqueue on `stream` and
 // return the hipError_t of the launch.

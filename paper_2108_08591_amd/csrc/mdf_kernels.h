@@ -51,10 +51,14 @@ namespace {
 // quantity reads it).  R is the index of the first moving population (1
 // after the rest population, 0 on lattices without one) and K the index of
 // the population that closes the zeroth-moment identity of the collision
-// (the rest population, else the last moving one).  On every lattice here
-// all moving weights are equal (w1) and w1 / cs^2 = 1/2.
+// (the rest population, else the last moving one).  w[i] is the weight of
+// direction i and wc[i] its class (0 rest, 1 axis, 2 diagonal: the index of
+// the case's rest-value table); DIAG marks lattices with diagonal links.
 struct LatD2Q5 {
     static constexpr int D = 2, Q = 5, NS = 3, A0 = 0, R = 1, K = 0;
+    static constexpr bool DIAG = false;
+    static constexpr double w[5] = {1.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0};
+    static constexpr int wc[5] = {0, 1, 1, 1, 1};
     static constexpr int cx[5] = {0, 1, 0, -1, 0};
     static constexpr int cy[5] = {0, 0, 1, 0, -1};
     static constexpr int cz[5] = {0, 0, 0, 0, 0};
@@ -66,6 +70,9 @@ struct LatD2Q5 {
 // D3Q7 (eq. d3q7).
 struct LatD3Q7 {
     static constexpr int D = 3, Q = 7, NS = 4, A0 = 0, R = 1, K = 0;
+    static constexpr bool DIAG = false;
+    static constexpr double w[7] = {1.0 / 4.0, 1.0 / 8.0, 1.0 / 8.0, 1.0 / 8.0, 1.0 / 8.0, 1.0 / 8.0, 1.0 / 8.0};
+    static constexpr int wc[7] = {0, 1, 1, 1, 1, 1, 1};
     static constexpr int cx[7] = {0, 1, -1, 0, 0, 0, 0};
     static constexpr int cy[7] = {0, 0, 0, 1, -1, 0, 0};
     static constexpr int cz[7] = {0, 0, 0, 0, 0, 1, -1};
@@ -78,6 +85,9 @@ struct LatD3Q7 {
 // stands for a moving weight in expressions shared with the other lattices.
 struct LatD2Q4 {
     static constexpr int D = 2, Q = 4, NS = 3, A0 = 0, R = 0, K = 3;
+    static constexpr bool DIAG = false;
+    static constexpr double w[4] = {1.0 / 4.0, 1.0 / 4.0, 1.0 / 4.0, 1.0 / 4.0};
+    static constexpr int wc[4] = {1, 1, 1, 1};
     static constexpr int cx[4] = {1, 0, -1, 0};
     static constexpr int cy[4] = {0, 1, 0, -1};
     static constexpr int cz[4] = {0, 0, 0, 0};
@@ -88,6 +98,9 @@ struct LatD2Q4 {
 
 struct LatD3Q6 {
     static constexpr int D = 3, Q = 6, NS = 4, A0 = 0, R = 0, K = 5;
+    static constexpr bool DIAG = false;
+    static constexpr double w[6] = {1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0};
+    static constexpr int wc[6] = {1, 1, 1, 1, 1, 1};
     static constexpr int cx[6] = {1, -1, 0, 0, 0, 0};
     static constexpr int cy[6] = {0, 0, 1, -1, 0, 0};
     static constexpr int cz[6] = {0, 0, 0, 0, 1, -1};
@@ -95,6 +108,49 @@ struct LatD3Q6 {
     static constexpr double w0 = 1.0 / 6.0, w1 = 1.0 / 6.0;
     static constexpr double cs2 = 1.0 / 3.0, inv_cs2 = 3.0;
 };
+
+// D2Q9 (eq. d2q9) and D3Q15 (eq. d3q15), in the printed column order: a
+// rest population, axis links and diagonal links with weights of their own
+// (w / cs^2 = 1/3 on the axes, 1/12 and 1/24 on the diagonals).
+struct LatD2Q9 {
+    static constexpr int D = 2, Q = 9, NS = 3, A0 = 0, R = 1, K = 0;
+    static constexpr bool DIAG = true;
+    static constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    static constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    static constexpr int cz[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    static constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    static constexpr double w[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                                    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+    static constexpr int wc[9] = {0, 1, 1, 1, 1, 2, 2, 2, 2};
+    static constexpr double w0 = 4.0 / 9.0, w1 = 1.0 / 9.0;
+    static constexpr double cs2 = 1.0 / 3.0, inv_cs2 = 3.0;
+};
+
+struct LatD3Q15 {
+    static constexpr int D = 3, Q = 15, NS = 4, A0 = 0, R = 1, K = 0;
+    static constexpr bool DIAG = true;
+    static constexpr int cx[15] = {0, 1, -1, 0, 0, 0, 0, 1, 1, 1, -1, -1, -1, 1, -1};
+    static constexpr int cy[15] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, 1, -1, 1, -1, -1};
+    static constexpr int cz[15] = {0, 0, 0, 0, 0, 1, -1, 1, -1, 1, 1, 1, -1, -1, -1};
+    static constexpr int opp[15] = {0, 2, 1, 4, 3, 6, 5, 14, 11, 12, 13, 8, 9, 10, 7};
+    static constexpr double w[15] = {2.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                                     1.0 / 72.0, 1.0 / 72.0, 1.0 / 72.0, 1.0 / 72.0, 1.0 / 72.0, 1.0 / 72.0,
+                                     1.0 / 72.0, 1.0 / 72.0};
+    static constexpr int wc[15] = {0, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2};
+    static constexpr double w0 = 2.0 / 9.0, w1 = 1.0 / 9.0;
+    static constexpr double cs2 = 1.0 / 3.0, inv_cs2 = 3.0;
+};
+
+// The table of opposite directions: c_opp(i) = -c_i for every i.
+template <class L>
+constexpr bool opposites_ok()
+{
+    for (int i = 0; i < L::Q; ++i)
+        if (L::cx[L::opp[i]] != -L::cx[i] || L::cy[L::opp[i]] != -L::cy[i] || L::cz[L::opp[i]] != -L::cz[i])
+            return false;
+    return true;
+}
+static_assert(opposites_ok<LatD2Q9>() && opposites_ok<LatD3Q15>(), "opposite-direction tables");
 
 // The same lattices storing only the velocity sets a = 1..d.
 struct LatD2Q5V : LatD2Q5 {
@@ -107,6 +163,12 @@ struct LatD2Q4V : LatD2Q4 {
     static constexpr int NS = 2, A0 = 1;
 };
 struct LatD3Q6V : LatD3Q6 {
+    static constexpr int NS = 3, A0 = 1;
+};
+struct LatD2Q9V : LatD2Q9 {
+    static constexpr int NS = 2, A0 = 1;
+};
+struct LatD3Q15V : LatD3Q15 {
     static constexpr int NS = 3, A0 = 1;
 };
 
@@ -290,7 +352,7 @@ template <class L, class C>
 __device__ __forceinline__ C rest_value(const KCase &p, int a, int i)
 {
     if (a + L::A0 != 0) return C(0);
-    return kpar<C>(p.restd[i != 0], p.restf[i != 0]);
+    return kpar<C>(p.restd[L::wc[i]], p.restf[L::wc[i]]);
 }
 
 // ----------------------------------------------------------------- node state
@@ -357,18 +419,26 @@ __device__ __forceinline__ bool gather(const KCase &p, const typename Store<ST>:
                 else if (sx >= p.nx) { if (p.bc[1] == MDF_WALL) face = 1; else sx -= p.nx; }
             }
             if (L::cy[i] != 0) {
-                if (sy < 0) { if (p.bc[2] == MDF_WALL) face = 2; else sy += p.ny; }
-                else if (sy >= p.ny) { if (p.bc[3] == MDF_WALL) face = 3; else sy -= p.ny; }
+                if (sy < 0) { if (p.bc[2] == MDF_WALL) { if (face < 0) face = 2; } else sy += p.ny; }
+                else if (sy >= p.ny) { if (p.bc[3] == MDF_WALL) { if (face < 0) face = 3; } else sy -= p.ny; }
             }
             if (L::cz[i] != 0) {
-                if (sz < 0) { if (p.bc[4] == MDF_WALL) face = 4; else sz += p.nz; }
-                else if (sz >= p.nz) { if (p.bc[5] == MDF_WALL) face = 5; else sz -= p.nz; }
+                if (sz < 0) { if (p.bc[4] == MDF_WALL) { if (face < 0) face = 4; } else sz += p.nz; }
+                else if (sz >= p.nz) { if (p.bc[5] == MDF_WALL) { if (face < 0) face = 5; } else sz -= p.nz; }
             }
-            if (MASK && face < 0 && ((lb >> i) & 1u)) face = 6;
+            if (MASK && face < 0) {
+                if constexpr (L::DIAG) {
+                    // more moving directions than link bits: read the
+                    // upstream node's solid flag
+                    if (links[((long long)sz * p.ny + sy) * p.pitch + sx] & 0x80u) face = 6;
+                } else if ((lb >> i) & 1u) {
+                    face = 6;
+                }
+            }
         } else {
             sx = x; sy = y; sz = z;
         }
-        const C w = C(i == 0 ? L::w0 : L::w1);
+        const C w = C(L::w[i]);
         if (face < 0) {
             const long long k = ((long long)sz * p.ny + sy) * p.pitch + sx;
 #pragma unroll
@@ -430,14 +500,14 @@ __device__ __forceinline__ void gather_vec(const KCase &p, const typename Store<
         int sy = y - L::cy[i], sz = z - L::cz[i];
         int face = -1;
         if (L::cy[i] != 0) {
-            if (sy < 0) { if (p.bc[2] == MDF_WALL) face = 2; else sy += p.ny; }
-            else if (sy >= p.ny) { if (p.bc[3] == MDF_WALL) face = 3; else sy -= p.ny; }
+            if (sy < 0) { if (p.bc[2] == MDF_WALL) { if (face < 0) face = 2; } else sy += p.ny; }
+            else if (sy >= p.ny) { if (p.bc[3] == MDF_WALL) { if (face < 0) face = 3; } else sy -= p.ny; }
         }
         if (L::cz[i] != 0) {
-            if (sz < 0) { if (p.bc[4] == MDF_WALL) face = 4; else sz += p.nz; }
-            else if (sz >= p.nz) { if (p.bc[5] == MDF_WALL) face = 5; else sz -= p.nz; }
+            if (sz < 0) { if (p.bc[4] == MDF_WALL) { if (face < 0) face = 4; } else sz += p.nz; }
+            else if (sz >= p.nz) { if (p.bc[5] == MDF_WALL) { if (face < 0) face = 5; } else sz -= p.nz; }
         }
-        const C w = C(i == 0 ? L::w0 : L::w1);
+        const C w = C(L::w[i]);
         const int j = L::opp[i];
 #pragma unroll
         for (int a = 0; a < L::NS; ++a) {
@@ -537,7 +607,6 @@ __device__ __forceinline__ void moments(const KCase &p, const Node<L, C> &n, Mom
 template <class L, class C>
 __device__ __forceinline__ void equilibrium(C ub, const C (&flux)[L::D], C (&feq)[L::Q])
 {
-    const C even = C(L::w1) * ub;
     C rest = ub;
 #pragma unroll
     for (int i = L::R; i < L::Q; ++i) {
@@ -547,7 +616,8 @@ __device__ __forceinline__ void equilibrium(C ub, const C (&flux)[L::D], C (&feq
             if (cdir<L>(i, b) > 0) cf += flux[b];
             else if (cdir<L>(i, b) < 0) cf -= flux[b];
         }
-        feq[i] = even + C(L::w1 * L::inv_cs2) * cf;
+        const C even = C(L::w[i]) * ub;
+        feq[i] = even + C(L::w[i] * L::inv_cs2) * cf;
         rest -= even;
     }
     if (L::R == 1) feq[0] = rest;
@@ -593,11 +663,11 @@ __device__ __forceinline__ void collide_set(const KCase &p, const Node<L, C> &n,
                                             const C (&ne)[L::Q], C (&out)[L::Q], C fb)
 {
     const C s1 = kpar<C>(p.s1, p.s1f), s2 = kpar<C>(p.s2, p.s2f);
-    const C wf = C(L::w1) * fb * kpar<C>(p.fmove, p.fmovef);
     C dsum = C(0);
 #pragma unroll
     for (int i = L::R; i < L::Q; ++i) {
         if (i == L::K) continue;
+        const C wf = C(L::w[i]) * fb * kpar<C>(p.fmove, p.fmovef);
         const int j = L::opp[i];
         const C odd = C(0.5) * (ne[i] - ne[j]);
         const C even = C(0.5) * (ne[i] + ne[j]);
@@ -1064,11 +1134,11 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int gy, int t
                 else if (sx >= p.nx) { if (p.bc[1] == MDF_WALL) face = 1; }
             }
             if (L::cy[i] != 0) {
-                if (sy < 0) { if (p.bc[2] == MDF_WALL) face = 2; }
-                else if (sy >= p.ny) { if (p.bc[3] == MDF_WALL) face = 3; }
+                if (sy < 0) { if (p.bc[2] == MDF_WALL) { if (face < 0) face = 2; } }
+                else if (sy >= p.ny) { if (p.bc[3] == MDF_WALL) { if (face < 0) face = 3; } }
             }
             if (MASK && face < 0 && ((lb >> i) & 1u)) face = 6;
-            const C w = C(i == 0 ? L::w0 : L::w1);
+            const C w = C(L::w[i]);
             if (face < 0) {
                 const int k = le - L::cx[i] - L::cy[i] * W;
 #pragma unroll
@@ -1301,17 +1371,17 @@ k_init(KCase p, typename Store<ST>::T *__restrict__ pre, typename Store<ST>::T *
                     else if (cdir<L>(i, b) < 0) cg -= g;
                 }
                 // f^eq (eq. 2-4) + f^ne with f^ne = -(1/s1) w_i c_i . grad u_a
-                n.f[a][i] = feq[i] - (C(1) / C(p.s1)) * C(L::w1) * cg;
+                n.f[a][i] = feq[i] - (C(1) / C(p.s1)) * C(L::w[i]) * cg;
             }
             if (p.forcing == MDF_FORCING_SCHEME2) {
                 // stored state fbar = f - w_i Fbar_a / 2, so that eq. 2-7a
                 // gives back the initial ubar_a
                 const C hf = C(0.5) * source_of<C>(p, pa, node);
-                const C whf = C(L::w1) * hf;
                 C moved = C(0);
 #pragma unroll
                 for (int i = L::R; i < L::Q; ++i) {
                     if (i == L::K) continue;
+                    const C whf = C(L::w[i]) * hf;
                     n.f[a][i] -= whf;
                     moved += whf;
                 }
@@ -1349,6 +1419,7 @@ __global__ void __launch_bounds__(256) k_links(KCase p, const uint8_t *__restric
     unsigned bits = (solid && solid[node]) ? 0x80u : 0u;
 #pragma unroll
     for (int i = L::R; i < L::Q; ++i) {
+        if (L::DIAG) break;               // diagonal lattices read the upstream flag instead
         int s[3] = {x - L::cx[i], y - L::cy[i], z - L::cz[i]};
         const int nn[3] = {p.nx, p.ny, p.nz};
         bool outside = false;
@@ -1391,7 +1462,9 @@ hipError_t step_dispatch(const KCase &p, const CaseBufs &b, int src, bool check,
     T *o = static_cast<T *>(b.pop[src ^ 1]);
     C *emit = static_cast<C *>(out);
     C *snap = static_cast<C *>(b.snap);
-    const int vx = s.vx > 1 ? S::VX : 1;
+    // the vector form exists for axis-link lattices only
+    constexpr int VW = L::DIAG ? 1 : S::VX;
+    const int vx = s.vx > 1 ? VW : 1;
     const Tiling tl = tiling_of(p, s, vx);
     const dim3 grid(tl.nb, 1, 1), block(s.bx, s.by, 1);
     const bool emit_on = (fields != 0) && out != nullptr;
@@ -1399,7 +1472,7 @@ hipError_t step_dispatch(const KCase &p, const CaseBufs &b, int src, bool check,
 #define MDF_STEP_LAUNCH1(E, K, M, V) \
     hipLaunchKernelGGL((k_step<L, ST, E, K, M, V>), grid, block, 0, stream, p, tl, in, o, b.links, fields, emit, snap, b.partial)
 #define MDF_STEP_LAUNCH(E, K, M) \
-    do { if (vx > 1) MDF_STEP_LAUNCH1(E, K, M, S::VX); else MDF_STEP_LAUNCH1(E, K, M, 1); } while (0)
+    do { if (vx > 1) MDF_STEP_LAUNCH1(E, K, M, VW); else MDF_STEP_LAUNCH1(E, K, M, 1); } while (0)
     if (mask) {
         if (emit_on) { if (check) MDF_STEP_LAUNCH(true, true, true); else MDF_STEP_LAUNCH(true, false, true); }
         else { if (check) MDF_STEP_LAUNCH(false, true, true); else MDF_STEP_LAUNCH(false, false, true); }
@@ -1419,7 +1492,7 @@ hipError_t step2_dispatch(const KCase &p, const CaseBufs &b, int src, uint32_t f
     using S = Store<ST>;
     using T = typename S::T;
     using C = typename S::C;
-    if constexpr (L::D != 2) {
+    if constexpr (L::D != 2 || L::DIAG) {
         return hipErrorInvalidValue;
     } else {
         const T *in = static_cast<const T *>(b.pop[src]);
@@ -1495,12 +1568,13 @@ template <class L, int ST>
 hipError_t batch_dispatch(const BatchLaunch &bl, bool check, bool emit, hipStream_t stream)
 {
     using S = Store<ST>;
+    constexpr int VW = L::DIAG ? 1 : S::VX;      // the vector form exists for axis-link lattices only
     const dim3 grid(bl.grid, 1, 1), block(bl.shape.bx, bl.shape.by, 1);
 #define MDF_BATCH_LAUNCH1(E, K, M, V)                                                                      \
     hipLaunchKernelGGL((k_step_batch<L, ST, E, K, M, V>), grid, block, 0, stream, bl.tab, bl.meta, bl.tile_start, \
                        bl.active, bl.parity, bl.fields, bl.shape.groups)
 #define MDF_BATCH_LAUNCH(E, K, M) \
-    do { if (bl.shape.vx > 1) MDF_BATCH_LAUNCH1(E, K, M, S::VX); else MDF_BATCH_LAUNCH1(E, K, M, 1); } while (0)
+    do { if (bl.shape.vx > 1) MDF_BATCH_LAUNCH1(E, K, M, VW); else MDF_BATCH_LAUNCH1(E, K, M, 1); } while (0)
     if (bl.mask) {
         if (emit) { if (check) MDF_BATCH_LAUNCH(true, true, true); else MDF_BATCH_LAUNCH(true, false, true); }
         else { if (check) MDF_BATCH_LAUNCH(false, true, true); else MDF_BATCH_LAUNCH(false, false, true); }
@@ -1516,7 +1590,7 @@ hipError_t batch_dispatch(const BatchLaunch &bl, bool check, bool emit, hipStrea
 template <class L, int ST>
 hipError_t batch2_dispatch(const BatchLaunch &bl, bool emit, hipStream_t stream)
 {
-    if constexpr (L::D != 2) {
+    if constexpr (L::D != 2 || L::DIAG) {
         return hipErrorInvalidValue;
     } else {
         const dim3 grid(bl.grid, 1, 1), block(Fuse2Rows<ST>::NT, 1, 1);
@@ -1533,7 +1607,7 @@ hipError_t batch2_dispatch(const BatchLaunch &bl, bool emit, hipStream_t stream)
 template <class L, int ST>
 hipError_t batch2_capacity(bool mask, int *blocks_per_cu)
 {
-    if constexpr (L::D != 2) {
+    if constexpr (L::D != 2 || L::DIAG) {
         return hipErrorInvalidValue;
     } else {
         if (mask)
@@ -1549,13 +1623,14 @@ hipError_t batch_capacity(LaunchShape shape, bool mask, int *blocks_per_cu)
 {
     // resident blocks per CU of the heaviest variant (emit + check)
     using S = Store<ST>;
+    constexpr int VW = L::DIAG ? 1 : S::VX;
     const int threads = shape.bx * shape.by;
     if (shape.vx > 1) {
         if (mask)
             return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                blocks_per_cu, k_step_batch<L, ST, true, true, true, S::VX>, threads, 0);
+                blocks_per_cu, k_step_batch<L, ST, true, true, true, VW>, threads, 0);
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu,
-                                                            k_step_batch<L, ST, true, true, false, S::VX>, threads, 0);
+                                                            k_step_batch<L, ST, true, true, false, VW>, threads, 0);
     }
     if (mask)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_step_batch<L, ST, true, true, true, 1>,

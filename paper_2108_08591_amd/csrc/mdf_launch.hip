@@ -69,6 +69,10 @@ const LatOps *ops_of(int lattice)
     case MDF_D3Q6: return &lat_ops_d3q6();
     case MDF_D2Q4_V: return &lat_ops_d2q4v();
     case MDF_D3Q6_V: return &lat_ops_d3q6v();
+    case MDF_D2Q9: return &lat_ops_d2q9();
+    case MDF_D3Q15: return &lat_ops_d3q15();
+    case MDF_D2Q9_V: return &lat_ops_d2q9v();
+    case MDF_D3Q15_V: return &lat_ops_d3q15v();
     }
     return nullptr;
 }

@@ -22,7 +22,8 @@ LIB_PATH = os.path.join(HERE, "libmdf.so")
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
 D2Q5, D3Q7 = 0, 1
 D2Q4, D3Q6 = 4, 5      # lattices without a rest population
-_NQ = {D2Q5: 5, D3Q7: 7, D2Q4: 4, D3Q6: 6}
+D2Q9, D3Q15 = 8, 9     # lattices with diagonal links
+_NQ = {D2Q5: 5, D3Q7: 7, D2Q4: 4, D3Q6: 6, D2Q9: 9, D3Q15: 15}
 F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
 PERIODIC, WALL = 0, 1
 FIELD_MOMENTS, FIELD_GRAD, FIELD_DIV, FIELD_STRAIN, FIELD_STRESS, FIELD_VORT = 1, 2, 4, 8, 16, 32

@@ -57,7 +57,7 @@ def test_velocity_set_lattices_store_d_of_d_plus_one_sets():
         one_set = 2 * q * spec.nodes * 4          # both ping-pong buffers, FP32
         assert full - vel == pytest.approx(one_set, rel=0.02)
         assert full > (d + 1) * one_set
-    assert mdf.lib().mdf_workspace_size(8, mdf.F32, c, 1, 0) == 0
+    assert mdf.lib().mdf_workspace_size(12, mdf.F32, c, 1, 0) == 0
 
 
 def test_rest_free_lattices_store_q_minus_one_planes():
@@ -72,6 +72,17 @@ def test_rest_free_lattices_store_q_minus_one_planes():
         assert full - rest_free == pytest.approx((q_full - q) * plane, rel=0.02)
     c3 = (mdf.MdfCase * 1)(mdf._case_struct(C.tgv3d_case(N=16, u0=0.05, Re=100.0)))
     assert mdf.lib().mdf_workspace_size(mdf.D2Q4, mdf.F32, c3, 1, 0) == 0
+
+
+def test_diagonal_lattices_store_q_planes():
+    """MDF_D2Q9 / MDF_D3Q15 (eq. d2q9, d3q15) keep 9 and 15 planes per set."""
+    for spec, lat, q_full, q in ((C.cavity_case(N=256, Re=100), mdf.D2Q9, 5, 9),
+                                 (C.tgv3d_case(N=64, u0=0.05, Re=100.0), mdf.D3Q15, 7, 15)):
+        c = (mdf.MdfCase * 1)(mdf._case_struct(spec))
+        base = mdf.lib().mdf_workspace_size(spec.lattice, mdf.F32, c, 1, 0)
+        diag = mdf.lib().mdf_workspace_size(lat, mdf.F32, c, 1, 0)
+        plane = 2 * (spec.d + 1) * spec.nodes * 4
+        assert diag - base == pytest.approx((q - q_full) * plane, rel=0.02)
 
 
 @pytest.mark.parametrize("mutate,msg", [
@@ -106,7 +117,7 @@ def test_init_rejects_before_touching_the_device():
                     None, 0, None, None)
     assert st == mdf.ENOMEM
     # bad lattice / storage / init kind
-    assert L.mdf_init(ctypes.byref(ctx), 8, mdf.F32, cases, 1, ctypes.c_void_p(256), 1 << 30,
+    assert L.mdf_init(ctypes.byref(ctx), 12, mdf.F32, cases, 1, ctypes.c_void_p(256), 1 << 30,
                       None, 0, None, None) == mdf.EINVAL
     assert L.mdf_init(ctypes.byref(ctx), mdf.D2Q5, 9, cases, 1, ctypes.c_void_p(256), 1 << 30,
                       None, 0, None, None) == mdf.EINVAL

@@ -1,7 +1,8 @@
-"""The lattices without a rest population, D2Q4 and D3Q6 (eq. d2q4, eq. d3q6),
-on the HIP path: parity with the FP64 oracle, identity of every launch form,
-the velocity-set variant, batches, and FP32 conservation of the zeroth
-moment (the population that closes it is a moving one on these lattices).
+"""The lattices beyond D2Q5/D3Q7 on the HIP path: D2Q4 and D3Q6 without a
+rest population (eq. d2q4, eq. d3q6), and D2Q9 and D3Q15 with diagonal links
+(eq. d2q9, eq. d3q15, one node per thread).  Parity with the FP64 oracle,
+identity of every launch form, the velocity-set variant, batches, and FP32
+conservation of the zeroth moment.
 
 Bar: FP64 storage within 1e-12 relative L2, FP32 within 1e-5; sizes ragged.
 """
@@ -54,7 +55,30 @@ def _setups():
     mask = np.zeros(spec.fshape, np.uint8)
     mask[2:5, 3:7, 8:12] = 1
     out.append(("d3q6_walls_mask", spec, mask))
+    # diagonal links: a cavity whose corners exercise the x-before-y wall
+    # tie-break, a periodic box with a force, obstacles in 2D and 3D
+    wall = np.zeros((6, 3))
+    wall[3] = (0.08, 0.01, 0)
+    wall[0] = (0.0, -0.03, 0)
+    out.append(("d2q9_walls", C.CaseSpec(C.D2Q9, (53, 37), 0.93, bc=(1, 1, 1, 1, 0, 0), wall_u=wall), None))
+    spec = C.CaseSpec(C.D2Q9, (66, 33), 1.6, bc=(0, 0, 1, 1, 0, 0), force=(2e-5, 0), forcing=C.SCHEME2)
+    mask = np.zeros(spec.fshape, np.uint8)
+    mask[10:18, 20:31] = 1
+    mask[20:25, 60:66] = 1
+    out.append(("d2q9_mask_scheme2", spec, mask))
+    out.append(("d3q15_periodic", C.CaseSpec(C.D3Q15, (21, 13, 9), 1.45, force=(1e-4, 2e-4, -3e-4), R=1e-4),
+                None))
+    wall = np.zeros((6, 3))
+    wall[3] = (0.05, 0, 0.02)
+    wall[4] = (0.0, 0.01, 0.0)
+    spec = C.CaseSpec(C.D3Q15, (19, 11, 7), 0.9, bc=(0, 0, 1, 1, 1, 1), wall_u=wall)
+    mask = np.zeros(spec.fshape, np.uint8)
+    mask[2:5, 3:7, 8:12] = 1
+    out.append(("d3q15_walls_mask", spec, mask))
     return out
+
+
+DIAG = (C.D2Q9, C.D3Q15)
 
 
 SETUPS = _setups()
@@ -67,8 +91,8 @@ def test_rest_free_steps_from_random_populations(idx, storage, form):
     """Arbitrary populations, then 1 and 3 more steps (one and two steps per
     launch in 2D): every population and field matches the oracle."""
     name, spec, mask = SETUPS[idx]
-    if form == 2 and spec.d == 3:
-        pytest.skip("two steps per launch is a 2D form")
+    if form == 2 and (spec.d == 3 or spec.lattice in DIAG):
+        pytest.skip("two steps per launch is a form of the 2D axis-link lattices")
     _say(f"[lattices] random populations {name} {storage} form {form} shape={spec.shape}")
     f0 = _cast(C.random_populations(spec, seed=200 + idx, scale=0.05), storage)
     s = mdf.Solver([spec], storage=storage, solid=None if mask is None else [mask],
@@ -85,16 +109,17 @@ def test_rest_free_steps_from_random_populations(idx, storage, form):
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-@pytest.mark.parametrize("lat", [C.D2Q4, C.D3Q6])
+@pytest.mark.parametrize("lat", [C.D2Q4, C.D3Q6, C.D2Q9, C.D3Q15])
 def test_rest_free_cavity_from_rest(lat, storage):
-    """A lid-driven box from rest, 600 steps, against the oracle."""
-    if lat == C.D2Q4:
-        spec = C.cavity_case(N=80, Re=100.0, U=0.1, lattice=C.D2Q4)
+    """A lid-driven box from rest, 600 steps, against the oracle (with
+    diagonal links the lid corners take the x-before-y tie-break)."""
+    if C.DIM[lat] == 2:
+        spec = C.cavity_case(N=80, Re=100.0, U=0.1, lattice=lat)
         spec.shape = (80, 66)
     else:
         wall = np.zeros((6, 3))
         wall[3] = (0.05, 0, 0)
-        spec = C.CaseSpec(C.D3Q6, (22, 18, 13), 1.2, bc=(C.WALL,) * 6, wall_u=wall)
+        spec = C.CaseSpec(lat, (22, 18, 13), 1.2, bc=(C.WALL,) * 6, wall_u=wall)
     _say(f"[lattices] cavity from rest {spec.shape} {storage}")
     s = mdf.Solver([spec], storage=storage, device=DEV)
     o = oracle_for(spec).init(0.0, np.zeros((spec.d,) + spec.fshape))
@@ -116,7 +141,14 @@ def _shape_cases():
                      wall_u=((0, 0, 0), (0, 0, 0), (0, 0, 0), (0.05, 0, 0), (0, 0, 0), (0, 0.02, 0)))
     wide = C.cavity_case(N=300, Re=300.0, lattice=C.D2Q4)
     wide.shape = (302, 90)
-    return [("cavity", cav, None), ("periodic+mask", per, mask), ("box3d", box, None), ("wide cavity", wide, None)]
+    cav9 = C.cavity_case(N=102, Re=100.0, lattice=C.D2Q9)
+    cav9.shape = (102, 70)
+    per9 = C.tgv2d_case(N=70, u0=0.02, Re=20.0, lattice=C.D2Q9)
+    per9.shape = (70, 46)
+    box15 = C.CaseSpec(C.D3Q15, (38, 22, 14), 1.1, bc=(C.PERIODIC, C.PERIODIC, C.WALL, C.WALL, C.WALL, C.WALL),
+                       wall_u=((0, 0, 0), (0, 0, 0), (0, 0, 0), (0.05, 0, 0), (0, 0, 0), (0, 0.02, 0)))
+    return [("cavity", cav, None), ("periodic+mask", per, mask), ("box3d", box, None), ("wide cavity", wide, None),
+            ("d2q9 cavity", cav9, None), ("d2q9 periodic+mask", per9, mask), ("d3q15 box", box15, None)]
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16dev", "bf16dev"])
@@ -124,8 +156,11 @@ def test_rest_free_launch_shapes_bitwise_identical(storage):
     """Scalar, vector and two-step kernels and any tile shape give the same
     populations and emitted fields bit for bit."""
     for name, spec, mask in _shape_cases():
-        shapes = [(64, 4, 8, 0), (64, 4, 8, 1), (256, 1, 8, 1), (128, 2, 3, 1), (32, 8, 8, 0)]
-        if spec.d == 2:
+        if spec.lattice in DIAG:
+            shapes = [(64, 4, 8, 0), (256, 1, 8, 0), (128, 2, 3, 0), (32, 8, 1, 0)]
+        else:
+            shapes = [(64, 4, 8, 0), (64, 4, 8, 1), (256, 1, 8, 1), (128, 2, 3, 1), (32, 8, 8, 0)]
+        if spec.d == 2 and spec.lattice not in DIAG:
             shapes += [(64, 4, 8, 2), (128, 2, 1, 2)]
         pops, outs = [], []
         for bx, by, g, form in shapes:
@@ -145,15 +180,15 @@ def test_rest_free_launch_shapes_bitwise_identical(storage):
             assert torch.equal(o, outs[0])
 
 
-@pytest.mark.parametrize("lat", [C.D2Q4, C.D3Q6])
+@pytest.mark.parametrize("lat", [C.D2Q4, C.D3Q6, C.D2Q9, C.D3Q15])
 def test_rest_free_velocity_sets_equal_full_form(lat):
-    """Only the d velocity sets (Remark IV) on the rest-free lattices: the
-    same velocity-set populations and fields as all d + 1 sets, bit for bit."""
-    if lat == C.D2Q4:
-        spec = C.cavity_case(N=96, Re=150.0, lattice=C.D2Q4)
+    """Only the d velocity sets (Remark IV) on these lattices: the same
+    velocity-set populations and fields as all d + 1 sets, bit for bit."""
+    if C.DIM[lat] == 2:
+        spec = C.cavity_case(N=96, Re=150.0, lattice=lat)
         spec.shape = (98, 71)
     else:
-        spec = C.CaseSpec(C.D3Q6, (30, 20, 12), 1.2, bc=(C.PERIODIC, C.PERIODIC, C.WALL, C.WALL, C.WALL, C.WALL),
+        spec = C.CaseSpec(lat, (30, 20, 12), 1.2, bc=(C.PERIODIC, C.PERIODIC, C.WALL, C.WALL, C.WALL, C.WALL),
                           wall_u=((0, 0, 0), (0, 0, 0), (0, 0, 0), (0.04, 0, 0), (0, 0, 0), (0, 0, 0)))
     _say(f"[lattices] velocity sets vs full, lattice {lat}")
     full = mdf.Solver([spec], storage="f32", device=DEV)
@@ -164,12 +199,13 @@ def test_rest_free_velocity_sets_equal_full_form(lat):
     assert torch.equal(full.gradients(mdf.FIELD_ALL)[1:], vel.gradients(mdf.FIELD_ALL)[1:])
 
 
-def test_rest_free_batch_matches_oracle():
-    """Three uneven D2Q4 cases in one batched context (persistent launches)."""
-    specs = [C.CaseSpec(C.D2Q4, (40, 33), 1.2, force=(2e-5, 0.0)),
-             C.cavity_case(N=65, Re=80.0, lattice=C.D2Q4),
-             C.CaseSpec(C.D2Q4, (31, 47), 1.5, bc=(C.PERIODIC, C.PERIODIC, C.WALL, C.WALL, 0, 0))]
-    _say("[lattices] D2Q4 batch of 3, f64")
+@pytest.mark.parametrize("lat", [C.D2Q4, C.D2Q9])
+def test_rest_free_batch_matches_oracle(lat):
+    """Three uneven cases in one batched context (persistent launches)."""
+    specs = [C.CaseSpec(lat, (40, 33), 1.2, force=(2e-5, 0.0)),
+             C.cavity_case(N=65, Re=80.0, lattice=lat),
+             C.CaseSpec(lat, (31, 47), 1.5, bc=(C.PERIODIC, C.PERIODIC, C.WALL, C.WALL, 0, 0))]
+    _say(f"[lattices] batch of 3, lattice {lat}, f64")
     s = mdf.Solver(specs, storage="f64", device=DEV)
     s.step(37)
     for k, spec in enumerate(specs):
@@ -178,19 +214,34 @@ def test_rest_free_batch_matches_oracle():
         assert rel_err(o.populations(), _np(s.populations(k))) < 1e-12, k
 
 
-@pytest.mark.parametrize("lat", [C.D2Q4, C.D3Q6])
+@pytest.mark.parametrize("lat", [C.D2Q4, C.D3Q6, C.D2Q9, C.D3Q15])
 def test_rest_free_fp32_zeroth_moment_does_not_drift(lat):
     """FP32 on lattices whose weight 1/6 (D3Q6) does not round to a sum of
     one: the total of ubar_0 in a closed box stays within unbiased rounding,
     because a moving population closes the zeroth moment of the collision."""
-    if lat == C.D2Q4:
-        spec = C.cavity_case(N=256, Re=400.0, lattice=C.D2Q4)
+    if C.DIM[lat] == 2:
+        spec = C.cavity_case(N=256, Re=400.0, lattice=lat)
     else:
         wall = np.zeros((6, 3))
         wall[3] = (0.05, 0, 0)
-        spec = C.CaseSpec(C.D3Q6, (48, 48, 48), 1.3, bc=(C.WALL,) * 6, wall_u=wall)
+        spec = C.CaseSpec(lat, (48, 48, 48), 1.3, bc=(C.WALL,) * 6, wall_u=wall)
     _say(f"[lattices] fp32 mass drift, lattice {lat}")
     s = mdf.Solver([spec], storage="f32", device=DEV)
     m0 = s.invariants()[0]
     s.step(5000)
     assert abs(s.invariants()[0] / m0 - 1) < 2e-6
+
+
+@pytest.mark.parametrize("lat", [C.D2Q9, C.D3Q15])
+def test_diagonal_lattices_refuse_vector_and_two_step_forms(lat):
+    """One node per thread is the only form with diagonal links: forms 1 and
+    2 are refused with MDF_EINVAL and the context keeps stepping."""
+    spec = C.cavity_case(N=40, Re=50.0, lattice=lat) if C.DIM[lat] == 2 else \
+        C.CaseSpec(lat, (12, 10, 8), 1.2, bc=(C.WALL,) * 6)
+    s = mdf.Solver([spec], storage="f32", device=DEV)
+    for form in (1, 2):
+        with pytest.raises(mdf.MdfError):
+            s.set_launch(64, 4, 8, form)
+    s.set_launch(128, 2, 8, 0)
+    s.step(3)
+    assert torch.isfinite(s.populations()).all()
