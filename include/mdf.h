@@ -258,6 +258,27 @@ mdf_status mdf_invariants(const mdf_ctx *ctx, int32_t case_id, double *out, void
  * mdf_invariants follows it. */
 mdf_status mdf_set_launch(mdf_ctx *ctx, int32_t bx, int32_t by, int32_t groups, int32_t form);
 
+/* Checkpoint and resume.  The state of a context at its current time is
+ * both population buffers of every case (f*(t), and f*(t-1) that the read
+ * calls pull f(t) from), the time, the residual snapshot of mdf_check and
+ * the active flags, with a self-describing header.  The case parameters
+ * (rates, forces, walls, masks, a force field) are not part of it: they are
+ * those of the context it is loaded into, which must have the same lattice,
+ * storage and grids.
+ *   mdf_state_size: bytes of that state (0 for NULL).
+ *   mdf_save: writes it to dst, device memory or pinned host memory of at
+ *       least mdf_state_size() bytes, in stream order; returns after the
+ *       stream has passed the copies.
+ *   mdf_load: restores a state written by mdf_save from src (device or
+ *       pinned host memory, `bytes` long); steps and reads after it are
+ *       bitwise those the saved context would have produced.  Returns after
+ *       the copies; src may then be freed.
+ * MDF_EINVAL for NULL pointers, a short buffer, a blob that is not a saved
+ * state or one saved from a different lattice, storage or grid. */
+size_t mdf_state_size(const mdf_ctx *ctx);
+mdf_status mdf_save(mdf_ctx *ctx, void *dst, size_t bytes, void *stream);
+mdf_status mdf_load(mdf_ctx *ctx, const void *src, size_t bytes, void *stream);
+
 /* Per-node force (eq. 2-6 with a space-dependent F, as in the four-roll
  * mill of Section 4.2) for case `case_id`: F_b(x) at force[b * nodes + node]
  * for b = 0..d-1, node = (z * ny + y) * nx + x, in the compute dtype (double

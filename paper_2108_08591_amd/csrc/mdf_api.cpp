@@ -945,6 +945,158 @@ const char *mdf_last_error(const mdf_ctx *ctx)
     return ctx->err.c_str();
 }
 
+}  // extern "C"
+
+// ----------------------------------------------------------------- checkpoint
+
+namespace {
+
+struct StateHeader {
+    char magic[8];          // "MDFSTAT1"
+    int32_t lattice, storage, ncases, reserved;
+    uint64_t total_bytes;
+};
+
+struct StateCase {
+    int32_t nx, ny, nz, pitch;
+    int64_t time, snap_time;
+    int32_t enabled, reserved;
+    uint64_t pop_bytes, snap_bytes;     // one population buffer; the velocity snapshot
+};
+
+const char kStateMagic[8] = {'M', 'D', 'F', 'S', 'T', 'A', 'T', '1'};
+
+size_t case_pop_bytes(const mdf_ctx *ctx, int k)
+{
+    return size_t(lat_ns(ctx->lattice)) * ctx->q * size_t(ctx->kc[k].dstride) * storage_bytes(ctx->storage);
+}
+
+size_t case_snap_bytes(const mdf_ctx *ctx, int k)
+{
+    const KCase &p = ctx->kc[k];
+    return size_t(ctx->d) * size_t(p.nx) * p.ny * p.nz * compute_bytes(ctx->storage);
+}
+
+size_t state_bytes(const mdf_ctx *ctx)
+{
+    size_t n = sizeof(StateHeader) + size_t(ctx->ncases) * sizeof(StateCase);
+    for (int k = 0; k < ctx->ncases; ++k) n += 2 * case_pop_bytes(ctx, k) + case_snap_bytes(ctx, k);
+    return n;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mdf_state_size(const mdf_ctx *ctx)
+{
+    return ctx ? state_bytes(ctx) : 0;
+}
+
+mdf_status mdf_save(mdf_ctx *ctx, void *dst, size_t bytes, void *stream)
+{
+    if (!ctx) return fail(nullptr, MDF_EINVAL, "mdf_save: ctx is NULL");
+    if (ctx->latched != hipSuccess) return fail(ctx, MDF_EDEVICE, "earlier device error: %s",
+                                                hipGetErrorString(ctx->latched));
+    if (!dst) return fail(ctx, MDF_EINVAL, "mdf_save: dst is NULL");
+    const size_t need = state_bytes(ctx);
+    if (bytes < need) return fail(ctx, MDF_EINVAL, "mdf_save: %zu bytes given, %zu needed", bytes, need);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::vector<char> head(sizeof(StateHeader) + size_t(ctx->ncases) * sizeof(StateCase));
+    StateHeader h;
+    std::memset(&h, 0, sizeof h);
+    std::memcpy(h.magic, kStateMagic, 8);
+    h.lattice = ctx->lattice;
+    h.storage = ctx->storage;
+    h.ncases = ctx->ncases;
+    h.total_bytes = need;
+    std::memcpy(head.data(), &h, sizeof h);
+    char *out = static_cast<char *>(dst);
+    size_t off = head.size();
+    for (int k = 0; k < ctx->ncases; ++k) {
+        StateCase c;
+        std::memset(&c, 0, sizeof c);
+        c.nx = ctx->kc[k].nx;
+        c.ny = ctx->kc[k].ny;
+        c.nz = ctx->kc[k].nz;
+        c.pitch = ctx->kc[k].pitch;
+        c.time = ctx->time[k];
+        c.snap_time = ctx->snap_time[k];
+        c.enabled = ctx->enabled[k];
+        c.pop_bytes = case_pop_bytes(ctx, k);
+        c.snap_bytes = case_snap_bytes(ctx, k);
+        std::memcpy(head.data() + sizeof h + size_t(k) * sizeof c, &c, sizeof c);
+        // the buffer holding f*(t) first, then the one the read kernels pull from
+        const int cur = ctx->cur[k];
+        hipError_t e = hipMemcpyAsync(out + off, ctx->bufs[k].pop[cur], c.pop_bytes, hipMemcpyDefault, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(out + off + c.pop_bytes, ctx->bufs[k].pop[cur ^ 1], c.pop_bytes, hipMemcpyDefault, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(out + off + 2 * c.pop_bytes, ctx->bufs[k].snap, c.snap_bytes, hipMemcpyDefault, st);
+        if (e != hipSuccess) return device_error(ctx, e, "mdf_save copy");
+        off += 2 * c.pop_bytes + c.snap_bytes;
+    }
+    hipError_t e = hipMemcpyAsync(out, head.data(), head.size(), hipMemcpyDefault, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);      // `head` is a host temporary
+    if (e != hipSuccess) return device_error(ctx, e, "mdf_save header");
+    return MDF_OK;
+}
+
+mdf_status mdf_load(mdf_ctx *ctx, const void *src, size_t bytes, void *stream)
+{
+    if (!ctx) return fail(nullptr, MDF_EINVAL, "mdf_load: ctx is NULL");
+    if (ctx->latched != hipSuccess) return fail(ctx, MDF_EDEVICE, "earlier device error: %s",
+                                                hipGetErrorString(ctx->latched));
+    if (!src) return fail(ctx, MDF_EINVAL, "mdf_load: src is NULL");
+    const size_t need = state_bytes(ctx);
+    const size_t head_bytes = sizeof(StateHeader) + size_t(ctx->ncases) * sizeof(StateCase);
+    if (bytes < head_bytes) return fail(ctx, MDF_EINVAL, "mdf_load: %zu bytes is not a saved state", bytes);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::vector<char> head(head_bytes);
+    hipError_t e = hipMemcpyAsync(head.data(), src, head_bytes, hipMemcpyDefault, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return device_error(ctx, e, "mdf_load header");
+    StateHeader h;
+    std::memcpy(&h, head.data(), sizeof h);
+    if (std::memcmp(h.magic, kStateMagic, 8) != 0) return fail(ctx, MDF_EINVAL, "mdf_load: not a saved state");
+    if (h.lattice != ctx->lattice || h.storage != ctx->storage || h.ncases != ctx->ncases)
+        return fail(ctx, MDF_EINVAL, "mdf_load: saved with lattice %d, storage %d, %d cases; context has %d, %d, %d",
+                    h.lattice, h.storage, h.ncases, ctx->lattice, ctx->storage, ctx->ncases);
+    if (h.total_bytes != need || bytes < need)
+        return fail(ctx, MDF_EINVAL, "mdf_load: state of %llu bytes (%zu given), context needs %zu",
+                    (unsigned long long)h.total_bytes, bytes, need);
+    std::vector<StateCase> cs(ctx->ncases);
+    for (int k = 0; k < ctx->ncases; ++k) {
+        std::memcpy(&cs[k], head.data() + sizeof h + size_t(k) * sizeof(StateCase), sizeof(StateCase));
+        const StateCase &c = cs[k];
+        const KCase &p = ctx->kc[k];
+        if (c.nx != p.nx || c.ny != p.ny || c.nz != p.nz || c.pitch != p.pitch ||
+            c.pop_bytes != case_pop_bytes(ctx, k) || c.snap_bytes != case_snap_bytes(ctx, k))
+            return fail(ctx, MDF_EINVAL, "mdf_load: case %d was %d x %d x %d, context has %d x %d x %d", k, c.nx,
+                        c.ny, c.nz, p.nx, p.ny, p.nz);
+    }
+    const char *in = static_cast<const char *>(src);
+    size_t off = head_bytes;
+    for (int k = 0; k < ctx->ncases; ++k) {
+        const StateCase &c = cs[k];
+        e = hipMemcpyAsync(ctx->bufs[k].pop[0], in + off, c.pop_bytes, hipMemcpyDefault, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ctx->bufs[k].pop[1], in + off + c.pop_bytes, c.pop_bytes, hipMemcpyDefault, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ctx->bufs[k].snap, in + off + 2 * c.pop_bytes, c.snap_bytes, hipMemcpyDefault, st);
+        if (e != hipSuccess) return device_error(ctx, e, "mdf_load copy");
+        off += 2 * c.pop_bytes + c.snap_bytes;
+        ctx->cur[k] = 0;
+        ctx->time[k] = c.time;
+        ctx->snap_time[k] = c.snap_time;
+        ctx->enabled[k] = c.enabled ? 1 : 0;
+    }
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return device_error(ctx, e, "mdf_load synchronize");
+    drop_graphs(ctx);            // captured launches name the old buffer parity
+    return MDF_OK;
+}
+
 mdf_status mdf_destroy(mdf_ctx *ctx)
 {
     if (ctx) drop_graphs(ctx);

@@ -35,7 +35,7 @@ STORAGE_NAMES = {"f64": F64, "f32": F32, "f16dev": F16DEV, "bf16dev": BF16DEV}
 EXPORTED = ["mdf_workspace_size", "mdf_init", "mdf_step", "mdf_step_emit", "mdf_moments",
             "mdf_gradients", "mdf_populations", "mdf_check", "mdf_run_steady", "mdf_invariants",
             "mdf_set_launch", "mdf_set_active", "mdf_set_force_field", "mdf_autotune", "mdf_time",
-            "mdf_last_error",
+            "mdf_last_error", "mdf_state_size", "mdf_save", "mdf_load",
             "mdf_destroy"]
 
 
@@ -89,6 +89,10 @@ def lib():
         L.mdf_autotune.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl), vp]
         L.mdf_set_active.argtypes = [vp, ctypes.POINTER(i32)]
         L.mdf_set_force_field.argtypes = [vp, i32, vp]
+        L.mdf_state_size.argtypes = [vp]
+        L.mdf_state_size.restype = ctypes.c_size_t
+        L.mdf_save.argtypes = [vp, vp, ctypes.c_size_t, vp]
+        L.mdf_load.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.mdf_time.argtypes = [vp, i32]
         L.mdf_time.restype = i64
         L.mdf_last_error.argtypes = [vp]
@@ -96,7 +100,8 @@ def lib():
         L.mdf_destroy.argtypes = [vp]
         for name in ("mdf_init", "mdf_step", "mdf_step_emit", "mdf_moments", "mdf_gradients",
                      "mdf_populations", "mdf_check", "mdf_run_steady", "mdf_invariants",
-                     "mdf_set_launch", "mdf_set_active", "mdf_set_force_field", "mdf_autotune", "mdf_destroy"):
+                     "mdf_set_launch", "mdf_set_active", "mdf_set_force_field", "mdf_autotune", "mdf_destroy",
+                     "mdf_save", "mdf_load"):
             getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -300,6 +305,33 @@ class Solver:
         self._force[case] = t
         torch.cuda.current_stream().synchronize()
         _check(lib().mdf_set_force_field(self._ctx, case, ctypes.c_void_p(t.data_ptr())), self._ctx)
+
+    def state_size(self) -> int:
+        return int(lib().mdf_state_size(self._ctx))
+
+    def save(self, device=None) -> torch.Tensor:
+        """The solver's state (mdf_save) as a uint8 tensor on `device` (the
+        solver's device by default; "cpu" gives pinned host memory)."""
+        n = self.state_size()
+        dev = self.device if device is None else torch.device(device)
+        if dev.type == "cpu":
+            blob = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+        else:
+            blob = torch.empty(n, dtype=torch.uint8, device=dev)
+        self._handoff(blob)
+        _check(lib().mdf_save(self._ctx, ctypes.c_void_p(blob.data_ptr()), n, _stream_ptr(self.stream)),
+               self._ctx)
+        return blob
+
+    def load(self, blob: torch.Tensor):
+        """Restore a state written by save() (any device; copied to the
+        solver's device first when it is in pageable host memory)."""
+        b = blob.contiguous()
+        if b.device.type == "cpu" and not b.is_pinned():
+            b = b.to(self.device)
+            torch.cuda.current_stream(self.device).synchronize()
+        _check(lib().mdf_load(self._ctx, ctypes.c_void_p(b.data_ptr()), b.numel(), _stream_ptr(self.stream)),
+               self._ctx)
 
     def set_active(self, active):
         """Enable (non-zero) or disable (0) each case."""

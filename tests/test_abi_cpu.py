@@ -132,6 +132,9 @@ def test_init_rejects_before_touching_the_device():
 
 def test_null_context_calls_fail_cleanly():
     L = mdf.lib()
+    assert L.mdf_state_size(None) == 0
+    assert L.mdf_save(None, None, 0, None) == mdf.EINVAL
+    assert L.mdf_load(None, None, 0, None) == mdf.EINVAL
     assert L.mdf_step(None, 1, None) == mdf.EINVAL
     assert L.mdf_set_launch(None, 64, 4, 8, 1) == mdf.EINVAL
     assert L.mdf_time(None, 0) == -1
