@@ -52,6 +52,30 @@ def measured_traffic(kernel_key, launches_bytes):
     return ent.get("bytes_per_launch")
 
 
+def device_copy_bandwidth(nbytes=1 << 30, reps=5):
+    """Context for the roofline: a plain device-to-device copy of `nbytes`
+    (torch copy_, one read and one write per byte), HIP events, best of reps."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    best = None
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    torch.cuda.empty_cache()
+    return {"GBps": round(2 * nbytes / (best / 1e3) / 1e9, 1), "bytes_copied": nbytes,
+            "kind": "torch copy_ device to device, read + write bytes, HIP events, best of %d" % reps}
+
+
 def cpu_baseline(spec, target_s=15.0):
     """The FP64 oracle as it stands, timed on a bounded sample of the same
     cavity (full 1024^2 grid, a few steps)."""
@@ -954,6 +978,7 @@ def main():
         "MLUPS": round(big.nodes * steps_per_launch / (big_ms / 1e3) / 1e6, 1)}
     del bsolver, bout
     torch.cuda.empty_cache()
+    result["device_copy"] = device_copy_bandwidth()
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(spec)
     print(json.dumps(result), flush=True)

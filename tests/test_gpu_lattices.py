@@ -87,7 +87,7 @@ SETUPS = _setups()
 @pytest.mark.parametrize("form", [0, 2])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 @pytest.mark.parametrize("idx", range(len(SETUPS)), ids=[s[0] for s in SETUPS])
-def test_rest_free_steps_from_random_populations(idx, storage, form):
+def test_lattice_steps_from_random_populations(idx, storage, form):
     """Arbitrary populations, then 1 and 3 more steps (one and two steps per
     launch in 2D): every population and field matches the oracle."""
     name, spec, mask = SETUPS[idx]
@@ -110,7 +110,7 @@ def test_rest_free_steps_from_random_populations(idx, storage, form):
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 @pytest.mark.parametrize("lat", [C.D2Q4, C.D3Q6, C.D2Q9, C.D3Q15])
-def test_rest_free_cavity_from_rest(lat, storage):
+def test_lattice_cavity_from_rest(lat, storage):
     """A lid-driven box from rest, 600 steps, against the oracle (with
     diagonal links the lid corners take the x-before-y tie-break)."""
     if C.DIM[lat] == 2:
@@ -152,7 +152,7 @@ def _shape_cases():
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16dev", "bf16dev"])
-def test_rest_free_launch_shapes_bitwise_identical(storage):
+def test_lattice_launch_shapes_bitwise_identical(storage):
     """Scalar, vector and two-step kernels and any tile shape give the same
     populations and emitted fields bit for bit."""
     for name, spec, mask in _shape_cases():
@@ -181,7 +181,7 @@ def test_rest_free_launch_shapes_bitwise_identical(storage):
 
 
 @pytest.mark.parametrize("lat", [C.D2Q4, C.D3Q6, C.D2Q9, C.D3Q15])
-def test_rest_free_velocity_sets_equal_full_form(lat):
+def test_lattice_velocity_sets_equal_full_form(lat):
     """Only the d velocity sets (Remark IV) on these lattices: the same
     velocity-set populations and fields as all d + 1 sets, bit for bit."""
     if C.DIM[lat] == 2:
@@ -200,7 +200,7 @@ def test_rest_free_velocity_sets_equal_full_form(lat):
 
 
 @pytest.mark.parametrize("lat", [C.D2Q4, C.D2Q9])
-def test_rest_free_batch_matches_oracle(lat):
+def test_lattice_batch_matches_oracle(lat):
     """Three uneven cases in one batched context (persistent launches)."""
     specs = [C.CaseSpec(lat, (40, 33), 1.2, force=(2e-5, 0.0)),
              C.cavity_case(N=65, Re=80.0, lattice=lat),
@@ -215,10 +215,11 @@ def test_rest_free_batch_matches_oracle(lat):
 
 
 @pytest.mark.parametrize("lat", [C.D2Q4, C.D3Q6, C.D2Q9, C.D3Q15])
-def test_rest_free_fp32_zeroth_moment_does_not_drift(lat):
-    """FP32 on lattices whose weight 1/6 (D3Q6) does not round to a sum of
-    one: the total of ubar_0 in a closed box stays within unbiased rounding,
-    because a moving population closes the zeroth moment of the collision."""
+def test_lattice_fp32_zeroth_moment_does_not_drift(lat):
+    """FP32 on every further lattice (on D3Q6 six FP32 weights 1/6 do not
+    sum to one): the total of ubar_0 in a closed box stays within unbiased
+    rounding, because one population closes the zeroth moment of the
+    collision (the rest population, or a moving one on D2Q4/D3Q6)."""
     if C.DIM[lat] == 2:
         spec = C.cavity_case(N=256, Re=400.0, lattice=lat)
     else:
