@@ -441,7 +441,7 @@ mdf::BatchLaunch batch_args(mdf_ctx *ctx, uint32_t fields, int grid)
 }
 
 // nsteps batched steps of the uploaded active cases; the last one fused with
-// the check when `check`.  With the two-step form (D2Q5), pairs of steps run
+// the check when `check`.  With the two-step form (2D axis-link lattices), pairs of steps run
 // as one launch of k_step2_batch and the chunk ends with at least one
 // one-step launch (which carries the check and leaves f*(t - 1) in the other
 // buffer for the read kernels).  A chunk whose length, form, check flag,

@@ -59,7 +59,7 @@ struct LaunchShape {
     int bx, by;             // threads per block along x and y (bx * by <= 256)
     int groups;             // > 1: hand out tiles in `groups` contiguous bands, one per XCD
     int vx;                 // > 1: step kernels give each thread the storage's vector width of x-nodes
-    int fuse;               // 1: advance two steps per launch where possible (D2Q5, single-case contexts)
+    int fuse;               // 1: advance two steps per launch where possible (2D axis-link lattices)
 };
 
 // Tile grid of one launch: gx * gy * gz tiles of bx * by threads, launched
@@ -81,7 +81,7 @@ struct BatchEntry {
     double *result;
     void *out;              // emitted fields of the current call, or null
     int gx, gy, ntiles;     // tile grid of the case for the batch launch shape
-    int gx2, gy2, ntiles2;  // tile grid of two-step launches (D2Q5), else 0
+    int gx2, gy2, ntiles2;  // tile grid of two-step launches (2D axis-link lattices), else 0
     int cur;                // buffer holding f*(t) when the table was uploaded
 };
 
@@ -135,7 +135,7 @@ hipError_t launch_links(int lattice, const KCase &p, const uint8_t *solid, uint8
                         hipStream_t stream);
 hipError_t launch_init(int lattice, int storage, const KCase &p, const CaseBufs &b, int cur,
                        int kind, const void *data, hipStream_t stream);
-// Two steps in one launch (D2Q5 only): f*(t) in pop[src] -> f*(t+2) in
+// Two steps in one launch (D2Q5, D2Q4 and their *_V forms): f*(t) in pop[src] -> f*(t+2) in
 // pop[src ^ 1]; fields (if any) emitted at both steps.
 hipError_t launch_step2(int lattice, int storage, const KCase &p, const CaseBufs &b, int src, uint32_t fields,
                         void *out, LaunchShape shape, hipStream_t stream);
@@ -148,10 +148,10 @@ hipError_t launch_read(int lattice, int storage, const KCase &p, const CaseBufs 
 hipError_t launch_finalize(const CaseBufs &b, int nblocks, hipStream_t stream);
 hipError_t launch_step_batch(int lattice, int storage, const BatchLaunch &bl, bool check, hipStream_t stream);
 hipError_t batch_blocks_per_cu(int lattice, int storage, LaunchShape shape, bool mask, int *blocks_per_cu);
-// Batched two steps per launch (D2Q5) over the two-step tile list.
+// Batched two steps per launch (the same lattices) over the two-step tile list.
 hipError_t launch_step2_batch(int lattice, int storage, const BatchLaunch &bl, hipStream_t stream);
 hipError_t batch2_blocks_per_cu(int lattice, int storage, bool mask, int *blocks_per_cu);
-// Two-step tile grid of a case (D2Q5): tiles of 64 x rows nodes.
+// Two-step tile grid of a case: tiles of 64 x rows nodes.
 int step2_rows(int storage);
 hipError_t launch_finalize_batch(const BatchEntry *tab, const int *meta, const int *active, int nactive,
                                  hipStream_t stream);

@@ -971,7 +971,7 @@ k_step(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, typena
                                                     snap, partial);
 }
 
-// ----------------------------------------------------------------- two steps per pass (D2Q5)
+// ----------------------------------------------------------------- two steps per pass (2D, axis links)
 
 // Output rows of one tile of k_step2 per storage, so that the LDS copy of
 // the intermediate state (NS * Q planes of (64 + 2) x (rows + 2) stored
@@ -1059,6 +1059,8 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int gy, int t
         Node<L, C> n[G];
         bool fluid[G], interior[G];
         long long node[G];
+        // issue this batch's loads ahead of other waves' arithmetic
+        __builtin_amdgcn_s_setprio(2);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int e = tid + (k0 + g) * NT;
@@ -1080,6 +1082,7 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int gy, int t
             node[g] = (long long)y * p.nx + x;
             fluid[g] = gather<L, ST, MASK, true>(p, src, links, x, y, 0, n[g]);   // false: solid node
         }
+        __builtin_amdgcn_s_setprio(0);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             if (!fluid[g]) continue;

@@ -287,7 +287,7 @@ class Solver:
     def set_launch(self, bx: int, by: int, groups: int = 8, form: int = 0):
         """Tile of bx x by threads, XCD bands, and the step-kernel form: 0 one
         node per thread, 1 vector (several x-nodes per thread), 2 two steps
-        per launch (D2Q5)."""
+        per launch (2D lattices with axis links)."""
         _check(lib().mdf_set_launch(self._ctx, bx, by, groups, int(form)), self._ctx)
 
     def set_force_field(self, force, case: int = 0):
