@@ -832,7 +832,9 @@ __device__ __forceinline__ void step_tile(const KCase &p, int gx, int gy, int ti
     Node<L, C> n;
     Moments<L, C> m;
     bool fluid = false;
+    __builtin_amdgcn_s_setprio(2);          // issue the node's loads ahead of other waves' arithmetic
     if (inside) fluid = gather<L, ST, MASK, true>(p, src, links, x, y, z, n);
+    __builtin_amdgcn_s_setprio(0);
     const long long nodes = (long long)p.nx * p.ny * p.nz;
     const long long node = ((long long)z * p.ny + y) * p.nx + x;
     if (fluid) {
