@@ -174,6 +174,9 @@ size_t mdf_workspace_size(mdf_lattice lattice, mdf_storage storage, const mdf_ca
  * the halfway anti-bounce-back of Section 4 (formula not printed there):
  *   a >= 1: f_{i,a}(x, t+1) = -f*_{ibar,a}(x, t) + 2 w_i U_{w,a}
  *   a = 0 : f_{i,0}(x, t+1) =  f*_{ibar,0}(x, t)
+ * When the population buffers of all cases together exceed 256 MB (the
+ * Infinity Cache), the step kernels write populations with a non-temporal
+ * hint; results are the same either way.
  * Errors: MDF_EINVAL (bad lattice/storage/sizes/rates/bc pairing/pointers),
  * MDF_ENOMEM (ws_bytes too small), MDF_EDEVICE. */
 mdf_status mdf_init(mdf_ctx **out, mdf_lattice lattice, mdf_storage storage,

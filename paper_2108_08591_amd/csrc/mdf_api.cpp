@@ -634,6 +634,14 @@ mdf_status mdf_init(mdf_ctx **out, mdf_lattice lattice, mdf_storage storage, con
             return s;
         }
     }
+    // Populations the next launch cannot find in the 256 MB Infinity Cache
+    // are written with a non-temporal hint (measured: +3.4-4.4 % on 8192^2
+    // and 256^3 grids, -23 % on a 1024^2 grid that fits the cache).
+    size_t pop_total = 0;
+    for (int k = 0; k < ncases; ++k)
+        pop_total += 2 * size_t(lat_ns(lattice)) * lat_q(lattice) * size_t(ctx->kc[k].dstride) * storage_bytes(storage);
+    const size_t kInfinityCacheBytes = size_t(256) << 20;
+    for (int k = 0; k < ncases; ++k) ctx->kc[k].ntstore = pop_total > kInfinityCacheBytes ? 1 : 0;
     *out = ctx;
     return MDF_OK;
 }

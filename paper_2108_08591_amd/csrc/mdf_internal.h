@@ -43,6 +43,9 @@ struct KCase {
     int forcing;
     double fmove;
     float fmovef;
+    // 1: the step kernels write populations with a non-temporal hint (the
+    // context's population buffers exceed the Infinity Cache)
+    int ntstore;
 };
 
 // Device pointers of one case inside the workspace.

@@ -202,6 +202,20 @@ __device__ __forceinline__ int block_tile(const Tiling &t)
 // FP32, 8 bytes for the 16-bit formats.
 template <int ST> struct Store;
 
+// One stored value, written with a non-temporal hint when `nt`: populations
+// that the next launch will not find in the 256 MB Infinity Cache anyway skip
+// it, which leaves L2 and the cache to the halo and neighbour reads.  On
+// working sets that fit the cache the plain store keeps them there for the
+// next launch.  NT is a template parameter all the way down: with a run-time
+// flag the optimizer merges the two stores of the same value before
+// inlining and drops the hint.
+template <bool NT, class T>
+__device__ __forceinline__ void put_value(T *p, long long k, T x)
+{
+    if constexpr (NT) __builtin_nontemporal_store(x, &p[k]);
+    else p[k] = x;
+}
+
 template <> struct Store<MDF_F64> {
     using T = double;
     using C = double;
@@ -210,6 +224,11 @@ template <> struct Store<MDF_F64> {
     static __device__ __forceinline__ T encode(C v, C, float) { return v; }
     static __device__ __forceinline__ C load(const T *p, long long k, C, float) { return p[k]; }
     static __device__ __forceinline__ void store(T *p, long long k, C v, C, float) { p[k] = v; }
+    template <bool NT>
+    static __device__ __forceinline__ void store_hint(T *p, long long k, C v, C, float)
+    {
+        put_value<NT>(p, k, v);
+    }
 };
 
 template <> struct Store<MDF_F32> {
@@ -220,6 +239,11 @@ template <> struct Store<MDF_F32> {
     static __device__ __forceinline__ T encode(C v, C, float) { return v; }
     static __device__ __forceinline__ C load(const T *p, long long k, C, float) { return p[k]; }
     static __device__ __forceinline__ void store(T *p, long long k, C v, C, float) { p[k] = v; }
+    template <bool NT>
+    static __device__ __forceinline__ void store_hint(T *p, long long k, C v, C, float)
+    {
+        put_value<NT>(p, k, v);
+    }
 };
 
 // 16-bit deviation storage: stored = (f - rest) / scale, round to nearest even.
@@ -242,6 +266,11 @@ template <> struct Store<MDF_F16DEV> {
     static __device__ __forceinline__ void store(T *p, long long k, C v, C rest, float inv_scale)
     {
         p[k] = encode(v, rest, inv_scale);
+    }
+    template <bool NT>
+    static __device__ __forceinline__ void store_hint(T *p, long long k, C v, C rest, float inv_scale)
+    {
+        put_value<NT>(p, k, encode(v, rest, inv_scale));
     }
 };
 
@@ -272,6 +301,11 @@ template <> struct Store<MDF_BF16DEV> {
     static __device__ __forceinline__ void store(T *p, long long k, C v, C rest, float inv_scale)
     {
         p[k] = encode(v, rest, inv_scale);
+    }
+    template <bool NT>
+    static __device__ __forceinline__ void store_hint(T *p, long long k, C v, C rest, float inv_scale)
+    {
+        put_value<NT>(p, k, encode(v, rest, inv_scale));
     }
 };
 
@@ -815,7 +849,7 @@ __device__ __forceinline__ void check_values(const Moments<L, C> &m, bool valid,
 // One tile of one time step: pull, wall rule, moments, optional fields and
 // check, collision + forcing, write.  Shared by the single-case and the
 // batched kernels, so both produce bitwise identical populations.
-template <class L, int ST, bool EMIT, bool CHECK, bool MASK>
+template <class L, int ST, bool EMIT, bool CHECK, bool MASK, bool NTST = false>
 __device__ __forceinline__ void step_tile(const KCase &p, int gx, int gy, int tile,
                                           const typename Store<ST>::T *__restrict__ src,
                                           typename Store<ST>::T *__restrict__ dst, const uint8_t *__restrict__ links,
@@ -848,8 +882,8 @@ __device__ __forceinline__ void step_tile(const KCase &p, int gx, int gy, int ti
             collide_set<L, C>(p, n, a, ne, fo, m.fb[a + L::A0]);
 #pragma unroll
             for (int i = 0; i < L::Q; ++i)
-                S::store(dst + (long long)(a * L::Q + i) * p.dstride, own, fo[i], rest_value<L, C>(p, a, i),
-                         p.inv_scale);
+                S::template store_hint<NTST>(dst + (long long)(a * L::Q + i) * p.dstride, own, fo[i],
+                                             rest_value<L, C>(p, a, i), p.inv_scale);
         }
     } else if (EMIT && inside) {
         // solid node: every emitted channel is zero
@@ -959,15 +993,15 @@ __device__ __forceinline__ void step_tile_vec(const KCase &p, int gx, int gy, in
     if (CHECK) block_reduce_store(acc, partial, tile);
 }
 
-template <class L, int ST, bool EMIT, bool CHECK, bool MASK, int VX>
+template <class L, int ST, bool EMIT, bool CHECK, bool MASK, int VX, bool NTST = false>
 __global__ void __launch_bounds__(256)
 k_step(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, typename Store<ST>::T *__restrict__ dst,
        const uint8_t *__restrict__ links, uint32_t fields, typename Store<ST>::C *__restrict__ out,
        typename Store<ST>::C *__restrict__ snap, double *__restrict__ partial)
 {
     if constexpr (VX == 1)
-        step_tile<L, ST, EMIT, CHECK, MASK>(p, tl.gx, tl.gy, block_tile(tl), src, dst, links, fields, out, snap,
-                                            partial);
+        step_tile<L, ST, EMIT, CHECK, MASK, NTST>(p, tl.gx, tl.gy, block_tile(tl), src, dst, links, fields, out,
+                                                snap, partial);
     else
         step_tile_vec<L, ST, EMIT, CHECK, MASK, VX>(p, tl.gx, tl.gy, block_tile(tl), src, dst, links, fields, out,
                                                     snap, partial);
@@ -1032,7 +1066,7 @@ struct Step2Lds {
     typename Store<ST>::T v[L::NS * L::Q * NE];
 };
 
-template <class L, int ST, bool EMIT, bool MASK>
+template <class L, int ST, bool EMIT, bool MASK, bool NTST = false>
 __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int gy, int tile, const typename Store<ST>::T *__restrict__ src,
                                            typename Store<ST>::T *__restrict__ dst, const uint8_t *__restrict__ links,
                                            uint32_t fields, typename Store<ST>::C *__restrict__ out,
@@ -1174,19 +1208,19 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int gy, int t
             collide_set<L, C>(p, n, a, ne, fo, m.fb[a + L::A0]);
 #pragma unroll
             for (int i = 0; i < L::Q; ++i)
-                S::store(dst + (long long)(a * L::Q + i) * p.dstride, own, fo[i], rest_value<L, C>(p, a, i),
-                         p.inv_scale);
+                S::template store_hint<NTST>(dst + (long long)(a * L::Q + i) * p.dstride, own, fo[i],
+                                             rest_value<L, C>(p, a, i), p.inv_scale);
         }
     }
 }
 
-template <class L, int ST, bool EMIT, bool MASK>
+template <class L, int ST, bool EMIT, bool MASK, bool NTST = false>
 __global__ void __launch_bounds__(Fuse2Rows<ST>::NT)
 k_step2(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, typename Store<ST>::T *__restrict__ dst,
         const uint8_t *__restrict__ links, uint32_t fields, typename Store<ST>::C *__restrict__ out)
 {
     __shared__ Step2Lds<L, ST> lds;
-    step2_tile<L, ST, EMIT, MASK>(p, tl.gx, tl.gy, block_tile(tl), src, dst, links, fields, out, lds.v);
+    step2_tile<L, ST, EMIT, MASK, NTST>(p, tl.gx, tl.gy, block_tile(tl), src, dst, links, fields, out, lds.v);
 }
 
 // Batched two steps per launch: the persistent walk of k_step_batch over
@@ -1474,10 +1508,15 @@ hipError_t step_dispatch(const KCase &p, const CaseBufs &b, int src, bool check,
     const dim3 grid(tl.nb, 1, 1), block(s.bx, s.by, 1);
     const bool emit_on = (fields != 0) && out != nullptr;
     const bool mask = b.links != nullptr;
-#define MDF_STEP_LAUNCH1(E, K, M, V) \
-    hipLaunchKernelGGL((k_step<L, ST, E, K, M, V>), grid, block, 0, stream, p, tl, in, o, b.links, fields, emit, snap, b.partial)
-#define MDF_STEP_LAUNCH(E, K, M) \
-    do { if (vx > 1) MDF_STEP_LAUNCH1(E, K, M, VW); else MDF_STEP_LAUNCH1(E, K, M, 1); } while (0)
+#define MDF_STEP_LAUNCH1(E, K, M, V, N) \
+    hipLaunchKernelGGL((k_step<L, ST, E, K, M, V, N>), grid, block, 0, stream, p, tl, in, o, b.links, fields, emit, snap, \
+                       b.partial)
+#define MDF_STEP_LAUNCH(E, K, M)                                                                   \
+    do {                                                                                           \
+        if (vx > 1) MDF_STEP_LAUNCH1(E, K, M, VW, false);                                          \
+        else if (p.ntstore) MDF_STEP_LAUNCH1(E, K, M, 1, true);                                    \
+        else MDF_STEP_LAUNCH1(E, K, M, 1, false);                                                  \
+    } while (0)
     if (mask) {
         if (emit_on) { if (check) MDF_STEP_LAUNCH(true, true, true); else MDF_STEP_LAUNCH(true, false, true); }
         else { if (check) MDF_STEP_LAUNCH(false, true, true); else MDF_STEP_LAUNCH(false, false, true); }
@@ -1510,12 +1549,15 @@ hipError_t step2_dispatch(const KCase &p, const CaseBufs &b, int src, uint32_t f
         tl.groups = s.groups > 1 ? s.groups : 1;
         const bool emit_on = (fields != 0) && out != nullptr;
         const bool mask = b.links != nullptr;
+#define MDF_STEP2_LAUNCH1(E, M, N)                                                                       \
+    hipLaunchKernelGGL((k_step2<L, ST, E, M, N>), dim3(tl.nb), dim3(Fuse2Rows<ST>::NT), 0, stream, p, tl, in, o, \
+                       b.links, fields, emit)
 #define MDF_STEP2_LAUNCH(E, M) \
-    hipLaunchKernelGGL((k_step2<L, ST, E, M>), dim3(tl.nb), dim3(Fuse2Rows<ST>::NT), 0, stream, p, tl, in, o, b.links, \
-                       fields, emit)
+    do { if (p.ntstore) MDF_STEP2_LAUNCH1(E, M, true); else MDF_STEP2_LAUNCH1(E, M, false); } while (0)
         if (mask) { if (emit_on) MDF_STEP2_LAUNCH(true, true); else MDF_STEP2_LAUNCH(false, true); }
         else { if (emit_on) MDF_STEP2_LAUNCH(true, false); else MDF_STEP2_LAUNCH(false, false); }
 #undef MDF_STEP2_LAUNCH
+#undef MDF_STEP2_LAUNCH1
         return hipGetLastError();
     }
 }
