@@ -835,11 +835,11 @@ def main():
         fdb, wdb, cfdb, cwdb, out_md = args.summarize_traffic
         nodes = 1024 * 1024
         if args.traffic_kernel == "step2":
-            md, ent = summarize_traffic(fdb, wdb, cfdb, cwdb, "k_step2<LatD2Q5, 1, true, false, false>",
+            md, ent = summarize_traffic(fdb, wdb, cfdb, cwdb, "k_step2<LatD2Q5, 1, true, false, false, true>",
                                         nodes * (2 * 15 * 4 + 2 * 4 * 4), "k_step2<D2Q5,F32,emit>_cavity1024",
                                         args.command.split(" ;; "))
         else:
-            md, ent = summarize_traffic(fdb, wdb, cfdb, cwdb, "k_step<LatD2Q5, 1, true, false, false, 1, false>",
+            md, ent = summarize_traffic(fdb, wdb, cfdb, cwdb, "k_step<LatD2Q5, 1, true, false, false, 1, false, true>",
                                         nodes * (2 * 15 * 4 + 4 * 4), "k_step<D2Q5,F32,emit>_cavity1024",
                                         args.command.split(" ;; "))
         with open(out_md, "w") as fh:

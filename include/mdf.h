@@ -177,6 +177,9 @@ size_t mdf_workspace_size(mdf_lattice lattice, mdf_storage storage, const mdf_ca
  * When the population buffers of all cases together exceed 256 MB (the
  * Infinity Cache), the step kernels write populations with a non-temporal
  * hint; results are the same either way.
+ * Size limits per case: at most 2e9 stored populations, and every stored
+ * population plane (rows padded to 128 bytes) and every field channel
+ * within 4 GiB; mdf_workspace_size and mdf_init refuse larger cases.
  * Errors: MDF_EINVAL (bad lattice/storage/sizes/rates/bc pairing/pointers),
  * MDF_ENOMEM (ws_bytes too small), MDF_EDEVICE. */
 mdf_status mdf_init(mdf_ctx **out, mdf_lattice lattice, mdf_storage storage,

@@ -87,7 +87,7 @@ struct SharedLayout {
 // (bx >= 32, bx * by >= 64): at most ceil(nx/32) * ny * nz.
 int max_blocks_of(const mdf_case &c) { return (c.nx + 31) / 32 * c.ny * c.nz; }
 
-bool validate_case(int lattice, const mdf_case &c, std::string &why)
+bool validate_case(int lattice, int storage, const mdf_case &c, std::string &why)
 {
     char buf[256];
     const int d = lat_d(lattice);
@@ -95,6 +95,12 @@ bool validate_case(int lattice, const mdf_case &c, std::string &why)
     if (d == 2 && c.nz != 1) { why = "D2Q5 needs nz = 1"; return false; }
     const double nodes = double(c.nx) * c.ny * c.nz;
     if (nodes * lat_q(lattice) * lat_ns(lattice) > 2.0e9) { why = "case too large (>2e9 populations)"; return false; }
+    // the step kernels address nodes by 32-bit byte offsets within a plane
+    const double plane_bytes = double(row_pitch(c.nx, storage)) * c.ny * c.nz * storage_bytes(storage);
+    if (plane_bytes > 4294967296.0 || nodes * compute_bytes(storage) > 4294967296.0) {
+        why = "a population plane or field channel beyond 4 GiB";
+        return false;
+    }
     if (!(c.s1 > 0.0 && c.s1 < 2.0)) {
         snprintf(buf, sizeof buf, "s1 = %g outside (0, 2)", c.s1);
         why = buf;
@@ -541,7 +547,7 @@ size_t mdf_workspace_size(mdf_lattice lattice, mdf_storage storage, const mdf_ca
     }
     std::string why;
     for (int k = 0; k < ncases; ++k)
-        if (!validate_case(lattice, cases[k], why)) {
+        if (!validate_case(lattice, storage, cases[k], why)) {
             fail(nullptr, MDF_EINVAL, "mdf_workspace_size: case %d: %s", k, why.c_str());
             return 0;
         }
@@ -564,7 +570,7 @@ mdf_status mdf_init(mdf_ctx **out, mdf_lattice lattice, mdf_storage storage, con
         return fail(nullptr, MDF_EINVAL, "mdf_init: workspace not 256-byte aligned");
     std::string why;
     for (int k = 0; k < ncases; ++k)
-        if (!validate_case(lattice, cases[k], why))
+        if (!validate_case(lattice, storage, cases[k], why))
             return fail(nullptr, MDF_EINVAL, "mdf_init: case %d: %s", k, why.c_str());
     if (init_kind != MDF_INIT_REST) {
         if (!init_data) return fail(nullptr, MDF_EINVAL, "mdf_init: init_data is NULL");

@@ -46,6 +46,18 @@ def test_workspace_size_scales_with_storage_and_grid():
     assert _ws(big) > 3.5 * w32
 
 
+def test_planes_beyond_4gib_are_refused():
+    """The step kernels address nodes by 32-bit byte offsets within a plane:
+    a case whose padded population plane would exceed 4 GiB (a 1 x 40 M FP32
+    column pads every row to 32 values: 5.1 GB per plane, with only 6e8
+    populations) is refused; one just below the bound is accepted."""
+    narrow = C.CaseSpec(C.D2Q5, (1, 40_000_000), 1.2)
+    assert _ws(narrow) == 0
+    assert "4 GiB" in mdf.lib().mdf_last_error(None).decode()
+    ok = C.CaseSpec(C.D2Q5, (1, 33_554_432), 1.2)          # 32 * 2^25 * 4 B = 4 GiB exactly
+    assert _ws(ok) > 0
+
+
 def test_velocity_set_lattices_store_d_of_d_plus_one_sets():
     """MDF_D2Q5_V / MDF_D3Q7_V keep only the d velocity sets (Remark IV):
     the population part of the workspace shrinks by d/(d+1)."""

@@ -1,7 +1,8 @@
 """Parity on contexts whose population buffers exceed the 256 MB Infinity
-Cache, where the step kernels store populations with a non-temporal hint:
-the 2D cavity in FP32 and FP64 (two-step and one-step launches) and the 3D
-Taylor-Green vortex at its full 256^3 size in FP32.  After some steps from
+Cache, where the step kernels store populations with a non-temporal hint and
+address nodes by 32-bit byte offsets: the 2D cavity in FP32 and FP64
+(two-step and one-step launches) and the 3D Taylor-Green vortex at its full
+256^3 size in FP32.  After some steps from
 the GPU's own run, one and then two or three more steps are checked node by
 node against the FP64 oracle on sampled patches (corners, walls, periodic
 faces, interior); the oracle starts from the GPU's state on each patch
@@ -37,14 +38,15 @@ def _pop_bytes(solver, spec):
     return 2 * solver.nsets * solver.q * int(np.prod(spec.shape)) * nbytes
 
 
-def _cavity_patch_oracle(spec, f_t, x0, y0, P, h, N):
+def _cavity_patch_oracle(spec, f_t, x0, y0, P, h):
     """Oracle on the P x P patch at (x0, y0) widened by h on every side that
     is not a wall; a widened side that is not a wall is made periodic (its
     halo values are wrong but reach only h - 1 nodes inward in h steps)."""
-    ex0, ex1 = max(x0 - h, 0), min(x0 + P + h, N)
-    ey0, ey1 = max(y0 - h, 0), min(y0 + P + h, N)
-    bc = [C.WALL if ex0 == 0 else C.PERIODIC, C.WALL if ex1 == N else C.PERIODIC,
-          C.WALL if ey0 == 0 else C.PERIODIC, C.WALL if ey1 == N else C.PERIODIC, 0, 0]
+    NX, NY = spec.shape
+    ex0, ex1 = max(x0 - h, 0), min(x0 + P + h, NX)
+    ey0, ey1 = max(y0 - h, 0), min(y0 + P + h, NY)
+    bc = [C.WALL if ex0 == 0 else C.PERIODIC, C.WALL if ex1 == NX else C.PERIODIC,
+          C.WALL if ey0 == 0 else C.PERIODIC, C.WALL if ey1 == NY else C.PERIODIC, 0, 0]
     for ax in range(2):                      # periodic faces come in pairs
         if bc[2 * ax] != bc[2 * ax + 1]:
             bc[2 * ax] = bc[2 * ax + 1] = C.WALL
@@ -72,7 +74,7 @@ def test_cavity_beyond_the_cache(storage, N, form):
         fl = s.fields(mdf.FIELD_ALL)
         big = {k: float(v.abs().max()) for k, v in fl.items() if k in ("u", "vort", "S", "P")}
         for (x0, y0) in patches:
-            o, (iy, ix) = _cavity_patch_oracle(spec, f_t, x0, y0, P, nsteps, N)
+            o, (iy, ix) = _cavity_patch_oracle(spec, f_t, x0, y0, P, nsteps)
             o.run(nsteps)
             got = _np(f_t1[:, :, y0:y0 + P, x0:x0 + P])
             assert rel_err(o.populations()[:, :, iy, ix], got) < TOL[storage], (nsteps, x0, y0)
@@ -115,3 +117,4 @@ def test_tgv3d_full_size_beyond_the_cache():
             got = _np(f_t1.index_select(2, inn[0]).index_select(3, inn[1]).index_select(4, inn[2]))
             assert rel_err(ref, got) < 1e-5, (nsteps, x0, y0, z0)
         del f_t, f_t1
+
