@@ -442,6 +442,7 @@ mdf::BatchLaunch batch_args(mdf_ctx *ctx, uint32_t fields, int grid)
     bl.fields = fields;
     bl.grid = grid;
     bl.mask = ctx->any_mask;
+    bl.ntstore = ctx->kc[0].ntstore != 0;   // the same for every case of a context
     bl.shape = ctx->shape;
     return bl;
 }

@@ -99,6 +99,7 @@ struct BatchLaunch {
     uint32_t fields;        // emitted fields (0: none)
     int grid;               // blocks of the persistent launch
     bool mask;              // any case has obstacles
+    bool ntstore;           // non-temporal stores and 32-bit node offsets
     LaunchShape shape;
 };
 

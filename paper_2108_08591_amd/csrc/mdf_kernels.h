@@ -1281,7 +1281,7 @@ k_step2(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, typen
 // Batched two steps per launch: the persistent walk of k_step_batch over
 // the flat list of the active cases' two-step tiles (prefix offsets
 // tile_start2, total meta[2]).
-template <class L, int ST, bool EMIT, bool MASK>
+template <class L, int ST, bool EMIT, bool MASK, bool NTST = false, bool WIDE = true>
 __global__ void __launch_bounds__(Fuse2Rows<ST>::NT)
 k_step2_batch(const BatchEntry *__restrict__ tab, const int *__restrict__ meta,
               const int *__restrict__ tile_start2, const int *__restrict__ active, int parity, uint32_t fields,
@@ -1304,9 +1304,10 @@ k_step2_batch(const BatchEntry *__restrict__ tab, const int *__restrict__ meta,
         const int sel = (e.cur + parity) & 1;
         using T = typename Store<ST>::T;
         using C = typename Store<ST>::C;
-        step2_tile<L, ST, EMIT, MASK>(e.p, e.gx2, e.gy2, t - tile_start2[lo], static_cast<const T *>(e.pop[sel]),
-                                      static_cast<T *>(e.pop[sel ^ 1]), e.links, fields, static_cast<C *>(e.out),
-                                      lds.v);
+        step2_tile<L, ST, EMIT, MASK, NTST, WIDE>(e.p, e.gx2, e.gy2, t - tile_start2[lo],
+                                                  static_cast<const T *>(e.pop[sel]),
+                                                  static_cast<T *>(e.pop[sel ^ 1]), e.links, fields,
+                                                  static_cast<C *>(e.out), lds.v);
         __syncthreads();   // the next tile's step 1 overwrites the LDS this tile's step 2 reads
     }
 }
@@ -1317,7 +1318,7 @@ k_step2_batch(const BatchEntry *__restrict__ tab, const int *__restrict__ meta,
 // to the resident capacity of the chip and each block walks the list.  Tiles
 // are dealt in XCD bands: blocks b with b % groups == g take the g-th
 // contiguous band of the list, so neighbouring tiles of a case share an L2.
-template <class L, int ST, bool EMIT, bool CHECK, bool MASK, int VX>
+template <class L, int ST, bool EMIT, bool CHECK, bool MASK, int VX, bool NTST = false, bool WIDE = true>
 __global__ void __launch_bounds__(256)
 k_step_batch(const BatchEntry *__restrict__ tab, const int *__restrict__ meta, const int *__restrict__ tile_start,
              const int *__restrict__ active, int parity, uint32_t fields, int groups)
@@ -1339,10 +1340,11 @@ k_step_batch(const BatchEntry *__restrict__ tab, const int *__restrict__ meta, c
         using T = typename Store<ST>::T;
         using C = typename Store<ST>::C;
         if constexpr (VX == 1)
-            step_tile<L, ST, EMIT, CHECK, MASK>(e.p, e.gx, e.gy, t - tile_start[lo],
-                                                static_cast<const T *>(e.pop[sel]), static_cast<T *>(e.pop[sel ^ 1]),
-                                                e.links, fields, static_cast<C *>(e.out), static_cast<C *>(e.snap),
-                                                e.partial);
+            step_tile<L, ST, EMIT, CHECK, MASK, NTST, WIDE>(e.p, e.gx, e.gy, t - tile_start[lo],
+                                                            static_cast<const T *>(e.pop[sel]),
+                                                            static_cast<T *>(e.pop[sel ^ 1]), e.links, fields,
+                                                            static_cast<C *>(e.out), static_cast<C *>(e.snap),
+                                                            e.partial);
         else
             step_tile_vec<L, ST, EMIT, CHECK, MASK, VX>(e.p, e.gx, e.gy, t - tile_start[lo],
                                                         static_cast<const T *>(e.pop[sel]),
@@ -1679,11 +1681,16 @@ hipError_t batch_dispatch(const BatchLaunch &bl, bool check, bool emit, hipStrea
     using S = Store<ST>;
     constexpr int VW = L::DIAG ? 1 : S::VX;      // the vector form exists for axis-link lattices only
     const dim3 grid(bl.grid, 1, 1), block(bl.shape.bx, bl.shape.by, 1);
-#define MDF_BATCH_LAUNCH1(E, K, M, V)                                                                      \
-    hipLaunchKernelGGL((k_step_batch<L, ST, E, K, M, V>), grid, block, 0, stream, bl.tab, bl.meta, bl.tile_start, \
-                       bl.active, bl.parity, bl.fields, bl.shape.groups)
-#define MDF_BATCH_LAUNCH(E, K, M) \
-    do { if (bl.shape.vx > 1) MDF_BATCH_LAUNCH1(E, K, M, VW); else MDF_BATCH_LAUNCH1(E, K, M, 1); } while (0)
+#define MDF_BATCH_LAUNCH1(E, K, M, V, N, X)                                                                  \
+    hipLaunchKernelGGL((k_step_batch<L, ST, E, K, M, V, N, X>), grid, block, 0, stream, bl.tab, bl.meta,           \
+                       bl.tile_start, bl.active, bl.parity, bl.fields, bl.shape.groups)
+    // the store and offset forms of the single-case launches
+#define MDF_BATCH_LAUNCH(E, K, M)                                                                  \
+    do {                                                                                           \
+        if (bl.shape.vx > 1) MDF_BATCH_LAUNCH1(E, K, M, VW, false, true);                          \
+        else if (!bl.ntstore) MDF_BATCH_LAUNCH1(E, K, M, 1, false, true);                          \
+        else MDF_BATCH_LAUNCH1(E, K, M, 1, true, false);                                           \
+    } while (0)
     if (bl.mask) {
         if (emit) { if (check) MDF_BATCH_LAUNCH(true, true, true); else MDF_BATCH_LAUNCH(true, false, true); }
         else { if (check) MDF_BATCH_LAUNCH(false, true, true); else MDF_BATCH_LAUNCH(false, false, true); }
@@ -1703,12 +1710,18 @@ hipError_t batch2_dispatch(const BatchLaunch &bl, bool emit, hipStream_t stream)
         return hipErrorInvalidValue;
     } else {
         const dim3 grid(bl.grid, 1, 1), block(Fuse2Rows<ST>::NT, 1, 1);
-#define MDF_BATCH2_LAUNCH(E, M)                                                                              \
-    hipLaunchKernelGGL((k_step2_batch<L, ST, E, M>), grid, block, 0, stream, bl.tab, bl.meta, bl.tile_start2, \
+#define MDF_BATCH2_LAUNCH1(E, M, N, X)                                                                    \
+    hipLaunchKernelGGL((k_step2_batch<L, ST, E, M, N, X>), grid, block, 0, stream, bl.tab, bl.meta, bl.tile_start2, \
                        bl.active, bl.parity, bl.fields, bl.shape.groups)
+#define MDF_BATCH2_LAUNCH(E, M)                                                                    \
+    do {                                                                                           \
+        if (!bl.ntstore) MDF_BATCH2_LAUNCH1(E, M, false, true);                                    \
+        else MDF_BATCH2_LAUNCH1(E, M, true, false);                                                \
+    } while (0)
         if (bl.mask) { if (emit) MDF_BATCH2_LAUNCH(true, true); else MDF_BATCH2_LAUNCH(false, true); }
         else { if (emit) MDF_BATCH2_LAUNCH(true, false); else MDF_BATCH2_LAUNCH(false, false); }
 #undef MDF_BATCH2_LAUNCH
+#undef MDF_BATCH2_LAUNCH1
         return hipGetLastError();
     }
 }

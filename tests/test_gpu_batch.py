@@ -74,6 +74,43 @@ def test_batch_bitwise_equals_single_cases(with_mask, form):
 
 
 @pytest.mark.parametrize("form", [0, 2])
+def test_batch_beyond_the_cache_bitwise_equals_single_cases(form):
+    """A batch whose population buffers together exceed the 256 MB Infinity
+    Cache (336 MB): its launches store with the non-temporal hint and address
+    nodes by 32-bit offsets, while each case alone fits the cache and runs the
+    plain form.  Populations and fields agree bit for bit."""
+    cav = C.cavity_case(N=1100, Re=1000.0)
+    ch = C.poiseuille_case(900, 700, umax=0.05, s1=1.3)
+    box = C.cavity_case(N=1000, Re=400.0, U=0.08)
+    box.shape = (1000, 900)
+    specs = [cav, ch, box]
+    mask = np.zeros(box.fshape, np.uint8)
+    mask[300:360, 400:470] = 1
+    masks = [None, None, mask]
+    stream = torch.cuda.Stream()
+    _say(f"[batch] beyond the cache, bitwise vs single, form={form}")
+    b = mdf.Solver(specs, storage="f32", solid=masks, device=DEV, stream=stream)
+    total = sum(2 * 15 * 4 * ((s.shape[0] + 31) // 32 * 32) * s.shape[1] for s in specs)
+    assert total > 256 << 20
+    b.set_launch(128, 2, 8, form)
+    fields = mdf.FIELD_VORT | mdf.FIELD_STRAIN
+    out_b = b.new_field_buffers(fields)
+    b.step(5)
+    b.step_emit(6, fields, out_b)
+    stream.synchronize()
+    for k, s in enumerate(specs):
+        single = mdf.Solver([s], storage="f32", solid=[masks[k]] if masks[k] is not None else None, device=DEV,
+                            stream=stream)
+        out_s = single.new_field_buffers(fields)
+        single.step(5)
+        single.step_emit(6, fields, out_s)
+        stream.synchronize()
+        assert torch.equal(b.populations(k), single.populations()), k
+        assert torch.equal(out_b[k], out_s[0]), k
+        del single
+
+
+@pytest.mark.parametrize("form", [0, 2])
 def test_batch_run_steady_matches_single_cases(form):
     """Per-case convergence inside one batch: same stopping step, same FP64
     residual and same state as solving each case alone."""
