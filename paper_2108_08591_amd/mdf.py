@@ -67,8 +67,7 @@ def lib():
     global _LIB
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} not built: run __graft_entry__.build() "
-                               "(or python paper_2108_08591_amd/build.py)")
+            raise RuntimeError(f"{LIB_PATH} not built: run python paper_2108_08591_amd/build.py")
         L = ctypes.CDLL(LIB_PATH)
         vp, cp = ctypes.c_void_p, ctypes.POINTER(MdfCase)
         i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
