@@ -1064,13 +1064,15 @@ k_step(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, typena
 
 // ----------------------------------------------------------------- two steps per pass (2D, axis links)
 
-// Output rows of one tile of k_step2 per storage, so that the LDS copy of
-// the intermediate state (NS * Q planes of (64 + 2) x (rows + 2) stored
-// values) stays within 64 KB: 47.5 KB for FP64, 39.6 KB for FP32, 35.6 KB
-// for the 16-bit formats.
-template <int ST> struct Fuse2Rows { static constexpr int TY = 16, NT = 256; };
+// Output rows of one tile of k_step2 per storage.  The LDS copy of the
+// intermediate state (NS * Q planes of (64 + 2) x (rows + 2) stored values)
+// is 47.5 KB for FP64, 39.6 KB for FP32 and 19.8 KB for the 16-bit formats
+// (D2Q5, three sets).  The 16-bit formats keep 8 rows rather than 16: their
+// step 1 then pulls the halo tile in one batch of three nodes per thread,
+// not two, and more blocks fit per CU (measured +19-25 % at 4096^2 and
+// 8192^2).
+template <int ST> struct Fuse2Rows { static constexpr int TY = 8, NT = 256; };
 template <> struct Fuse2Rows<MDF_F64> { static constexpr int TY = 4, NT = 256; };
-template <> struct Fuse2Rows<MDF_F32> { static constexpr int TY = 8, NT = 256; };
 
 constexpr int kF2X = 64;                 // output columns of a tile
 constexpr int kF2W = kF2X + 2;           // columns of the tile plus its one-node halo
