@@ -204,14 +204,6 @@ __device__ __forceinline__ int block_tile(const Tiling &t)
 // FP32, 8 bytes for the 16-bit formats.
 template <int ST> struct Store;
 
-// One stored value, written with a non-temporal hint when `nt`: populations
-// that the next launch will not find in the 256 MB Infinity Cache anyway skip
-// it, which leaves L2 and the cache to the halo and neighbour reads.  On
-// working sets that fit the cache the plain store keeps them there for the
-// next launch.  NT is a template parameter all the way down: with a run-time
-// flag the optimizer merges the two stores of the same value before
-// inlining and drops the hint.
-//
 // A node's place in a plane is an element index: 64-bit in general, or an
 // Ix32 when every population plane and field channel of the launch spans at
 // most 4 GiB.  With an Ix32 the address of an access is the plane's base,
@@ -228,10 +220,11 @@ __device__ __forceinline__ T *elem(T *p, long long k)
     return p + k;
 }
 
-// The plane base goes through readfirstlane: it is uniform anyway, and the
+// Element i of the plane at p, a global-memory address that every lane of
+// the wavefront passes alike.  The base goes through readfirstlane: the
 // opaque copy keeps the optimizer from folding the per-plane part of the
-// address into a shared 64-bit vector address, which would bring the 64-bit
-// vector arithmetic back.
+// address into one shared 64-bit vector address, which would bring the
+// 64-bit vector arithmetic back.
 template <class T>
 __device__ __forceinline__ T *elem(T *p, Ix32 i)
 {
@@ -254,6 +247,13 @@ __device__ __forceinline__ auto grid_ix(int x, int y, int z, int ny, int pitch)
         return Ix32{(uint32_t(z) * uint32_t(ny) + uint32_t(y)) * uint32_t(pitch) + uint32_t(x)};
 }
 
+// One stored value, written with a non-temporal hint when NT: populations
+// that the next launch will not find in the 256 MB Infinity Cache anyway skip
+// it, which leaves L2 and the cache to the halo and neighbour reads.  On
+// working sets that fit the cache the plain store keeps them there for the
+// next launch.  NT is a template parameter all the way down: with a run-time
+// flag the optimizer merges the two stores of the same value before
+// inlining and drops the hint.
 template <bool NT, class T, class IX>
 __device__ __forceinline__ void put_value(T *p, IX k, T x)
 {
