@@ -250,15 +250,18 @@ mdf_status mdf_invariants(const mdf_ctx *ctx, int32_t case_id, double *out, void
  *   1  vector: each thread of the step kernels owns consecutive x-nodes (2
  *      for MDF_STORAGE_F64, 4 for the other storages), read and written as one
  *      16-byte (8-byte for the 16-bit storages) access per plane;
- *   2  two steps per launch (D2Q5, D2Q4 and their *_V forms): tiles of 64 x 4/8/16 nodes
- *      (FP64/FP32/16-bit) take one step on the tile and a one-node halo into
- *      LDS and the second from LDS, so the state crosses HBM once per two
- *      steps.  mdf_step, mdf_step_emit and mdf_run_steady (single-case and
- *      batched contexts) run pairs of steps this way and the last step of
- *      each call (and of each K-step chunk) as form 0 with these bx, by.
+ *   2  two steps per launch (the lattices with axis links only: D2Q5, D2Q4,
+ *      D3Q7, D3Q6 and their *_V forms).  2D: tiles of 64 x 4/8 nodes
+ *      (FP64/other storages) take one step on the tile and a one-node halo
+ *      into LDS and the second from LDS.  3D: tiles of 32 x 4/8 nodes walk a
+ *      chunk of z-planes, keeping the intermediate state of three planes in
+ *      LDS.  Either way the state crosses HBM once per two steps.  mdf_step,
+ *      mdf_step_emit and mdf_run_steady run pairs of steps this way and the
+ *      last step of each call (and of each K-step chunk) as form 0 with these
+ *      bx, by; batched 3D contexts run every step as form 0.
  * The read kernels always use one node per thread.  Default 64 x 4, 8
- * groups, form 2 where it exists and form 0 elsewhere.  MDF_EINVAL otherwise
- * (also form 2 on a 3D lattice, forms 1 and 2 on D2Q9 / D3Q15).  Any shape
+ * groups, form 2 on the 2D axis-link lattices and form 0 elsewhere.
+ * MDF_EINVAL otherwise (also forms 1 and 2 on D2Q9 / D3Q15).  Any shape
  * and form give bitwise identical populations and fields; only the
  * summation order of the FP64 sums of mdf_check, mdf_run_steady and
  * mdf_invariants follows it. */
@@ -313,6 +316,35 @@ mdf_status mdf_set_active(mdf_ctx *ctx, const int32_t *active);
  * step, or NULL.  Waits for the device. */
 mdf_status mdf_autotune(mdf_ctx *ctx, int32_t trial_steps, int32_t *chosen, double *best_ms,
                         void *stream);
+
+/* How the batched steps of this context were launched (the persistent,
+ * graph-captured launch of a multi-case context; see mdf_step).  stats:
+ * host int64[4] receiving
+ *   [0] K-step chunks captured as HIP graphs,
+ *   [1] chunks run by replaying a captured graph,
+ *   [2] chunks run as plain launches (the null stream, chunks of fewer
+ *       than 4 steps, or after a failed capture),
+ *   [3] captures that failed; the context then uses plain launches for
+ *       the rest of its life, with the same results.
+ * capture_error (or NULL): receives the HIP message of the last failed
+ * capture ("" if none), valid until the next call on the context.
+ * Single-case contexts launch per step and report zeros.  MDF_EINVAL on
+ * NULL arguments. */
+mdf_status mdf_graph_stats(const mdf_ctx *ctx, int64_t *stats, const char **capture_error);
+
+/* Device address and size in bytes of one population buffer of a case, in
+ * the storage layout [set][direction][z][y][row pitch] (the ping-pong pair
+ * of the pull scheme of eq. 3-21).  which = 0: the buffer holding the
+ * post-collision state f*(t) that the next step reads; which = 1: the other
+ * one, which the next step overwrites and from which the read calls
+ * (mdf_moments, mdf_gradients, mdf_populations, mdf_check) pull f(t).  The
+ * memory stays the caller's workspace.  A caller may overwrite buffer 1
+ * before a call to mdf_step or mdf_step_emit (no step reads it before
+ * writing it), but not before a read call, nor before mdf_run_steady, which
+ * begins with a read unless mdf_check ran at the current time.  Meant for
+ * inspection and tests.  MDF_EINVAL on a bad case, `which` or NULL output. */
+mdf_status mdf_population_buffer(const mdf_ctx *ctx, int32_t case_id, int32_t which, void **ptr,
+                                 size_t *bytes);
 
 /* Current time of a case (steps taken since mdf_init; cases stopped by
  * mdf_run_steady stay at their stopping time).  -1 on a bad argument. */

@@ -772,6 +772,92 @@ int orc_run(const orc_case *cs, const uint8_t *solid, const double *force_field,
     return 0;
 }
 
+/* ------------------------------------------------ 16-bit deviation storage
+ *
+ * Not in the paper: the library can store each post-collision population as
+ * a 16-bit floating-point deviation from the rest state,
+ *     stored = (f - f_rest) / u_ref,   f = f_rest + u_ref * stored,
+ * f_rest_{i,0} = w_i rho0 and f_rest_{i,a>=1} = 0, and collide in binary32.
+ * The oracle keeps its FP64 arithmetic and takes the one rounding decision
+ * of the format in the precision the library takes it in: f, f_rest and
+ * 1/u_ref are rounded to binary32, the deviation is formed and scaled in
+ * binary32, and the result is rounded to the nearest value of the 16-bit
+ * format, ties to even.  The decoded value is then formed in FP64.
+ *   ORC_BINARY16: IEEE 754 binary16, 11-bit significand, exponents -14..15
+ *                 (subnormals below 2^-14), largest finite 65504.
+ *   ORC_BFLOAT16: bfloat16, 8-bit significand, the exponent range of
+ *                 binary32 (subnormals below 2^-126). */
+#define ORC_BINARY16 2
+#define ORC_BFLOAT16 3
+
+/* Nearest value of the 16-bit format to the binary32 value x, ties to even:
+ * x is a multiple of the spacing of its binade, q = 2^(e - p + 1) with e the
+ * exponent of x (at least emin) and p the significand bits, so x / q is
+ * exact in FP64 and rint() (round to nearest even, the default mode) picks
+ * the neighbour.  Beyond the largest finite value the result is infinite. */
+static double round16(int fmt, float x)
+{
+    const int p = (fmt == ORC_BINARY16) ? 11 : 8;
+    const int emin = (fmt == ORC_BINARY16) ? -14 : -126;
+    const int emax = (fmt == ORC_BINARY16) ? 15 : 127;
+    double v = (double)x;
+    if (isnan(v) || isinf(v) || v == 0.0) return v;
+    int e = ilogb(v);
+    if (e < emin) e = emin;
+    double q = ldexp(1.0, e - p + 1);
+    double y = rint(v / q) * q;
+    /* largest finite value (2 - 2^(1-p)) 2^emax; a result above it overflowed */
+    double big = ldexp(2.0 - ldexp(1.0, 1 - p), emax);
+    if (fabs(y) > big) return copysign(INFINITY, v);
+    return y;
+}
+
+/* out[k] = the 16-bit value nearest to in[k] (binary32), as a double. */
+int orc_round16(int fmt, const float *in, double *out, long n)
+{
+    if (fmt != ORC_BINARY16 && fmt != ORC_BFLOAT16) return -1;
+    for (long k = 0; k < n; ++k) out[k] = round16(fmt, in[k]);
+    return 0;
+}
+
+/* Replace every population of the fluid nodes of f ([node][set][dir]) by
+ * its round trip through the 16-bit deviation storage described above. */
+int orc_store16(const orc_case *cs, const uint8_t *solid, int fmt, double u_ref, double *f)
+{
+    lattice_t L;
+    if (check_case(cs, &L) != 0) return -1;
+    if ((fmt != ORC_BINARY16 && fmt != ORC_BFLOAT16) || !(u_ref > 0.0)) return -1;
+    long N = nodes_of(cs);
+    int d = L.d, q = L.q, ns = d + 1;
+    const float inv32 = (float)(1.0 / u_ref);
+    for (long n = 0; n < N; ++n) {
+        if (solid && solid[n]) continue;
+        double *fn = f + n * ns * q;
+        for (int a = 0; a < ns; ++a)
+            for (int i = 0; i < q; ++i) {
+                const double rest = (a == 0) ? L.w[i] * cs->rho0 : 0.0;
+                const float v32 = (float)fn[a * q + i];
+                const float r32 = (float)rest;
+                const float dev32 = (v32 - r32) * inv32;        /* binary32 operations */
+                fn[a * q + i] = rest + u_ref * round16(fmt, dev32);
+            }
+    }
+    return 0;
+}
+
+/* nsteps steps with the 16-bit storage: collide, store the post-collision
+ * populations through the format, stream. */
+int orc_run16(const orc_case *cs, const uint8_t *solid, const double *force_field, int fmt, double u_ref,
+              double *f, double *tmp, long nsteps)
+{
+    for (long s = 0; s < nsteps; ++s) {
+        if (orc_collide(cs, solid, force_field, f, tmp) != 0) return -1;
+        if (orc_store16(cs, solid, fmt, u_ref, tmp) != 0) return -1;
+        if (orc_stream(cs, solid, tmp, f) != 0) return -1;
+    }
+    return 0;
+}
+
 /* Global sums over fluid nodes of pre-collision f(., t):
  *   out[a] = sum_x ubar_a for a = 0..d,
  *   out[d+1] = sum_x sum_{a>=1} J_{a,a}.

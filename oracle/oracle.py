@@ -27,6 +27,9 @@ PERIODIC = 0
 WALL = 1
 PLAIN = 0        # forcing of eq. 3-21
 SCHEME2 = 1      # forcing of Scheme II, eq. 2-3c / 2-7a
+BINARY16 = 2     # 16-bit deviation storage formats (orc_store16)
+BFLOAT16 = 3
+FORMATS = {"f16dev": BINARY16, "bf16dev": BFLOAT16}
 
 _LIB = None
 
@@ -70,9 +73,13 @@ def lib():
         L.orc_step.argtypes = [cp, u8p, dp, dp, dp]
         L.orc_run.argtypes = [cp, u8p, dp, dp, dp, ctypes.c_long]
         L.orc_invariants.argtypes = [cp, u8p, dp, dp, dp]
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.orc_round16.argtypes = [ctypes.c_int, fp, dp, ctypes.c_long]
+        L.orc_store16.argtypes = [cp, u8p, ctypes.c_int, ctypes.c_double, dp]
+        L.orc_run16.argtypes = [cp, u8p, dp, ctypes.c_int, ctypes.c_double, dp, dp, ctypes.c_long]
         for name in ("orc_lattice_info", "orc_collision_matrix", "orc_init", "orc_collide",
                      "orc_stream", "orc_fields", "orc_num_fields", "orc_step", "orc_run",
-                     "orc_invariants"):
+                     "orc_invariants", "orc_round16", "orc_store16", "orc_run16"):
             getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -218,6 +225,28 @@ class Oracle:
         self.t += int(nsteps)
         return self
 
+    def run16(self, nsteps, fmt, u_ref):
+        """nsteps steps with the post-collision populations stored through
+        the 16-bit deviation format `fmt` (BINARY16 or BFLOAT16) with scale
+        u_ref (orc_run16)."""
+        _ok(lib().orc_run16(ctypes.byref(self._cs), _u8(self.solid), _dp(self.force_field), int(fmt),
+                            float(u_ref), _dp(self.f), _dp(self._tmp), int(nsteps)), "run16")
+        self.t += int(nsteps)
+        return self
+
+    def post16(self, fmt, u_ref):
+        """Post-collision f*(., t) stored through the 16-bit deviation format
+        `fmt` with scale u_ref (orc_collide, then orc_store16), as [set][dir] +
+        field shape (state unchanged)."""
+        c = self.case
+        out = np.zeros_like(self.f)
+        _ok(lib().orc_collide(ctypes.byref(self._cs), _u8(self.solid), _dp(self.force_field),
+                              _dp(self.f), _dp(out)), "collide")
+        _ok(lib().orc_store16(ctypes.byref(self._cs), _u8(self.solid), int(fmt), float(u_ref), _dp(out)),
+            "store16")
+        f = out.reshape(c.N, c.d + 1, c.q).transpose(1, 2, 0)
+        return np.ascontiguousarray(f).reshape((c.d + 1, c.q) + c.fshape)
+
     def collide(self):
         """Post-collision f*(., t) as [set][dir] + field shape (state unchanged)."""
         c = self.case
@@ -259,6 +288,16 @@ class Oracle:
         _ok(lib().orc_invariants(ctypes.byref(self._cs), _u8(self.solid), _dp(self.force_field), _dp(self.f), _dp(out)),
             "invariants")
         return out
+
+
+def round16(fmt, x):
+    """The 16-bit value (BINARY16 or BFLOAT16) nearest to each binary32 value
+    of x, ties to even, as float64 (orc_round16)."""
+    a = np.ascontiguousarray(np.asarray(x, np.float32).reshape(-1))
+    out = np.zeros(a.size)
+    _ok(lib().orc_round16(int(fmt), a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _dp(out), a.size),
+        "round16")
+    return out.reshape(np.shape(x))
 
 
 def residual(u_now, u_prev, K):

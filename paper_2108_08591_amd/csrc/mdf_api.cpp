@@ -33,8 +33,11 @@ bool lat_ok(int lattice) { return lattice >= MDF_D2Q5 && lattice <= MDF_D3Q15_V;
 bool lat_2d(int lattice) { return (lattice & 1) == 0; }
 bool lat_restfree(int lattice) { return (lattice & 4) != 0; }
 bool lat_diag(int lattice) { return (lattice & 8) != 0; }
-// two steps per launch: 2D lattices with axis links
-bool lat_fusable(int lattice) { return lat_2d(lattice) && !lat_diag(lattice); }
+// two steps per launch: lattices with axis links (2D tiles, or 3D tiles
+// walking z-planes)
+bool lat_fusable(int lattice) { return !lat_diag(lattice); }
+// the default form: two steps per launch in 2D
+bool lat_fused_default(int lattice) { return lat_2d(lattice) && !lat_diag(lattice); }
 int lat_d(int lattice) { return lat_2d(lattice) ? 2 : 3; }
 int lat_q(int lattice)
 {
@@ -212,6 +215,9 @@ struct mdf_ctx {
     int num_cu = 0;
     std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
     bool use_graphs = true;
+    // graph bookkeeping reported by mdf_graph_stats
+    int64_t graphs_captured = 0, graph_launches = 0, plain_chunks = 0, capture_failures = 0;
+    std::string capture_error;
 };
 
 namespace {
@@ -311,7 +317,7 @@ mdf_status advance_case(mdf_ctx *ctx, int k, int64_t nsteps, bool check_last, ui
                         hipStream_t st, int *nblocks)
 {
     int64_t pairs = 0;
-    if (ctx->shape.fuse && lat_2d(ctx->lattice) && nsteps >= 3) pairs = (nsteps - 1) / 2;
+    if (ctx->shape.fuse && lat_fusable(ctx->lattice) && nsteps >= 3) pairs = (nsteps - 1) / 2;
     for (int64_t s = 0; s < pairs; ++s) {
         hipError_t e = mdf::launch_step2(ctx->lattice, ctx->storage, ctx->kc[k], ctx->bufs[k], ctx->cur[k], fields,
                                          out, ctx->shape, st);
@@ -498,20 +504,35 @@ mdf_status batch_steps(mdf_ctx *ctx, int nsteps, bool check, uint32_t fields, hi
             if (e == hipSuccess) e = e2;
             if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
             if (graph) (void)hipGraphDestroy(graph);
-            if (e == hipSuccess) ctx->graphs.push_back({key, exec});
-            else exec = nullptr;
-            if (e != hipSuccess) {
-                (void)hipGetLastError();     // capture unsupported here: plain launches
-                ctx->use_graphs = false;
+            if (e == hipSuccess) {
+                ctx->graphs.push_back({key, exec});
+                ctx->graphs_captured += 1;
+            } else {
+                exec = nullptr;
             }
+            if (e != hipSuccess) {
+                // capture unsupported on this stream: the context goes on with
+                // plain launches, and mdf_graph_stats reports the failure
+                ctx->capture_error = hipGetErrorString(e);
+                (void)hipGetLastError();
+                ctx->use_graphs = false;
+                ctx->capture_failures += 1;
+            }
+        } else {
+            ctx->capture_error = hipGetErrorString(e);
+            (void)hipGetLastError();
+            ctx->use_graphs = false;
+            ctx->capture_failures += 1;
         }
     }
     if (exec) {
         hipError_t e = hipGraphLaunch(exec, st);
         if (e != hipSuccess) return device_error(ctx, e, "graph launch");
+        ctx->graph_launches += 1;
     } else {
         hipError_t e = enqueue();
         if (e != hipSuccess) return device_error(ctx, e, "batched step launch");
+        ctx->plain_chunks += 1;
     }
     const int launches = pairs + singles;
     ctx->launches_since_upload += launches;
@@ -589,7 +610,7 @@ mdf_status mdf_init(mdf_ctx **out, mdf_lattice lattice, mdf_storage storage, con
 
     mdf_ctx *ctx = new mdf_ctx;
     ctx->lattice = lattice;
-    ctx->shape.fuse = lat_fusable(lattice) ? 1 : 0;     // two steps per launch by default in 2D
+    ctx->shape.fuse = lat_fused_default(lattice) ? 1 : 0;     // two steps per launch by default in 2D
     ctx->storage = storage;
     ctx->d = lat_d(lattice);
     ctx->q = lat_q(lattice);
@@ -662,7 +683,7 @@ mdf_status mdf_set_launch(mdf_ctx *ctx, int32_t bx, int32_t by, int32_t groups, 
     if (groups < 0 || groups > 64) return fail(ctx, MDF_EINVAL, "mdf_set_launch: groups outside [0, 64]");
     if (form < 0 || form > 2) return fail(ctx, MDF_EINVAL, "mdf_set_launch: form must be 0, 1 or 2");
     if (form == 2 && !lat_fusable(ctx->lattice))
-        return fail(ctx, MDF_EINVAL, "mdf_set_launch: two steps per launch needs a 2D lattice with axis links");
+        return fail(ctx, MDF_EINVAL, "mdf_set_launch: two steps per launch needs a lattice with axis links");
     if (form == 1 && lat_diag(ctx->lattice))
         return fail(ctx, MDF_EINVAL, "mdf_set_launch: the vector form needs a lattice with axis links");
     ctx->shape = LaunchShape{bx, by, groups, form == 1 ? 2 : 1, form == 2 ? 1 : 0};
@@ -919,7 +940,7 @@ mdf_status mdf_autotune(mdf_ctx *ctx, int32_t trial_steps, int32_t *chosen, doub
     int bi = 0;
     mdf_status r = MDF_OK;
     for (int c = 0; c < int(sizeof cand / sizeof cand[0]) && r == MDF_OK; ++c) {
-        // two steps per launch: 2D contexts only
+        // two steps per launch: lattices with axis links
         if (cand[c][3] == 2 && !lat_fusable(ctx->lattice)) continue;
         if (cand[c][3] == 1 && lat_diag(ctx->lattice)) continue;
         r = mdf_set_launch(ctx, cand[c][0], cand[c][1], cand[c][2], cand[c][3]);
@@ -946,6 +967,30 @@ mdf_status mdf_autotune(mdf_ctx *ctx, int32_t trial_steps, int32_t *chosen, doub
         for (int k = 0; k < 4; ++k) chosen[k] = cand[bi][k];
     if (best_ms) *best_ms = double(best) / trial_steps;
     return r;
+}
+
+mdf_status mdf_graph_stats(const mdf_ctx *ctx, int64_t *stats, const char **capture_error)
+{
+    if (!ctx) return fail(nullptr, MDF_EINVAL, "mdf_graph_stats: ctx is NULL");
+    if (!stats) return fail(const_cast<mdf_ctx *>(ctx), MDF_EINVAL, "mdf_graph_stats: stats is NULL");
+    stats[0] = ctx->graphs_captured;
+    stats[1] = ctx->graph_launches;
+    stats[2] = ctx->plain_chunks;
+    stats[3] = ctx->capture_failures;
+    if (capture_error) *capture_error = ctx->capture_error.c_str();
+    return MDF_OK;
+}
+
+mdf_status mdf_population_buffer(const mdf_ctx *ctx, int32_t case_id, int32_t which, void **ptr, size_t *bytes)
+{
+    if (!ctx) return fail(nullptr, MDF_EINVAL, "mdf_population_buffer: ctx is NULL");
+    mdf_ctx *c = const_cast<mdf_ctx *>(ctx);
+    if (!case_ok(ctx, case_id)) return fail(c, MDF_EINVAL, "case_id %d out of range", case_id);
+    if (which != 0 && which != 1) return fail(c, MDF_EINVAL, "mdf_population_buffer: which must be 0 or 1");
+    if (!ptr || !bytes) return fail(c, MDF_EINVAL, "mdf_population_buffer: NULL output");
+    *ptr = ctx->bufs[case_id].pop[which == 0 ? ctx->cur[case_id] : ctx->cur[case_id] ^ 1];
+    *bytes = size_t(lat_ns(ctx->lattice)) * ctx->q * size_t(ctx->kc[case_id].dstride) * storage_bytes(ctx->storage);
+    return MDF_OK;
 }
 
 int64_t mdf_time(const mdf_ctx *ctx, int32_t case_id)

@@ -66,9 +66,11 @@ struct LaunchShape {
 };
 
 // Tile grid of one launch: gx * gy * gz tiles of bx * by threads, launched
-// as a 1D grid of nb = gx * gy * gz blocks.
+// as a 1D grid of nb = gx * gy * gz blocks.  zc: z-planes per tile of the
+// three-dimensional two-step kernel (which walks a chunk of planes), else 1.
 struct Tiling {
     int gx, gy, nb, groups;
+    int zc = 1;
 };
 
 enum ReadMode { kReadFields = 0, kReadPops = 1, kReadCheck = 2, kReadSums = 3 };

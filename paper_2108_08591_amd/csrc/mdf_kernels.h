@@ -1103,18 +1103,20 @@ __device__ __forceinline__ void strip_tile(int t, int gx, int gy, int &tx, int &
     }
 }
 
-// Two time steps in one pass over HBM (temporal blocking, 2D only).  A block
+// Two time steps in one pass over HBM (temporal blocking, 2D).  A block
 // owns a tile of 64 x TY nodes.  Step 1 runs on the tile and a one-node
 // halo with the one-step code (pull from the post-collision state f*(t) in
-// HBM, wall rule, moments, fields, collision); its result f*(t+1) goes to
-// LDS in the storage format (encoded exactly as a one-step launch would store
-// it).  Halo nodes across a periodic face are the wrapped nodes; halo nodes
-// behind a wall are not needed (step 2 takes the wall rule there).  Step 2
-// pulls f(t+2) from LDS, applies the same wall rule, emits the fields and
-// writes f*(t+2) to HBM.  Every population, field and emitted value is
-// bitwise that of two one-step launches; HBM traffic per step drops from one
-// read and one write of the state to about half of that plus the halo
-// re-reads ((64 + 2)(TY + 2) / (64 TY) of a read per two steps).
+// HBM, wall rule, moments, collision); its result f*(t+1) goes to LDS in the
+// storage format (encoded exactly as a one-step launch would store it).
+// Halo nodes across a periodic face are the wrapped nodes; halo nodes behind
+// a wall are not needed (step 2 takes the wall rule there).  Step 2 pulls
+// f(t+2) from LDS, applies the same wall rule, emits the fields and writes
+// f*(t+2) to HBM.  The fields of step 1 are not written: the emission buffer
+// holds the fields of the latest step, and step 2 overwrites the same
+// channels.  Every population, field and emitted value is bitwise that of
+// two one-step launches; HBM traffic per step drops from one read and one
+// write of the state to about half of that plus the halo re-reads
+// ((64 + 2)(TY + 2) / (64 TY) of a read per two steps).
 // The caller keeps f*(t+1) out of HBM, so the buffer the read kernels pull
 // from is stale after this kernel until the next one-step launch.
 template <class L, int ST>
@@ -1150,20 +1152,16 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int gy, int t
 #pragma unroll
     for (int k0 = 0; k0 < K1; k0 += G) {
         Node<L, C> n[G];
-        bool fluid[G], interior[G];
-        decltype(grid_ix<WIDE>(0, 0, 0, 0, 0)) node[G];
+        bool fluid[G];
         // issue this batch's loads ahead of other waves' arithmetic
         __builtin_amdgcn_s_setprio(2);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int e = tid + (k0 + g) * NT;
             fluid[g] = false;
-            interior[g] = false;
-            node[g] = grid_ix<WIDE>(0, 0, 0, 0, 0);
             if (k0 + g >= K1 || e >= NE) continue;
             const int ex = e % W, ey = e / W;
             int x = x0 - 1 + ex, y = y0 - 1 + ey;
-            interior[g] = ex >= 1 && ex <= kF2X && ey >= 1 && ey <= TY && x < p.nx && y < p.ny;
             if (x < 0 || x >= p.nx) {
                 if (p.bc[x < 0 ? 0 : 1] == MDF_WALL) continue;
                 x = ((x % p.nx) + p.nx) % p.nx;
@@ -1172,7 +1170,6 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int gy, int t
                 if (p.bc[y < 0 ? 2 : 3] == MDF_WALL) continue;
                 y = ((y % p.ny) + p.ny) % p.ny;
             }
-            node[g] = grid_ix<WIDE>(x, y, 0, p.ny, p.nx);
             fluid[g] = gather<L, ST, MASK, true, WIDE>(p, src, links, x, y, 0, n[g]);   // false: solid node
         }
         __builtin_amdgcn_s_setprio(0);
@@ -1182,7 +1179,6 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int gy, int t
             const int e = tid + (k0 + g) * NT;
             Moments<L, C> m;
             moments<L, C>(p, n[g], m);
-            if (EMIT && interior[g]) write_fields<L, C>(p, n[g], m, fields, out, node[g], nodes);
 #pragma unroll
             for (int a = 0; a < L::NS; ++a) {
                 C ne[L::Q], fo[L::Q];
@@ -1311,6 +1307,331 @@ k_step2_batch(const BatchEntry *__restrict__ tab, const int *__restrict__ meta,
                                                   static_cast<T *>(e.pop[sel ^ 1]), e.links, fields,
                                                   static_cast<C *>(e.out), lds.v);
         __syncthreads();   // the next tile's step 1 overwrites the LDS this tile's step 2 reads
+    }
+}
+
+// ----------------------------------------------------------------- two steps per pass (3D, axis links)
+
+// Output tile of k_step2z per storage: TX x TY nodes of an x-y plane, one
+// thread each, walking a chunk of z-planes.  The LDS copy of the
+// intermediate state f*(t+1) (see Step2ZLds) is 68 KB for FP32, 34 KB for
+// the 16-bit formats and 70 KB for FP64 (D3Q7, four sets), so two (four)
+// blocks fit a CU's 160 KB.
+template <int ST> struct Fuse2Z { static constexpr int TX = 32, TY = 8; };
+template <> struct Fuse2Z<MDF_F64> { static constexpr int TX = 32, TY = 4; };
+
+// The directions of an axis-link 3D lattice by their z-component: the
+// in-plane ones (c_z = 0) in lattice order, and the +z and -z links.
+template <class L>
+struct ZSplit {
+    static constexpr int count_ip()
+    {
+        int n = 0;
+        for (int i = 0; i < L::Q; ++i) n += (L::cz[i] == 0) ? 1 : 0;
+        return n;
+    }
+    // rank of direction i among the in-plane directions (-1 for a z link)
+    static constexpr int rank(int i)
+    {
+        if (L::cz[i] != 0) return -1;
+        int r = 0;
+        for (int k = 0; k < i; ++k) r += (L::cz[k] == 0) ? 1 : 0;
+        return r;
+    }
+    static constexpr int find_z(int sgn)
+    {
+        for (int i = 0; i < L::Q; ++i)
+            if (L::cz[i] == sgn) return i;
+        return -1;
+    }
+    static constexpr int NIP = count_ip();
+    static constexpr int ZP = find_z(1), ZM = find_z(-1);
+};
+
+// LDS of k_step2z: f*(t+1) of the planes step 2 reads, in the storage
+// encoding.  Two in-plane slots (the plane step 2 works on and the next
+// one) hold the in-plane directions of the TX x TY tile nodes and, of the
+// halo ring (no corners), only the direction that streams into the tile:
+// +x of the column left of the tile, -x right of it, +y below, -y above.
+// Three z slots (planes z - 1, z, z + 1) hold the +z and -z directions of
+// the tile nodes.
+template <class L, int ST>
+struct Step2ZLds {
+    static constexpr int TX = Fuse2Z<ST>::TX, TY = Fuse2Z<ST>::TY;
+    static constexpr int NI = TX * TY, NH = 2 * (TX + TY);
+    static constexpr int IPS = L::NS * ZSplit<L>::NIP * NI + L::NS * NH;   // one in-plane slot
+    static constexpr int ZS = L::NS * 2 * NI;                              // one z slot
+    typename Store<ST>::T v[2 * IPS + 3 * ZS];
+};
+
+// Which values of a plane's f*(t+1) step 1 keeps: everything step 2 reads
+// (the planes step 2 works on), or only the +z (-z) links of the tile nodes
+// (the plane below (above) the chunk).
+enum { kZKeepAll = 0, kZKeepUp = 1, kZKeepDown = 2 };
+
+// Step 1 of k_step2z on local plane r (global z = z0 - 1 + r): the one-step
+// update from f*(t) in HBM to f*(t+1), for the tile nodes and (KEEP ==
+// kZKeepAll) the halo ring, written to LDS.  Nodes behind a wall face are
+// skipped (step 2 takes the wall rule there); across a periodic face the
+// wrapped node is computed.  Each thread takes positions tid and tid + NT
+// and issues both nodes' loads before computing either.
+template <class L, int ST, int KEEP, bool MASK, bool WIDE>
+__device__ __forceinline__ void step2z_plane1(const KCase &p, const typename Store<ST>::T *__restrict__ src,
+                                              const uint8_t *__restrict__ links, int x0, int y0, int z,
+                                              typename Store<ST>::T *__restrict__ ip,
+                                              typename Store<ST>::T *__restrict__ zs)
+{
+    using S = Store<ST>;
+    using C = typename S::C;
+    using LD = Step2ZLds<L, ST>;
+    using Z = ZSplit<L>;
+    constexpr int TX = LD::TX, TY = LD::TY, NI = LD::NI, NH = LD::NH, NT = NI;
+    constexpr int NPOS = (KEEP == kZKeepAll) ? NI + NH : NI;
+    constexpr int G = (NPOS + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    if (z < 0 || z >= p.nz) {
+        if (p.bc[z < 0 ? 4 : 5] == MDF_WALL) return;
+        z = ((z % p.nz) + p.nz) % p.nz;
+    }
+    Node<L, C> n[G];
+    bool fluid[G];
+    int pos[G];
+    __builtin_amdgcn_s_setprio(2);          // issue the loads ahead of other waves' arithmetic
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int e = tid + g * NT;
+        pos[g] = e;
+        fluid[g] = false;
+        if (e >= NPOS) continue;
+        int lx, ly;
+        if (e < NI) {
+            lx = e % TX;
+            ly = e / TX;
+        } else {
+            const int h = e - NI;
+            if (h < TY) { lx = -1; ly = h; }
+            else if (h < 2 * TY) { lx = TX; ly = h - TY; }
+            else if (h < 2 * TY + TX) { lx = h - 2 * TY; ly = -1; }
+            else { lx = h - 2 * TY - TX; ly = TY; }
+        }
+        int x = x0 + lx, y = y0 + ly;
+        if (x < 0 || x >= p.nx) {
+            if (p.bc[x < 0 ? 0 : 1] == MDF_WALL) continue;
+            x = ((x % p.nx) + p.nx) % p.nx;
+        }
+        if (y < 0 || y >= p.ny) {
+            if (p.bc[y < 0 ? 2 : 3] == MDF_WALL) continue;
+            y = ((y % p.ny) + p.ny) % p.ny;
+        }
+        fluid[g] = gather<L, ST, MASK, true, WIDE>(p, src, links, x, y, z, n[g]);   // false: solid node
+    }
+    __builtin_amdgcn_s_setprio(0);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        if (!fluid[g]) continue;
+        const int e = pos[g];
+        Moments<L, C> m;
+        moments<L, C>(p, n[g], m);
+#pragma unroll
+        for (int a = 0; a < L::NS; ++a) {
+            C ne[L::Q], fo[L::Q];
+            nonequilibrium<L, C>(n[g], m, a, ne);
+            collide_set<L, C>(p, n[g], a, ne, fo, m.fb[a + L::A0]);
+            if (e < NI) {
+                if (KEEP == kZKeepAll) {
+#pragma unroll
+                    for (int i = 0; i < L::Q; ++i) {
+                        if (L::cz[i] != 0) continue;
+                        ip[(a * Z::NIP + Z::rank(i)) * NI + e] = S::encode(fo[i], rest_value<L, C>(p, a, i), p.inv_scale);
+                    }
+                }
+                if (KEEP != kZKeepDown)
+                    zs[(a * 2 + 0) * NI + e] = S::encode(fo[Z::ZP], rest_value<L, C>(p, a, Z::ZP), p.inv_scale);
+                if (KEEP != kZKeepUp)
+                    zs[(a * 2 + 1) * NI + e] = S::encode(fo[Z::ZM], rest_value<L, C>(p, a, Z::ZM), p.inv_scale);
+            } else {
+                // a halo node keeps the one link that streams into the tile
+                const int h = e - NI;
+                int dir = 0;
+#pragma unroll
+                for (int i = 0; i < L::Q; ++i) {
+                    if (h < TY && L::cx[i] == 1) dir = i;
+                    else if (h >= TY && h < 2 * TY && L::cx[i] == -1) dir = i;
+                    else if (h >= 2 * TY && h < 2 * TY + TX && L::cy[i] == 1) dir = i;
+                    else if (h >= 2 * TY + TX && L::cy[i] == -1) dir = i;
+                }
+                C v = fo[0];
+#pragma unroll
+                for (int i = 1; i < L::Q; ++i)
+                    if (i == dir) v = fo[i];
+                ip[L::NS * Z::NIP * NI + a * NH + h] = S::encode(v, rest_value<L, C>(p, a, dir), p.inv_scale);
+            }
+        }
+    }
+}
+
+// Step 2 of k_step2z on local plane r (global z): pull f(t+2) from the LDS
+// copy of f*(t+1) with the same wall and solid rules, emit the fields, write
+// f*(t+2) to HBM.
+template <class L, int ST, bool EMIT, bool MASK, bool NTST, bool WIDE>
+__device__ __forceinline__ void step2z_plane2(const KCase &p, typename Store<ST>::T *__restrict__ dst,
+                                              const uint8_t *__restrict__ links, uint32_t fields,
+                                              typename Store<ST>::C *__restrict__ out, int x0, int y0, int z,
+                                              const typename Store<ST>::T *__restrict__ ip,
+                                              const typename Store<ST>::T *__restrict__ zdown,
+                                              const typename Store<ST>::T *__restrict__ zown,
+                                              const typename Store<ST>::T *__restrict__ zup)
+{
+    using S = Store<ST>;
+    using C = typename S::C;
+    using LD = Step2ZLds<L, ST>;
+    using Z = ZSplit<L>;
+    constexpr int TX = LD::TX, TY = LD::TY, NI = LD::NI, NH = LD::NH;
+    const int e = threadIdx.x;
+    const int lx = e % TX, ly = e / TX;
+    const int x = x0 + lx, y = y0 + ly;
+    if (x >= p.nx || y >= p.ny) return;
+    const long long nodes = (long long)p.nx * p.ny * p.nz;
+    const auto own = grid_ix<WIDE>(x, y, z, p.ny, p.pitch);
+    const auto node = grid_ix<WIDE>(x, y, z, p.ny, p.nx);
+    unsigned lb = 0;
+    if (MASK) lb = *elem(links, own);
+    if (MASK && (lb & 0x80u)) {
+        if (EMIT) {
+            int nch = 0;
+            if (fields & MDF_FIELD_MOMENTS) nch += L::D + 2;
+            if (fields & MDF_FIELD_GRAD) nch += L::D * L::D;
+            if (fields & MDF_FIELD_DIV) nch += 1;
+            if (fields & MDF_FIELD_STRAIN) nch += L::D * (L::D + 1) / 2;
+            if (fields & MDF_FIELD_STRESS) nch += L::D * (L::D + 1) / 2;
+            if (fields & MDF_FIELD_VORT) nch += 3;
+            for (int ch = 0; ch < nch; ++ch) put_value<false>(out + ch * nodes, node, C(0));
+        }
+        return;
+    }
+    // LDS index of the stored value of direction j at the own node
+    auto own_value = [&](int a, int j) -> C {
+        typename S::T raw;
+        if (L::cz[j] == 0) raw = ip[(a * Z::NIP + Z::rank(j)) * NI + e];
+        else raw = zown[(a * 2 + (L::cz[j] > 0 ? 0 : 1)) * NI + e];
+        return S::decode(raw, rest_value<L, C>(p, a, j), p.scale);
+    };
+    Node<L, C> n;
+    load_sources<L, C>(p, ((long long)z * p.ny + y) * p.nx + x, n);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const int sx = x - L::cx[i], sy = y - L::cy[i], sz = z - L::cz[i];
+        int face = -1;
+        if (L::cx[i] != 0) {
+            if (sx < 0) { if (p.bc[0] == MDF_WALL) face = 0; }
+            else if (sx >= p.nx) { if (p.bc[1] == MDF_WALL) face = 1; }
+        }
+        if (L::cy[i] != 0) {
+            if (sy < 0) { if (p.bc[2] == MDF_WALL) face = 2; }
+            else if (sy >= p.ny) { if (p.bc[3] == MDF_WALL) face = 3; }
+        }
+        if (L::cz[i] != 0) {
+            if (sz < 0) { if (p.bc[4] == MDF_WALL) face = 4; }
+            else if (sz >= p.nz) { if (p.bc[5] == MDF_WALL) face = 5; }
+        }
+        if (MASK && face < 0 && ((lb >> i) & 1u)) face = 6;
+        const C w = C(L::w[i]);
+        if (face < 0) {
+#pragma unroll
+            for (int a = 0; a < L::NS; ++a) {
+                typename S::T raw;
+                if (L::cz[i] > 0) {
+                    raw = zdown[(a * 2 + 0) * NI + e];
+                } else if (L::cz[i] < 0) {
+                    raw = zup[(a * 2 + 1) * NI + e];
+                } else {
+                    const int ux = lx - L::cx[i], uy = ly - L::cy[i];
+                    if (ux >= 0 && ux < TX && uy >= 0 && uy < TY) {
+                        raw = ip[(a * Z::NIP + Z::rank(i)) * NI + uy * TX + ux];
+                    } else {
+                        int h;
+                        if (ux < 0) h = uy;
+                        else if (ux >= TX) h = TY + uy;
+                        else if (uy < 0) h = 2 * TY + ux;
+                        else h = 2 * TY + TX + ux;
+                        raw = ip[L::NS * Z::NIP * NI + a * NH + h];
+                    }
+                }
+                n.f[a][i] = S::decode(raw, rest_value<L, C>(p, a, i), p.scale);
+            }
+        } else {
+            const int j = L::opp[i];
+#pragma unroll
+            for (int a = 0; a < L::NS; ++a) {
+                const C v = own_value(a, j);
+                if (a + L::A0 == 0) {
+                    n.f[a][i] = v;
+                } else {
+                    const int b = a + L::A0 - 1;
+                    const C uw = (face < 6) ? kpar<C>(p.wallu[face][b], p.walluf[face][b]) : C(0);
+                    n.f[a][i] = -v + C(2) * w * uw;
+                }
+            }
+        }
+    }
+    Moments<L, C> m;
+    moments<L, C>(p, n, m);
+    if (EMIT) write_fields<L, C>(p, n, m, fields, out, node, nodes);
+#pragma unroll
+    for (int a = 0; a < L::NS; ++a) {
+        C ne[L::Q], fo[L::Q];
+        nonequilibrium<L, C>(n, m, a, ne);
+        collide_set<L, C>(p, n, a, ne, fo, m.fb[a + L::A0]);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+            S::template store_hint<NTST>(dst + (long long)(a * L::Q + i) * p.dstride, own, fo[i],
+                                         rest_value<L, C>(p, a, i), p.inv_scale);
+    }
+}
+
+// Two time steps in one pass over HBM on a 3D axis-link lattice (temporal
+// blocking along z).  A block owns a TX x TY tile of an x-y plane and a chunk
+// of zc planes z0 .. z1 - 1, and walks it plane by plane: step 1 advances
+// the next plane (and a one-node halo ring in x and y) from f*(t) in HBM to
+// f*(t+1) in LDS, then step 2 advances the current plane from the three
+// planes of f*(t+1) around it to f*(t+2) in HBM.  The planes z0 - 1 and z1
+// (across a periodic face: the wrapped planes) give step 2 their +z and -z
+// links.  Every population, field and emitted value is bitwise that of two
+// one-step launches; the state crosses HBM once per two steps, plus the
+// halo ring ((TX + TY) 2 / (TX TY) of a read) and the two chunk-end planes
+// (2 / zc of a read).  Like k_step2, f*(t+1) never reaches HBM.
+template <class L, int ST, bool EMIT, bool MASK, bool NTST = false, bool WIDE = true>
+__global__ void __launch_bounds__(Fuse2Z<ST>::TX * Fuse2Z<ST>::TY)
+k_step2z(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, typename Store<ST>::T *__restrict__ dst,
+         const uint8_t *__restrict__ links, uint32_t fields, typename Store<ST>::C *__restrict__ out)
+{
+    static_assert(L::D == 3 && !L::DIAG, "z-walking two-step tiles are for 3D axis-link lattices");
+    using LD = Step2ZLds<L, ST>;
+    using T = typename Store<ST>::T;
+    __shared__ LD lds;
+    const int tile = block_tile(tl);
+    const int tx = tile % tl.gx, rest = tile / tl.gx;
+    const int ty = rest % tl.gy, chunk = rest / tl.gy;
+    const int x0 = tx * LD::TX, y0 = ty * LD::TY;
+    const int z0 = chunk * tl.zc;
+    const int z1 = (z0 + tl.zc < p.nz) ? z0 + tl.zc : p.nz;
+    // local plane r is global plane z0 - 1 + r; its slots are in-plane slot
+    // r % 2 and z slot r % 3
+    T *const base = lds.v;
+    auto ips = [&](int r) { return base + (r & 1) * LD::IPS; };
+    auto zsl = [&](int r) { return base + 2 * LD::IPS + (r % 3) * LD::ZS; };
+    step2z_plane1<L, ST, kZKeepUp, MASK, WIDE>(p, src, links, x0, y0, z0 - 1, ips(0), zsl(0));
+    step2z_plane1<L, ST, kZKeepAll, MASK, WIDE>(p, src, links, x0, y0, z0, ips(1), zsl(1));
+    const int nzc = z1 - z0;
+    for (int r = 1; r <= nzc; ++r) {
+        if (r < nzc)
+            step2z_plane1<L, ST, kZKeepAll, MASK, WIDE>(p, src, links, x0, y0, z0 + r, ips(r + 1), zsl(r + 1));
+        else
+            step2z_plane1<L, ST, kZKeepDown, MASK, WIDE>(p, src, links, x0, y0, z0 + r, ips(r + 1), zsl(r + 1));
+        __syncthreads();
+        step2z_plane2<L, ST, EMIT, MASK, NTST, WIDE>(p, dst, links, fields, out, x0, y0, z0 + r - 1, ips(r),
+                                                     zsl(r - 1), zsl(r), zsl(r + 1));
+        __syncthreads();
     }
 }
 
@@ -1592,6 +1913,11 @@ hipError_t step_dispatch(const KCase &p, const CaseBufs &b, int src, bool check,
     return hipGetLastError();
 }
 
+// z-planes per block of k_step2z: long enough that the two chunk-end
+// planes cost little (2/32 of a read), short enough for several blocks per
+// resident slot on 256^3-class grids.
+inline int step2z_chunk(int nz) { return nz < 32 ? nz : 32; }
+
 template <class L, int ST>
 hipError_t step2_dispatch(const KCase &p, const CaseBufs &b, int src, uint32_t fields, void *out, LaunchShape s,
                           hipStream_t stream)
@@ -1599,8 +1925,34 @@ hipError_t step2_dispatch(const KCase &p, const CaseBufs &b, int src, uint32_t f
     using S = Store<ST>;
     using T = typename S::T;
     using C = typename S::C;
-    if constexpr (L::D != 2 || L::DIAG) {
+    if constexpr (L::DIAG) {
         return hipErrorInvalidValue;
+    } else if constexpr (L::D == 3) {
+        const T *in = static_cast<const T *>(b.pop[src]);
+        T *o = static_cast<T *>(b.pop[src ^ 1]);
+        C *emit = static_cast<C *>(out);
+        constexpr int TX = Fuse2Z<ST>::TX, TY = Fuse2Z<ST>::TY;
+        Tiling tl;
+        tl.gx = (p.nx + TX - 1) / TX;
+        tl.gy = (p.ny + TY - 1) / TY;
+        tl.zc = step2z_chunk(p.nz);
+        tl.nb = tl.gx * tl.gy * ((p.nz + tl.zc - 1) / tl.zc);
+        tl.groups = s.groups > 1 ? s.groups : 1;
+        const bool emit_on = (fields != 0) && out != nullptr;
+        const bool mask = b.links != nullptr;
+#define MDF_STEP2Z_LAUNCH1(E, M, N, X)                                                                   \
+    hipLaunchKernelGGL((k_step2z<L, ST, E, M, N, X>), dim3(tl.nb), dim3(TX * TY), 0, stream, p, tl, in, o, \
+                       b.links, fields, emit)
+#define MDF_STEP2Z_LAUNCH(E, M)                                                                    \
+    do {                                                                                           \
+        if (!p.ntstore) MDF_STEP2Z_LAUNCH1(E, M, false, true);                                     \
+        else MDF_STEP2Z_LAUNCH1(E, M, true, false);                                                \
+    } while (0)
+        if (mask) { if (emit_on) MDF_STEP2Z_LAUNCH(true, true); else MDF_STEP2Z_LAUNCH(false, true); }
+        else { if (emit_on) MDF_STEP2Z_LAUNCH(true, false); else MDF_STEP2Z_LAUNCH(false, false); }
+#undef MDF_STEP2Z_LAUNCH
+#undef MDF_STEP2Z_LAUNCH1
+        return hipGetLastError();
     } else {
         const T *in = static_cast<const T *>(b.pop[src]);
         T *o = static_cast<T *>(b.pop[src ^ 1]);

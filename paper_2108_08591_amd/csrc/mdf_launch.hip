@@ -82,6 +82,9 @@ bool two_d(int lattice)
     return lattice == MDF_D2Q5 || lattice == MDF_D2Q5_V || lattice == MDF_D2Q4 || lattice == MDF_D2Q4_V;
 }
 
+// lattices with axis links only (every lattice but D2Q9 / D3Q15 and their *_V forms)
+bool axis_links(int lattice) { return lattice >= MDF_D2Q5 && lattice <= MDF_D3Q6_V; }
+
 }  // namespace
 
 int step_vx(int storage, LaunchShape s)
@@ -128,7 +131,7 @@ hipError_t launch_step2(int lattice, int storage, const KCase &p, const CaseBufs
                         void *out, LaunchShape shape, hipStream_t stream)
 {
     const LatOps *o = ops_of(lattice);
-    if (!o || !two_d(lattice) || p.nz != 1) return hipErrorInvalidValue;
+    if (!o || !axis_links(lattice) || (two_d(lattice) && p.nz != 1)) return hipErrorInvalidValue;
     return o->step2(storage, p, b, src, fields, out, shape, stream);
 }
 

@@ -36,7 +36,7 @@ EXPORTED = ["mdf_workspace_size", "mdf_init", "mdf_step", "mdf_step_emit", "mdf_
             "mdf_gradients", "mdf_populations", "mdf_check", "mdf_run_steady", "mdf_invariants",
             "mdf_set_launch", "mdf_set_active", "mdf_set_force_field", "mdf_autotune", "mdf_time",
             "mdf_last_error", "mdf_state_size", "mdf_save", "mdf_load",
-            "mdf_destroy"]
+            "mdf_graph_stats", "mdf_population_buffer", "mdf_destroy"]
 
 
 class MdfError(RuntimeError):
@@ -92,6 +92,8 @@ def lib():
         L.mdf_state_size.restype = ctypes.c_size_t
         L.mdf_save.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.mdf_load.argtypes = [vp, vp, ctypes.c_size_t, vp]
+        L.mdf_graph_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_char_p)]
+        L.mdf_population_buffer.argtypes = [vp, i32, i32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t)]
         L.mdf_time.argtypes = [vp, i32]
         L.mdf_time.restype = i64
         L.mdf_last_error.argtypes = [vp]
@@ -100,7 +102,7 @@ def lib():
         for name in ("mdf_init", "mdf_step", "mdf_step_emit", "mdf_moments", "mdf_gradients",
                      "mdf_populations", "mdf_check", "mdf_run_steady", "mdf_invariants",
                      "mdf_set_launch", "mdf_set_active", "mdf_set_force_field", "mdf_autotune", "mdf_destroy",
-                     "mdf_save", "mdf_load"):
+                     "mdf_save", "mdf_load", "mdf_graph_stats", "mdf_population_buffer"):
             getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -364,6 +366,26 @@ class Solver:
 
     def time(self, case: int = 0) -> int:
         return int(lib().mdf_time(self._ctx, case))
+
+    def graph_stats(self) -> Dict[str, object]:
+        """Chunks captured as HIP graphs, replayed, run as plain launches,
+        failed captures and the last capture error (mdf_graph_stats)."""
+        stats = (ctypes.c_int64 * 4)()
+        msg = ctypes.c_char_p()
+        _check(lib().mdf_graph_stats(self._ctx, stats, ctypes.byref(msg)), self._ctx)
+        return {"captured": stats[0], "replayed": stats[1], "plain": stats[2], "failed": stats[3],
+                "error": (msg.value or b"").decode(errors="replace")}
+
+    def population_buffer(self, which: int, case: int = 0) -> torch.Tensor:
+        """The raw bytes of population buffer `which` of a case
+        (mdf_population_buffer) as a uint8 view of the workspace: 0 holds
+        f*(t), 1 is the buffer the next step overwrites."""
+        ptr = ctypes.c_void_p()
+        nbytes = ctypes.c_size_t()
+        _check(lib().mdf_population_buffer(self._ctx, case, int(which), ctypes.byref(ptr), ctypes.byref(nbytes)),
+               self._ctx)
+        off = int(ptr.value) - self.workspace.data_ptr()
+        return self.workspace[off: off + int(nbytes.value)]
 
     # -------------------------------------------------------------- read-outs
     def gradients(self, fields: int, case: int = 0) -> torch.Tensor:

@@ -69,7 +69,8 @@ def _lib():
 NN_EXPORTED = ["mdfnn_conv3x3_fwd", "mdfnn_conv3x3_flip", "mdfnn_wgrad_scratch_bytes", "mdfnn_conv3x3_wgrad",
                "mdfnn_avgpool2_fwd", "mdfnn_avgpool2_bwd", "mdfnn_upsample2_fwd", "mdfnn_upsample2_bwd",
                "mdfnn_add", "mdfnn_head_fwd", "mdfnn_head_scratch_bytes", "mdfnn_head_bwd",
-               "mdfnn_loss_scratch_bytes", "mdfnn_mse", "mdfnn_adam", "mdfnn_to_bf16", "mdfnn_to_f32"]
+               "mdfnn_loss_scratch_bytes", "mdfnn_mse", "mdfnn_adam", "mdfnn_to_bf16",
+               "mdfnn_to_f32"]
 
 
 def _p(t):

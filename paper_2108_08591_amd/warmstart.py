@@ -76,6 +76,30 @@ def solve(cases: List[dict], storage="f32", tol=1e-8, K=100, max_steps=400000, i
     return solver, st, steps, res, time.perf_counter() - t0
 
 
+def solve_warm(cases: List[dict], init, storage="f64", tol=1e-8, K=100, max_steps=400000, stream=None,
+               window=20000, log: Optional[Callable[[str], None]] = None):
+    """Warm solves with the cold start as fallback: every case first runs
+    from its predicted initial state (init, as in solve()); each case that
+    goes non-finite or does not converge within max_steps is solved again
+    from rest, and its steps and wall time are added.  Returns (where,
+    status, steps, residual, wall seconds, fallback case indices), with
+    where[k] = (solver, index) holding case k's final state."""
+    warm, st, steps, res, wall = solve(cases, storage, tol=tol, K=K, max_steps=max_steps, init=init,
+                                       stream=stream, window=window, log=log)
+    where = [(warm, k) for k in range(len(cases))]
+    bad = [k for k in range(len(cases)) if st[k] != 0]
+    if bad:
+        cold, cst, csteps, cres, cwall = solve([cases[k] for k in bad], storage, tol=tol, K=K,
+                                               max_steps=max_steps, stream=stream, window=window, log=log)
+        for j, k in enumerate(bad):
+            where[k] = (cold, j)
+            st[k] = cst[j]
+            steps[k] += csteps[j]
+            res[k] = cres[j]
+        wall += cwall
+    return where, st, steps, res, wall, bad
+
+
 def coarse_cases(cases: List[dict], factor: int = 2, s1_max: float = 1.85) -> List[dict]:
     """The same cavities on a grid `factor` times coarser: same lid speed
     (the same flow in lattice velocity units) and Re, a node solid when any of
@@ -266,9 +290,10 @@ def prediction_error(init: np.ndarray, exact: np.ndarray, mask) -> Dict[str, flo
     return out
 
 
-def field_error(solver_a, solver_b, k) -> float:
-    """Relative L2 distance of the velocity fields of case k in two solvers."""
+def field_error(solver_a, solver_b, k, kb=None) -> float:
+    """Relative L2 distance of the velocity fields of case k in solver_a and
+    case kb (default k) in solver_b."""
     ua = solver_a.fields(mdf.FIELD_MOMENTS, k)["u"].double()
-    ub = solver_b.fields(mdf.FIELD_MOMENTS, k)["u"].double()
+    ub = solver_b.fields(mdf.FIELD_MOMENTS, k if kb is None else kb)["u"].double()
     torch.cuda.synchronize()
     return float(torch.linalg.vector_norm(ua - ub) / torch.linalg.vector_norm(ua))

@@ -30,6 +30,22 @@ def test_library_exports_every_declared_symbol():
     assert sorted(mdf.EXPORTED) == declared
 
 
+def _declared_nn_functions():
+    text = open(os.path.join(ROOT, "include", "mdfnn.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mdfnn_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_network_symbol():
+    from paper_2108_08591_amd import nn
+    L = nn._lib()
+    declared = _declared_nn_functions()
+    assert "mdfnn_conv3x3_fwd" in declared
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(nn.NN_EXPORTED) == declared
+
+
 def _ws(spec, storage=mdf.F32, solid=0):
     c = (mdf.MdfCase * 1)(mdf._case_struct(spec))
     return mdf.lib().mdf_workspace_size(spec.lattice, storage, c, 1, solid)
@@ -150,6 +166,10 @@ def test_null_context_calls_fail_cleanly():
     assert L.mdf_step(None, 1, None) == mdf.EINVAL
     assert L.mdf_set_launch(None, 64, 4, 8, 1) == mdf.EINVAL
     assert L.mdf_time(None, 0) == -1
+    stats = (ctypes.c_int64 * 4)()
+    assert L.mdf_graph_stats(None, stats, None) == mdf.EINVAL
+    ptr, nbytes = ctypes.c_void_p(), ctypes.c_size_t()
+    assert L.mdf_population_buffer(None, 0, 0, ctypes.byref(ptr), ctypes.byref(nbytes)) == mdf.EINVAL
     assert L.mdf_destroy(None) == mdf.OK
 
 

@@ -218,7 +218,8 @@ def test_scheme2_and_plain_cases_in_one_batch():
 
 def test_scheme2_velocity_sets_equal_full_form():
     """Scheme II with only the d velocity sets (Remark IV) agrees bit for bit
-    with all d + 1 sets (the source R of the set a = 0 reaches nothing)."""
+    with all d + 1 sets (the source R of the set a = 0 reaches nothing), and
+    with the oracle's sets a = 1..d within the FP32 bar."""
     spec, mask = _walled_2d()
     spec.forcing = C.SCHEME2
     spec.R = 1e-4
@@ -231,6 +232,12 @@ def test_scheme2_velocity_sets_equal_full_form():
         x.step(41)
     assert torch.equal(full.populations()[1:], vel.populations())
     assert torch.equal(full.gradients(mdf.FIELD_ALL)[1:], vel.gradients(mdf.FIELD_ALL)[1:])
+    # and against the oracle's velocity sets a = 1..d with the same field
+    o = _oracle_run(spec, mask, _cast(FF, "f32"), 41)
+    fluid = mask == 0
+    assert rel_err(o.populations()[1:][..., fluid], _np(vel.populations())[..., fluid]) < TOL["f32"]
+    compare_fields(o.fields(), gpu_fields_np(vel, mdf.FIELD_ALL), TOL["f32"],
+                   keys=("u", "P", "grad", "div", "S", "sigma", "vort"))
 
 
 def test_scheme2_poiseuille_exact_on_gpu():

@@ -86,22 +86,29 @@ def test_cavity_beyond_the_cache(storage, N, form):
         del f_t, f_t1, fl
 
 
-def test_tgv3d_full_size_beyond_the_cache():
-    """3D Taylor-Green at 256^3 in FP32 (3.8 GB of populations), the one-node
-    form: patches of 8^3 nodes, some wrapping across the periodic faces."""
+@pytest.mark.parametrize("storage,form", [("f32", 0), ("f32", 2), ("f64", 2)])
+def test_tgv3d_full_size_beyond_the_cache(storage, form):
+    """3D Taylor-Green at 256^3 (3.8 GB of populations in FP32, 7.5 GB in
+    FP64), one node per thread (form 0) and two steps per launch with tiles
+    walking z-planes (form 2): patches of 8^3 nodes, some wrapping across the
+    periodic faces, after one step and after three more (one two-step launch
+    and one one-step launch)."""
     N = 256
     spec = C.tgv3d_case(N=N, u0=0.05, Re=100.0)
-    _say("[hbm-resident] tgv3d 256^3 f32")
+    _say(f"[hbm-resident] tgv3d 256^3 {storage} form {form}")
     Pf, u = C.taylor_green_3d_initial(N, 0.05)
-    init = torch.tensor(np.concatenate([Pf[None], u]).astype(np.float32))
+    dt = np.float64 if storage == "f64" else np.float32
+    init = torch.tensor(np.concatenate([Pf[None], u]).astype(dt))
     del Pf, u
-    s = mdf.Solver([spec], storage="f32", init=("fields", [init]), device=DEV)
+    s = mdf.Solver([spec], storage=storage, init=("fields", [init]), device=DEV)
     del init
     assert _pop_bytes(s, spec) > CACHE_BYTES
+    s.set_launch(64, 4, 8, form)
     s.step(20)
     P = 8
-    corners = [(0, 0, 0), (N - 4, 3, 250), (128, 128, 128), (17, 200, N - 8), (N - 8, N - 8, N - 8), (60, 0, 99)]
-    for nsteps in (1, 2):
+    corners = [(0, 0, 0), (N - 4, 3, 250), (128, 128, 128), (17, 200, N - 8), (N - 8, N - 8, N - 8), (60, 0, 99),
+               (31, 7, 31), (32, 8, 32)]
+    for nsteps in (1, 3):
         f_t = s.populations()
         s.step(nsteps)
         f_t1 = s.populations()
@@ -115,6 +122,6 @@ def test_tgv3d_full_size_beyond_the_cache():
             o.run(nsteps)
             ref = o.populations()[:, :, h:h + P, h:h + P, h:h + P]
             got = _np(f_t1.index_select(2, inn[0]).index_select(3, inn[1]).index_select(4, inn[2]))
-            assert rel_err(ref, got) < 1e-5, (nsteps, x0, y0, z0)
+            assert rel_err(ref, got) < TOL[storage], (nsteps, x0, y0, z0)
         del f_t, f_t1
 

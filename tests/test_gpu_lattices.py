@@ -89,10 +89,11 @@ SETUPS = _setups()
 @pytest.mark.parametrize("idx", range(len(SETUPS)), ids=[s[0] for s in SETUPS])
 def test_lattice_steps_from_random_populations(idx, storage, form):
     """Arbitrary populations, then 1 and 3 more steps (one and two steps per
-    launch in 2D): every population and field matches the oracle."""
+    launch; in 3D the two-step tiles walk z-planes): every population and
+    field matches the oracle."""
     name, spec, mask = SETUPS[idx]
-    if form == 2 and (spec.d == 3 or spec.lattice in DIAG):
-        pytest.skip("two steps per launch is a form of the 2D axis-link lattices")
+    if form == 2 and spec.lattice in DIAG:
+        pytest.skip("two steps per launch is a form of the axis-link lattices")
     _say(f"[lattices] random populations {name} {storage} form {form} shape={spec.shape}")
     f0 = _cast(C.random_populations(spec, seed=200 + idx, scale=0.05), storage)
     s = mdf.Solver([spec], storage=storage, solid=None if mask is None else [mask],
@@ -160,7 +161,7 @@ def test_lattice_launch_shapes_bitwise_identical(storage):
             shapes = [(64, 4, 8, 0), (256, 1, 8, 0), (128, 2, 3, 0), (32, 8, 1, 0)]
         else:
             shapes = [(64, 4, 8, 0), (64, 4, 8, 1), (256, 1, 8, 1), (128, 2, 3, 1), (32, 8, 8, 0)]
-        if spec.d == 2 and spec.lattice not in DIAG:
+        if spec.lattice not in DIAG:
             shapes += [(64, 4, 8, 2), (128, 2, 1, 2)]
         pops, outs = [], []
         for bx, by, g, form in shapes:
@@ -183,7 +184,8 @@ def test_lattice_launch_shapes_bitwise_identical(storage):
 @pytest.mark.parametrize("lat", [C.D2Q4, C.D3Q6, C.D2Q9, C.D3Q15])
 def test_lattice_velocity_sets_equal_full_form(lat):
     """Only the d velocity sets (Remark IV) on these lattices: the same
-    velocity-set populations and fields as all d + 1 sets, bit for bit."""
+    velocity-set populations and fields as all d + 1 sets, bit for bit, and
+    the oracle's sets a = 1..d within the FP32 bar."""
     if C.DIM[lat] == 2:
         spec = C.cavity_case(N=96, Re=150.0, lattice=lat)
         spec.shape = (98, 71)
@@ -197,6 +199,12 @@ def test_lattice_velocity_sets_equal_full_form(lat):
         x.step(41)
     assert torch.equal(full.populations()[1:], vel.populations())
     assert torch.equal(full.gradients(mdf.FIELD_ALL)[1:], vel.gradients(mdf.FIELD_ALL)[1:])
+    # and against the oracle's velocity sets a = 1..d
+    o = oracle_for(spec).init(0.0, np.zeros((spec.d,) + spec.fshape))
+    o.run(41)
+    assert rel_err(o.populations()[1:], _np(vel.populations())) < TOL["f32"]
+    compare_fields(o.fields(), gpu_fields_np(vel, mdf.FIELD_ALL), TOL["f32"],
+                   keys=("u", "P", "grad", "div", "S", "sigma", "vort"))
 
 
 @pytest.mark.parametrize("lat", [C.D2Q4, C.D2Q9])

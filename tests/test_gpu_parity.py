@@ -291,8 +291,7 @@ def test_launch_shapes_bitwise_identical(storage):
         pops, outs = [], []
         shapes = [(64, 4, 8, 0), (64, 4, 8, 1), (64, 4, 1, 1), (256, 1, 8, 1), (128, 2, 3, 1), (32, 2, 8, 1),
                   (64, 1, 1, 1), (32, 8, 8, 0)]
-        if spec.lattice == C.D2Q5:
-            shapes += [(64, 4, 8, 2), (128, 2, 1, 2)]
+        shapes += [(64, 4, 8, 2), (128, 2, 1, 2)]
         for bx, by, g, form in shapes:
             _say(f"[gpu] {storage} {name} launch {bx}x{by} groups {g} form {form}")
             P, u = C.smooth_random_fields(spec, seed=5, amp=0.03)
@@ -312,10 +311,20 @@ def test_launch_shapes_bitwise_identical(storage):
 def test_two_step_form_state_and_reads():
     """Two steps per launch: after calls of every length (pairs plus a last
     one-step launch), the time, the populations, every read-out and the
-    steady-state residual equal those of one-step launches bit for bit; the
-    form is refused on D3Q7."""
-    spec = C.cavity_case(N=70, Re=100.0)
-    spec.shape = (70, 37)
+    steady-state residual equal those of one-step launches bit for bit, in
+    2D and in 3D (tiles walking chunks of z-planes, here with walls in z, a
+    ragged tile grid and a z-extent beyond one chunk); the form is refused
+    on D2Q9."""
+    cav = C.cavity_case(N=70, Re=100.0)
+    cav.shape = (70, 37)
+    box = C.CaseSpec(C.D3Q7, (37, 11, 70), 1.3, bc=(C.PERIODIC, C.PERIODIC, C.PERIODIC, C.PERIODIC, C.WALL, C.WALL),
+                     wall_u=((0, 0, 0), (0, 0, 0), (0, 0, 0), (0, 0, 0), (0, 0, 0), (0.05, 0.01, 0)))
+    for spec in (cav, box):
+        _two_step_runs(spec)
+    _two_step_refusal()
+
+
+def _two_step_runs(spec):
     runs = []
     for form in (0, 2):
         _say(f"[gpu] two-step form {form}")
@@ -335,10 +344,13 @@ def test_two_step_form_state_and_reads():
             assert torch.equal(a[2], b[2])
         else:
             assert abs(a[2] - b[2]) <= 1e-12 * abs(a[2])
-    box = C.CaseSpec(C.D3Q7, (16, 8, 8), 1.1)
-    s3 = mdf.Solver([box], storage="f32", device=DEV)
+
+
+def _two_step_refusal():
+    cav9 = C.cavity_case(N=40, Re=50.0, lattice=C.D2Q9)
+    s9 = mdf.Solver([cav9], storage="f32", device=DEV)
     with pytest.raises(mdf.MdfError):
-        s3.set_launch(64, 4, 8, 2)
+        s9.set_launch(64, 4, 8, 2)
 
 
 def test_invariants_and_residual_match_oracle():
@@ -389,7 +401,9 @@ def test_velocity_set_variant_equals_full_form(storage):
     """The *_V lattices (only the d velocity sets, Remark IV) against the
     full d + 1 sets: the velocity-set populations, every field except ubar_0
     and the steady residual agree bit for bit (nothing reads the set a = 0),
-    in 2D with obstacles (two steps per launch) and in 3D with walls."""
+    in 2D with obstacles (two steps per launch) and in 3D with walls.  In
+    FP64 and FP32 the velocity-set populations and fields also match the
+    oracle's sets a = 1..d at the parity bar."""
     cav = C.cavity_case(N=96, Re=150.0)
     cav.shape = (98, 71)
     mask = np.zeros((71, 98), np.uint8)
@@ -407,6 +421,18 @@ def test_velocity_set_variant_equals_full_form(storage):
         ff, fv = full.gradients(mdf.FIELD_ALL), vel.gradients(mdf.FIELD_ALL)
         assert torch.equal(ff[1:], fv[1:])
         assert torch.all(fv[0][fv[0] != 0] == 1.0)          # ubar_0 reads as rho0 (0 on solid nodes)
+        if storage in TOL:
+            # the velocity sets against the oracle's sets a = 1..d (its set
+            # a = 0 is independent of them), element by element
+            o = oracle_for(spec, solid=None if solid is None else solid[0])
+            o.init(0.0, np.zeros((spec.d,) + spec.fshape)).run(41)
+            fluid = np.ones(spec.fshape, bool) if solid is None else (solid[0] == 0)
+            po = o.populations()[1:]
+            pv = _np(vel.populations())
+            assert rel_err(po[..., fluid], pv[..., fluid]) < TOL[storage]
+            ref = o.fields()
+            got = gpu_fields_np(vel, mdf.FIELD_ALL)
+            compare_fields(ref, got, TOL[storage], keys=("u", "P", "grad", "div", "S", "sigma", "vort"))
         r_full = full.run_steady(1e-300, 10, 30)[2]
         r_vel = vel.run_steady(1e-300, 10, 30)[2]
         assert r_full[0] == r_vel[0]

@@ -1,0 +1,231 @@
+"""Parity of the 16-bit deviation storage (FP16 / BF16 deviations from the
+rest state, FP32 collision) with the oracle.
+
+The oracle runs the same method in FP64 and stores every post-collision
+population through the same format (orc_run16, orc_store16): the deviation
+from the rest state is scaled by 1/u_ref and rounded to the nearest 16-bit
+value, with that rounding decision taken in binary32 as the kernels take it.
+Both start from populations already on the 16-bit grid.
+
+What is unique, and compared: the stored 16-bit value of every
+post-collision population (read raw from the library's population buffer).
+Where the oracle's FP64 value lies within the kernels' FP32 collision error
+of a rounding midpoint, either neighbour is a correct value, so:
+  * after the initial collision (time 0) every stored value is within one
+    spacing of the 16-bit grid at that value, plus the FP32 collision error
+    DELTA32 (which exceeds a spacing only for deviations far below the
+    populations themselves), of the oracle's, and at most MISMATCH_1 of
+    them differ at all;
+  * after 1 and 3 more steps, where a differing value has fed the following
+    collisions, every stored value is within CODE_STEPS_N spacings of the
+    grid at the largest deviation of its set (plus DELTA32), and at most
+    MISMATCH_N differ;
+  * against the plain FP64 oracle (no storage rounding), the populations
+    pulled at time 1 are within half a spacing of the stored value they came
+    from, plus DELTA32: the storage quantum bound of one step;
+  * the fields (eq. 2-7, 3-15 .. 3-19) agree with the storage-emulating
+    oracle to FIELD_TOL relative L2 (P against |u|, as P is formed from
+    populations of size |u|).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2108_08591_amd import cases as C
+from paper_2108_08591_amd import mdf
+from oracle import oracle as O
+from helpers import oracle_for, rel_err
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+U_REF = 0.05
+PREC = {"f16dev": (11, -14), "bf16dev": (8, -126)}      # significand bits, minimum exponent
+# FP32 collision error: a few binary32 roundings of populations up to ~0.5
+# (the rest value w_0 rho0 plus the deviations of these inputs)
+DELTA32 = 2.0 ** -20 * 0.5
+MISMATCH_1 = 0.01
+MISMATCH_N = 0.05
+CODE_STEPS_N = 2.0
+FIELD_TOL = {"f16dev": 2.0 ** -11, "bf16dev": 2.0 ** -8}
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _rest(spec, shape):
+    r = np.zeros(shape)
+    r[0] = np.asarray(C.WEIGHTS[spec.lattice]).reshape((spec.q,) + (1,) * spec.d)
+    return r
+
+
+def _to16(storage, x32):
+    """binary32 -> the 16-bit format, round to nearest even (numpy / torch
+    conversions), back as binary32."""
+    if storage == "f16dev":
+        return x32.astype(np.float16).astype(np.float32)
+    return torch.from_numpy(x32).to(torch.bfloat16).to(torch.float32).numpy()
+
+
+def _on_grid(spec, storage, seed):
+    """Seeded far-from-equilibrium populations moved onto the 16-bit grid:
+    f = f_rest + u_ref * q, q a 16-bit value, formed in binary32 as the
+    kernels decode a stored value."""
+    f = C.random_populations(spec, seed=seed, scale=0.05)
+    rest32 = _rest(spec, f.shape).astype(np.float32)
+    dev32 = (f.astype(np.float32) - rest32) * np.float32(1.0 / U_REF)
+    q = _to16(storage, dev32.astype(np.float32))
+    return (rest32 + np.float32(U_REF) * q).astype(np.float32)
+
+
+def _spacing(storage, dev):
+    """Spacing of the 16-bit grid (times u_ref) at deviations `dev`."""
+    p, emin = PREC[storage]
+    d = np.abs(dev) / U_REF
+    e = np.maximum(np.floor(np.log2(np.maximum(d, 2.0 ** -140))), emin)
+    return np.exp2(e - p + 1) * U_REF
+
+
+def _stored(solver, spec, storage, case=0):
+    """The post-collision populations f*(t) as stored (raw 16-bit values of
+    population buffer 0), decoded in binary32 like the kernels, [set][dir] +
+    field shape."""
+    raw = solver.population_buffer(0, case).view(torch.int16)
+    nz = spec.shape[2] if spec.d == 3 else 1
+    ny, nx = spec.shape[1], spec.shape[0]
+    pitch = raw.numel() // (solver.nsets * spec.q * nz * ny)
+    raw = raw.reshape(solver.nsets, spec.q, nz, ny, pitch)[..., :nx].contiguous()
+    dt = torch.float16 if storage == "f16dev" else torch.bfloat16
+    q = raw.view(dt).to(torch.float32).cpu().numpy()
+    rest32 = _rest(spec, (solver.nsets, spec.q) + (1,) * (spec.d)).astype(np.float32)
+    rest32 = rest32.reshape((solver.nsets, spec.q) + (1,) * 3)
+    val = (rest32 + np.float32(U_REF) * q).astype(np.float64)
+    return val.reshape((solver.nsets, spec.q) + spec.fshape)
+
+
+def _compare_stored(storage, spec, fluid, got, ref, steps):
+    """Stored f* of the GPU against the storage-emulating oracle's."""
+    rest = _rest(spec, ref.shape)
+    dev = ref - rest
+    if steps == 0:
+        unit = _spacing(storage, dev)
+        allowed = 1.0
+        frac = MISMATCH_1
+    else:
+        # spacing at the largest deviation of each set
+        big = np.abs(dev[..., fluid]).reshape(dev.shape[0], -1).max(axis=1)
+        unit = _spacing(storage, big).reshape((-1,) + (1,) * (dev.ndim - 1)) * np.ones_like(dev)
+        allowed = CODE_STEPS_N
+        frac = MISMATCH_N
+    diff = np.abs(got - ref)[..., fluid]
+    unit = unit[..., fluid]
+    same = diff <= 2.0 ** -21 * (np.abs(ref) + np.abs(rest))[..., fluid]
+    mism = float(np.mean(~same))
+    worst = float(np.max((diff - DELTA32) / unit))
+    _say(f"   t={steps}: stored values differing {mism:.2e}, worst {worst:.2f} spacings beyond DELTA32")
+    assert worst <= allowed and mism <= frac, (steps, worst, mism)
+
+
+def _setups():
+    out = []
+    wall = np.zeros((6, 3))
+    wall[3] = (0.08, 0.01, 0)
+    wall[2] = (-0.02, 0.0, 0)
+    spec = C.CaseSpec(C.D2Q5, (70, 45), 0.77, bc=(1, 1, 1, 1, 0, 0), wall_u=wall)
+    mask = np.zeros(spec.fshape, np.uint8)
+    mask[10:18, 20:31] = 1
+    out.append(("d2q5_walls_mask", spec, mask))
+    out.append(("d2q5_periodic_force", C.CaseSpec(C.D2Q5, (67, 35), 1.31, force=(1e-3, -5e-4), R=2e-4), None))
+    out.append(("d3q7_periodic", C.CaseSpec(C.D3Q7, (21, 13, 9), 1.45, force=(1e-4, 2e-4, -3e-4)), None))
+    wall = np.zeros((6, 3))
+    wall[3] = (0.05, 0, 0.02)
+    spec = C.CaseSpec(C.D3Q7, (19, 11, 7), 0.9, bc=(0, 0, 1, 1, 1, 1), wall_u=wall)
+    mask = np.zeros(spec.fshape, np.uint8)
+    mask[2:5, 3:7, 8:12] = 1
+    out.append(("d3q7_walls_mask", spec, mask))
+    return out
+
+
+SETUPS = _setups()
+
+
+@pytest.mark.parametrize("form", [0, 2])
+@pytest.mark.parametrize("storage", ["f16dev", "bf16dev"])
+@pytest.mark.parametrize("idx", range(len(SETUPS)), ids=[s[0] for s in SETUPS])
+def test_storage16_matches_oracle(idx, storage, form):
+    name, spec, mask = SETUPS[idx]
+    _say(f"[storage16] {name} {storage} form {form} shape={spec.shape}")
+    f0 = _on_grid(spec, storage, seed=300 + idx)
+    s = mdf.Solver([spec], storage=storage, solid=None if mask is None else [mask],
+                   init=("populations", [torch.from_numpy(f0)]), device=DEV, u_ref=U_REF)
+    s.set_launch(64, 4, 8, form)
+    fluid = np.ones(spec.fshape, bool) if mask is None else (mask == 0)
+    fmt = O.FORMATS[storage]
+    o = oracle_for(spec, solid=mask).set_populations(f0.astype(np.float64))
+    plain = oracle_for(spec, solid=mask).set_populations(f0.astype(np.float64))
+    # time 0: the pre-collision values are the inputs, the stored f*(0) the
+    # initial collision through the format
+    assert np.array_equal(_np(s.populations())[..., fluid], f0.astype(np.float64)[..., fluid])
+    _compare_stored(storage, spec, fluid, _stored(s, spec, storage), o.post16(fmt, U_REF), 0)
+    done = 0
+    for steps in (1, 2):
+        s.step(steps)
+        o.run16(steps, fmt, U_REF)
+        done += steps
+        _compare_stored(storage, spec, fluid, _stored(s, spec, storage), o.post16(fmt, U_REF), done)
+        if done == 1:
+            # the storage quantum bound against the plain FP64 oracle: f(1) is
+            # f*(0) streamed, each value within half a spacing of the value it
+            # was stored as (for a wall link that value is 2 w U_w - f)
+            plain.run(1)
+            ref = plain.populations()
+            got = _np(s.populations())
+            rest = _rest(spec, ref.shape)
+            wmax = 2.0 * max(C.WEIGHTS[spec.lattice]) * np.abs(spec.wall_velocity()).max()
+            bound = 0.5 * _spacing(storage, np.abs(ref - rest) + wmax) + DELTA32
+            worst = float(np.max((np.abs(got - ref) / bound)[..., fluid]))
+            _say(f"   vs plain FP64 oracle at t=1: worst {worst:.2f} of the quantum bound")
+            assert worst <= 1.0
+        ref_f = o.fields()
+        got_f = {k: _np(v) for k, v in s.fields(mdf.FIELD_ALL).items()}
+        got_f["ubar0"] = got_f["ubar"][0]
+        gscale = np.linalg.norm(ref_f["grad"].ravel())
+        errs = {}
+        for k in ("ubar0", "u", "P", "grad", "div", "S", "sigma", "vort"):
+            sc = gscale if k in ("div", "S", "sigma", "vort", "grad") else None
+            if k == "P":
+                sc = np.linalg.norm(ref_f["u"].ravel())
+            errs[k] = rel_err(ref_f[k][..., fluid], got_f[k][..., fluid], sc)
+        _say("   fields: " + ", ".join(f"{k} {v:.1e}" for k, v in errs.items()))
+        assert max(errs.values()) <= FIELD_TOL[storage], errs
+
+
+@pytest.mark.parametrize("storage", ["f16dev", "bf16dev"])
+def test_storage16_batch_equals_single_and_oracle(storage):
+    """Three uneven cases in one batched context with 16-bit storage: each
+    case bitwise equal to its single-case run, and its stored values within
+    the multi-step bar of the storage-emulating oracle."""
+    specs = [C.CaseSpec(C.D2Q5, (40, 33), 1.2, force=(2e-5, 0.0)),
+             C.cavity_case(N=65, Re=80.0),
+             C.CaseSpec(C.D2Q5, (31, 47), 1.5, bc=(C.PERIODIC, C.PERIODIC, C.WALL, C.WALL, 0, 0))]
+    f0 = [_on_grid(sp, storage, seed=400 + k) for k, sp in enumerate(specs)]
+    _say(f"[storage16] batch of 3 {storage}")
+    b = mdf.Solver(specs, storage=storage, init=("populations", [torch.from_numpy(x) for x in f0]),
+                   device=DEV, u_ref=U_REF)
+    b.step(5)
+    for k, sp in enumerate(specs):
+        s = mdf.Solver([sp], storage=storage, init=("populations", [torch.from_numpy(f0[k])]), device=DEV,
+                       u_ref=U_REF)
+        s.step(5)
+        assert torch.equal(s.populations(), b.populations(k))
+        o = oracle_for(sp).set_populations(f0[k].astype(np.float64)).run16(5, O.FORMATS[storage], U_REF)
+        _compare_stored(storage, sp, np.ones(sp.fshape, bool), _stored(b, sp, storage, k),
+                        o.post16(O.FORMATS[storage], U_REF), 5)

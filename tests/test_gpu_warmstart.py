@@ -6,8 +6,15 @@
    feeds, checked without the network.
 2. A network trained on the GPU by the project's kernels, on steady fields
    the solver generated, warm-starts held-out cases in fewer total steps than
-   the cold start from rest, and every warm solve reaches the cold solve's
-   steady state (relative L2 of u within the stopping rule's own band).
+   the cold start from rest, and every warm solve (with the cold start as its
+   fallback) reaches the cold solve's steady state: velocity within 1e-4
+   relative L2.
+
+The residual rule stops a solve at r < tol, which leaves it about tau * tol
+from the fixed point (tau: the slowest decay time, up to ~1e4 steps on these
+cavities), so two solves stopped at 1e-8 may differ by ~1e-4 without either
+being wrong.  The held-out solves here therefore run to 1e-9: both then lie
+within ~1e-5 of the fixed point, well inside the 1e-4 comparison.
 """
 import sys
 
@@ -20,6 +27,7 @@ from paper_2108_08591_amd import warmstart as WS
 
 pytestmark = pytest.mark.gpu
 N = 64
+TOL = 1e-9        # residual of the held-out solves (see the module notes)
 
 
 def _say(msg):
@@ -34,7 +42,7 @@ def _fluid_frac_ok(cases):
 @pytest.fixture(scope="module")
 def held_out():
     cases = _fluid_frac_ok(WS.warmstart_cases(12, N=N, seed=4242))[:6]
-    cold, st, steps, _, _ = WS.solve(cases, "f64", tol=1e-8, max_steps=200000)
+    cold, st, steps, _, _ = WS.solve(cases, "f64", tol=TOL, max_steps=400000)
     assert (st == 0).all(), st
     return cases, cold, steps
 
@@ -43,7 +51,7 @@ def test_exact_fields_restart_converges_fast_to_same_state(held_out):
     cases, cold, csteps = held_out
     _say(f"exact restart: {len(cases)} cases at {N}^2, cold steps {csteps.tolist()}")
     init = [WS.solution_init(cold, k) for k in range(len(cases))]
-    warm, st, steps, _, _ = WS.solve(cases, "f64", tol=1e-8, max_steps=200000, init=init)
+    warm, st, steps, _, _ = WS.solve(cases, "f64", tol=TOL, max_steps=400000, init=init)
     _say(f"exact restart steps {steps.tolist()}")
     assert (st == 0).all()
     assert csteps.sum() >= 3 * steps.sum()
@@ -70,11 +78,10 @@ def test_trained_network_beats_cold_start(held_out):
     _say(f"loss {hist[0]:.4f} -> {hist[-1]:.4f}")
     assert hist[-1] < 0.5 * hist[0]
     init = WS.predict(model, cases, with_grad=True)
-    warm, wst, wsteps, _, _ = WS.solve(cases, "f64", tol=1e-8, max_steps=200000, init=init)
-    _say(f"cold steps {csteps.tolist()} warm steps {wsteps.tolist()}")
+    where, wst, wsteps, _, _, fallback = WS.solve_warm(cases, init, "f64", tol=TOL, max_steps=400000)
+    _say(f"cold steps {csteps.tolist()} warm steps {wsteps.tolist()} (cold fallbacks: {fallback})")
     assert (wst == 0).all()
     assert wsteps.sum() < csteps.sum()
-    for k in range(len(cases)):
-        # both solves stop at r < 1e-8; each may sit ~tau * 1e-8 (tau: the
-        # slowest decay time, up to ~1e4 steps here) from the fixed point
-        assert WS.field_error(cold, warm, k) < 1e-3
+    errs = [WS.field_error(cold, where[k][0], k, where[k][1]) for k in range(len(cases))]
+    _say(f"warm vs cold velocity, relative L2: {[f'{e:.1e}' for e in errs]}")
+    assert max(errs) < 1e-4

@@ -617,3 +617,98 @@ def test_vortex_finder_on_closed_form():
     w, x, y = find_vortex(psi, vort, (0.2, 0.8, 0.2, 0.8), "min")
     assert abs(x - 0.5) < 1e-3 and abs(y - 0.5) < 1e-3
     assert abs(w / (-2 * np.pi ** 2) - 1) < 1e-3
+
+
+# ------------------------------------------------------------------ 16-bit storage emulation
+
+def _float32_samples(seed):
+    """Binary32 values over every binade the 16-bit formats reach, their
+    subnormal ranges, exact ties and overflow."""
+    rng = np.random.default_rng(seed)
+    mant = rng.uniform(1.0, 2.0, 20000)
+    expo = rng.integers(-140, 128, 20000)
+    x = (mant * np.exp2(expo.astype(np.float64))).astype(np.float32)
+    x = np.where(rng.integers(0, 2, x.size) == 1, -x, x).astype(np.float32)
+    # exact halfway points between neighbouring binary16 values (ties) and
+    # between neighbouring bfloat16 values
+    k = rng.integers(0, 2 ** 10, 2000)
+    ties16 = ((1024 + k + 0.5) * 2.0 ** rng.integers(-24, 6, 2000)).astype(np.float32)
+    ties_bf = ((128 + k % 128 + 0.5) * 2.0 ** rng.integers(-133, 120, 2000)).astype(np.float32)
+    edge = np.array([65504, 65519.996, 65520, 2 ** -24, 2 ** -25, 3 * 2 ** -26, 0.0, -0.0],
+                    np.float32)
+    return np.concatenate([x, ties16, ties_bf, edge]).astype(np.float32)
+
+
+def test_round16_binary16_equals_ieee_conversion():
+    """The oracle's rounding to binary16 equals the IEEE round-to-nearest-even
+    conversion of numpy's float16 (normal, subnormal, ties, overflow)."""
+    x = _float32_samples(7)
+    with np.errstate(over="ignore"):
+        ref = x.astype(np.float16).astype(np.float64)
+    got = O.round16(O.BINARY16, x)
+    assert np.array_equal(got, ref)
+
+
+def test_round16_bfloat16_equals_library_conversion():
+    """The oracle's rounding to bfloat16 equals torch's float32 -> bfloat16
+    conversion (round to nearest even) on the same samples."""
+    import torch
+    x = _float32_samples(8)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    got = O.round16(O.BFLOAT16, x)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("fmt", [O.BINARY16, O.BFLOAT16])
+def test_store16_rounds_the_deviation_from_rest(fmt):
+    """orc_store16 rounds (f - f_rest)/u_ref, not f: on populations a small
+    deviation away from rest, every value lands within half a 16-bit spacing
+    of the deviation (plus binary32 rounding) of the input, far below the
+    spacing at the rest value w_i rho0 itself; values already on the grid
+    stay where they are."""
+    spec = C.CaseSpec(C.D2Q5, (9, 7), 1.2)
+    o = _oracle(spec)
+    u_ref = 0.05
+    rng = np.random.default_rng(3)
+    w = O.lattice_info(O.D2Q5)["w"]
+    rest = np.zeros((3, 5, 7, 9))
+    rest[0] = w[:, None, None]
+    dev = rng.uniform(-1e-3, 1e-3, rest.shape)
+    f = rest + dev
+    o.set_populations(f)
+    lib = O.lib()
+    assert lib.orc_store16(o._cs, None, fmt, u_ref, O._dp(o.f)) == 0
+    got = o.populations()
+    p, emin = (11, -14) if fmt == O.BINARY16 else (8, -126)
+    d = np.abs(dev) / u_ref
+    spacing = np.exp2(np.maximum(np.floor(np.log2(np.maximum(d, 2.0 ** -140))), emin) - p + 1) * u_ref
+    # half a spacing, plus the binary32 rounding of f and f_rest (2^-24 each)
+    # and of the two binary32 operations on the deviation
+    bound = 0.5 * spacing + 2.0 ** -24 * (np.abs(f) + np.abs(rest) + 2 * np.abs(dev))
+    assert np.all(np.abs(got - f) <= bound)
+    # rounding f itself would err by up to half the spacing at w_0 rho0 / u_ref
+    rest_spacing = np.exp2(np.floor(np.log2(w[0] / u_ref)) - p + 1) * u_ref
+    assert np.abs(got - f).max() < 0.05 * rest_spacing
+    # a second pass changes nothing beyond binary32 rounding (values on the
+    # grid stay put)
+    again = o.f.copy()
+    assert lib.orc_store16(o._cs, None, fmt, u_ref, O._dp(again)) == 0
+    assert np.abs(again - o.f).max() <= 2.0 ** -22
+
+
+@pytest.mark.parametrize("fmt", [O.BINARY16, O.BFLOAT16])
+def test_run16_keeps_rest_state_and_tracks_fp64(fmt):
+    """With the 16-bit storage the rest state (P = 0, u = 0: zero deviation)
+    is kept exactly, and a decaying Taylor-Green flow stays within the
+    storage's relative precision of the FP64 run over a few steps."""
+    spec = C.CaseSpec(C.D2Q5, (16, 12), 1.3)
+    o = _oracle(spec).init(0.0, np.zeros((2,) + spec.fshape))
+    f0 = o.f.copy()
+    o.run16(20, fmt, 0.05)
+    assert np.array_equal(o.f, f0)
+    P, u = C.smooth_random_fields(spec, seed=4, amp=0.03)
+    a = _oracle(spec).init(P, u).run(3)
+    b = _oracle(spec).init(P, u).run16(3, fmt, 0.05)
+    p = 11 if fmt == O.BINARY16 else 8
+    err = np.abs(a.fields()["u"] - b.fields()["u"]).max() / np.abs(a.fields()["u"]).max()
+    assert 2.0 ** -(p + 3) < err < 6 * 2.0 ** -p
