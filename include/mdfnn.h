@@ -35,6 +35,7 @@ extern "C" {
 
 #define MDFNN_OK 0
 #define MDFNN_EINVAL (-1)
+#define MDFNN_ETOOBIG (-2)
 #define MDFNN_EDEVICE (-3)
 
 /* y = act(conv3x3(concat(x1, x2)) + bias).  x1: [B,H,W,c1], x2: [B,H,W,c2]
@@ -99,6 +100,22 @@ int mdfnn_head_bwd(const uint16_t *x, const float *dy, int P, int cin, const flo
 size_t mdfnn_loss_scratch_bytes(int P);
 int mdfnn_mse(const float *y, const float *t, const float *wt, int P, int C, float *dy, float *loss,
               void *scratch, void *stream);
+
+/* mdfnn_mse without a scratch argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  The same kernels and the same results as
+ * mdfnn_mse; the partial sums live in a static device array of
+ * 2 * ceil(MDFNN_MSE_NOALLOC_MAX_P / 256) + 2 floats (256 KiB) that each
+ * GPU the library runs on holds until the process ends.  The call allocates
+ * nothing: on its first use on a device it only looks up that array's
+ * address (hipGetSymbolAddress) with the device current.  Every call on one
+ * GPU shares the array: calls that overlap on one GPU (on different
+ * streams, or from several threads) race; calls on one stream are ordered.
+ * Returns MDFNN_ETOOBIG (nothing launched) when P > MDFNN_MSE_NOALLOC_MAX_P,
+ * MDFNN_EINVAL on null pointers or sizes < 1, MDFNN_EDEVICE on a HIP error. */
+#define MDFNN_MSE_NOALLOC_MAX_P (1 << 23)
+int mdfnn_mse_noalloc(const float *y, const float *t, const float *wt, int P, int C, float *dy,
+                      float *loss, void *stream);
 
 /* Adam update with FP32 master weights (Kingma & Ba): for n parameters,
  *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;

@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "mdfnn.h"
 
 namespace mdfnn {
@@ -709,6 +711,69 @@ int mdfnn_mse(const float *y, const float *t, const float *wt, int P, int C, flo
     const int nblk = (P + 255) / 256;
     float *part = static_cast<float *>(scratch);
     float *totals = part + 2 * nblk;
+    hipLaunchKernelGGL(k_mse_partial, dim3(nblk), dim3(256), 0, st, y, t, wt, P, C, part);
+    hipLaunchKernelGGL(k_mse_total, dim3(1), dim3(256), 0, st, part, nblk, C, totals, loss);
+    hipLaunchKernelGGL(k_mse_grad, dim3(nblk), dim3(256), 0, st, y, t, wt, P, C, totals, dy);
+    return status(hipGetLastError());
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ allocation-free loss
+
+namespace mdfnn {
+namespace {
+
+// Device scratch of mdfnn_mse_noalloc: the per-block partial sums and the two
+// totals of the loss, for at most kMseStaticMaxP pixels.  Each GPU holds its
+// own copy for the life of the process.  In host code `scratch` names a
+// host-side stand-in; kernels get the device address that
+// hipGetSymbolAddress returns for the current device.
+constexpr int kMseStaticMaxP = MDFNN_MSE_NOALLOC_MAX_P;
+constexpr int kMseStaticFloats = 2 * ((kMseStaticMaxP + 255) / 256) + 2;
+__device__ __align__(256) float scratch[kMseStaticFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_lock;
+float *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's `scratch`, looked up once per device with
+// that device current.
+hipError_t mse_scratch(float **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_lock);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<float *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+}  // namespace mdfnn
+
+extern "C" {
+
+int mdfnn_mse_noalloc(const float *y, const float *t, const float *wt, int P, int C, float *dy, float *loss,
+                      void *stream)
+{
+    if (!y || !t || !wt || !dy || P < 1 || C < 1) return MDFNN_EINVAL;
+    if (P > kMseStaticMaxP) return MDFNN_ETOOBIG;
+    float *part = nullptr;
+    hipError_t e = mse_scratch(&part);
+    if (e != hipSuccess) return MDFNN_EDEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int nblk = (P + 255) / 256;
+    float *totals = part + 2 * nblk;
+    // every partial and both totals are written before they are read: nothing
+    // left by an earlier call is used
     hipLaunchKernelGGL(k_mse_partial, dim3(nblk), dim3(256), 0, st, y, t, wt, P, C, part);
     hipLaunchKernelGGL(k_mse_total, dim3(1), dim3(256), 0, st, part, nblk, C, totals, loss);
     hipLaunchKernelGGL(k_mse_grad, dim3(nblk), dim3(256), 0, st, y, t, wt, P, C, totals, dy);

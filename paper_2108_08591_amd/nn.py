@@ -54,13 +54,14 @@ def _lib():
         L.mdfnn_loss_scratch_bytes.argtypes = [i32]
         L.mdfnn_loss_scratch_bytes.restype = sz
         L.mdfnn_mse.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, vp]
+        L.mdfnn_mse_noalloc.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp]
         L.mdfnn_adam.argtypes = [vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp, vp]
         L.mdfnn_to_bf16.argtypes = [vp, i64, vp, vp]
         L.mdfnn_to_f32.argtypes = [vp, i64, vp, vp]
         for n in ("mdfnn_conv3x3_fwd", "mdfnn_conv3x3_flip", "mdfnn_conv3x3_wgrad", "mdfnn_avgpool2_fwd",
                   "mdfnn_avgpool2_bwd", "mdfnn_upsample2_fwd", "mdfnn_upsample2_bwd", "mdfnn_add",
-                  "mdfnn_head_fwd", "mdfnn_head_bwd", "mdfnn_mse", "mdfnn_adam", "mdfnn_to_bf16",
-                  "mdfnn_to_f32"):
+                  "mdfnn_head_fwd", "mdfnn_head_bwd", "mdfnn_mse", "mdfnn_mse_noalloc", "mdfnn_adam",
+                  "mdfnn_to_bf16", "mdfnn_to_f32"):
             getattr(L, n).restype = ctypes.c_int
         _DECLARED = True
     return L
@@ -69,7 +70,7 @@ def _lib():
 NN_EXPORTED = ["mdfnn_conv3x3_fwd", "mdfnn_conv3x3_flip", "mdfnn_wgrad_scratch_bytes", "mdfnn_conv3x3_wgrad",
                "mdfnn_avgpool2_fwd", "mdfnn_avgpool2_bwd", "mdfnn_upsample2_fwd", "mdfnn_upsample2_bwd",
                "mdfnn_add", "mdfnn_head_fwd", "mdfnn_head_scratch_bytes", "mdfnn_head_bwd",
-               "mdfnn_loss_scratch_bytes", "mdfnn_mse", "mdfnn_adam", "mdfnn_to_bf16",
+               "mdfnn_loss_scratch_bytes", "mdfnn_mse", "mdfnn_mse_noalloc", "mdfnn_adam", "mdfnn_to_bf16",
                "mdfnn_to_f32"]
 
 
@@ -172,6 +173,17 @@ def head_scratch_bytes(P, cin, cout):
 def mse(y, t, wt, dy, loss, scratch, stream=None):
     P, C = y.shape[0], y.shape[1]
     _ok(_lib().mdfnn_mse(_p(y), _p(t), _p(wt), P, C, _p(dy), _p(loss), _p(scratch), _st(stream)), "mse")
+
+
+def mse_noalloc(y, t, wt, dy, loss, stream=None):
+    """mse() without a scratch buffer (mdfnn_mse_noalloc): the partial sums
+    live in the library's static device array; at most MSE_NOALLOC_MAX_P
+    pixels."""
+    P, C = y.shape[0], y.shape[1]
+    _ok(_lib().mdfnn_mse_noalloc(_p(y), _p(t), _p(wt), P, C, _p(dy), _p(loss), _st(stream)), "mse_noalloc")
+
+
+MSE_NOALLOC_MAX_P = 1 << 23
 
 
 def loss_scratch_bytes(P):

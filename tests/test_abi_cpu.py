@@ -40,10 +40,22 @@ def test_library_exports_every_declared_network_symbol():
     from paper_2108_08591_amd import nn
     L = nn._lib()
     declared = _declared_nn_functions()
-    assert "mdfnn_conv3x3_fwd" in declared
+    assert "mdfnn_conv3x3_fwd" in declared and "mdfnn_mse_noalloc" in declared
     for name in declared:
         assert hasattr(L, name), name
     assert sorted(nn.NN_EXPORTED) == declared
+
+
+def test_noalloc_loss_refuses_sizes_beyond_its_scratch():
+    """mdfnn_mse_noalloc checks P against its static scratch before touching
+    the device: MDFNN_ETOOBIG (-2) above the maximum, MDFNN_EINVAL (-1) for
+    null pointers; nothing is launched (the pointers are never read)."""
+    from paper_2108_08591_amd import nn
+    L = nn._lib()
+    fake = ctypes.c_void_p(256)
+    assert L.mdfnn_mse_noalloc(fake, fake, fake, nn.MSE_NOALLOC_MAX_P + 1, 7, fake, fake, None) == -2
+    assert L.mdfnn_mse_noalloc(None, fake, fake, 16, 7, fake, fake, None) == -1
+    assert L.mdfnn_mse_noalloc(fake, fake, fake, 0, 7, fake, fake, None) == -1
 
 
 def _ws(spec, storage=mdf.F32, solid=0):
