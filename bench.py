@@ -334,8 +334,6 @@ def sweep(out_path):
             alg = nodes * 2 * q * ns * sb[st]
             n = max(5, min(400, int(2e10 / alg)))
             for bx, by, g, form in shapes:
-                if form == 2 and lat != "d2q5":
-                    continue
                 solver.set_launch(bx, by, g, form)
                 solver.step(2)
                 ms = time_launches(solver, stream, n)
@@ -347,6 +345,36 @@ def sweep(out_path):
                 print(json.dumps(rec), flush=True)
             del solver
             torch.cuda.empty_cache()
+
+
+def tgv3d_timing(storage, form, N=256, groups=8):
+    """The 3D Taylor-Green vortex of the precision configuration (D3Q7, four
+    sets, Re 100, u0 = 0.05) at N^3: time per step of the step kernel in one
+    storage and form, HIP events, median of 5, and its per-step fraction of
+    the HBM roofline (2 x 28 values per node and step)."""
+    import numpy as np
+    import torch
+    from paper_2108_08591_amd import cases as C
+    from paper_2108_08591_amd import mdf
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    spec = C.tgv3d_case(N=N, u0=0.05, Re=100.0)
+    P, u = C.taylor_green_3d_initial(N, 0.05)
+    dt = np.float64 if storage == "f64" else np.float32
+    init = torch.tensor(np.concatenate([P[None], u]).astype(dt))
+    del P, u
+    solver = mdf.Solver([spec], storage=storage, init=("fields", [init]), device=dev, stream=stream, u_ref=0.05)
+    del init
+    solver.set_launch(64, 4, groups, form)
+    solver.step(3)
+    n = 41 if form == 2 else 40
+    ms = time_launches(solver, stream, n, reps=5)
+    sb = {"f64": 8, "f32": 4, "f16dev": 2, "bf16dev": 2}[storage]
+    mlups = spec.nodes / ms / 1e3
+    print(json.dumps({"workload": f"3D Taylor-Green {N}^3, D3Q7 x 4 sets", "storage": storage, "form": form,
+                      "groups": groups,
+                      "ms_per_step": round(ms, 5), "MLUPS": round(mlups, 1),
+                      "per_step_frac": round(mlups * 1e6 * 2 * 28 * sb / (HBM_PEAK_GBS * 1e9), 4)}), flush=True)
 
 
 def _rel(ref, got, scale=None):
@@ -973,8 +1001,12 @@ def main():
                     metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB", "OUT_MD"),
                     help="calibrated HBM traffic of the step kernel from rocprofv3 counter databases")
     ap.add_argument("--command", default="", help="command recorded in a summary")
-    ap.add_argument("--traffic-kernel", default="step", choices=["step", "step2"],
-                    help="kernel whose counters --summarize-traffic reads (one-step or two-step)")
+    ap.add_argument("--traffic-kernel", default="batch2", choices=["batch2", "step2z", "step2"],
+                    help="kernel whose counters --summarize-traffic reads: the headline's batched two-step "
+                         "kernel, the 3D two-step kernel, or the 1024^2 cavity's two-step kernel")
+    ap.add_argument("--tgv3d", nargs="+", metavar="STORAGE FORM [GROUPS]",
+                    help="time the 3D Taylor-Green step kernel (256^3) in one storage and form (XCD groups, "
+                         "default 8)")
     ap.add_argument("--precision-study", metavar="OUT_JSON", help="FP16/BF16/FP32 vs FP64 storage, 3D TGV")
     ap.add_argument("--batch-study", metavar="OUT_JSON", help="512-case uneven batch to steady state")
     ap.add_argument("--batch-max-steps", type=int, default=400000)
@@ -1020,20 +1052,34 @@ def main():
         warmstart_study(args.warmstart_study, n_train=args.ws_train, N=args.ws_n, epochs=args.ws_epochs,
                         lr=args.ws_lr, clip=args.ws_clip or None, batch=args.ws_batch)
         return
+    if args.tgv3d:
+        tgv3d_timing(args.tgv3d[0], int(args.tgv3d[1]), groups=int(args.tgv3d[2]) if len(args.tgv3d) > 2 else 8)
+        return
     if args.summarize_trace:
         with open(args.summarize_trace[1], "w") as fh:
             fh.write(summarize_trace(args.summarize_trace[0], args.command))
         return
     if args.summarize_traffic:
         fdb, wdb, cfdb, cwdb, out_md = args.summarize_traffic
-        nodes = 1024 * 1024
-        if args.traffic_kernel == "step2":
-            md, ent = summarize_traffic(fdb, wdb, cfdb, cwdb, "k_step2<LatD2Q5, 1, true, false, false, true>",
-                                        nodes * (2 * 15 * 4 + 2 * 4 * 4), "k_step2<D2Q5,F32,emit>_cavity1024",
+        if args.traffic_kernel == "batch2":
+            # the headline's dominant kernel: two-step batched launches of the
+            # 512-case FP64 batch (no emission, no masks, non-temporal stores,
+            # 32-bit node offsets); per-step algorithmic bytes of both steps
+            from paper_2108_08591_amd import cases as C
+            nodes = sum(b.spec.nodes for b in C.batch_cases(n=512))
+            md, ent = summarize_traffic(fdb, wdb, cfdb, cwdb, "k_step2_batch<LatD2Q5, 0, false, false, true, false>",
+                                        nodes * 2 * (2 * 15 * 8), "k_step2_batch<D2Q5,F64>_c4_512",
+                                        args.command.split(" ;; "))
+        elif args.traffic_kernel == "step2z":
+            # the 3D Taylor-Green kernel at 256^3, two steps per launch, FP32
+            nodes = 256 ** 3
+            md, ent = summarize_traffic(fdb, wdb, cfdb, cwdb, "k_step2z<LatD3Q7, 1, false, false, true, false>",
+                                        nodes * 2 * (2 * 28 * 4), "k_step2z<D3Q7,F32>_tgv256",
                                         args.command.split(" ;; "))
         else:
-            md, ent = summarize_traffic(fdb, wdb, cfdb, cwdb, "k_step<LatD2Q5, 1, true, false, false, 1, false, true>",
-                                        nodes * (2 * 15 * 4 + 4 * 4), "k_step<D2Q5,F32,emit>_cavity1024",
+            nodes = 1024 * 1024
+            md, ent = summarize_traffic(fdb, wdb, cfdb, cwdb, "k_step2<LatD2Q5, 1, true, false, false, true>",
+                                        nodes * (2 * 15 * 4 + 2 * 4 * 4), "k_step2<D2Q5,F32,emit>_cavity1024",
                                         args.command.split(" ;; "))
         with open(out_md, "w") as fh:
             fh.write(md)

@@ -10,11 +10,12 @@
    fallback) reaches the cold solve's steady state: velocity within 1e-4
    relative L2.
 
-The residual rule stops a solve at r < tol, which leaves it about tau * tol
-from the fixed point (tau: the slowest decay time, up to ~1e4 steps on these
-cavities), so two solves stopped at 1e-8 may differ by ~1e-4 without either
-being wrong.  The held-out solves here therefore run to 1e-9: both then lie
-within ~1e-5 of the fixed point, well inside the 1e-4 comparison.
+Step counts are those to the residual rule r < 1e-8.  That rule leaves a
+solve about tau * 1e-8 from the fixed point (tau: the slowest decay time, up
+to ~1e4 steps on these cavities), so two solves stopped there may differ by
+~1e-4 without either being wrong.  For the field comparison both solves are
+therefore continued to r < 1e-9 (within ~1e-5 of the fixed point), well
+inside the 1e-4 bar.
 """
 import sys
 
@@ -27,7 +28,8 @@ from paper_2108_08591_amd import warmstart as WS
 
 pytestmark = pytest.mark.gpu
 N = 64
-TOL = 1e-9        # residual of the held-out solves (see the module notes)
+TOL = 1e-8        # the stopping rule whose step counts are compared
+TIGHT = 1e-9      # the residual both solves are continued to before fields are compared
 
 
 def _say(msg):
@@ -39,11 +41,19 @@ def _fluid_frac_ok(cases):
     return [c for c in cases if c["Re"] < 400]
 
 
+def _tighten(solver, n):
+    """Continue every case of a solved context to r < TIGHT."""
+    solver.set_active(np.ones(n, bool))
+    st, _, _ = solver.run_steady(TIGHT, 100, 400000)
+    assert (st == 0).all(), st
+
+
 @pytest.fixture(scope="module")
 def held_out():
     cases = _fluid_frac_ok(WS.warmstart_cases(12, N=N, seed=4242))[:6]
     cold, st, steps, _, _ = WS.solve(cases, "f64", tol=TOL, max_steps=400000)
     assert (st == 0).all(), st
+    _tighten(cold, len(cases))
     return cases, cold, steps
 
 
@@ -55,6 +65,7 @@ def test_exact_fields_restart_converges_fast_to_same_state(held_out):
     _say(f"exact restart steps {steps.tolist()}")
     assert (st == 0).all()
     assert csteps.sum() >= 3 * steps.sum()
+    _tighten(warm, len(cases))
     for k in range(len(cases)):
         assert WS.field_error(cold, warm, k) < 1e-4
 
@@ -82,6 +93,8 @@ def test_trained_network_beats_cold_start(held_out):
     _say(f"cold steps {csteps.tolist()} warm steps {wsteps.tolist()} (cold fallbacks: {fallback})")
     assert (wst == 0).all()
     assert wsteps.sum() < csteps.sum()
+    for sv in {id(w[0]): w[0] for w in where}.values():
+        _tighten(sv, len(sv.specs))
     errs = [WS.field_error(cold, where[k][0], k, where[k][1]) for k in range(len(cases))]
     _say(f"warm vs cold velocity, relative L2: {[f'{e:.1e}' for e in errs]}")
     assert max(errs) < 1e-4
