@@ -299,6 +299,52 @@ def variants_study(out_path):
                 torch.cuda.empty_cache()
 
 
+def lattice_per_set_study(out_path):
+    """A lattice per set against the plain diagonal lattice on the same grid:
+    D2Q9 at 8192^2 and D3Q15 at 256^3, all d + 1 sets on the large lattice,
+    the set a = 0 on D2Q5 / D3Q7 (23 and 52 planes per buffer instead of 27
+    and 60), and the velocity sets only; one node per thread, no emission.
+    Algorithmic bytes per step: one read and one write of every stored
+    population."""
+    import torch
+    from paper_2108_08591_amd import cases as C
+    from paper_2108_08591_amd import mdf
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    sb = {"f64": 8, "f32": 4, "f16dev": 2, "bf16dev": 2}
+    runs = [(2, 8192, "f32"), (2, 8192, "f64"), (3, 256, "f32"), (3, 256, "f64")]
+    with open(out_path, "w") as fh:
+        for d, N, st in runs:
+            big, mixed = (C.D2Q9, C.D2Q9_Q5) if d == 2 else (C.D3Q15, C.D3Q15_Q7)
+            base = None
+            for lid, sets, label in ((big, "all", "large lattice, d+1 sets"),
+                                     (mixed, "all", "lattice per set"),
+                                     (big, "velocity", "large lattice, velocity sets")):
+                if d == 2:
+                    spec = C.cavity_case(N=N, Re=1000.0, lattice=lid)
+                else:
+                    spec = C.tgv3d_case(N=N, u0=0.05, Re=100.0, lattice=lid)
+                solver = mdf.Solver([spec], storage=st, device=dev, stream=stream, sets=sets)
+                solver.step(3)
+                ms = time_launches(solver, stream, 41)
+                q = spec.q
+                planes = (2 * d + 1 + d * q) if lid == mixed else solver.nsets * q
+                step_bytes = spec.nodes * 2 * planes * sb[st]
+                rec = {"lattice": label, "lattice_id": lid, "d": d, "N": N, "storage": st, "planes": planes,
+                       "ms_per_step": round(ms, 5), "MLUPS": round(spec.nodes / ms / 1e3, 1),
+                       "step_bytes_MB": round(step_bytes / 1e6, 1),
+                       "GBps_per_step": round(step_bytes / ms / 1e6, 1),
+                       "roofline_frac": round(step_bytes / ms / 1e6 / HBM_PEAK_GBS, 4)}
+                if base is None:
+                    base = ms
+                else:
+                    rec["speedup_vs_large_lattice"] = round(base / ms, 3)
+                print(json.dumps(rec), file=fh, flush=True)
+                print(json.dumps(rec), flush=True)
+                del solver
+                torch.cuda.empty_cache()
+
+
 def sweep(out_path):
     """Step-kernel timing over grid sizes (incl. working sets far beyond the
     256 MB Infinity Cache), storages, lattices and launch shapes."""
@@ -1007,6 +1053,8 @@ def main():
     ap.add_argument("--tgv3d", nargs="+", metavar="STORAGE FORM [GROUPS]",
                     help="time the 3D Taylor-Green step kernel (256^3) in one storage and form (XCD groups, "
                          "default 8)")
+    ap.add_argument("--lattice-per-set-study", metavar="OUT_JSONL",
+                    help="a lattice per set against the plain D2Q9 / D3Q15 (one node per thread)")
     ap.add_argument("--precision-study", metavar="OUT_JSON", help="FP16/BF16/FP32 vs FP64 storage, 3D TGV")
     ap.add_argument("--batch-study", metavar="OUT_JSON", help="512-case uneven batch to steady state")
     ap.add_argument("--batch-max-steps", type=int, default=400000)
@@ -1051,6 +1099,9 @@ def main():
     if args.warmstart_study:
         warmstart_study(args.warmstart_study, n_train=args.ws_train, N=args.ws_n, epochs=args.ws_epochs,
                         lr=args.ws_lr, clip=args.ws_clip or None, batch=args.ws_batch)
+        return
+    if args.lattice_per_set_study:
+        lattice_per_set_study(args.lattice_per_set_study)
         return
     if args.tgv3d:
         tgv3d_timing(args.tgv3d[0], int(args.tgv3d[1]), groups=int(args.tgv3d[2]) if len(args.tgv3d) > 2 else 8)

@@ -77,11 +77,23 @@ typedef enum {
  * odd under c -> -c with s1 and every even one with s2 (the structure of
  * eq. 4-3 carried to the larger moment sets).  A diagonal link whose
  * upstream point lies behind two or three wall faces takes the first of them
- * in the order x, y, z.  They run one node per thread (form 0) only. */
+ * in the order x, y, z.  They run one node per thread (form 0) only.
+ * MDF_D2Q9_Q5 and MDF_D3Q15_Q7 take a lattice per set (allowed by the
+ * remark after eq. d3q15): the velocity sets a = 1..d on D2Q9 / D3Q15 as
+ * above, the set a = 0, which only advects rho0, on D2Q5 / D3Q7 with that
+ * lattice's weights and cs^2.  The D2Q5 / D3Q7 velocities are the first five
+ * / seven columns of the larger lattice, so a set-0 population keeps its
+ * direction index.  One buffer holds 5 + 2 x 9 = 23 (2D) or 7 + 3 x 15 = 52
+ * (3D) population planes, set 0's first.  Populations (mdf_populations,
+ * MDF_INIT_POPULATIONS) keep the [set][dir] layout of the full lattice, the
+ * set a = 0 padded with zeros at directions 2d+1 .. q-1 (read back as zero,
+ * ignored on input).  Velocity sets, P and every derived field follow the
+ * D2Q9 / D3Q15 lattice.  Form 0 only. */
 typedef enum {
     MDF_D2Q5 = 0, MDF_D3Q7 = 1, MDF_D2Q5_V = 2, MDF_D3Q7_V = 3,
     MDF_D2Q4 = 4, MDF_D3Q6 = 5, MDF_D2Q4_V = 6, MDF_D3Q6_V = 7,
-    MDF_D2Q9 = 8, MDF_D3Q15 = 9, MDF_D2Q9_V = 10, MDF_D3Q15_V = 11
+    MDF_D2Q9 = 8, MDF_D3Q15 = 9, MDF_D2Q9_V = 10, MDF_D3Q15_V = 11,
+    MDF_D2Q9_Q5 = 12, MDF_D3Q15_Q7 = 13
 } mdf_lattice;
 
 /* Storage of the populations.  MDF_F16DEV / MDF_BF16DEV keep
@@ -253,14 +265,16 @@ mdf_status mdf_invariants(const mdf_ctx *ctx, int32_t case_id, double *out, void
  *   2  two steps per launch (the lattices with axis links only: D2Q5, D2Q4,
  *      D3Q7, D3Q6 and their *_V forms).  2D: tiles of 64 x 4/8 nodes
  *      (FP64/other storages) take one step on the tile and a one-node halo
- *      into LDS and the second from LDS.  3D: tiles of 32 x 4/8 nodes walk a
+ *      into LDS and the second from LDS.  3D: tiles of 32 x 4 (FP64), 32 x 8
+ *      (FP32) or 64 x 4 (16-bit) nodes walk a
  *      chunk of z-planes, keeping the intermediate state of three planes in
  *      LDS.  Either way the state crosses HBM once per two steps.  mdf_step,
  *      mdf_step_emit and mdf_run_steady run pairs of steps this way and the
  *      last step of each call (and of each K-step chunk) as form 0 with these
  *      bx, by; batched 3D contexts run every step as form 0.
  * The read kernels always use one node per thread.  Default 64 x 4, 8
- * groups, form 2 on the 2D axis-link lattices and form 0 elsewhere.
+ * groups, form 2 on the axis-link lattices (in 3D with FP64 and FP32
+ * storage) and form 0 elsewhere.
  * MDF_EINVAL otherwise (also forms 1 and 2 on D2Q9 / D3Q15).  Any shape
  * and form give bitwise identical populations and fields; only the
  * summation order of the FP64 sums of mdf_check, mdf_run_steady and

@@ -32,6 +32,13 @@
  *
  * Lattice units throughout: dx = dt = c = 1.
  *
+ * The paper allows a different lattice for each set a (remark after eq.
+ * d3q15).  Lattice ids ORC_D2Q9_Q5 and ORC_D3Q15_Q7 run the velocity sets
+ * a >= 1 on D2Q9 / D3Q15 and the set a = 0 on D2Q5 / D3Q7: every set
+ * collides and streams on its own lattice (its own weights, collision matrix
+ * and links); the set a = 0 occupies the first q0 entries of its row of the
+ * state, the rest stay zero.
+ *
  * Readings where the paper gives no formula (each is listed with its reason
  * in the design notes of the repository):
  *   - walls: the paper names an "anti-halfway bounce-back" rule for velocity
@@ -63,6 +70,10 @@
 #define ORC_D3Q6 5
 #define ORC_D2Q9 8
 #define ORC_D3Q15 9
+/* a lattice per set (the remark after eq. d3q15): the velocity sets a >= 1
+ * on D2Q9 / D3Q15, the set a = 0 on D2Q5 / D3Q7 */
+#define ORC_D2Q9_Q5 12
+#define ORC_D3Q15_Q7 13
 #define ORC_PERIODIC 0
 #define ORC_WALL 1
 #define ORC_PLAIN 0
@@ -282,6 +293,8 @@ static void make_d3q15(lattice_t *L)
 
 static int make_lattice(int lattice, lattice_t *L)
 {
+    if (lattice == ORC_D2Q9_Q5) { make_d2q9(L); return 0; }
+    if (lattice == ORC_D3Q15_Q7) { make_d3q15(L); return 0; }
     if (lattice == ORC_D2Q5) { make_d2q5(L); return 0; }
     if (lattice == ORC_D3Q7) { make_d3q7(L); return 0; }
     if (lattice == ORC_D2Q4) { make_d2q4(L); return 0; }
@@ -289,6 +302,15 @@ static int make_lattice(int lattice, lattice_t *L)
     if (lattice == ORC_D2Q9) { make_d2q9(L); return 0; }
     if (lattice == ORC_D3Q15) { make_d3q15(L); return 0; }
     return -1;
+}
+
+/* The lattice of the set a = 0: its own for a mixed lattice id, else the
+ * lattice of every set. */
+static int make_set0_lattice(int lattice, lattice_t *L0)
+{
+    if (lattice == ORC_D2Q9_Q5) { make_d2q5(L0); return 0; }
+    if (lattice == ORC_D3Q15_Q7) { make_d3q7(L0); return 0; }
+    return make_lattice(lattice, L0);
 }
 
 /* opposite direction: the j with c_j = -c_i */
@@ -385,19 +407,20 @@ static void node_source(const orc_case *cs, int d, const double *force_field, lo
 
 /* Moments of the stored populations fn of one node.  Fbar is used only by
  * Scheme II, whose ubar is eq. 2-7a. */
-static void node_moments(const lattice_t *L, const orc_case *cs,
+static void node_moments(const lattice_t *L, const lattice_t *L0, const orc_case *cs,
                          const double *fn /* [set][dir] */, const double *Fbar, moments_t *m)
 {
     int d = L->d, q = L->q;
     memset(m, 0, sizeof(*m));
     for (int a = 0; a <= d; ++a) {
+        const lattice_t *La = (a == 0) ? L0 : L;      /* the lattice of set a */
         double s = 0.0;
-        for (int i = 0; i < q; ++i) s += fn[a * q + i];
+        for (int i = 0; i < La->q; ++i) s += fn[a * q + i];
         if (cs->forcing == ORC_SCHEME2) s += 0.5 * Fbar[a];      /* eq. 2-7a */
         m->ubar[a] = s;
         for (int b = 0; b < d; ++b) {
             double j = 0.0;
-            for (int i = 0; i < q; ++i) j += L->c[i][b] * fn[a * q + i];
+            for (int i = 0; i < La->q; ++i) j += La->c[i][b] * fn[a * q + i];
             m->J[a][b] = j;
         }
     }
@@ -428,9 +451,10 @@ static long nodes_of(const orc_case *cs)
     return (long)cs->nx * cs->ny * cs->nz;
 }
 
-static int check_case(const orc_case *cs, lattice_t *L)
+static int check_case(const orc_case *cs, lattice_t *L, lattice_t *L0)
 {
     if (make_lattice(cs->lattice, L) != 0) return -1;
+    if (make_set0_lattice(cs->lattice, L0) != 0) return -1;
     if (cs->nx < 1 || cs->ny < 1 || cs->nz < 1) return -1;
     if (L->d == 2 && cs->nz != 1) return -1;
     if (!(cs->s1 > 0.0 && cs->s1 < 2.0)) return -1;
@@ -455,6 +479,17 @@ int orc_lattice_info(int lattice, int *d, int *q, int *c, double *w, double *cs2
         for (int k = 0; k < L.q; ++k) M[i * L.q + k] = L.M[i][k];
     }
     return 0;
+}
+
+/* Lattice id of the set a = 0 for a lattice id (the id itself unless the
+ * set a = 0 has a lattice of its own), or -1. */
+int orc_set0_lattice(int lattice)
+{
+    lattice_t L;
+    if (make_lattice(lattice, &L) != 0) return -1;
+    if (lattice == ORC_D2Q9_Q5) return ORC_D2Q5;
+    if (lattice == ORC_D3Q15_Q7) return ORC_D3Q7;
+    return lattice;
 }
 
 /* Collision matrix L = M^{-1} S_d M, row-major q x q.  s2 <= 0 selects the
@@ -483,29 +518,28 @@ int orc_collision_matrix(int lattice, double s0, double s1, double s2, double *o
 int orc_init(const orc_case *cs, const uint8_t *solid, const double *force_field,
              const double *P, const double *u, const double *grad, double *f)
 {
-    lattice_t L;
-    if (check_case(cs, &L) != 0) return -1;
+    lattice_t L, L0;
+    if (check_case(cs, &L, &L0) != 0) return -1;
     long N = nodes_of(cs);
     int d = L.d, q = L.q, ns = d + 1;
     for (long n = 0; n < N; ++n) {
         double *fn = f + n * ns * q;
-        if (solid && solid[n]) {
-            for (int k = 0; k < ns * q; ++k) fn[k] = 0.0;
-            continue;
-        }
+        for (int k = 0; k < ns * q; ++k) fn[k] = 0.0;
+        if (solid && solid[n]) continue;
         double un[3] = {0, 0, 0};
         for (int b = 0; b < d; ++b) un[b] = u[b * N + n];
         for (int a = 0; a <= d; ++a) {
+            const lattice_t *La = (a == 0) ? &L0 : &L;
             double ubar_a = (a == 0) ? cs->rho0 : un[a - 1];
             double feq[QMAX];
-            equilibrium(&L, a, ubar_a, un, P[n], feq);
-            for (int i = 0; i < q; ++i) {
+            equilibrium(La, a, ubar_a, un, P[n], feq);
+            for (int i = 0; i < La->q; ++i) {
                 double fne = 0.0;
                 if (grad && a >= 1) {
                     double cg = 0.0;
                     for (int b = 0; b < d; ++b)
-                        cg += L.c[i][b] * grad[((a - 1) * d + b) * N + n];
-                    fne = -(1.0 / cs->s1) * L.w[i] * cg;
+                        cg += La->c[i][b] * grad[((a - 1) * d + b) * N + n];
+                    fne = -(1.0 / cs->s1) * La->w[i] * cg;
                 }
                 fn[a * q + i] = feq[i] + fne;
             }
@@ -513,8 +547,10 @@ int orc_init(const orc_case *cs, const uint8_t *solid, const double *force_field
         if (cs->forcing == ORC_SCHEME2) {
             double Fbar[4];
             node_source(cs, d, force_field, N, n, Fbar);
-            for (int a = 0; a <= d; ++a)
-                for (int i = 0; i < q; ++i) fn[a * q + i] -= 0.5 * L.w[i] * Fbar[a];
+            for (int a = 0; a <= d; ++a) {
+                const lattice_t *La = (a == 0) ? &L0 : &L;
+                for (int i = 0; i < La->q; ++i) fn[a * q + i] -= 0.5 * La->w[i] * Fbar[a];
+            }
         }
     }
     return 0;
@@ -530,36 +566,40 @@ int orc_init(const orc_case *cs, const uint8_t *solid, const double *force_field
 int orc_collide(const orc_case *cs, const uint8_t *solid, const double *force_field,
                 const double *f, double *fpost)
 {
-    lattice_t L;
-    double Lam[QMAX][QMAX];
-    if (check_case(cs, &L) != 0) return -1;
+    lattice_t L, L0;
+    double Lam[QMAX][QMAX], Lam0[QMAX][QMAX];
+    if (check_case(cs, &L, &L0) != 0) return -1;
     if (collision_matrix(&L, cs->s0, cs->s1, relax_s2(cs), Lam) != 0) return -1;
+    if (collision_matrix(&L0, cs->s0, cs->s1, relax_s2(cs), Lam0) != 0) return -1;
     long N = nodes_of(cs);
     int d = L.d, q = L.q, ns = d + 1;
 #pragma omp parallel for schedule(static)
     for (long n = 0; n < N; ++n) {
         const double *fn = f + n * ns * q;
         double *fo = fpost + n * ns * q;
-        if (solid && solid[n]) {
-            for (int k = 0; k < ns * q; ++k) fo[k] = 0.0;
-            continue;
-        }
+        for (int k = 0; k < ns * q; ++k) fo[k] = 0.0;
+        if (solid && solid[n]) continue;
         double Fbar[4];
         node_source(cs, d, force_field, N, n, Fbar);
         moments_t m;
-        node_moments(&L, cs, fn, Fbar, &m);
+        node_moments(&L, &L0, cs, fn, Fbar, &m);
         for (int a = 0; a <= d; ++a) {
+            /* each set collides on its own lattice (the same for every set
+             * unless the set a = 0 has one of its own) */
+            const lattice_t *La = (a == 0) ? &L0 : &L;
+            double (*LamA)[QMAX] = (a == 0) ? Lam0 : Lam;
+            const int qa = La->q;
             double feq[QMAX], fne[QMAX];
-            equilibrium(&L, a, m.ubar[a], m.u, m.P, feq);
-            for (int i = 0; i < q; ++i) fne[i] = fn[a * q + i] - feq[i];
-            for (int i = 0; i < q; ++i) {
+            equilibrium(La, a, m.ubar[a], m.u, m.P, feq);
+            for (int i = 0; i < qa; ++i) fne[i] = fn[a * q + i] - feq[i];
+            for (int i = 0; i < qa; ++i) {
                 double coll = 0.0;
-                for (int k = 0; k < q; ++k) coll += Lam[i][k] * fne[k];
-                double src = L.w[i] * Fbar[a];
+                for (int k = 0; k < qa; ++k) coll += LamA[i][k] * fne[k];
+                double src = La->w[i] * Fbar[a];
                 if (cs->forcing == ORC_SCHEME2) {
                     /* (I - L/2) applied to F_{k,a} = w_k Fbar_a */
                     double lf = 0.0;
-                    for (int k = 0; k < q; ++k) lf += Lam[i][k] * L.w[k] * Fbar[a];
+                    for (int k = 0; k < qa; ++k) lf += LamA[i][k] * La->w[k] * Fbar[a];
                     src -= 0.5 * lf;
                 }
                 fo[a * q + i] = fn[a * q + i] - coll + src;
@@ -596,44 +636,42 @@ static int upstream(const orc_case *cs, const lattice_t *L, int x, int y, int z,
  * the halfway anti-bounce-back reading stated in the file header. */
 int orc_stream(const orc_case *cs, const uint8_t *solid, const double *fpost, double *f)
 {
-    lattice_t L;
-    if (check_case(cs, &L) != 0) return -1;
+    lattice_t L, L0;
+    if (check_case(cs, &L, &L0) != 0) return -1;
     int d = L.d, q = L.q, ns = d + 1;
-    int opp[QMAX];
-    for (int i = 0; i < q; ++i) opp[i] = opposite(&L, i);
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < cs->nz; ++z)
         for (int y = 0; y < cs->ny; ++y)
             for (int x = 0; x < cs->nx; ++x) {
                 long n = ((long)z * cs->ny + y) * cs->nx + x;
                 double *fn = f + n * ns * q;
-                if (solid && solid[n]) {
-                    for (int k = 0; k < ns * q; ++k) fn[k] = 0.0;
-                    continue;
-                }
+                for (int k = 0; k < ns * q; ++k) fn[k] = 0.0;
+                if (solid && solid[n]) continue;
                 const double *own = fpost + n * ns * q;
-                for (int i = 0; i < q; ++i) {
-                    int sx = 0, sy = 0, sz = 0;
-                    int face = upstream(cs, &L, x, y, z, i, &sx, &sy, &sz);
-                    const double *Uw = NULL;
-                    static const double zero[3] = {0, 0, 0};
-                    if (face >= 0) {
-                        Uw = cs->wall_u[face];
-                    } else {
-                        long sn = ((long)sz * cs->ny + sy) * cs->nx + sx;
-                        if (solid && solid[sn]) {
-                            Uw = zero;
+                for (int a = 0; a < ns; ++a) {
+                    const lattice_t *La = (a == 0) ? &L0 : &L;     /* the lattice of set a */
+                    for (int i = 0; i < La->q; ++i) {
+                        int sx = 0, sy = 0, sz = 0;
+                        int face = upstream(cs, La, x, y, z, i, &sx, &sy, &sz);
+                        const double *Uw = NULL;
+                        static const double zero[3] = {0, 0, 0};
+                        if (face >= 0) {
+                            Uw = cs->wall_u[face];
                         } else {
-                            for (int a = 0; a < ns; ++a)
+                            long sn = ((long)sz * cs->ny + sy) * cs->nx + sx;
+                            if (solid && solid[sn]) {
+                                Uw = zero;
+                            } else {
                                 fn[a * q + i] = fpost[sn * ns * q + a * q + i];
-                            continue;
+                                continue;
+                            }
                         }
+                        /* link crosses a wall: bounce back (a = 0) or
+                         * anti-bounce-back with the wall velocity (a >= 1) */
+                        const int j = opposite(La, i);
+                        if (a == 0) fn[i] = own[j];
+                        else fn[a * q + i] = -own[a * q + j] + 2.0 * La->w[i] * Uw[a - 1];
                     }
-                    /* link crosses a wall: bounce back (a = 0) or
-                     * anti-bounce-back with the wall velocity (a >= 1) */
-                    fn[0 * q + i] = own[0 * q + opp[i]];
-                    for (int a = 1; a < ns; ++a)
-                        fn[a * q + i] = -own[a * q + opp[i]] + 2.0 * L.w[i] * Uw[a - 1];
                 }
             }
     return 0;
@@ -666,8 +704,8 @@ int orc_num_fields(int lattice)
 int orc_fields(const orc_case *cs, const uint8_t *solid, const double *force_field,
                const double *f, double *out)
 {
-    lattice_t L;
-    if (check_case(cs, &L) != 0) return -1;
+    lattice_t L, L0;
+    if (check_case(cs, &L, &L0) != 0) return -1;
     long N = nodes_of(cs);
     int d = L.d, q = L.q, ns = d + 1;
     int nch = orc_num_fields(cs->lattice);
@@ -681,7 +719,7 @@ int orc_fields(const orc_case *cs, const uint8_t *solid, const double *force_fie
         double Fbar[4];
         node_source(cs, d, force_field, N, n, Fbar);
         moments_t m;
-        node_moments(&L, cs, fn, Fbar, &m);
+        node_moments(&L, &L0, cs, fn, Fbar, &m);
         /* first moment of the non-equilibrium part, mne[a][b] =
          * sum_i c_{i,b} f^ne_{i,a}, a = 1..d */
         double mne[4][3];
@@ -824,8 +862,8 @@ int orc_round16(int fmt, const float *in, double *out, long n)
  * its round trip through the 16-bit deviation storage described above. */
 int orc_store16(const orc_case *cs, const uint8_t *solid, int fmt, double u_ref, double *f)
 {
-    lattice_t L;
-    if (check_case(cs, &L) != 0) return -1;
+    lattice_t L, L0;
+    if (check_case(cs, &L, &L0) != 0) return -1;
     if ((fmt != ORC_BINARY16 && fmt != ORC_BFLOAT16) || !(u_ref > 0.0)) return -1;
     long N = nodes_of(cs);
     int d = L.d, q = L.q, ns = d + 1;
@@ -834,8 +872,8 @@ int orc_store16(const orc_case *cs, const uint8_t *solid, int fmt, double u_ref,
         if (solid && solid[n]) continue;
         double *fn = f + n * ns * q;
         for (int a = 0; a < ns; ++a)
-            for (int i = 0; i < q; ++i) {
-                const double rest = (a == 0) ? L.w[i] * cs->rho0 : 0.0;
+            for (int i = 0; i < ((a == 0) ? L0.q : q); ++i) {
+                const double rest = (a == 0) ? L0.w[i] * cs->rho0 : 0.0;
                 const float v32 = (float)fn[a * q + i];
                 const float r32 = (float)rest;
                 const float dev32 = (v32 - r32) * inv32;        /* binary32 operations */
@@ -865,8 +903,8 @@ int orc_run16(const orc_case *cs, const uint8_t *solid, const double *force_fiel
 int orc_invariants(const orc_case *cs, const uint8_t *solid, const double *force_field,
                    const double *f, double *out)
 {
-    lattice_t L;
-    if (check_case(cs, &L) != 0) return -1;
+    lattice_t L, L0;
+    if (check_case(cs, &L, &L0) != 0) return -1;
     long N = nodes_of(cs);
     int d = L.d, q = L.q, ns = d + 1;
     for (int k = 0; k < d + 2; ++k) out[k] = 0.0;
@@ -875,7 +913,7 @@ int orc_invariants(const orc_case *cs, const uint8_t *solid, const double *force
         double Fbar[4];
         node_source(cs, d, force_field, N, n, Fbar);
         moments_t m;
-        node_moments(&L, cs, f + n * ns * q, Fbar, &m);
+        node_moments(&L, &L0, cs, f + n * ns * q, Fbar, &m);
         for (int a = 0; a <= d; ++a) out[a] += m.ubar[a];
         for (int a = 1; a <= d; ++a) out[d + 1] += m.J[a][a - 1];
     }

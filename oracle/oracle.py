@@ -22,7 +22,11 @@ D2Q4 = 4
 D3Q6 = 5
 D2Q9 = 8
 D3Q15 = 9
-_DQ = {D2Q5: (2, 5), D3Q7: (3, 7), D2Q4: (2, 4), D3Q6: (3, 6), D2Q9: (2, 9), D3Q15: (3, 15)}
+# a lattice per set: the velocity sets on D2Q9 / D3Q15, the set a = 0 on D2Q5 / D3Q7
+D2Q9_Q5 = 12
+D3Q15_Q7 = 13
+_DQ = {D2Q5: (2, 5), D3Q7: (3, 7), D2Q4: (2, 4), D3Q6: (3, 6), D2Q9: (2, 9), D3Q15: (3, 15),
+       D2Q9_Q5: (2, 9), D3Q15_Q7: (3, 15)}
 PERIODIC = 0
 WALL = 1
 PLAIN = 0        # forcing of eq. 3-21
@@ -73,13 +77,14 @@ def lib():
         L.orc_step.argtypes = [cp, u8p, dp, dp, dp]
         L.orc_run.argtypes = [cp, u8p, dp, dp, dp, ctypes.c_long]
         L.orc_invariants.argtypes = [cp, u8p, dp, dp, dp]
+        L.orc_set0_lattice.argtypes = [ctypes.c_int]
         fp = ctypes.POINTER(ctypes.c_float)
         L.orc_round16.argtypes = [ctypes.c_int, fp, dp, ctypes.c_long]
         L.orc_store16.argtypes = [cp, u8p, ctypes.c_int, ctypes.c_double, dp]
         L.orc_run16.argtypes = [cp, u8p, dp, ctypes.c_int, ctypes.c_double, dp, dp, ctypes.c_long]
         for name in ("orc_lattice_info", "orc_collision_matrix", "orc_init", "orc_collide",
                      "orc_stream", "orc_fields", "orc_num_fields", "orc_step", "orc_run",
-                     "orc_invariants", "orc_round16", "orc_store16", "orc_run16"):
+                     "orc_invariants", "orc_round16", "orc_store16", "orc_run16", "orc_set0_lattice"):
             getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -121,6 +126,15 @@ def lattice_info(lattice):
         "cs2": float(cs2[0]),
         "M": M[: qn * qn].reshape(qn, qn).copy(),
     }
+
+
+def set0_lattice(lattice):
+    """Lattice id of the set a = 0 (differs from `lattice` only for the ids
+    with a lattice per set)."""
+    r = lib().orc_set0_lattice(int(lattice))
+    if r < 0:
+        raise ValueError(f"unknown lattice {lattice}")
+    return r
 
 
 def collision_matrix(lattice, s0, s1, s2=0.0):
@@ -206,7 +220,9 @@ class Oracle:
         return self
 
     def set_populations(self, f):
-        """f given as [set][dir][node] (set-major), converted to the oracle's layout."""
+        """f given as [set][dir][node] (set-major), converted to the oracle's
+        layout.  With a lattice per set, the set a = 0 uses the first q0
+        directions (the rest must be zero)."""
         c = self.case
         f = np.asarray(f, float).reshape(c.d + 1, c.q, c.N)
         self.f[:] = np.ascontiguousarray(f.transpose(2, 0, 1)).reshape(-1)

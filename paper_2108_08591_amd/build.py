@@ -16,7 +16,8 @@ LIB = os.path.join(HERE, "libmdf.so")
 # compile in parallel.
 LATTICE_UNITS = ["lat_d2q5.hip", "lat_d3q7.hip", "lat_d2q5v.hip", "lat_d3q7v.hip",
                  "lat_d2q4.hip", "lat_d3q6.hip", "lat_d2q4v.hip", "lat_d3q6v.hip",
-                 "lat_d2q9.hip", "lat_d3q15.hip", "lat_d2q9v.hip", "lat_d3q15v.hip"]
+                 "lat_d2q9.hip", "lat_d3q15.hip", "lat_d2q9v.hip", "lat_d3q15v.hip",
+                 "lat_d2q9q5.hip", "lat_d3q15q7.hip"]
 SOURCES = LATTICE_UNITS + ["mdf_launch.hip", "mdf_api.cpp", "nn_kernels.hip"]
 # sources whose text determines the step kernels' machine code
 KERNEL_SOURCES = ["mdf_kernels.h", "mdf_internal.h"] + LATTICE_UNITS

@@ -25,13 +25,28 @@ D2Q4 = 4        # no rest population
 D3Q6 = 5        # no rest population
 D2Q9 = 8        # diagonal links
 D3Q15 = 9       # diagonal links
-CS2 = {D2Q5: 1.0 / 3.0, D3Q7: 1.0 / 4.0, D2Q4: 1.0 / 2.0, D3Q6: 1.0 / 3.0, D2Q9: 1.0 / 3.0, D3Q15: 1.0 / 3.0}
-DIM = {D2Q5: 2, D3Q7: 3, D2Q4: 2, D3Q6: 3, D2Q9: 2, D3Q15: 3}
-NQ = {D2Q5: 5, D3Q7: 7, D2Q4: 4, D3Q6: 6, D2Q9: 9, D3Q15: 15}
+D2Q9_Q5 = 12    # a lattice per set: velocity sets on D2Q9, the set a = 0 on D2Q5
+D3Q15_Q7 = 13   # velocity sets on D3Q15, the set a = 0 on D3Q7
+# lattice of the set a = 0 (the lattice itself but for the two ids above)
+SET0_LATTICE = {D2Q9_Q5: D2Q5, D3Q15_Q7: D3Q7}
+# CS2, NQ and WEIGHTS describe the velocity sets' lattice
+CS2 = {D2Q5: 1.0 / 3.0, D3Q7: 1.0 / 4.0, D2Q4: 1.0 / 2.0, D3Q6: 1.0 / 3.0, D2Q9: 1.0 / 3.0, D3Q15: 1.0 / 3.0,
+       D2Q9_Q5: 1.0 / 3.0, D3Q15_Q7: 1.0 / 3.0}
+DIM = {D2Q5: 2, D3Q7: 3, D2Q4: 2, D3Q6: 3, D2Q9: 2, D3Q15: 3, D2Q9_Q5: 2, D3Q15_Q7: 3}
+NQ = {D2Q5: 5, D3Q7: 7, D2Q4: 4, D3Q6: 6, D2Q9: 9, D3Q15: 15, D2Q9_Q5: 9, D3Q15_Q7: 15}
 # weights in the population order of the C ABI (eq. d2q5, d3q7, d2q4, d3q6,
 # d2q9, d3q15: the printed column order)
 WEIGHTS = {D2Q5: [1 / 3] + [1 / 6] * 4, D3Q7: [1 / 4] + [1 / 8] * 6, D2Q4: [1 / 4] * 4, D3Q6: [1 / 6] * 6,
            D2Q9: [4 / 9] + [1 / 9] * 4 + [1 / 36] * 4, D3Q15: [2 / 9] + [1 / 9] * 6 + [1 / 72] * 8}
+WEIGHTS[D2Q9_Q5] = WEIGHTS[D2Q9]
+WEIGHTS[D3Q15_Q7] = WEIGHTS[D3Q15]
+
+
+def set0_weights(lattice: int) -> list:
+    """Weights of the set a = 0 over the q directions of the lattice: those of
+    its own lattice, zero-padded where it has fewer directions."""
+    w = WEIGHTS[SET0_LATTICE.get(lattice, lattice)]
+    return list(w) + [0.0] * (NQ[lattice] - len(w))
 
 PERIODIC = 0
 WALL = 1
@@ -222,8 +237,10 @@ def random_populations(spec: CaseSpec, seed: int, scale: float = 0.05, rest: flo
     q = spec.q
     ns = spec.d + 1
     f = rng.uniform(-scale, scale, size=(ns, q) + spec.fshape)
-    w = np.array(WEIGHTS[spec.lattice])
+    w = np.array(set0_weights(spec.lattice))
     f[0] += (rest * w).reshape((q,) + (1,) * spec.d)
+    if spec.lattice in SET0_LATTICE:
+        f[0, NQ[SET0_LATTICE[spec.lattice]]:] = 0.0      # directions the set a = 0 does not have
     return f
 
 

@@ -28,16 +28,25 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 // Lattice ids: bit 0 selects 3D, bit 1 the velocity sets only (*_V), bit 2
 // the lattices without a rest population (D2Q4, D3Q6), bit 3 those with
-// diagonal links (D2Q9, D3Q15).
-bool lat_ok(int lattice) { return lattice >= MDF_D2Q5 && lattice <= MDF_D3Q15_V; }
+// diagonal links (D2Q9, D3Q15).  The two ids with a lattice per set
+// (MDF_D2Q9_Q5, MDF_D3Q15_Q7: velocity sets with diagonal links, the set
+// a = 0 on D2Q5 / D3Q7) are the exception to bit 2.
+bool lat_mixed(int lattice) { return lattice == MDF_D2Q9_Q5 || lattice == MDF_D3Q15_Q7; }
+bool lat_ok(int lattice) { return (lattice >= MDF_D2Q5 && lattice <= MDF_D3Q15_V) || lat_mixed(lattice); }
 bool lat_2d(int lattice) { return (lattice & 1) == 0; }
-bool lat_restfree(int lattice) { return (lattice & 4) != 0; }
+bool lat_restfree(int lattice) { return (lattice & 4) != 0 && !lat_mixed(lattice); }
 bool lat_diag(int lattice) { return (lattice & 8) != 0; }
 // two steps per launch: lattices with axis links (2D tiles, or 3D tiles
 // walking z-planes)
 bool lat_fusable(int lattice) { return !lat_diag(lattice); }
-// the default form: two steps per launch in 2D
-bool lat_fused_default(int lattice) { return lat_2d(lattice) && !lat_diag(lattice); }
+// the default form: two steps per launch on the axis-link lattices, except
+// 3D with 16-bit storage (measured slower there than one node per thread)
+bool lat_fused_default(int lattice, int storage)
+{
+    if (lat_diag(lattice)) return false;
+    if (lat_2d(lattice)) return true;
+    return storage == MDF_F64 || storage == MDF_F32;
+}
 int lat_d(int lattice) { return lat_2d(lattice) ? 2 : 3; }
 int lat_q(int lattice)
 {
@@ -46,13 +55,21 @@ int lat_q(int lattice)
 }
 // stored distribution sets: all d + 1, or the d velocity sets (the *_V lattices)
 int lat_ns(int lattice) { return (lattice & 2) ? lat_d(lattice) : lat_d(lattice) + 1; }
-// weight of the rest (k = 0), axis (1) and diagonal (2) directions (eq.
-// d2q5, d3q7, d2q4, d3q6, d2q9, d3q15; without a rest population the rest
-// entry repeats the moving weight)
+// population planes of one buffer: every stored set has q directions, but for
+// the set a = 0 of a lattice per set, which has 2d + 1
+int lat_planes(int lattice)
+{
+    if (lat_mixed(lattice)) return 2 * lat_d(lattice) + 1 + lat_d(lattice) * lat_q(lattice);
+    return lat_ns(lattice) * lat_q(lattice);
+}
+// weight of the rest (k = 0), axis (1) and diagonal (2) directions of the set
+// a = 0 (eq. d2q5, d3q7, d2q4, d3q6, d2q9, d3q15; without a rest population
+// the rest entry repeats the moving weight; a lattice per set takes the
+// weights of D2Q5 / D3Q7 there)
 double lat_wclass(int lattice, int k)
 {
     if (lat_restfree(lattice)) return 1.0 / lat_q(lattice);
-    if (lat_diag(lattice)) {
+    if (lat_diag(lattice) && !lat_mixed(lattice)) {
         static const double w2[3] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 36.0}, w3[3] = {2.0 / 9.0, 1.0 / 9.0, 1.0 / 72.0};
         return lat_2d(lattice) ? w2[k] : w3[k];
     }
@@ -97,7 +114,7 @@ bool validate_case(int lattice, int storage, const mdf_case &c, std::string &why
     if (c.nx < 1 || c.ny < 1 || c.nz < 1) { why = "grid sizes must be >= 1"; return false; }
     if (d == 2 && c.nz != 1) { why = "D2Q5 needs nz = 1"; return false; }
     const double nodes = double(c.nx) * c.ny * c.nz;
-    if (nodes * lat_q(lattice) * lat_ns(lattice) > 2.0e9) { why = "case too large (>2e9 populations)"; return false; }
+    if (nodes * lat_planes(lattice) > 2.0e9) { why = "case too large (>2e9 populations)"; return false; }
     // the step kernels address nodes by 32-bit byte offsets within a plane
     const double plane_bytes = double(row_pitch(c.nx, storage)) * c.ny * c.nz * storage_bytes(storage);
     if (plane_bytes > 4294967296.0 || nodes * compute_bytes(storage) > 4294967296.0) {
@@ -163,7 +180,7 @@ size_t layout(int lattice, int storage, const mdf_case *cases, int ncases, bool 
         CaseLayout L;
         const size_t pitch = row_pitch(c.nx, storage);
         const size_t plane = pitch * c.ny * c.nz;
-        const size_t popb = size_t(lat_ns(lattice)) * q * plane * storage_bytes(storage);
+        const size_t popb = size_t(lat_planes(lattice)) * plane * storage_bytes(storage);
         const size_t nodes = size_t(c.nx) * c.ny * c.nz;
         for (int b = 0; b < 2; ++b) { L.pop[b] = off; off = align256(off + popb); }
         L.links = off;
@@ -610,7 +627,7 @@ mdf_status mdf_init(mdf_ctx **out, mdf_lattice lattice, mdf_storage storage, con
 
     mdf_ctx *ctx = new mdf_ctx;
     ctx->lattice = lattice;
-    ctx->shape.fuse = lat_fused_default(lattice) ? 1 : 0;     // two steps per launch by default in 2D
+    ctx->shape.fuse = lat_fused_default(lattice, storage) ? 1 : 0;
     ctx->storage = storage;
     ctx->d = lat_d(lattice);
     ctx->q = lat_q(lattice);
@@ -667,7 +684,7 @@ mdf_status mdf_init(mdf_ctx **out, mdf_lattice lattice, mdf_storage storage, con
     // and 256^3 grids, -23 % on a 1024^2 grid that fits the cache).
     size_t pop_total = 0;
     for (int k = 0; k < ncases; ++k)
-        pop_total += 2 * size_t(lat_ns(lattice)) * lat_q(lattice) * size_t(ctx->kc[k].dstride) * storage_bytes(storage);
+        pop_total += 2 * size_t(lat_planes(lattice)) * size_t(ctx->kc[k].dstride) * storage_bytes(storage);
     const size_t kInfinityCacheBytes = size_t(256) << 20;
     for (int k = 0; k < ncases; ++k) ctx->kc[k].ntstore = pop_total > kInfinityCacheBytes ? 1 : 0;
     *out = ctx;
@@ -989,7 +1006,7 @@ mdf_status mdf_population_buffer(const mdf_ctx *ctx, int32_t case_id, int32_t wh
     if (which != 0 && which != 1) return fail(c, MDF_EINVAL, "mdf_population_buffer: which must be 0 or 1");
     if (!ptr || !bytes) return fail(c, MDF_EINVAL, "mdf_population_buffer: NULL output");
     *ptr = ctx->bufs[case_id].pop[which == 0 ? ctx->cur[case_id] : ctx->cur[case_id] ^ 1];
-    *bytes = size_t(lat_ns(ctx->lattice)) * ctx->q * size_t(ctx->kc[case_id].dstride) * storage_bytes(ctx->storage);
+    *bytes = size_t(lat_planes(ctx->lattice)) * size_t(ctx->kc[case_id].dstride) * storage_bytes(ctx->storage);
     return MDF_OK;
 }
 
@@ -1028,7 +1045,7 @@ const char kStateMagic[8] = {'M', 'D', 'F', 'S', 'T', 'A', 'T', '1'};
 
 size_t case_pop_bytes(const mdf_ctx *ctx, int k)
 {
-    return size_t(lat_ns(ctx->lattice)) * ctx->q * size_t(ctx->kc[k].dstride) * storage_bytes(ctx->storage);
+    return size_t(lat_planes(ctx->lattice)) * size_t(ctx->kc[k].dstride) * storage_bytes(ctx->storage);
 }
 
 size_t case_snap_bytes(const mdf_ctx *ctx, int k)

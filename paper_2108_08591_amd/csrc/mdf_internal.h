@@ -134,6 +134,8 @@ const LatOps &lat_ops_d2q9();
 const LatOps &lat_ops_d3q15();
 const LatOps &lat_ops_d2q9v();
 const LatOps &lat_ops_d3q15v();
+const LatOps &lat_ops_d2q9q5();
+const LatOps &lat_ops_d3q15q7();
 
 // Launchers (implemented in mdf_launch.hip).  All enqueue on `stream` and
 // return the hipError_t of the launch.

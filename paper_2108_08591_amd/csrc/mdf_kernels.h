@@ -174,6 +174,57 @@ struct LatD3Q15V : LatD3Q15 {
     static constexpr int NS = 3, A0 = 1;
 };
 
+// A lattice per set (the paper allows a different lattice for each set a,
+// remark after eq. d3q15): the velocity sets on D2Q9 / D3Q15, the set a = 0
+// on D2Q5 / D3Q7, whose velocities are the first five / seven of the larger
+// lattice in the same order (so opposite directions, weight classes and
+// link bits carry over).  The set a = 0 only advects rho0, so it can take
+// the cheaper lattice: 5 + 2 x 9 planes instead of 27 in 2D, 7 + 3 x 15
+// instead of 60 in 3D.  Members Q0, w_set0 and inv_cs2_set0 describe the set
+// a = 0.
+struct LatD2Q9Q5 : LatD2Q9 {
+    static constexpr int Q0 = 5;
+    static constexpr double w_set0[5] = {1.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0};
+    static constexpr double inv_cs2_set0 = 3.0;
+};
+struct LatD3Q15Q7 : LatD3Q15 {
+    static constexpr int Q0 = 7;
+    static constexpr double w_set0[7] = {1.0 / 4.0, 1.0 / 8.0, 1.0 / 8.0, 1.0 / 8.0, 1.0 / 8.0, 1.0 / 8.0, 1.0 / 8.0};
+    static constexpr double inv_cs2_set0 = 4.0;
+};
+
+template <class L, class = void> struct HasSet0Lattice : std::false_type {};
+template <class L> struct HasSet0Lattice<L, std::void_t<decltype(L::Q0)>> : std::true_type {};
+
+// Directions, weights and 1/cs^2 of set pa (the set index a of eq. 2-2).
+template <class L>
+__device__ __forceinline__ constexpr int qset(int pa)
+{
+    if constexpr (HasSet0Lattice<L>::value) return pa == 0 ? L::Q0 : L::Q;
+    else return L::Q;
+}
+template <class L>
+__device__ __forceinline__ constexpr double wset(int pa, int i)
+{
+    if constexpr (HasSet0Lattice<L>::value) return pa == 0 ? L::w_set0[i < L::Q0 ? i : 0] : L::w[i];
+    else return L::w[i];
+}
+template <class L>
+__device__ __forceinline__ constexpr double inv_cs2_set(int pa)
+{
+    if constexpr (HasSet0Lattice<L>::value) return pa == 0 ? L::inv_cs2_set0 : L::inv_cs2;
+    else return L::inv_cs2;
+}
+
+// Plane of stored set a, direction i: the sets one after the other, each
+// with its own number of directions.
+template <class L>
+__device__ __host__ __forceinline__ constexpr long long plane_of(int a, int i)
+{
+    if constexpr (HasSet0Lattice<L>::value) return a == 0 ? i : L::Q0 + (long long)(a - 1) * L::Q + i;
+    else return (long long)a * L::Q + i;
+}
+
 template <class L>
 __device__ __forceinline__ constexpr int cdir(int i, int b)
 {
@@ -530,15 +581,16 @@ __device__ __forceinline__ bool gather(const KCase &p, const typename Store<ST>:
         if (face < 0) {
             const auto k = grid_ix<WIDE>(sx, sy, sz, p.ny, p.pitch);
 #pragma unroll
-            for (int a = 0; a < L::NS; ++a)
-                n.f[a][i] = S::load(src + (long long)(a * L::Q + i) * p.dstride, k, rest_value<L, C>(p, a, i),
-                                    p.scale);
+            for (int a = 0; a < L::NS; ++a) {
+                if (i >= qset<L>(a + L::A0)) { n.f[a][i] = C(0); continue; }
+                n.f[a][i] = S::load(src + plane_of<L>(a, i) * p.dstride, k, rest_value<L, C>(p, a, i), p.scale);
+            }
         } else {
             const int j = L::opp[i];
 #pragma unroll
             for (int a = 0; a < L::NS; ++a) {
-                C v = S::load(src + (long long)(a * L::Q + j) * p.dstride, own, rest_value<L, C>(p, a, j),
-                              p.scale);
+                if (i >= qset<L>(a + L::A0)) { n.f[a][i] = C(0); continue; }
+                C v = S::load(src + plane_of<L>(a, j) * p.dstride, own, rest_value<L, C>(p, a, j), p.scale);
                 if (a + L::A0 == 0) {
                     n.f[a][i] = v;
                 } else {
@@ -599,8 +651,8 @@ __device__ __forceinline__ void gather_vec(const KCase &p, const typename Store<
         const int j = L::opp[i];
 #pragma unroll
         for (int a = 0; a < L::NS; ++a) {
-            const T *plane = src + (long long)(a * L::Q + i) * p.dstride;
-            const T *oplane = src + (long long)(a * L::Q + j) * p.dstride;
+            const T *plane = src + plane_of<L>(a, i) * p.dstride;
+            const T *oplane = src + plane_of<L>(a, j) * p.dstride;
             const C rest_i = rest_value<L, C>(p, a, i), rest_j = rest_value<L, C>(p, a, j);
             VecT<T, VX> vec;
 #pragma unroll
@@ -693,19 +745,20 @@ __device__ __forceinline__ void moments(const KCase &p, const Node<L, C> &n, Mom
 // drift by that fraction every step.)  Without a rest population the
 // collision closes the zeroth moment instead (collide_set()).
 template <class L, class C>
-__device__ __forceinline__ void equilibrium(C ub, const C (&flux)[L::D], C (&feq)[L::Q])
+__device__ __forceinline__ void equilibrium(C ub, const C (&flux)[L::D], C (&feq)[L::Q], int pa)
 {
     C rest = ub;
 #pragma unroll
     for (int i = L::R; i < L::Q; ++i) {
+        if (i >= qset<L>(pa)) { feq[i] = C(0); continue; }
         C cf = C(0);
 #pragma unroll
         for (int b = 0; b < L::D; ++b) {
             if (cdir<L>(i, b) > 0) cf += flux[b];
             else if (cdir<L>(i, b) < 0) cf -= flux[b];
         }
-        const C even = C(L::w[i]) * ub;
-        feq[i] = even + C(L::w[i] * L::inv_cs2) * cf;
+        const C even = C(wset<L>(pa, i)) * ub;
+        feq[i] = even + C(wset<L>(pa, i) * inv_cs2_set<L>(pa)) * cf;
         rest -= even;
     }
     if (L::R == 1) feq[0] = rest;
@@ -722,7 +775,7 @@ __device__ __forceinline__ void nonequilibrium(const Node<L, C> &n, const Moment
 #pragma unroll
     for (int b = 0; b < L::D; ++b) flux[b] = ub * m.u[b] + ((pa >= 1 && b == pa - 1) ? m.P : C(0));
     C feq[L::Q];
-    equilibrium<L, C>(ub, flux, feq);
+    equilibrium<L, C>(ub, flux, feq, pa);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) ne[i] = n.f[a][i] - feq[i];
 }
@@ -751,11 +804,13 @@ __device__ __forceinline__ void collide_set(const KCase &p, const Node<L, C> &n,
                                             const C (&ne)[L::Q], C (&out)[L::Q], C fb)
 {
     const C s1 = kpar<C>(p.s1, p.s1f), s2 = kpar<C>(p.s2, p.s2f);
+    const int pa = a + L::A0;
     C dsum = C(0);
 #pragma unroll
     for (int i = L::R; i < L::Q; ++i) {
         if (i == L::K) continue;
-        const C wf = C(L::w[i]) * fb * kpar<C>(p.fmove, p.fmovef);
+        if (i >= qset<L>(pa)) { out[i] = C(0); continue; }
+        const C wf = C(wset<L>(pa, i)) * fb * kpar<C>(p.fmove, p.fmovef);
         const int j = L::opp[i];
         const C odd = C(0.5) * (ne[i] - ne[j]);
         const C even = C(0.5) * (ne[i] + ne[j]);
@@ -936,9 +991,11 @@ __device__ __forceinline__ void step_tile(const KCase &p, int gx, int gy, int ti
             nonequilibrium<L, C>(n, m, a, ne);
             collide_set<L, C>(p, n, a, ne, fo, m.fb[a + L::A0]);
 #pragma unroll
-            for (int i = 0; i < L::Q; ++i)
-                S::template store_hint<NTST>(dst + (long long)(a * L::Q + i) * p.dstride, own, fo[i],
+            for (int i = 0; i < L::Q; ++i) {
+                if (i >= qset<L>(a + L::A0)) continue;
+                S::template store_hint<NTST>(dst + plane_of<L>(a, i) * p.dstride, own, fo[i],
                                              rest_value<L, C>(p, a, i), p.inv_scale);
+            }
         }
     } else if (EMIT && inside) {
         // solid node: every emitted channel is zero
@@ -1031,7 +1088,8 @@ __device__ __forceinline__ void step_tile_vec(const KCase &p, int gx, int gy, in
         }
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
-            T *plane = dst + (long long)(a * L::Q + i) * p.dstride;
+            if (i >= qset<L>(a + L::A0)) continue;
+            T *plane = dst + plane_of<L>(a, i) * p.dstride;
             const C rest_i = rest_value<L, C>(p, a, i);
             VecT<T, VX> ov;
 #pragma unroll
@@ -1133,7 +1191,6 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int gy, int t
 {
     static_assert(L::D == 2, "two-step tiles are two-dimensional");
     using S = Store<ST>;
-    using T = typename S::T;
     using C = typename S::C;
     constexpr int TY = Fuse2Rows<ST>::TY, NT = Fuse2Rows<ST>::NT;
     constexpr int W = kF2W, NE = kF2W * (TY + 2);
@@ -1260,9 +1317,11 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int gy, int t
             nonequilibrium<L, C>(n, m, a, ne);
             collide_set<L, C>(p, n, a, ne, fo, m.fb[a + L::A0]);
 #pragma unroll
-            for (int i = 0; i < L::Q; ++i)
-                S::template store_hint<NTST>(dst + (long long)(a * L::Q + i) * p.dstride, own, fo[i],
+            for (int i = 0; i < L::Q; ++i) {
+                if (i >= qset<L>(a + L::A0)) continue;
+                S::template store_hint<NTST>(dst + plane_of<L>(a, i) * p.dstride, own, fo[i],
                                              rest_value<L, C>(p, a, i), p.inv_scale);
+            }
         }
     }
 }
@@ -1313,11 +1372,14 @@ k_step2_batch(const BatchEntry *__restrict__ tab, const int *__restrict__ meta,
 // ----------------------------------------------------------------- two steps per pass (3D, axis links)
 
 // Output tile of k_step2z per storage: TX x TY nodes of an x-y plane, one
-// thread each, walking a chunk of z-planes.  The LDS copy of the
-// intermediate state f*(t+1) (see Step2ZLds) is 68 KB for FP32, 34 KB for
-// the 16-bit formats and 70 KB for FP64 (D3Q7, four sets), so two (four)
-// blocks fit a CU's 160 KB.
-template <int ST> struct Fuse2Z { static constexpr int TX = 32, TY = 8; };
+// thread each, walking a chunk of z-planes.  A tile row is TX x (bytes per
+// value) = 128 bytes (FP32, 16-bit) or 256 bytes (FP64): whole cache lines
+// for every population plane.  The LDS copy of the intermediate state
+// f*(t+1) (see Step2ZLds) is 68 KB for FP32, 70 KB for FP64 and 35 KB for
+// the 16-bit formats (D3Q7, four sets), so two (four) blocks fit a CU's
+// 160 KB.
+template <int ST> struct Fuse2Z { static constexpr int TX = 64, TY = 4; };
+template <> struct Fuse2Z<MDF_F32> { static constexpr int TX = 32, TY = 8; };
 template <> struct Fuse2Z<MDF_F64> { static constexpr int TX = 32, TY = 4; };
 
 // The directions of an axis-link 3D lattice by their z-component: the
@@ -1583,9 +1645,11 @@ __device__ __forceinline__ void step2z_plane2(const KCase &p, typename Store<ST>
         nonequilibrium<L, C>(n, m, a, ne);
         collide_set<L, C>(p, n, a, ne, fo, m.fb[a + L::A0]);
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i)
-            S::template store_hint<NTST>(dst + (long long)(a * L::Q + i) * p.dstride, own, fo[i],
+        for (int i = 0; i < L::Q; ++i) {
+            if (i >= qset<L>(a + L::A0)) continue;
+            S::template store_hint<NTST>(dst + plane_of<L>(a, i) * p.dstride, own, fo[i],
                                          rest_value<L, C>(p, a, i), p.inv_scale);
+        }
     }
 }
 
@@ -1747,8 +1811,8 @@ k_init(KCase p, typename Store<ST>::T *__restrict__ pre, typename Store<ST>::T *
     const long long node = ((long long)z * p.ny + y) * p.nx + x;
     if (MASK && (links[own] & 0x80u)) {
         for (int a = 0; a < L::NS; ++a)
-            for (int i = 0; i < L::Q; ++i) {
-                const long long k = (long long)(a * L::Q + i) * p.dstride + own;
+            for (int i = 0; i < qset<L>(a + L::A0); ++i) {
+                const long long k = plane_of<L>(a, i) * p.dstride + own;
                 S::store(pre, k, rest_value<L, C>(p, a, i), rest_value<L, C>(p, a, i), p.inv_scale);
                 S::store(post, k, rest_value<L, C>(p, a, i), rest_value<L, C>(p, a, i), p.inv_scale);
             }
@@ -1759,7 +1823,8 @@ k_init(KCase p, typename Store<ST>::T *__restrict__ pre, typename Store<ST>::T *
 #pragma unroll
         for (int a = 0; a < L::NS; ++a)
 #pragma unroll
-            for (int i = 0; i < L::Q; ++i) n.f[a][i] = data[(long long)(a * L::Q + i) * nodes + node];
+            for (int i = 0; i < L::Q; ++i)
+                n.f[a][i] = i < qset<L>(a + L::A0) ? data[(long long)(a * L::Q + i) * nodes + node] : C(0);
     } else {
         C P = C(0), u[L::D];
 #pragma unroll
@@ -1776,10 +1841,11 @@ k_init(KCase p, typename Store<ST>::T *__restrict__ pre, typename Store<ST>::T *
             C flux[L::D], feq[L::Q];
 #pragma unroll
             for (int b = 0; b < L::D; ++b) flux[b] = ub * u[b] + ((pa >= 1 && b == pa - 1) ? P : C(0));
-            equilibrium<L, C>(ub, flux, feq);
+            equilibrium<L, C>(ub, flux, feq, pa);
             if (L::R == 1) n.f[a][0] = feq[0];
 #pragma unroll
             for (int i = L::R; i < L::Q; ++i) {
+                if (i >= qset<L>(pa)) { n.f[a][i] = C(0); continue; }
                 C cg = C(0);
 #pragma unroll
                 for (int b = 0; b < L::D; ++b) {
@@ -1799,8 +1865,8 @@ k_init(KCase p, typename Store<ST>::T *__restrict__ pre, typename Store<ST>::T *
                 C moved = C(0);
 #pragma unroll
                 for (int i = L::R; i < L::Q; ++i) {
-                    if (i == L::K) continue;
-                    const C whf = C(L::w[i]) * hf;
+                    if (i == L::K || i >= qset<L>(pa)) continue;
+                    const C whf = C(wset<L>(pa, i)) * hf;
                     n.f[a][i] -= whf;
                     moved += whf;
                 }
@@ -1818,7 +1884,8 @@ k_init(KCase p, typename Store<ST>::T *__restrict__ pre, typename Store<ST>::T *
         collide_set<L, C>(p, n, a, ne, fo, m.fb[a + L::A0]);
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
-            const long long k = (long long)(a * L::Q + i) * p.dstride + own;
+            if (i >= qset<L>(a + L::A0)) continue;
+            const long long k = plane_of<L>(a, i) * p.dstride + own;
             S::store(pre, k, n.f[a][i], rest_value<L, C>(p, a, i), p.inv_scale);
             S::store(post, k, fo[i], rest_value<L, C>(p, a, i), p.inv_scale);
         }

@@ -73,6 +73,8 @@ const LatOps *ops_of(int lattice)
     case MDF_D3Q15: return &lat_ops_d3q15();
     case MDF_D2Q9_V: return &lat_ops_d2q9v();
     case MDF_D3Q15_V: return &lat_ops_d3q15v();
+    case MDF_D2Q9_Q5: return &lat_ops_d2q9q5();
+    case MDF_D3Q15_Q7: return &lat_ops_d3q15q7();
     }
     return nullptr;
 }

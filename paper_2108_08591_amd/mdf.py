@@ -23,7 +23,8 @@ OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
 D2Q5, D3Q7 = 0, 1
 D2Q4, D3Q6 = 4, 5      # lattices without a rest population
 D2Q9, D3Q15 = 8, 9     # lattices with diagonal links
-_NQ = {D2Q5: 5, D3Q7: 7, D2Q4: 4, D3Q6: 6, D2Q9: 9, D3Q15: 15}
+D2Q9_Q5, D3Q15_Q7 = 12, 13   # a lattice per set (set a = 0 on D2Q5 / D3Q7)
+_NQ = {D2Q5: 5, D3Q7: 7, D2Q4: 4, D3Q6: 6, D2Q9: 9, D3Q15: 15, D2Q9_Q5: 9, D3Q15_Q7: 15}
 F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
 PERIODIC, WALL = 0, 1
 FIELD_MOMENTS, FIELD_GRAD, FIELD_DIV, FIELD_STRAIN, FIELD_STRESS, FIELD_VORT = 1, 2, 4, 8, 16, 32
@@ -203,6 +204,9 @@ class Solver:
             raise ValueError("sets must be 'all' or 'velocity'")
         self.nsets = self.d + 1 if sets == "all" else self.d
         if sets == "velocity":
+            if self.lattice in (D2Q9_Q5, D3Q15_Q7):
+                raise ValueError("a lattice per set differs only in the set a = 0: use D2Q9 / D3Q15 "
+                                 "with sets='velocity'")
             self.lattice += 2          # the *_V lattice ids
         self.device = torch.device(device)
         self.dtype = torch.float64 if self.storage == F64 else torch.float32

@@ -97,7 +97,8 @@ def test_velocity_set_lattices_store_d_of_d_plus_one_sets():
         one_set = 2 * q * spec.nodes * 4          # both ping-pong buffers, FP32
         assert full - vel == pytest.approx(one_set, rel=0.02)
         assert full > (d + 1) * one_set
-    assert mdf.lib().mdf_workspace_size(12, mdf.F32, c, 1, 0) == 0
+    assert mdf.lib().mdf_workspace_size(14, mdf.F32, c, 1, 0) == 0
+    assert mdf.lib().mdf_workspace_size(-1, mdf.F32, c, 1, 0) == 0
 
 
 def test_rest_free_lattices_store_q_minus_one_planes():
@@ -123,6 +124,21 @@ def test_diagonal_lattices_store_q_planes():
         diag = mdf.lib().mdf_workspace_size(lat, mdf.F32, c, 1, 0)
         plane = 2 * (spec.d + 1) * spec.nodes * 4
         assert diag - base == pytest.approx((q - q_full) * plane, rel=0.02)
+
+
+def test_lattice_per_set_stores_fewer_set0_planes():
+    """MDF_D2Q9_Q5 / MDF_D3Q15_Q7 (a lattice per set, remark after eq. d3q15)
+    keep the set a = 0 on D2Q5 / D3Q7: 5 + 2 x 9 and 7 + 3 x 15 planes per
+    buffer, against (d + 1) q for D2Q9 / D3Q15."""
+    for spec, pure, mixed, saved in ((C.cavity_case(N=256, Re=100), mdf.D2Q9, mdf.D2Q9_Q5, 9 - 5),
+                                     (C.tgv3d_case(N=64, u0=0.05, Re=100.0), mdf.D3Q15, mdf.D3Q15_Q7, 15 - 7)):
+        c = (mdf.MdfCase * 1)(mdf._case_struct(spec))
+        full = mdf.lib().mdf_workspace_size(pure, mdf.F32, c, 1, 0)
+        per_set = mdf.lib().mdf_workspace_size(mixed, mdf.F32, c, 1, 0)
+        plane = 2 * spec.nodes * 4                    # one plane, both buffers, FP32
+        assert full - per_set == pytest.approx(saved * plane, rel=0.02)
+    c3 = (mdf.MdfCase * 1)(mdf._case_struct(C.tgv3d_case(N=16, u0=0.05, Re=100.0)))
+    assert mdf.lib().mdf_workspace_size(mdf.D2Q9_Q5, mdf.F32, c3, 1, 0) == 0
 
 
 @pytest.mark.parametrize("mutate,msg", [
@@ -157,7 +173,7 @@ def test_init_rejects_before_touching_the_device():
                     None, 0, None, None)
     assert st == mdf.ENOMEM
     # bad lattice / storage / init kind
-    assert L.mdf_init(ctypes.byref(ctx), 12, mdf.F32, cases, 1, ctypes.c_void_p(256), 1 << 30,
+    assert L.mdf_init(ctypes.byref(ctx), 14, mdf.F32, cases, 1, ctypes.c_void_p(256), 1 << 30,
                       None, 0, None, None) == mdf.EINVAL
     assert L.mdf_init(ctypes.byref(ctx), mdf.D2Q5, 9, cases, 1, ctypes.c_void_p(256), 1 << 30,
                       None, 0, None, None) == mdf.EINVAL

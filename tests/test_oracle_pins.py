@@ -303,6 +303,105 @@ def test_passive_set_is_advected_downstream():
     assert abs(centroid() - x0 - 200 * U) < 0.05
 
 
+# ------------------------------------------------------------------ a lattice per set
+
+PER_SET = [(O.D2Q9_Q5, O.D2Q9, O.D2Q5), (O.D3Q15_Q7, O.D3Q15, O.D3Q7)]
+
+
+@pytest.mark.parametrize("mixed,big,small", PER_SET)
+def test_lattice_per_set_velocity_sets_follow_the_large_lattice(mixed, big, small):
+    """A lattice per set (remark after eq. d3q15): P and the velocity sets
+    never read the set a = 0 (eq. 3-15 sums a = 1..d), so with the set a = 0
+    on the small lattice the velocity sets, u, P and the gradients are
+    exactly those of the large lattice, walls, obstacles and force included."""
+    assert O.set0_lattice(mixed) == small and O.set0_lattice(big) == big
+    d = C.DIM[big]
+    wall = np.zeros((6, 3))
+    wall[3] = (0.06, 0.0, 0.01)
+    shape = (26, 19) if d == 2 else (14, 11, 9)
+    bc = (C.PERIODIC, C.PERIODIC, C.WALL, C.WALL) + ((C.PERIODIC,) * 2 if d == 3 else (0, 0))
+    runs = []
+    for lat in (big, mixed):
+        spec = C.CaseSpec(lat, shape, 1.35, bc=bc, wall_u=wall, force=(2e-5, 0.0, 1e-5))
+        mask = np.zeros(spec.fshape, np.uint8)
+        mask[(slice(2, 5),) * (d - 2) + (slice(6, 10), slice(8, 13))] = 1
+        P, u = C.smooth_random_fields(spec, seed=12, amp=0.03)
+        o = _oracle(spec, solid=mask).init(P, u)
+        o.run(40)
+        runs.append(o)
+    a, b = runs
+    assert np.array_equal(a.populations()[1:], b.populations()[1:])
+    fa, fb = a.fields(), b.fields()
+    for k in ("u", "P", "grad", "div", "S", "sigma", "vort"):
+        assert np.array_equal(fa[k], fb[k]), k
+    # the set a = 0 differs: it has the small lattice's directions only
+    q0 = C.NQ[small]
+    assert np.all(b.populations()[0, q0:] == 0.0)
+    assert not np.allclose(a.populations()[0], b.populations()[0])
+
+
+def _set0_blob(lattice, spec, U, blob):
+    """Equilibrium of eq. 2-4 for the set a = 0 on `lattice` (rho0 + blob
+    advected by the uniform velocity U along x), over the spec's q slots."""
+    d = C.DIM[lattice]
+    w = np.array(C.WEIGHTS[lattice])
+    cs2 = C.CS2[lattice]
+    cx = np.array(O.lattice_info(lattice)["c"])[:, 0]
+    rho = 1.0 + blob
+    f0 = np.zeros((spec.q,) + spec.fshape)
+    for i in range(len(w)):
+        f0[i] = w[i] * rho * (1.0 + cx[i] * U / cs2)
+    return f0
+
+
+@pytest.mark.parametrize("mixed,big,small", PER_SET)
+def test_lattice_per_set_set0_follows_the_small_lattice(mixed, big, small):
+    """Under a uniform velocity U the set a = 0 solves the convection-diffusion
+    equation of eq. 2-2 on its own lattice: with a lattice per set it evolves
+    as the small lattice's set a = 0 does (weights, cs^2 and directions of
+    eq. d2q5 / d3q7), its centroid moves with +U, and in a closed box with an
+    obstacle its total is conserved (bounce-back, reading R1)."""
+    d = C.DIM[big]
+    N = 48
+    shape = (N, 6) if d == 2 else (N, 5, 4)
+    U = 0.04
+    x = np.arange(N) + 0.5
+    blob = 0.1 * np.exp(-((x - 16) ** 2) / 18.0) * np.ones(shape[::-1])
+    runs = []
+    for lat in (small, mixed):
+        spec = C.CaseSpec(lat, shape, 1.45)
+        u = np.zeros((d,) + spec.fshape)
+        u[0] = U
+        o = _oracle(spec).init(0.0, u)
+        f = o.populations()
+        f[0] = _set0_blob(small, spec, U, blob)
+        o.set_populations(f)
+        runs.append(o)
+    ref, got = runs
+    q0 = C.NQ[small]
+
+    def centroid(o):
+        r = o.fields()["ubar0"] - 1.0
+        r = r.reshape(-1, N).mean(0)
+        return float((r * x).sum() / r.sum())
+    c0 = centroid(got)
+    for o in runs:
+        o.run(150)
+    assert np.abs(got.populations()[0, :q0] - ref.populations()[0]).max() < 1e-14
+    assert np.all(got.populations()[0, q0:] == 0.0)
+    assert abs(centroid(got) - c0 - 150 * U) < 0.05
+    # closed box with an obstacle: the set a = 0 is bounced back
+    wall = np.zeros((6, 3))
+    wall[3] = (0.05, 0.0, 0.0)
+    spec = C.CaseSpec(mixed, (30, 26) if d == 2 else (14, 12, 10), 1.2, bc=(C.WALL,) * 6, wall_u=wall)
+    mask = np.zeros(spec.fshape, np.uint8)
+    mask[(slice(3, 6),) * (d - 2) + (slice(8, 13), slice(9, 14))] = 1
+    o = _oracle(spec, solid=mask).init(0.0, np.zeros((d,) + spec.fshape))
+    m0 = o.invariants()[0]
+    o.run(300)
+    assert abs(o.invariants()[0] - m0) < 1e-12 * m0
+
+
 # ------------------------------------------------------------------ closed-form flows
 
 def test_tgv2d_c1_against_closed_form():
