@@ -345,6 +345,92 @@ def lattice_per_set_study(out_path):
                 torch.cuda.empty_cache()
 
 
+BF16_DENSE_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 matrix peak (no sparsity)
+
+
+def conv_study(out_path, B=16, N=256, reps=5):
+    """The warm-start network's 3x3 convolutions at the configured image size
+    (N^2, batch B), layer by layer: forward, data gradient (forward with the
+    flipped weights, cout <-> cin) and weight gradient, each timed with HIP
+    events (median of reps) and priced at 2 * pixels * cout * 9 * cin flops
+    against the dense BF16 matrix peak."""
+    import torch
+    from paper_2108_08591_amd import nn
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    g = torch.Generator(device="cpu").manual_seed(7)
+    layers = []
+    H = N
+    cin = nn.IN_CH
+    for l, c in enumerate(nn.LEVELS):
+        layers.append((f"enc{l}a", H, cin, 0, c))
+        layers.append((f"enc{l}b", H, c, 0, c))
+        cin = c
+        if l < len(nn.LEVELS) - 1:
+            H //= 2
+    for l in range(len(nn.LEVELS) - 2, -1, -1):
+        H *= 2
+        c = nn.LEVELS[l]
+        layers.append((f"dec{l}a", H, nn.LEVELS[l + 1], c, c))
+        layers.append((f"dec{l}b", H, c, 0, c))
+
+    def rnd(*shape):
+        return nn.to_bf16((torch.randn(*shape, generator=g) * 0.1).to(dev))
+
+    def timed(fn):
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            with torch.cuda.stream(stream):
+                e0.record(stream)
+                fn()
+                e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return sorted(ts)[len(ts) // 2]
+
+    recs = []
+    with open(out_path, "w") as fh:
+        for name, HH, c1, c2, co in layers:
+            x1 = rnd(B, HH, HH, c1)
+            x2 = rnd(B, HH, HH, c2) if c2 else None
+            w = rnd(co, 9, c1 + c2)
+            bias = torch.zeros(co, device=dev)
+            y = nn.bf16_empty((B, HH, HH, co), dev)
+            dy = rnd(B, HH, HH, co)
+            dx = nn.bf16_empty((B, HH, HH, c1), dev)
+            wt = nn.bf16_empty((c1 + c2, 9, co), dev)
+            dw = torch.zeros(co, 9, c1 + c2, device=dev)
+            db = torch.zeros(co, device=dev)
+            scratch = torch.empty(nn.wgrad_scratch_bytes(B, HH, HH, c1 + c2, co), dtype=torch.uint8, device=dev)
+            nn.conv_flip(w, wt, stream)
+            flops = 2.0 * B * HH * HH * co * 9 * (c1 + c2)
+            fwd = lambda: nn.conv_fwd(x1, x2, w, bias, True, out_bf16=y, stream=stream)
+            dgrad = lambda: nn.conv_fwd(dy, None, wt[:c1], None, False, out_bf16=dx, stream=stream)
+            wgrad = lambda: nn.conv_wgrad(x1, x2, dy, dw, db, scratch, stream)
+            for kind, fn, fl in (("fwd", fwd, flops), ("dgrad", dgrad, 2.0 * B * HH * HH * c1 * 9 * co),
+                                 ("wgrad", wgrad, flops)):
+                fn()
+                ms = timed(fn)
+                tf = fl / ms / 1e9
+                rec = {"layer": name, "kind": kind, "B": B, "H": HH, "cin": c1 + c2, "cout": co,
+                       "ms": round(ms, 4), "GFLOP": round(fl / 1e9, 2), "TFLOPs": round(tf, 1),
+                       "frac_bf16_peak": round(tf / BF16_DENSE_PEAK_TFLOPS, 4)}
+                recs.append(rec)
+                print(json.dumps(rec), file=fh, flush=True)
+                print(json.dumps(rec), flush=True)
+            del x1, x2, w, y, dy, dx, wt, dw, scratch
+            torch.cuda.empty_cache()
+        tot_ms = sum(r["ms"] for r in recs)
+        tot_fl = sum(r["GFLOP"] for r in recs)
+        summ = {"summary": "one training step's convolutions", "B": B, "N": N, "ms": round(tot_ms, 3),
+                "GFLOP": round(tot_fl, 1), "TFLOPs": round(tot_fl / tot_ms, 1),
+                "frac_bf16_peak": round(tot_fl / tot_ms / BF16_DENSE_PEAK_TFLOPS, 4)}
+        print(json.dumps(summ), file=fh, flush=True)
+        print(json.dumps(summ), flush=True)
+
+
 def sweep(out_path):
     """Step-kernel timing over grid sizes (incl. working sets far beyond the
     256 MB Infinity Cache), storages, lattices and launch shapes."""
@@ -1053,6 +1139,8 @@ def main():
     ap.add_argument("--tgv3d", nargs="+", metavar="STORAGE FORM [GROUPS]",
                     help="time the 3D Taylor-Green step kernel (256^3) in one storage and form (XCD groups, "
                          "default 8)")
+    ap.add_argument("--conv-study", metavar="OUT_JSONL",
+                    help="the warm-start network's 3x3 convolutions at 256^2, batch 16: TFLOP/s per layer")
     ap.add_argument("--lattice-per-set-study", metavar="OUT_JSONL",
                     help="a lattice per set against the plain D2Q9 / D3Q15 (one node per thread)")
     ap.add_argument("--precision-study", metavar="OUT_JSON", help="FP16/BF16/FP32 vs FP64 storage, 3D TGV")
@@ -1099,6 +1187,9 @@ def main():
     if args.warmstart_study:
         warmstart_study(args.warmstart_study, n_train=args.ws_train, N=args.ws_n, epochs=args.ws_epochs,
                         lr=args.ws_lr, clip=args.ws_clip or None, batch=args.ws_batch)
+        return
+    if args.conv_study:
+        conv_study(args.conv_study)
         return
     if args.lattice_per_set_study:
         lattice_per_set_study(args.lattice_per_set_study)

@@ -125,6 +125,137 @@ k_conv_fwd(const uint16_t *__restrict__ x1, int c1, const uint16_t *__restrict__
             }
 }
 
+// LDS-staged implicit GEMM for the forward and data-gradient products.
+// Block: 4 waves, a 128-pixel x BN-channel output tile; wave (wm, wn) owns
+// pixels [64 wm, +64) and channels [wn BN/2, +BN/2) as 4 x (BN/32) MFMA
+// blocks of 16 x 16.  Each K step (one tap, 32 input channels) stages the
+// shifted 128 x 32 input tile and the BN x 32 weight tile in LDS, every
+// global value read once per block; the next step's global loads are
+// issued before the current step's products (double-buffered LDS, one
+// barrier per step).  Rows of the LDS tiles are 32 + 8 values long, so
+// the 16 rows one MFMA operand reads start in distinct banks.
+constexpr int kCvBM = 128;
+constexpr int kCvLd = 40;
+
+template <int BN>
+__global__ void __launch_bounds__(256)
+k_conv_fwd_lds(const uint16_t *__restrict__ x1, int c1, const uint16_t *__restrict__ x2, int c2,
+               const uint16_t *__restrict__ w, const float *__restrict__ bias, int B, int H, int W, int cout,
+               int relu, const uint16_t *__restrict__ mask, uint16_t *__restrict__ yb, float *__restrict__ yf)
+{
+    constexpr int NBW = BN / 32;                 // 16-wide channel blocks per wave
+    constexpr int BCH = BN * 4 / 256;            // 16-byte weight chunks per thread (BN >= 64)
+    __shared__ uint4 sA4[2][kCvBM * kCvLd / 8];
+    __shared__ uint4 sB4[2][BN * kCvLd / 8];
+    const int cin = c1 + c2;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int i = lane & 15, g = lane >> 4, wm = wave >> 1, wn = wave & 1;
+    const long long M = (long long)B * H * W;
+    const long long pbase = (long long)blockIdx.x * kCvBM;
+    const int co0 = blockIdx.y * BN;
+    // staging roles: input rows (2 per thread: pixel t / 4 and t / 4 + 64,
+    // channel chunk t % 4), weight rows (co = idx / 4, chunk idx % 4)
+    const int ach = t & 3;
+    int spb[2], spy[2], spx[2];
+    bool spv[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const long long p = pbase + (t >> 2) + 64 * r;
+        spv[r] = p < M;
+        const long long pp = spv[r] ? p : 0;
+        spb[r] = (int)(pp / ((long long)H * W));
+        const int rem = (int)(pp % ((long long)H * W));
+        spy[r] = rem / W;
+        spx[r] = rem % W;
+    }
+    const int nk = 9 * (cin / 32);
+    uint4 ra[2], rb[BCH > 0 ? BCH : 1];
+    auto fetch = [&](int ks) {
+        const int tap = ks / (cin / 32), c0 = (ks % (cin / 32)) * 32;
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        const uint16_t *src = (c0 < c1) ? x1 : x2;
+        const int cs = (c0 < c1) ? c1 : c2;
+        const int cc = (c0 < c1) ? c0 : c0 - c1;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int yy = spy[r] + dy, xx = spx[r] + dx;
+            ra[r] = uint4{0u, 0u, 0u, 0u};
+            if (spv[r] && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                ra[r] = *reinterpret_cast<const uint4 *>(src + (((long long)spb[r] * H + yy) * W + xx) * cs + cc +
+                                                        8 * ach);
+        }
+        if constexpr (BCH > 0) {
+#pragma unroll
+            for (int r = 0; r < BCH; ++r) {
+                const int idx = t + 256 * r;
+                const int co = co0 + (idx >> 2);
+                rb[r] = *reinterpret_cast<const uint4 *>(w + ((long long)co * 9 + tap) * cin + c0 + 8 * (idx & 3));
+            }
+        } else {
+            if (t < BN * 4) {
+                const int co = co0 + (t >> 2);
+                rb[0] = *reinterpret_cast<const uint4 *>(w + ((long long)co * 9 + tap) * cin + c0 + 8 * (t & 3));
+            }
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) sA4[buf][((t >> 2) + 64 * r) * (kCvLd / 8) + ach] = ra[r];
+        if constexpr (BCH > 0) {
+#pragma unroll
+            for (int r = 0; r < BCH; ++r) {
+                const int idx = t + 256 * r;
+                sB4[buf][(idx >> 2) * (kCvLd / 8) + (idx & 3)] = rb[r];
+            }
+        } else {
+            if (t < BN * 4) sB4[buf][(t >> 2) * (kCvLd / 8) + (t & 3)] = rb[0];
+        }
+    };
+    f32x4 acc[4][NBW];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < NBW; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int ks = 0; ks < nk; ++ks) {
+        const int buf = ks & 1;
+        if (ks + 1 < nk) fetch(ks + 1);
+        bf16x8 fa[4], fb[NBW];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+            fa[mb] = __builtin_bit_cast(bf16x8, sA4[buf][(wm * 64 + 16 * mb + i) * (kCvLd / 8) + g]);
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb)
+            fb[nb] = __builtin_bit_cast(bf16x8, sB4[buf][(wn * (BN / 2) + 16 * nb + i) * (kCvLd / 8) + g]);
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb)
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[mb], fb[nb], acc[mb][nb], 0, 0, 0);
+        if (ks + 1 < nk) stash(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const long long p = pbase + wm * 64 + 16 * mb + 4 * g + r;
+                const int co = co0 + wn * (BN / 2) + 16 * nb + i;
+                if (p >= M) continue;
+                float v = acc[mb][nb][r];
+                if (bias) v += bias[co];
+                if (relu) v = v > 0.f ? v : 0.f;
+                const long long k = p * cout + co;
+                if (mask && !(bf2f(mask[k]) > 0.f)) v = 0.f;
+                if (yb) yb[k] = f2bf(v);
+                if (yf) yf[k] = v;
+            }
+}
+
 // wt[ci][tap][co] = w[co][8 - tap][ci]
 __global__ void __launch_bounds__(256) k_flip(const uint16_t *__restrict__ w, int cout, int cin, uint16_t *__restrict__ wt)
 {
@@ -553,13 +684,16 @@ int mdfnn_conv3x3_fwd(const uint16_t *x1, int c1, const uint16_t *x2, int c2, co
     const long long M = (long long)B * H * W;
     if (M > (1LL << 31)) return MDFNN_EINVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const unsigned gx = (unsigned)((M + 127) / 128);
-    if (cout % 64 == 0)
-        hipLaunchKernelGGL(k_conv_fwd<4>, dim3(gx, cout / 64), dim3(256), 0, st, x1, c1, x2, c2, w, bias, B, H, W, cout,
-                           relu, mask, y_bf16, y_f32);
+    const unsigned gx = (unsigned)((M + kCvBM - 1) / kCvBM);
+    if (cout % 128 == 0)
+        hipLaunchKernelGGL(k_conv_fwd_lds<128>, dim3(gx, cout / 128), dim3(256), 0, st, x1, c1, x2, c2, w, bias, B, H,
+                           W, cout, relu, mask, y_bf16, y_f32);
+    else if (cout % 64 == 0)
+        hipLaunchKernelGGL(k_conv_fwd_lds<64>, dim3(gx, cout / 64), dim3(256), 0, st, x1, c1, x2, c2, w, bias, B, H, W,
+                           cout, relu, mask, y_bf16, y_f32);
     else
-        hipLaunchKernelGGL(k_conv_fwd<2>, dim3(gx, cout / 32), dim3(256), 0, st, x1, c1, x2, c2, w, bias, B, H, W, cout,
-                           relu, mask, y_bf16, y_f32);
+        hipLaunchKernelGGL(k_conv_fwd_lds<32>, dim3(gx, cout / 32), dim3(256), 0, st, x1, c1, x2, c2, w, bias, B, H, W,
+                           cout, relu, mask, y_bf16, y_f32);
     return status(hipGetLastError());
 }
 

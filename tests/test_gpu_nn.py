@@ -36,7 +36,8 @@ def _rel(ref, got):
     return float(np.linalg.norm((ref - np.asarray(got, np.float64)).ravel()) / np.linalg.norm(ref.ravel()))
 
 
-@pytest.mark.parametrize("shape", [(2, 9, 13, 32, 0, 32), (1, 17, 10, 64, 32, 64), (3, 8, 8, 32, 64, 96)])
+@pytest.mark.parametrize("shape", [(2, 9, 13, 32, 0, 32), (1, 17, 10, 64, 32, 64), (3, 8, 8, 32, 64, 96),
+                                   (2, 40, 37, 64, 64, 128), (1, 16, 16, 128, 0, 256)])
 def test_conv_forward_and_gradients(shape):
     B, H, W, c1, c2, co = shape
     _say(f"[nn] conv {shape}")

@@ -75,15 +75,23 @@ def _to16(storage, x32):
     return torch.from_numpy(x32).to(torch.bfloat16).to(torch.float32).numpy()
 
 
+def _decode(rest32, q):
+    """A stored 16-bit value q decoded as the kernels decode it: one fused
+    multiply-add f = rest + u_ref q rounded once to binary32 (the product of
+    a binary32 and a 16-bit significand, and its sum with rest, are exact in
+    binary64)."""
+    return (rest32.astype(np.float64) + np.float64(np.float32(U_REF)) * q.astype(np.float64)).astype(np.float32)
+
+
 def _on_grid(spec, storage, seed):
     """Seeded far-from-equilibrium populations moved onto the 16-bit grid:
-    f = f_rest + u_ref * q, q a 16-bit value, formed in binary32 as the
-    kernels decode a stored value."""
+    f = f_rest + u_ref * q, q a 16-bit value, formed as the kernels decode a
+    stored value."""
     f = C.random_populations(spec, seed=seed, scale=0.05)
     rest32 = _rest(spec, f.shape).astype(np.float32)
     dev32 = (f.astype(np.float32) - rest32) * np.float32(1.0 / U_REF)
     q = _to16(storage, dev32.astype(np.float32))
-    return (rest32 + np.float32(U_REF) * q).astype(np.float32)
+    return _decode(rest32, q)
 
 
 def _spacing(storage, dev):
@@ -96,8 +104,8 @@ def _spacing(storage, dev):
 
 def _stored(solver, spec, storage, case=0):
     """The post-collision populations f*(t) as stored (raw 16-bit values of
-    population buffer 0), decoded in binary32 like the kernels, [set][dir] +
-    field shape."""
+    population buffer 0), decoded like the kernels, [set][dir] + field
+    shape."""
     raw = solver.population_buffer(0, case).view(torch.int16)
     nz = spec.shape[2] if spec.d == 3 else 1
     ny, nx = spec.shape[1], spec.shape[0]
@@ -107,7 +115,7 @@ def _stored(solver, spec, storage, case=0):
     q = raw.view(dt).to(torch.float32).cpu().numpy()
     rest32 = _rest(spec, (solver.nsets, spec.q) + (1,) * (spec.d)).astype(np.float32)
     rest32 = rest32.reshape((solver.nsets, spec.q) + (1,) * 3)
-    val = (rest32 + np.float32(U_REF) * q).astype(np.float64)
+    val = _decode(np.broadcast_to(rest32, q.shape), q).astype(np.float64)
     return val.reshape((solver.nsets, spec.q) + spec.fshape)
 
 
