@@ -8,9 +8,10 @@
 // accumulation).  For that instruction lane l of a wave holds
 //   A[l % 16][8 (l / 16) + j], B[8 (l / 16) + j][l % 16]   (j = 0..7)
 //   C[4 (l / 16) + r][l % 16]                              (r = 0..3).
-// Activations are NHWC, so one K step of 32 (one tap, 32 consecutive
-// channels) is a single 16-byte load per lane for both operands of the
-// forward product; the weight gradient stages pixel tiles through LDS.
+// Activations are NHWC, so one K step of 32 of the forward product (one
+// tap, 32 consecutive channels) is one 16-byte chunk per pixel and weight
+// row, staged through LDS as [row][32 channels]; the weight gradient, whose
+// K steps are 32 pixels, stages its tiles transposed ([channel][pixel]).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -48,83 +49,6 @@ __device__ __forceinline__ bf16x8 zero8()
 
 // ------------------------------------------------------------------ conv fwd
 
-// Block: 4 waves, 128 pixels x (16 NB) output channels; wave w owns pixels
-// [32 w, 32 w + 32) of the block as two 16-row MFMA blocks.
-template <int NB>
-__global__ void __launch_bounds__(256)
-k_conv_fwd(const uint16_t *__restrict__ x1, int c1, const uint16_t *__restrict__ x2, int c2,
-           const uint16_t *__restrict__ w, const float *__restrict__ bias, int B, int H, int W, int cout,
-           int relu, const uint16_t *__restrict__ mask, uint16_t *__restrict__ yb, float *__restrict__ yf)
-{
-    const int cin = c1 + c2;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i = lane & 15, g = lane >> 4;
-    const long long M = (long long)B * H * W;
-    const long long p0 = (long long)blockIdx.x * 128 + wave * 32;
-    const int co0 = blockIdx.y * (16 * NB);
-    int pbb[2], py[2], px[2];
-    bool pv[2];
-#pragma unroll
-    for (int pb = 0; pb < 2; ++pb) {
-        const long long p = p0 + 16 * pb + i;
-        pv[pb] = p < M;
-        const long long pp = pv[pb] ? p : 0;
-        pbb[pb] = (int)(pp / ((long long)H * W));
-        const int r = (int)(pp % ((long long)H * W));
-        py[pb] = r / W;
-        px[pb] = r % W;
-    }
-    f32x4 acc[2][NB];
-#pragma unroll
-    for (int pb = 0; pb < 2; ++pb)
-#pragma unroll
-        for (int cb = 0; cb < NB; ++cb) acc[pb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int tap = 0; tap < 9; ++tap) {
-        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-        long long off[2];
-        bool in[2];
-#pragma unroll
-        for (int pb = 0; pb < 2; ++pb) {
-            const int yy = py[pb] + dy, xx = px[pb] + dx;
-            in[pb] = pv[pb] && yy >= 0 && yy < H && xx >= 0 && xx < W;
-            off[pb] = in[pb] ? (((long long)pbb[pb] * H + yy) * W + xx) : 0;
-        }
-        for (int c0 = 0; c0 < cin; c0 += 32) {
-            const uint16_t *src = (c0 < c1) ? x1 : x2;
-            const int cs = (c0 < c1) ? c1 : c2;
-            const int cc = (c0 < c1) ? c0 : c0 - c1;
-            bf16x8 a[2];
-#pragma unroll
-            for (int pb = 0; pb < 2; ++pb) a[pb] = in[pb] ? load8(src + off[pb] * cs + cc + 8 * g) : zero8();
-#pragma unroll
-            for (int cb = 0; cb < NB; ++cb) {
-                const int co = co0 + 16 * cb + i;
-                const bf16x8 b = load8(w + ((long long)co * 9 + tap) * cin + c0 + 8 * g);
-#pragma unroll
-                for (int pb = 0; pb < 2; ++pb)
-                    acc[pb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[pb], b, acc[pb][cb], 0, 0, 0);
-            }
-        }
-    }
-#pragma unroll
-    for (int pb = 0; pb < 2; ++pb)
-#pragma unroll
-        for (int cb = 0; cb < NB; ++cb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const long long p = p0 + 16 * pb + 4 * g + r;
-                const int co = co0 + 16 * cb + i;
-                if (p >= M) continue;
-                float v = acc[pb][cb][r];
-                if (bias) v += bias[co];
-                if (relu) v = v > 0.f ? v : 0.f;
-                const long long k = p * cout + co;
-                if (mask && !(bf2f(mask[k]) > 0.f)) v = 0.f;
-                if (yb) yb[k] = f2bf(v);
-                if (yf) yf[k] = v;
-            }
-}
-
 // LDS-staged implicit GEMM for the forward and data-gradient products.
 // Block: 4 waves, a 128-pixel x BN-channel output tile; wave (wm, wn) owns
 // pixels [64 wm, +64) and channels [wn BN/2, +BN/2) as 4 x (BN/32) MFMA
@@ -144,7 +68,6 @@ k_conv_fwd_lds(const uint16_t *__restrict__ x1, int c1, const uint16_t *__restri
                int relu, const uint16_t *__restrict__ mask, uint16_t *__restrict__ yb, float *__restrict__ yf)
 {
     constexpr int NBW = BN / 32;                 // 16-wide channel blocks per wave
-    constexpr int BCH = BN * 4 / 256;            // 16-byte weight chunks per thread (BN >= 64)
     __shared__ uint4 sA4[2][kCvBM * kCvLd / 8];
     __shared__ uint4 sB4[2][BN * kCvLd / 8];
     const int cin = c1 + c2;
@@ -169,8 +92,8 @@ k_conv_fwd_lds(const uint16_t *__restrict__ x1, int c1, const uint16_t *__restri
         spx[r] = rem % W;
     }
     const int nk = 9 * (cin / 32);
-    uint4 ra[2], rb[BCH > 0 ? BCH : 1];
-    auto fetch = [&](int ks) {
+    uint4 ra[2], rb0 = uint4{0u, 0u, 0u, 0u}, rb1 = uint4{0u, 0u, 0u, 0u};
+    auto fetch = [&](int ks) __attribute__((always_inline)) {
         const int tap = ks / (cin / 32), c0 = (ks % (cin / 32)) * 32;
         const int dy = tap / 3 - 1, dx = tap % 3 - 1;
         const uint16_t *src = (c0 < c1) ? x1 : x2;
@@ -184,32 +107,16 @@ k_conv_fwd_lds(const uint16_t *__restrict__ x1, int c1, const uint16_t *__restri
                 ra[r] = *reinterpret_cast<const uint4 *>(src + (((long long)spb[r] * H + yy) * W + xx) * cs + cc +
                                                         8 * ach);
         }
-        if constexpr (BCH > 0) {
-#pragma unroll
-            for (int r = 0; r < BCH; ++r) {
-                const int idx = t + 256 * r;
-                const int co = co0 + (idx >> 2);
-                rb[r] = *reinterpret_cast<const uint4 *>(w + ((long long)co * 9 + tap) * cin + c0 + 8 * (idx & 3));
-            }
-        } else {
-            if (t < BN * 4) {
-                const int co = co0 + (t >> 2);
-                rb[0] = *reinterpret_cast<const uint4 *>(w + ((long long)co * 9 + tap) * cin + c0 + 8 * (t & 3));
-            }
-        }
+        const uint16_t *wk = w + (long long)tap * cin + c0 + 8 * (t & 3);
+        if (BN * 4 >= 256 || t < BN * 4) rb0 = *reinterpret_cast<const uint4 *>(wk + (long long)(co0 + (t >> 2)) * 9 * cin);
+        if constexpr (BN * 4 > 256)
+            rb1 = *reinterpret_cast<const uint4 *>(wk + (long long)(co0 + 64 + (t >> 2)) * 9 * cin);
     };
-    auto stash = [&](int buf) {
+    auto stash = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
         for (int r = 0; r < 2; ++r) sA4[buf][((t >> 2) + 64 * r) * (kCvLd / 8) + ach] = ra[r];
-        if constexpr (BCH > 0) {
-#pragma unroll
-            for (int r = 0; r < BCH; ++r) {
-                const int idx = t + 256 * r;
-                sB4[buf][(idx >> 2) * (kCvLd / 8) + (idx & 3)] = rb[r];
-            }
-        } else {
-            if (t < BN * 4) sB4[buf][(t >> 2) * (kCvLd / 8) + (t & 3)] = rb[0];
-        }
+        if (BN * 4 >= 256 || t < BN * 4) sB4[buf][(t >> 2) * (kCvLd / 8) + (t & 3)] = rb0;
+        if constexpr (BN * 4 > 256) sB4[buf][(64 + (t >> 2)) * (kCvLd / 8) + (t & 3)] = rb1;
     };
     f32x4 acc[4][NBW];
 #pragma unroll
@@ -270,135 +177,176 @@ __global__ void __launch_bounds__(256) k_flip(const uint16_t *__restrict__ w, in
 
 // ------------------------------------------------------------------ weight grad
 
-// Block: 4 waves, an MT (cout) x NT (cin) tile of one tap over a contiguous
-// range of pixels; partial sums per pixel range go to scratch and are summed
-// in a fixed order by k_wgrad_reduce.  Wave (wm, wn) owns rows
-// [wm MT/2, +MT/2) and columns [wn NT/2, +NT/2), as (MT/32) x (NT/32) MFMA
-// blocks of 16 x 16.  MT, NT in {32, 64}.
-constexpr int kWgSplitMax = 64;
+constexpr int kWgBlocks = 1024;    // target blocks of one weight-gradient launch
 
+// Weight gradient with all nine taps in one block.  The K dimension (pixels)
+// is walked in segments of 32 consecutive pixels of one image row; per
+// segment the block stages, transposed to [channel][pixel] in LDS so that
+// every MFMA operand is one 16-byte read, the output-gradient row segment
+// (MT channels) once and the input window of rows y-1..y+1 (NT channels)
+// in three copies shifted by dx = -1, 0, +1, and takes the products of all
+// nine taps from them: each dy value is read from global memory once per
+// block instead of once per tap.  Wave (wm, wn) owns channels
+// [wm MT/2, +MT/2) x [wn NT/2, +NT/2) of every tap.  Pixels beyond the row
+// end contribute zero (their dy is staged as zero); input pixels outside the
+// image are zero.  Segments [s0, s1) of split blockIdx.z; partial sums per
+// split are reduced in a fixed order by k_wgrad_reduce.
 template <int MT, int NT>
 __global__ void __launch_bounds__(256)
-k_conv_wgrad(const uint16_t *__restrict__ x1, int c1, const uint16_t *__restrict__ x2, int c2,
-             const uint16_t *__restrict__ dyp, int B, int H, int W, int cout, int nsplit,
-             float *__restrict__ partial)
+k_conv_wgrad9(const uint16_t *__restrict__ x1, int c1, const uint16_t *__restrict__ x2, int c2,
+              const uint16_t *__restrict__ dyp, int B, int H, int W, int cout, int nsplit,
+              float *__restrict__ partial, float *__restrict__ bpart)
 {
     constexpr int MB = MT / 32, NB = NT / 32;
-    __shared__ uint16_t sA[32][MT + 8];     // dy tile  [pixel][co]
-    __shared__ uint16_t sB[32][NT + 8];     // x tile   [pixel][ci]
+    constexpr int LD = 40;                              // row: 32 pixels + 8 pad
+    constexpr int NDY = 32 * MT / 8;                    // 16-byte dy chunks per segment
+    constexpr int NX = 3 * 34 * NT / 8;                 // 16-byte input chunks per window
+    constexpr int KX = (NX + 255) / 256;
+    __shared__ uint16_t ys[MT * LD];
+    __shared__ uint16_t xw[9 * NT * LD];                // [dx + 1][row][ci][pixel]
     const int cin = c1 + c2;
-    const int nci = cin / NT;
-    const int co0 = blockIdx.x * MT;
-    const int tap = blockIdx.y / nci, ci0 = (blockIdx.y % nci) * NT;
-    const int split = blockIdx.z;
-    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-    const long long M = (long long)B * H * W;
-    const long long per = (M + nsplit - 1) / nsplit;
-    const long long k0 = split * per, k1 = (k0 + per < M) ? k0 + per : M;
+    const int co0 = blockIdx.x * MT, ci0 = blockIdx.y * NT;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int i = lane & 15, g = lane >> 4, wm = wave >> 1, wn = wave & 1;
     const uint16_t *src = (ci0 < c1) ? x1 : x2;
     const int cs = (ci0 < c1) ? c1 : c2;
     const int cc = (ci0 < c1) ? ci0 : ci0 - c1;
-    f32x4 acc[MB][NB];
+    const int S = (W + 31) / 32;                        // segments per image row
+    const long long nseg = (long long)B * H * S;
+    const long long per = (nseg + nsplit - 1) / nsplit;
+    const long long s0 = blockIdx.z * per, s1 = (s0 + per < nseg) ? s0 + per : nseg;
+    f32x4 acc[9][MB][NB];
 #pragma unroll
-    for (int a = 0; a < MB; ++a)
+    for (int k = 0; k < 9; ++k)
 #pragma unroll
-        for (int b = 0; b < NB; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (long long kb = k0; kb < k1; kb += 32) {
-        // dy tile: 32 pixels x MT channels, 8 channels per load
-        for (int idx = t; idx < 32 * (MT / 8); idx += 256) {
-            const int lp = idx / (MT / 8), lc = (idx % (MT / 8)) * 8;
-            const long long p = kb + lp;
-            uint4 va = {0u, 0u, 0u, 0u};
-            if (p < k1) va = *reinterpret_cast<const uint4 *>(dyp + p * cout + co0 + lc);
-            const uint16_t *ua = reinterpret_cast<const uint16_t *>(&va);
+        for (int a = 0; a < MB; ++a)
 #pragma unroll
-            for (int j = 0; j < 8; ++j) sA[lp][lc + j] = ua[j];
+            for (int b = 0; b < NB; ++b) acc[k][a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    uint4 rdy, rx[KX];
+    // bias gradient (blocks of the first input-channel tile): the thread that
+    // stages dy chunk (pixel j, channels 8 c8 ..) sums those channels over the
+    // block's segments; the 32 pixel slots are added in order at the end
+    const bool bias = bpart != nullptr && blockIdx.y == 0;
+    float bacc[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) bacc[e] = 0.f;
+    auto fetch = [&](long long sg) __attribute__((always_inline)) {
+        const int xs = (int)(sg % S) * 32;
+        const long long row = sg / S;                   // b * H + y
+        const int y = (int)(row % H);
+        rdy = uint4{0u, 0u, 0u, 0u};
+        if (t < NDY) {
+            const int j = t / (MT / 8), c8 = t % (MT / 8);
+            if (xs + j < W) rdy = *reinterpret_cast<const uint4 *>(dyp + (row * W + xs + j) * cout + co0 + 8 * c8);
         }
-        // shifted input tile: 32 pixels x NT channels
-        for (int idx = t; idx < 32 * (NT / 8); idx += 256) {
-            const int lp = idx / (NT / 8), lc = (idx % (NT / 8)) * 8;
-            const long long p = kb + lp;
-            uint4 vb = {0u, 0u, 0u, 0u};
-            if (p < k1) {
-                const int b = (int)(p / ((long long)H * W));
-                const int r = (int)(p % ((long long)H * W));
-                const int yy = r / W + dy, xx = r % W + dx;
+#pragma unroll
+        for (int r = 0; r < KX; ++r) {
+            const int idx = t + 256 * r;
+            rx[r] = uint4{0u, 0u, 0u, 0u};
+            if (idx < NX) {
+                const int wr = idx / (34 * NT / 8), rem = idx % (34 * NT / 8);
+                const int c = rem / (NT / 8), c8 = rem % (NT / 8);
+                const int yy = y - 1 + wr, xx = xs - 1 + c;
                 if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                    vb = *reinterpret_cast<const uint4 *>(src + (((long long)b * H + yy) * W + xx) * cs + cc + lc);
+                    rx[r] = *reinterpret_cast<const uint4 *>(src + ((row - y + yy) * W + xx) * cs + cc + 8 * c8);
             }
-            const uint16_t *ub = reinterpret_cast<const uint16_t *>(&vb);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) sB[lp][lc + j] = ub[j];
         }
+    };
+    auto stash = [&]() __attribute__((always_inline)) {
+        if (t < NDY) {
+            const int j = t / (MT / 8), c8 = t % (MT / 8);
+            const uint16_t *u = reinterpret_cast<const uint16_t *>(&rdy);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) ys[(8 * c8 + e) * LD + j] = u[e];
+            if (bias) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) bacc[e] += bf2f(u[e]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < KX; ++r) {
+            const int idx = t + 256 * r;
+            if (idx >= NX) continue;
+            const int wr = idx / (34 * NT / 8), rem = idx % (34 * NT / 8);
+            const int c = rem / (NT / 8), c8 = rem % (NT / 8);
+            const uint16_t *u = reinterpret_cast<const uint16_t *>(&rx[r]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {               // copy d holds x[xs + j + d - 1]
+                const int j = c + 1 - d - 1 + 0;        // pixel c of the window is xs - 1 + c
+                if (j < 0 || j >= 32) continue;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) xw[((d * 3 + wr) * NT + 8 * c8 + e) * LD + j] = u[e];
+            }
+        }
+    };
+    if (s0 < s1) fetch(s0);
+    for (long long sg = s0; sg < s1; ++sg) {
+        __syncthreads();                                // the previous segment's reads are done
+        stash();
         __syncthreads();
-        bf16x8 fa[MB], fb[NB];
+        if (sg + 1 < s1) fetch(sg + 1);
+        bf16x8 fa[MB];
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            uint16_t tmp[8];
+        for (int mb = 0; mb < MB; ++mb)
+            fa[mb] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(&ys[(wm * (MT / 2) + 16 * mb + i) * LD + 8 * g]));
 #pragma unroll
-            for (int j = 0; j < 8; ++j) tmp[j] = sA[8 * g + j][wm * (MT / 2) + 16 * mb + i];
-            fa[mb] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(tmp));
+        for (int tap = 0; tap < 9; ++tap) {
+            const int wr = tap / 3, d = tap % 3;        // dy = wr - 1, dx = d - 1
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const bf16x8 fb = __builtin_bit_cast(
+                    bf16x8, *reinterpret_cast<const uint4 *>(&xw[((d * 3 + wr) * NT + wn * (NT / 2) + 16 * nb + i) * LD + 8 * g]));
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+                    acc[tap][mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[mb], fb, acc[tap][mb][nb], 0, 0, 0);
+            }
         }
+    }
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            uint16_t tmp[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) tmp[j] = sB[8 * g + j][wn * (NT / 2) + 16 * nb + i];
-            fb[nb] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(tmp));
-        }
+    for (int tap = 0; tap < 9; ++tap)
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb)
-                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[mb], fb[nb], acc[mb][nb], 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int co = co0 + wm * (MT / 2) + 16 * mb + 4 * g + r;
+                    const int ci = ci0 + wn * (NT / 2) + 16 * nb + i;
+                    partial[(((long long)blockIdx.z * cout + co) * 9 + tap) * cin + ci] = acc[tap][mb][nb][r];
+                }
+    if (bias) {
+        __syncthreads();                                // xw is free: reuse it as [pixel slot][co] floats
+        float *red = reinterpret_cast<float *>(xw);
+        static_assert(32 * MT * sizeof(float) <= sizeof(xw), "bias slots fit the input window");
+        if (t < NDY) {
+            const int j = t / (MT / 8), c8 = t % (MT / 8);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) red[j * MT + 8 * c8 + e] = bacc[e];
+        }
         __syncthreads();
+        if (t < MT) {
+            float sum = 0.f;
+            for (int j = 0; j < 32; ++j) sum += red[j * MT + t];
+            bpart[(long long)blockIdx.z * cout + co0 + t] = sum;
+        }
     }
-    // partial[split][co][tap][ci]
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int co = co0 + wm * (MT / 2) + 16 * mb + 4 * g + r;
-                const int ci = ci0 + wn * (NT / 2) + 16 * nb + i;
-                partial[(((long long)split * cout + co) * 9 + tap) * cin + ci] = acc[mb][nb][r];
-            }
 }
 
+// Sums of split partials: out[g][k] = sum of partial[sp][k] over the splits
+// sp of group g = blockIdx.y ([g chunk, (g + 1) chunk)), added in split
+// order.  One group (chunk >= nsplit) gives the final sums; with several, a
+// second pass over the group sums adds them in group order, so the result
+// is the same fixed-order sum whatever the launch.
 __global__ void __launch_bounds__(256)
-k_wgrad_reduce(const float *__restrict__ partial, long long n, int nsplit, float *__restrict__ dw)
+k_wgrad_reduce(const float *__restrict__ partial, long long n, int nsplit, int chunk, float *__restrict__ out)
 {
+    const int g = blockIdx.y;
+    const int sp0 = g * chunk, sp1 = (sp0 + chunk < nsplit) ? sp0 + chunk : nsplit;
     for (long long k = blockIdx.x * 256LL + threadIdx.x; k < n; k += (long long)gridDim.x * 256) {
         float s = 0.f;
-        for (int sp = 0; sp < nsplit; ++sp) s += partial[sp * n + k];
-        dw[k] = s;
+        for (int sp = sp0; sp < sp1; ++sp) s += partial[sp * n + k];
+        out[g * n + k] = s;
     }
-}
-
-// Column sums of a bf16 [P][C] matrix: partial[block][c], then fixed-order sum.
-__global__ void __launch_bounds__(256)
-k_colsum_partial(const uint16_t *__restrict__ x, long long P, int C, int rows_per_block, float *__restrict__ partial)
-{
-    const long long r0 = (long long)blockIdx.x * rows_per_block;
-    const long long r1 = (r0 + rows_per_block < P) ? r0 + rows_per_block : P;
-    for (int c = threadIdx.x; c < C; c += 256) {
-        float s = 0.f;
-        for (long long r = r0; r < r1; ++r) s += bf2f(x[r * C + c]);
-        partial[(long long)blockIdx.x * C + c] = s;
-    }
-}
-
-__global__ void __launch_bounds__(256)
-k_colsum_reduce(const float *__restrict__ partial, int nblk, int C, float *__restrict__ out)
-{
-    const int c = blockIdx.x * 256 + threadIdx.x;
-    if (c >= C) return;
-    float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += partial[(long long)b * C + c];
-    out[c] = s;
 }
 
 // ------------------------------------------------------------------ elementwise
@@ -705,23 +653,48 @@ int mdfnn_conv3x3_flip(const uint16_t *w, int cout, int cin, uint16_t *wt, void 
     return status(hipGetLastError());
 }
 
-static int wgrad_splits(long long M)
+// Channel tiles of the weight gradient: MT output x NT input channels; a
+// tile of input channels must not straddle x1 and x2.
+static int wgrad_mt(int cout) { return (cout % 64 == 0) ? 64 : 32; }
+static int wgrad_nt(int c1, int c2) { return (c1 % 64 == 0 && c2 % 64 == 0) ? 64 : 32; }
+
+// Splits of the pixel segments (32 pixels of one image row each): about 1024
+// blocks over the channel tiles, at least 8 segments per split.
+static int wgrad_splits(int B, int H, int W, int ntiles)
 {
-    long long s = (M + 4095) / 4096;
-    if (s > kWgSplitMax) s = kWgSplitMax;
+    const long long nseg = (long long)B * H * ((W + 31) / 32);
+    long long s = (kWgBlocks + ntiles - 1) / ntiles;
+    if (s > nseg / 8) s = nseg / 8;
     if (s < 1) s = 1;
     return (int)s;
 }
 
+// Splits per group of the first reduction pass.
+constexpr int kWgChunk = 32;
+
+// Fixed-order sum over ns split partials of n values each (two passes when
+// ns > kWgChunk, through mid: ceil(ns / kWgChunk) * n floats).
+static hipError_t reduce_splits(const float *partial, long long n, int ns, float *mid, float *out, hipStream_t st)
+{
+    if (ns <= kWgChunk) {
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3(grid1(n), 1), dim3(256), 0, st, partial, n, ns, ns, out);
+        return hipGetLastError();
+    }
+    const int G = (ns + kWgChunk - 1) / kWgChunk;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(grid1(n), G), dim3(256), 0, st, partial, n, ns, kWgChunk, mid);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(grid1(n), 1), dim3(256), 0, st, mid, n, G, G, out);
+    return hipGetLastError();
+}
+
 size_t mdfnn_wgrad_scratch_bytes(int B, int H, int W, int cin, int cout)
 {
-    const long long M = (long long)B * H * W;
-    const int ns = wgrad_splits(M);
-    const size_t wpart = (size_t)ns * cout * 9 * cin * sizeof(float);
-    const int rows = 1024;
-    const size_t nblk = (size_t)((M + rows - 1) / rows);
-    const size_t bpart = nblk * cout * sizeof(float);
-    return wpart + bpart + 256;
+    if (B < 1 || H < 1 || W < 1 || cin < 32 || cout < 32) return 0;
+    // the smallest tiles give the most splits
+    const int ns = wgrad_splits(B, H, W, (cout / 64 > 0 ? cout / 64 : 1) * (cin / 64 > 0 ? cin / 64 : 1));
+    const size_t G = (size_t)(ns + kWgChunk - 1) / kWgChunk;
+    const size_t n = (size_t)cout * 9 * cin;
+    // weight and bias partials, then the group sums of both
+    return ((size_t)ns * (n + cout) + G * (n + cout)) * sizeof(float) + 256;
 }
 
 int mdfnn_conv3x3_wgrad(const uint16_t *x1, int c1, const uint16_t *x2, int c2, const uint16_t *dy, int B, int H,
@@ -730,36 +703,31 @@ int mdfnn_conv3x3_wgrad(const uint16_t *x1, int c1, const uint16_t *x2, int c2, 
     if (!x1 || !dy || !dw || !scratch || B < 1 || H < 1 || W < 1) return MDFNN_EINVAL;
     const int cin = c1 + c2;
     if (c1 < 32 || c1 % 32 || c2 < 0 || c2 % 32 || (c2 > 0 && !x2) || cout < 32 || cout % 32) return MDFNN_EINVAL;
-    const long long M = (long long)B * H * W;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int ns = wgrad_splits(M);
+    const int mt = wgrad_mt(cout), nt = wgrad_nt(c1, c2);
+    const int ns = wgrad_splits(B, H, W, (cout / mt) * (cin / nt));
     float *wpart = static_cast<float *>(scratch);
-    // a cin tile must not straddle x1 and x2: 64-wide tiles need c1 % 64 == 0
-    const int mt = (cout % 64 == 0) ? 64 : 32;
-    const int nt = (c1 % 64 == 0 && c2 % 64 == 0) ? 64 : 32;
-    const dim3 grid(cout / mt, 9 * (cin / nt), ns);
+    float *bpart = db ? wpart + (size_t)ns * cout * 9 * cin : nullptr;
+    const dim3 grid(cout / mt, cin / nt, ns);
     if (mt == 64 && nt == 64)
-        hipLaunchKernelGGL((k_conv_wgrad<64, 64>), grid, dim3(256), 0, st, x1, c1, x2, c2, dy, B, H, W, cout, ns, wpart);
+        hipLaunchKernelGGL((k_conv_wgrad9<64, 64>), grid, dim3(256), 0, st, x1, c1, x2, c2, dy, B, H, W, cout, ns, wpart,
+                           bpart);
     else if (mt == 64)
-        hipLaunchKernelGGL((k_conv_wgrad<64, 32>), grid, dim3(256), 0, st, x1, c1, x2, c2, dy, B, H, W, cout, ns, wpart);
+        hipLaunchKernelGGL((k_conv_wgrad9<64, 32>), grid, dim3(256), 0, st, x1, c1, x2, c2, dy, B, H, W, cout, ns, wpart,
+                           bpart);
     else if (nt == 64)
-        hipLaunchKernelGGL((k_conv_wgrad<32, 64>), grid, dim3(256), 0, st, x1, c1, x2, c2, dy, B, H, W, cout, ns, wpart);
+        hipLaunchKernelGGL((k_conv_wgrad9<32, 64>), grid, dim3(256), 0, st, x1, c1, x2, c2, dy, B, H, W, cout, ns, wpart,
+                           bpart);
     else
-        hipLaunchKernelGGL((k_conv_wgrad<32, 32>), grid, dim3(256), 0, st, x1, c1, x2, c2, dy, B, H, W, cout, ns, wpart);
+        hipLaunchKernelGGL((k_conv_wgrad9<32, 32>), grid, dim3(256), 0, st, x1, c1, x2, c2, dy, B, H, W, cout, ns, wpart,
+                           bpart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return MDFNN_EDEVICE;
     const long long n = (long long)cout * 9 * cin;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(grid1(n)), dim3(256), 0, st, wpart, n, ns, dw);
-    e = hipGetLastError();
+    float *mid = wpart + (size_t)ns * (n + cout);
+    e = reduce_splits(wpart, n, ns, mid, dw, st);
     if (e != hipSuccess) return MDFNN_EDEVICE;
-    if (db) {
-        const int rows = 1024;
-        const int nblk = (int)((M + rows - 1) / rows);
-        float *bpart = wpart + (size_t)ns * cout * 9 * cin;
-        hipLaunchKernelGGL(k_colsum_partial, dim3(nblk), dim3(256), 0, st, dy, M, cout, rows, bpart);
-        hipLaunchKernelGGL(k_colsum_reduce, dim3((cout + 255) / 256), dim3(256), 0, st, bpart, nblk, cout, db);
-        e = hipGetLastError();
-    }
+    if (db) e = reduce_splits(bpart, cout, ns, mid + (size_t)((ns + kWgChunk - 1) / kWgChunk) * n, db, st);
     return status(e);
 }
 
