@@ -799,24 +799,49 @@ __device__ __forceinline__ void nonequilibrium(const Node<L, C> &n, const Moment
 // last moving population K takes that identity in the same way: in exact
 // arithmetic its value is unchanged, and in FP32 the zeroth moment does not
 // inherit the rounding of w = 1/6 (D3Q6) every step.
+// The update is taken per pair of opposite directions (i, j = opp(i)), which
+// share their weight and the even part of the equilibrium and have opposite
+// odd parts:
+//   f^eq_{i,j} = w ubar +- (w / cs^2) c_i . flux                     (eq. 2-4)
+//   n_i - n_j = (f_i - f_j) - 2 (w / cs^2) c_i . flux  (odd part of n)
+//   n_i + n_j = (f_i + f_j) - 2 w ubar                 (even part of n)
+//   d_{i,j} = w Fbar' - (s2/2)(n_i + n_j) -+ (s1/2)(n_i - n_j)
+// (Fbar' = Fbar, or (1 - s2/2) Fbar under Scheme II), and the rest
+// population (or K) closes the zeroth moment as above.  The equilibrium is
+// never formed per population, which halves the arithmetic of forming f^eq,
+// n = f - f^eq and the relaxation one population at a time.
 template <class L, class C>
-__device__ __forceinline__ void collide_set(const KCase &p, const Node<L, C> &n, int a,
-                                            const C (&ne)[L::Q], C (&out)[L::Q], C fb)
+__device__ __forceinline__ void collide_fused(const KCase &p, const Node<L, C> &n, const Moments<L, C> &m, int a,
+                                              C (&out)[L::Q], C fb)
 {
-    const C s1 = kpar<C>(p.s1, p.s1f), s2 = kpar<C>(p.s2, p.s2f);
     const int pa = a + L::A0;
+    const C ub = m.ubar[pa];
+    C flux[L::D];
+#pragma unroll
+    for (int b = 0; b < L::D; ++b) flux[b] = ub * m.u[b] + ((pa >= 1 && b == pa - 1) ? m.P : C(0));
+    const C s1h = C(0.5) * kpar<C>(p.s1, p.s1f), s2h = C(0.5) * kpar<C>(p.s2, p.s2f);
+    const C fm = fb * kpar<C>(p.fmove, p.fmovef);
     C dsum = C(0);
 #pragma unroll
     for (int i = L::R; i < L::Q; ++i) {
-        if (i == L::K) continue;
-        if (i >= qset<L>(pa)) { out[i] = C(0); continue; }
-        const C wf = C(wset<L>(pa, i)) * fb * kpar<C>(p.fmove, p.fmovef);
         const int j = L::opp[i];
-        const C odd = C(0.5) * (ne[i] - ne[j]);
-        const C even = C(0.5) * (ne[i] + ne[j]);
-        const C d = (-s1 * odd - s2 * even) + wf;
-        out[i] = n.f[a][i] + d;
-        dsum += d;
+        if (j < i) continue;                       // each pair once
+        if (i >= qset<L>(pa)) { out[i] = C(0); out[j] = C(0); continue; }
+        C cf = C(0);
+#pragma unroll
+        for (int b = 0; b < L::D; ++b) {
+            if (cdir<L>(i, b) > 0) cf += flux[b];
+            else if (cdir<L>(i, b) < 0) cf -= flux[b];
+        }
+        const C w = C(wset<L>(pa, i));
+        const C odd2 = C(2.0 * wset<L>(pa, i) * inv_cs2_set<L>(pa)) * cf;     // 2 (w / cs^2) c_i . flux
+        const C even2 = C(2) * w * ub;                                        // 2 w ubar
+        const C nodd = (n.f[a][i] - n.f[a][j]) - odd2;
+        const C neven = (n.f[a][i] + n.f[a][j]) - even2;
+        const C base = w * fm - s2h * neven;
+        const C di = base - s1h * nodd, dj = base + s1h * nodd;
+        if (i != L::K) { out[i] = n.f[a][i] + di; dsum += di; }
+        if (j != L::K) { out[j] = n.f[a][j] + dj; dsum += dj; }
     }
     out[L::K] = n.f[a][L::K] + (fb - dsum);
 }
@@ -987,9 +1012,8 @@ __device__ __forceinline__ void step_tile(const KCase &p, int gx, int gy, int ti
         const auto own = grid_ix<WIDE>(x, y, z, p.ny, p.pitch);
 #pragma unroll
         for (int a = 0; a < L::NS; ++a) {
-            C ne[L::Q], fo[L::Q];
-            nonequilibrium<L, C>(n, m, a, ne);
-            collide_set<L, C>(p, n, a, ne, fo, m.fb[a + L::A0]);
+            C fo[L::Q];
+            collide_fused<L, C>(p, n, m, a, fo, m.fb[a + L::A0]);
 #pragma unroll
             for (int i = 0; i < L::Q; ++i) {
                 if (i >= qset<L>(a + L::A0)) continue;
@@ -1080,9 +1104,8 @@ __device__ __forceinline__ void step_tile_vec(const KCase &p, int gx, int gy, in
 #pragma unroll
         for (int v = 0; v < VX; ++v) {
             if (!fluid[v]) continue;
-            C ne[L::Q], fo[L::Q];
-            nonequilibrium<L, C>(n[v], m[v], a, ne);
-            collide_set<L, C>(p, n[v], a, ne, fo, m[v].fb[a + L::A0]);
+            C fo[L::Q];
+            collide_fused<L, C>(p, n[v], m[v], a, fo, m[v].fb[a + L::A0]);
 #pragma unroll
             for (int i = 0; i < L::Q; ++i) n[v].f[a][i] = fo[i];
         }
@@ -1238,9 +1261,8 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int gy, int t
             moments<L, C>(p, n[g], m);
 #pragma unroll
             for (int a = 0; a < L::NS; ++a) {
-                C ne[L::Q], fo[L::Q];
-                nonequilibrium<L, C>(n[g], m, a, ne);
-                collide_set<L, C>(p, n[g], a, ne, fo, m.fb[a + L::A0]);
+                C fo[L::Q];
+                collide_fused<L, C>(p, n[g], m, a, fo, m.fb[a + L::A0]);
 #pragma unroll
                 for (int i = 0; i < L::Q; ++i)
                     lds[(a * L::Q + i) * NE + e] = S::encode(fo[i], rest_value<L, C>(p, a, i), p.inv_scale);
@@ -1313,9 +1335,8 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int gy, int t
         if (EMIT) write_fields<L, C>(p, n, m, fields, out, node, nodes);
 #pragma unroll
         for (int a = 0; a < L::NS; ++a) {
-            C ne[L::Q], fo[L::Q];
-            nonequilibrium<L, C>(n, m, a, ne);
-            collide_set<L, C>(p, n, a, ne, fo, m.fb[a + L::A0]);
+            C fo[L::Q];
+            collide_fused<L, C>(p, n, m, a, fo, m.fb[a + L::A0]);
 #pragma unroll
             for (int i = 0; i < L::Q; ++i) {
                 if (i >= qset<L>(a + L::A0)) continue;
@@ -1496,9 +1517,8 @@ __device__ __forceinline__ void step2z_plane1(const KCase &p, const typename Sto
         moments<L, C>(p, n[g], m);
 #pragma unroll
         for (int a = 0; a < L::NS; ++a) {
-            C ne[L::Q], fo[L::Q];
-            nonequilibrium<L, C>(n[g], m, a, ne);
-            collide_set<L, C>(p, n[g], a, ne, fo, m.fb[a + L::A0]);
+            C fo[L::Q];
+            collide_fused<L, C>(p, n[g], m, a, fo, m.fb[a + L::A0]);
             if (e < NI) {
                 if (KEEP == kZKeepAll) {
 #pragma unroll
@@ -1641,9 +1661,8 @@ __device__ __forceinline__ void step2z_plane2(const KCase &p, typename Store<ST>
     if (EMIT) write_fields<L, C>(p, n, m, fields, out, node, nodes);
 #pragma unroll
     for (int a = 0; a < L::NS; ++a) {
-        C ne[L::Q], fo[L::Q];
-        nonequilibrium<L, C>(n, m, a, ne);
-        collide_set<L, C>(p, n, a, ne, fo, m.fb[a + L::A0]);
+        C fo[L::Q];
+        collide_fused<L, C>(p, n, m, a, fo, m.fb[a + L::A0]);
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
             if (i >= qset<L>(a + L::A0)) continue;
@@ -1879,9 +1898,8 @@ k_init(KCase p, typename Store<ST>::T *__restrict__ pre, typename Store<ST>::T *
     moments<L, C>(p, n, m);
 #pragma unroll
     for (int a = 0; a < L::NS; ++a) {
-        C ne[L::Q], fo[L::Q];
-        nonequilibrium<L, C>(n, m, a, ne);
-        collide_set<L, C>(p, n, a, ne, fo, m.fb[a + L::A0]);
+        C fo[L::Q];
+        collide_fused<L, C>(p, n, m, a, fo, m.fb[a + L::A0]);
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
             if (i >= qset<L>(a + L::A0)) continue;
