@@ -33,11 +33,14 @@ HBM_PEAK_GBS = 8000.0
 
 
 def kernel_source_hash():
+    """Hash of what determines the step kernels' machine code: their sources
+    and the compiler flags."""
     from paper_2108_08591_amd import build as B
     h = hashlib.sha256()
     for name in B.KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2108_08591_amd", "csrc", name), "rb") as f:
             h.update(f.read())
+    h.update(" ".join(B.HIP_FLAGS).encode())
     return h.hexdigest()[:16]
 
 
