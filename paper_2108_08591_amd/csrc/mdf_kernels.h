@@ -27,7 +27,7 @@
 //     L n = s1 P_odd n + s2 P_even n + (s0 - s2) (e.n / Q) e,
 // with (P_odd n)_i = (n_i - n_ibar)/2, (P_even n)_i = (n_i + n_ibar)/2 for
 // i != 0, (P_odd n)_0 = 0, (P_even n)_0 = n_0.  For n = f - f^eq the last
-// term vanishes (e.n = 0, eq. 3-8); see collide_set().
+// term vanishes (e.n = 0, eq. 3-8); see collide_fused().
 //
 // Walls: a link whose upstream node lies behind a wall face or in a solid
 // node takes the halfway wall rule (Section 4 names an anti-bounce-back rule
@@ -738,12 +738,13 @@ __device__ __forceinline__ void moments(const KCase &p, const Node<L, C> &n, Mom
 
 // Equilibrium of one set (eq. 2-4), f^eq_i = w_i [ubar + c_i . flux / cs^2]
 // with flux = ubar u + P E_a, evaluated in a form that is exact in any
-// precision where the weights are not: w_i / cs^2 = 1/2 for every moving
-// population, and the rest weight is taken as w_0 = 1 - sum_{i>0} w_i, so
+// precision where the weights are not: w_i / cs^2 is 1/2 for every moving
+// population of D2Q5 and D3Q7, and the rest weight is taken as
+// w_0 = 1 - sum_{i>0} w_i, so
 // f^eq_0 = ubar - sum_{i>0} w_i ubar.  (With w_0 = 1/3 and w_1 = 1/6 rounded
 // to FP32, sum_i w_i differs from 1 by ~3e-8, and the zeroth moment would
 // drift by that fraction every step.)  Without a rest population the
-// collision closes the zeroth moment instead (collide_set()).
+// collision closes the zeroth moment instead (collide_fused()).
 template <class L, class C>
 __device__ __forceinline__ void equilibrium(C ub, const C (&flux)[L::D], C (&feq)[L::Q], int pa)
 {
