@@ -1181,8 +1181,8 @@ def main():
         steady_study(args.steady_study)
         return
     if args.coarse_warmstart_study:
-        coarse_warmstart_study(args.coarse_warmstart_study, n_train=args.ws_train, epochs=args.ws_epochs,
-                               lr=args.ws_lr, batch=args.ws_batch)
+        coarse_warmstart_study(args.coarse_warmstart_study, n_train=args.ws_train, N=args.ws_n,
+                               epochs=args.ws_epochs, lr=args.ws_lr, batch=args.ws_batch)
         return
     if args.restart_study:
         restart_study(args.restart_study)
