@@ -482,11 +482,12 @@ def sweep(out_path):
             torch.cuda.empty_cache()
 
 
-def tgv3d_timing(storage, form, N=256, groups=8):
+def tgv3d_timing(storage, form, N=256, groups=8, quiet=False):
     """The 3D Taylor-Green vortex of the precision configuration (D3Q7, four
     sets, Re 100, u0 = 0.05) at N^3: time per step of the step kernel in one
     storage and form, HIP events, median of 5, and its per-step fraction of
-    the HBM roofline (2 x 28 values per node and step)."""
+    the HBM roofline (2 x 28 values per node and step).  Returns the record
+    (and prints it unless quiet)."""
     import numpy as np
     import torch
     from paper_2108_08591_amd import cases as C
@@ -506,10 +507,14 @@ def tgv3d_timing(storage, form, N=256, groups=8):
     ms = time_launches(solver, stream, n, reps=5)
     sb = {"f64": 8, "f32": 4, "f16dev": 2, "bf16dev": 2}[storage]
     mlups = spec.nodes / ms / 1e3
-    print(json.dumps({"workload": f"3D Taylor-Green {N}^3, D3Q7 x 4 sets", "storage": storage, "form": form,
-                      "groups": groups,
-                      "ms_per_step": round(ms, 5), "MLUPS": round(mlups, 1),
-                      "per_step_frac": round(mlups * 1e6 * 2 * 28 * sb / (HBM_PEAK_GBS * 1e9), 4)}), flush=True)
+    rec = {"workload": f"3D Taylor-Green {N}^3, D3Q7 x 4 sets", "storage": storage, "form": form,
+           "groups": groups, "ms_per_step": round(ms, 5), "MLUPS": round(mlups, 1),
+           "per_step_frac": round(mlups * 1e6 * 2 * 28 * sb / (HBM_PEAK_GBS * 1e9), 4)}
+    del solver
+    torch.cuda.empty_cache()
+    if not quiet:
+        print(json.dumps(rec), flush=True)
+    return rec
 
 
 def _rel(ref, got, scale=None):
@@ -1248,6 +1253,10 @@ def main():
     if not args.headline_only:
         result["cavity1024_f32"] = cavity_leg(args, dev, stream, 1024, 4000)
         result["cavity8192_f32"] = cavity_leg(args, dev, stream, 8192, 41)
+        # the 3D Taylor-Green vortex of the precision configuration at 256^3 in
+        # each storage's default form (two steps per launch for FP64 and FP32)
+        result["tgv3d256"] = {st: tgv3d_timing(st, form, groups=1, quiet=True)
+                              for st, form in (("f64", 2), ("f32", 2), ("f16dev", 0))}
         result["device_copy"] = device_copy_bandwidth()
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline_batch()

@@ -847,6 +847,28 @@ __device__ __forceinline__ void collide_fused(const KCase &p, const Node<L, C> &
     out[L::K] = n.f[a][L::K] + (fb - dsum);
 }
 
+// Channels of the field selection `fields` (order of the MDF_FIELD_* bits).
+template <class L>
+__device__ __forceinline__ int field_channels(uint32_t fields)
+{
+    int nch = 0;
+    if (fields & MDF_FIELD_MOMENTS) nch += L::D + 2;
+    if (fields & MDF_FIELD_GRAD) nch += L::D * L::D;
+    if (fields & MDF_FIELD_DIV) nch += 1;
+    if (fields & MDF_FIELD_STRAIN) nch += L::D * (L::D + 1) / 2;
+    if (fields & MDF_FIELD_STRESS) nch += L::D * (L::D + 1) / 2;
+    if (fields & MDF_FIELD_VORT) nch += (L::D == 2 ? 1 : 3);
+    return nch;
+}
+
+// A solid node emits zero in every selected channel.
+template <class L, class C, class IX>
+__device__ __forceinline__ void write_zero_fields(uint32_t fields, C *__restrict__ out, IX node, long long nodes)
+{
+    const int nch = field_channels<L>(fields);
+    for (int ch = 0; ch < nch; ++ch) put_value<false>(out + ch * nodes, node, C(0));
+}
+
 // Derived fields of eq. 3-16..3-19 written channel-major for the selection
 // `fields` (order of the MDF_FIELD_* bits).
 template <class L, class C, class IX>
@@ -1024,14 +1046,7 @@ __device__ __forceinline__ void step_tile(const KCase &p, int gx, int gy, int ti
         }
     } else if (EMIT && inside) {
         // solid node: every emitted channel is zero
-        int nch = 0;
-        if (fields & MDF_FIELD_MOMENTS) nch += L::D + 2;
-        if (fields & MDF_FIELD_GRAD) nch += L::D * L::D;
-        if (fields & MDF_FIELD_DIV) nch += 1;
-        if (fields & MDF_FIELD_STRAIN) nch += L::D * (L::D + 1) / 2;
-        if (fields & MDF_FIELD_STRESS) nch += L::D * (L::D + 1) / 2;
-        if (fields & MDF_FIELD_VORT) nch += (L::D == 2 ? 1 : 3);
-        for (int ch = 0; ch < nch; ++ch) out[ch * nodes + node] = C(0);
+        write_zero_fields<L, C>(fields, out, node, nodes);
     }
     if (CHECK) {
         double v[kNRed];
@@ -1083,14 +1098,7 @@ __device__ __forceinline__ void step_tile_vec(const KCase &p, int gx, int gy, in
             moments<L, C>(p, n[v], m[v]);
             if (EMIT) write_fields<L, C>(p, n[v], m[v], fields, out, node, nodes);
         } else if (EMIT && inside) {
-            int nch = 0;
-            if (fields & MDF_FIELD_MOMENTS) nch += L::D + 2;
-            if (fields & MDF_FIELD_GRAD) nch += L::D * L::D;
-            if (fields & MDF_FIELD_DIV) nch += 1;
-            if (fields & MDF_FIELD_STRAIN) nch += L::D * (L::D + 1) / 2;
-            if (fields & MDF_FIELD_STRESS) nch += L::D * (L::D + 1) / 2;
-            if (fields & MDF_FIELD_VORT) nch += (L::D == 2 ? 1 : 3);
-            for (int ch = 0; ch < nch; ++ch) out[ch * nodes + node] = C(0);
+            write_zero_fields<L, C>(fields, out, node, nodes);
         }
         if (CHECK) {
             double vv[kNRed];
@@ -1284,14 +1292,7 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int gy, int t
         if (MASK) lb = *elem(links, own);
         if (MASK && (lb & 0x80u)) {
             if (EMIT) {
-                int nch = 0;
-                if (fields & MDF_FIELD_MOMENTS) nch += L::D + 2;
-                if (fields & MDF_FIELD_GRAD) nch += L::D * L::D;
-                if (fields & MDF_FIELD_DIV) nch += 1;
-                if (fields & MDF_FIELD_STRAIN) nch += L::D * (L::D + 1) / 2;
-                if (fields & MDF_FIELD_STRESS) nch += L::D * (L::D + 1) / 2;
-                if (fields & MDF_FIELD_VORT) nch += 1;
-                for (int ch = 0; ch < nch; ++ch) put_value<false>(out + ch * nodes, node, C(0));
+                write_zero_fields<L, C>(fields, out, node, nodes);
             }
             continue;
         }
@@ -1581,14 +1582,7 @@ __device__ __forceinline__ void step2z_plane2(const KCase &p, typename Store<ST>
     if (MASK) lb = *elem(links, own);
     if (MASK && (lb & 0x80u)) {
         if (EMIT) {
-            int nch = 0;
-            if (fields & MDF_FIELD_MOMENTS) nch += L::D + 2;
-            if (fields & MDF_FIELD_GRAD) nch += L::D * L::D;
-            if (fields & MDF_FIELD_DIV) nch += 1;
-            if (fields & MDF_FIELD_STRAIN) nch += L::D * (L::D + 1) / 2;
-            if (fields & MDF_FIELD_STRESS) nch += L::D * (L::D + 1) / 2;
-            if (fields & MDF_FIELD_VORT) nch += 3;
-            for (int ch = 0; ch < nch; ++ch) put_value<false>(out + ch * nodes, node, C(0));
+            write_zero_fields<L, C>(fields, out, node, nodes);
         }
         return;
     }
@@ -1787,14 +1781,7 @@ k_read(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, const 
         if (fluid) {
             write_fields<L, C>(p, n, m, fields, out, node, nodes);
         } else {
-            int nch = 0;
-            if (fields & MDF_FIELD_MOMENTS) nch += L::D + 2;
-            if (fields & MDF_FIELD_GRAD) nch += L::D * L::D;
-            if (fields & MDF_FIELD_DIV) nch += 1;
-            if (fields & MDF_FIELD_STRAIN) nch += L::D * (L::D + 1) / 2;
-            if (fields & MDF_FIELD_STRESS) nch += L::D * (L::D + 1) / 2;
-            if (fields & MDF_FIELD_VORT) nch += (L::D == 2 ? 1 : 3);
-            for (int ch = 0; ch < nch; ++ch) out[ch * nodes + node] = C(0);
+            write_zero_fields<L, C>(fields, out, node, nodes);
         }
     }
     if (MODE == kReadPops && inside) {
