@@ -517,6 +517,77 @@ def tgv3d_timing(storage, form, N=256, groups=8, quiet=False):
     return rec
 
 
+def grid2d_timing(storage, form, N=8192, groups=8, quiet=False):
+    """The lid-driven cavity of the channel-and-cavity configuration (D2Q5,
+    three sets, Re 1000, lid 0.1) at N^2 without field emission: time per
+    step of the step kernel in one storage and form, HIP events, median of
+    5, and its per-step fraction of the HBM roofline (2 x 15 values per node
+    and step).  Returns the record (and prints it unless quiet)."""
+    import torch
+    from paper_2108_08591_amd import cases as C
+    from paper_2108_08591_amd import mdf
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    spec = C.cavity_case(N=N, Re=1000.0, U=0.1)
+    solver = mdf.Solver([spec], storage=storage, device=dev, stream=stream, u_ref=0.1)
+    solver.set_launch(64, 4, groups, form)
+    solver.step(3)
+    n = 41 if form == 2 else 40
+    ms = time_launches(solver, stream, n, reps=5)
+    sb = {"f64": 8, "f32": 4, "f16dev": 2, "bf16dev": 2}[storage]
+    mlups = spec.nodes / ms / 1e3
+    rec = {"workload": f"lid-driven cavity {N}^2, D2Q5 x 3 sets", "storage": storage, "form": form,
+           "groups": groups, "ms_per_step": round(ms, 5), "MLUPS": round(mlups, 1),
+           "per_step_frac": round(mlups * 1e6 * 2 * 15 * sb / (HBM_PEAK_GBS * 1e9), 4)}
+    del solver
+    torch.cuda.empty_cache()
+    if not quiet:
+        print(json.dumps(rec), flush=True)
+    return rec
+
+
+def summarize_counters(db_paths, command, node_steps, kernel_prefix):
+    """Markdown summary of rocprofv3 --pmc runs for one kernel: the mean of
+    every counter per dispatch of the most frequent dispatch shape, and the
+    per-node-step figures the instruction counters give (SQ_INSTS_* count
+    wave instructions; one wave covers 64 node-steps of a one-node-per-thread
+    kernel, so per node-step = count x 64 / node_steps)."""
+    import sqlite3
+    import statistics
+    rows = {}
+    for db in db_paths:
+        cur = sqlite3.connect(db).cursor()
+        acc = {}
+        for name, g, cname, val in cur.execute("select kernel_name, grid_size, counter_name, value "
+                                               "from counters_collection"):
+            k = _short_kernel_name(name)
+            if not k.startswith(kernel_prefix):
+                continue
+            acc.setdefault((k, g, cname), []).append(val)
+        for (k, g, cname), v in acc.items():
+            rows.setdefault(cname, []).append((len(v), statistics.mean(v), k, g))
+    out = ["# rocprofv3 counters of `" + kernel_prefix + "`", "", "Commands (repository root, GPU box):", "",
+           "```"] + command.split(" ;; ") + ["```", "",
+           f"Node-steps per dispatch: {node_steps}.", "",
+           "| counter | dispatches | mean per dispatch | per node-step |", "|---|---|---|---|"]
+    vals = {}
+    for cname in sorted(rows):
+        n, mean, k, g = max(rows[cname])
+        vals[cname] = mean
+        per = ""
+        if cname.startswith("SQ_INSTS_"):
+            per = f"{mean * 64 / node_steps:.1f}"
+        out.append(f"| {cname} | {n} | {mean:.4g} | {per} |")
+    if "SQ_INSTS_VALU" in vals and "SQ_ACTIVE_INST_VALU" in vals and "SQ_BUSY_CU_CYCLES" in vals:
+        out += ["", f"* VALU issue: SQ_ACTIVE_INST_VALU / SQ_BUSY_CU_CYCLES = "
+                    f"{vals['SQ_ACTIVE_INST_VALU'] / vals['SQ_BUSY_CU_CYCLES']:.3f}"]
+    if "SQ_WAVE_CYCLES" in vals and "SQ_WAVES" in vals:
+        out += [f"* mean wave lifetime: {vals['SQ_WAVE_CYCLES'] / vals['SQ_WAVES']:.0f} cycles"]
+    if "SQ_WAIT_INST_ANY" in vals and "SQ_WAVE_CYCLES" in vals:
+        out += [f"* SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES = {vals['SQ_WAIT_INST_ANY'] / vals['SQ_WAVE_CYCLES']:.3f}"]
+    return "\n".join(out) + "\n"
+
+
 def _rel(ref, got, scale=None):
     import torch
     num = torch.linalg.vector_norm((ref - got.to(ref.dtype)).reshape(-1)).item()
@@ -1147,6 +1218,11 @@ def main():
     ap.add_argument("--tgv3d", nargs="+", metavar="STORAGE FORM [GROUPS]",
                     help="time the 3D Taylor-Green step kernel (256^3) in one storage and form (XCD groups, "
                          "default 8)")
+    ap.add_argument("--grid2d", nargs="+", metavar="STORAGE FORM [N [GROUPS]]",
+                    help="time the 2D cavity step kernel (D2Q5 x 3 sets, default 8192^2, no emission) in one "
+                         "storage and form")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DB",
+                    help="markdown summary of rocprofv3 --pmc databases: OUT_MD KERNEL_PREFIX NODE_STEPS DB...")
     ap.add_argument("--conv-study", metavar="OUT_JSONL",
                     help="the warm-start network's 3x3 convolutions at 256^2, batch 16: TFLOP/s per layer")
     ap.add_argument("--lattice-per-set-study", metavar="OUT_JSONL",
@@ -1204,6 +1280,15 @@ def main():
         return
     if args.tgv3d:
         tgv3d_timing(args.tgv3d[0], int(args.tgv3d[1]), groups=int(args.tgv3d[2]) if len(args.tgv3d) > 2 else 8)
+        return
+    if args.grid2d:
+        g = args.grid2d
+        grid2d_timing(g[0], int(g[1]), N=int(g[2]) if len(g) > 2 else 8192, groups=int(g[3]) if len(g) > 3 else 8)
+        return
+    if args.summarize_counters:
+        out_md, prefix, node_steps = args.summarize_counters[:3]
+        with open(out_md, "w") as fh:
+            fh.write(summarize_counters(args.summarize_counters[3:], args.command, int(node_steps), prefix))
         return
     if args.summarize_trace:
         with open(args.summarize_trace[1], "w") as fh:

@@ -157,7 +157,7 @@ bool validate_case(int lattice, int storage, const mdf_case &c, std::string &why
 size_t layout(int lattice, int storage, const mdf_case *cases, int ncases, bool has_solid,
               std::vector<CaseLayout> *out, SharedLayout *shared = nullptr)
 {
-    const int d = lat_d(lattice), q = lat_q(lattice);
+    const int d = lat_d(lattice);
     size_t off = 0;
     if (out) out->resize(ncases);
     // per-case FP64 results, contiguous (one read-back for a whole batch)
@@ -286,6 +286,9 @@ KCase make_kcase(int lattice, int storage, const mdf_case &c)
     p.s2f = float(p.s2);
     p.rho0f = float(p.rho0);
     p.Rf = float(p.R);
+    const double cs2 = mdf::lattice_cs2(lattice);
+    p.rps = cs2 * p.R / p.s1;
+    p.rpsf = float(cs2) * p.Rf / p.s1f;
     for (int a = 0; a < 4; ++a) p.fbarf[a] = float(p.fbar[a]);
     p.forcing = c.forcing;
     p.fmove = c.forcing == MDF_FORCING_SCHEME2 ? 1.0 - 0.5 * p.s2 : 1.0;

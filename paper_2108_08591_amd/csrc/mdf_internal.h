@@ -31,6 +31,11 @@ struct KCase {
     // 16-bit kernels compute in FP32), and the rest populations w_i rho0 of
     // the set a = 0 (index 0: i = 0, index 1: i > 0)
     float s1f, s2f, rho0f, Rf;
+    // cs^2 R / s1, the mass-source part of P (eq. 3-15), formed once on the
+    // host in the operation order the kernels used to form it per node:
+    // (cs^2 R) / s1, in FP64 and in FP32
+    double rps;
+    float rpsf;
     float fbarf[4];
     float walluf[6][3];
     double restd[3];        // w * rho0 by weight class: rest, axis, diagonal
@@ -121,6 +126,7 @@ struct LatOps {
     hipError_t (*batch_cap)(int storage, LaunchShape shape, bool mask, int *blocks_per_cu);
     hipError_t (*batch2_cap)(int storage, bool mask, int *blocks_per_cu);
     hipError_t (*links)(const KCase &p, const uint8_t *solid, uint8_t *links, hipStream_t stream);
+    double cs2;             // the lattice's c_s^2 (of the velocity sets, on a lattice per set)
 };
 const LatOps &lat_ops_d2q5();
 const LatOps &lat_ops_d3q7();
@@ -166,6 +172,8 @@ hipError_t launch_finalize_batch(const BatchEntry *tab, const int *meta, const i
 
 // Nodes per thread along x of the step kernels for a storage and shape.
 int step_vx(int storage, LaunchShape shape);
+// c_s^2 of a lattice's (velocity) sets, from its kernels' traits; 0 for an unknown id
+double lattice_cs2(int lattice);
 // Blocks of one step launch / one read launch.
 int grid_blocks(const KCase &p, int storage, LaunchShape shape);
 int read_blocks(const KCase &p, LaunchShape shape);

@@ -536,16 +536,65 @@ __device__ __forceinline__ void load_sources(const KCase &p, long long node, Nod
     for (int pa = 0; pa <= L::D; ++pa) n.fb[pa] = source_of<C>(p, pa, node);
 }
 
-// Pull the populations of node (x, y, z) at time t+1 out of the
-// post-collision planes of time t (or, with PULL = false, read the node's
-// own stored pre-collision values).  Returns false for a solid node.
-template <class L, int ST, bool MASK, bool PULL, bool WIDE = true>
-__device__ __forceinline__ bool gather(const KCase &p, const typename Store<ST>::T *__restrict__ src,
-                                       const uint8_t *__restrict__ links, int x, int y, int z,
-                                       Node<L, typename Store<ST>::C> &n)
+// Wall face a pull of direction i at node (x, y, z) crosses: 0..5 for a
+// wall face, 6 for a solid upstream node (MASK), -1 for a plain pull, whose
+// upstream node (wrapped across periodic faces) is returned in sx, sy, sz.
+// With PULL = false the node reads its own values: no face, (sx, sy, sz) =
+// (x, y, z).
+template <class L, bool MASK, bool PULL, bool WIDE>
+__device__ __forceinline__ int pull_face(const KCase &p, const uint8_t *__restrict__ links, unsigned lb, int x,
+                                         int y, int z, int i, int &sx, int &sy, int &sz)
 {
-    using S = Store<ST>;
-    using C = typename S::C;
+    sx = x - L::cx[i];
+    sy = y - L::cy[i];
+    sz = z - L::cz[i];
+    if (!PULL) {
+        sx = x; sy = y; sz = z;
+        return -1;
+    }
+    int face = -1;
+    if (L::cx[i] != 0) {
+        if (sx < 0) { if (p.bc[0] == MDF_WALL) face = 0; else sx += p.nx; }
+        else if (sx >= p.nx) { if (p.bc[1] == MDF_WALL) face = 1; else sx -= p.nx; }
+    }
+    if (L::cy[i] != 0) {
+        if (sy < 0) { if (p.bc[2] == MDF_WALL) { if (face < 0) face = 2; } else sy += p.ny; }
+        else if (sy >= p.ny) { if (p.bc[3] == MDF_WALL) { if (face < 0) face = 3; } else sy -= p.ny; }
+    }
+    if (L::cz[i] != 0) {
+        if (sz < 0) { if (p.bc[4] == MDF_WALL) { if (face < 0) face = 4; } else sz += p.nz; }
+        else if (sz >= p.nz) { if (p.bc[5] == MDF_WALL) { if (face < 0) face = 5; } else sz -= p.nz; }
+    }
+    if (MASK && face < 0) {
+        if constexpr (L::DIAG) {
+            // more moving directions than link bits: read the upstream
+            // node's solid flag
+            if (*elem(links, grid_ix<WIDE>(sx, sy, sz, p.ny, p.pitch)) & 0x80u) face = 6;
+        } else if ((lb >> i) & 1u) {
+            face = 6;
+        }
+    }
+    return face;
+}
+
+// A node's pull in the 16-bit formats, in two parts: gather_issue() issues
+// every population load (and finds the wall faces), gather_decode() decodes
+// and applies the wall rule.  A decode right after each load makes the node
+// wait for its loads one direction at a time (measured: 2.6x on the 3D
+// two-step kernel, +11 % on the 2D one); the tile kernels that pull several
+// nodes per thread issue all of their loads before decoding any.
+template <class L, int ST>
+struct Pulled {
+    typename Store<ST>::T raw[L::NS][L::Q];
+    int fc[L::Q];
+};
+
+template <class L, int ST, bool MASK, bool PULL, bool WIDE = true>
+__device__ __forceinline__ bool gather_issue(const KCase &p, const typename Store<ST>::T *__restrict__ src,
+                                             const uint8_t *__restrict__ links, int x, int y, int z,
+                                             Node<L, typename Store<ST>::C> &n, Pulled<L, ST> &r)
+{
+    using C = typename Store<ST>::C;
     const auto own = grid_ix<WIDE>(x, y, z, p.ny, p.pitch);
     unsigned lb = 0;
     if (MASK) {
@@ -553,57 +602,104 @@ __device__ __forceinline__ bool gather(const KCase &p, const typename Store<ST>:
         if (lb & 0x80u) return false;
     }
     load_sources<L, C>(p, ((long long)z * p.ny + y) * p.nx + x, n);
-    // The 16-bit formats issue every population's load first and decode them
-    // afterwards: a decode right after each load makes the node wait for its
-    // loads one direction at a time (measured: 2.6x on the 3D two-step kernel,
-    // +11 % on the 2D one).  FP32 and FP64 values need no decode and keep the
-    // single pass, which holds fewer registers.
-    constexpr bool SPLIT = sizeof(typename Store<ST>::T) == 2;
-    typename Store<ST>::T raw[SPLIT ? L::NS : 1][SPLIT ? L::Q : 1];
-    int fc[L::Q];
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        int sx = x - L::cx[i], sy = y - L::cy[i], sz = z - L::cz[i];
-        int face = -1;
-        if (PULL) {
-            if (L::cx[i] != 0) {
-                if (sx < 0) { if (p.bc[0] == MDF_WALL) face = 0; else sx += p.nx; }
-                else if (sx >= p.nx) { if (p.bc[1] == MDF_WALL) face = 1; else sx -= p.nx; }
-            }
-            if (L::cy[i] != 0) {
-                if (sy < 0) { if (p.bc[2] == MDF_WALL) { if (face < 0) face = 2; } else sy += p.ny; }
-                else if (sy >= p.ny) { if (p.bc[3] == MDF_WALL) { if (face < 0) face = 3; } else sy -= p.ny; }
-            }
-            if (L::cz[i] != 0) {
-                if (sz < 0) { if (p.bc[4] == MDF_WALL) { if (face < 0) face = 4; } else sz += p.nz; }
-                else if (sz >= p.nz) { if (p.bc[5] == MDF_WALL) { if (face < 0) face = 5; } else sz -= p.nz; }
-            }
-            if (MASK && face < 0) {
-                if constexpr (L::DIAG) {
-                    // more moving directions than link bits: read the
-                    // upstream node's solid flag
-                    if (*elem(links, grid_ix<WIDE>(sx, sy, sz, p.ny, p.pitch)) & 0x80u) face = 6;
-                } else if ((lb >> i) & 1u) {
-                    face = 6;
-                }
-            }
+        int sx, sy, sz;
+        const int face = pull_face<L, MASK, PULL, WIDE>(p, links, lb, x, y, z, i, sx, sy, sz);
+        r.fc[i] = face;
+        if (face < 0) {
+            const auto k = grid_ix<WIDE>(sx, sy, sz, p.ny, p.pitch);
+#pragma unroll
+            for (int a = 0; a < L::NS; ++a)
+                if (i < qset<L>(a + L::A0)) r.raw[a][i] = *elem(src + plane_of<L>(a, i) * p.dstride, k);
         } else {
-            sx = x; sy = y; sz = z;
+            const int j = L::opp[i];
+#pragma unroll
+            for (int a = 0; a < L::NS; ++a)
+                if (i < qset<L>(a + L::A0)) r.raw[a][i] = *elem(src + plane_of<L>(a, j) * p.dstride, own);
         }
-        fc[i] = face;
-        if constexpr (SPLIT) {
-            if (face < 0) {
-                const auto k = grid_ix<WIDE>(sx, sy, sz, p.ny, p.pitch);
+    }
+    return true;
+}
+
+template <class L, int ST>
+__device__ __forceinline__ void gather_decode(const KCase &p, const Pulled<L, ST> &r,
+                                              Node<L, typename Store<ST>::C> &n)
+{
+    using S = Store<ST>;
+    using C = typename S::C;
+    // (a direction and its opposite share their weight class, hence their
+    // rest value)
+    bool wall = false;
 #pragma unroll
-                for (int a = 0; a < L::NS; ++a)
-                    if (i < qset<L>(a + L::A0)) raw[a][i] = *elem(src + plane_of<L>(a, i) * p.dstride, k);
-            } else {
-                const int j = L::opp[i];
+    for (int i = 0; i < L::Q; ++i) {
+        wall |= r.fc[i] >= 0;
 #pragma unroll
-                for (int a = 0; a < L::NS; ++a)
-                    if (i < qset<L>(a + L::A0)) raw[a][i] = *elem(src + plane_of<L>(a, j) * p.dstride, own);
+        for (int a = 0; a < L::NS; ++a) {
+            if (i >= qset<L>(a + L::A0)) { n.f[a][i] = C(0); continue; }
+            n.f[a][i] = S::decode(r.raw[a][i], rest_value<L, C>(p, a, i), p.scale);
+        }
+    }
+    // The wall rule on the velocity sets, only in a wavefront where some
+    // lane pulled across a wall or from a solid node: a uniform branch that
+    // interior wavefronts skip (as selects it cost every node about five
+    // vector instructions per velocity-set population).
+    if (__builtin_amdgcn_ballot_w64(wall) != 0) {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            if (r.fc[i] < 0) continue;
+            const C w = C(L::w[i]);
+#pragma unroll
+            for (int a = 0; a < L::NS; ++a) {
+                if (a + L::A0 == 0 || i >= qset<L>(a + L::A0)) continue;
+                const int b = a + L::A0 - 1;
+                // the face's wall velocity, selected with constant indices (a
+                // run-time index into the case parameters here copied them to
+                // scratch memory)
+                C uw = C(0);
+#pragma unroll
+                for (int f = 0; f < 6; ++f)
+                    if (r.fc[i] == f) uw = kpar<C>(p.wallu[f][b], p.walluf[f][b]);
+                const C v = n.f[a][i];
+                n.f[a][i] = -v + C(2) * w * uw;
             }
-        } else {
+        }
+    }
+}
+
+// The storages whose pulls go through gather_issue() / gather_decode().
+template <int ST>
+constexpr bool kSplitPull = sizeof(typename Store<ST>::T) == 2;
+
+// Pull the populations of node (x, y, z) at time t+1 out of the
+// post-collision planes of time t (or, with PULL = false, read the node's
+// own stored pre-collision values).  Returns false for a solid node.
+// FP32 and FP64 values need no decode and are pulled in a single pass, which
+// holds fewer registers.
+template <class L, int ST, bool MASK, bool PULL, bool WIDE = true>
+__device__ __forceinline__ bool gather(const KCase &p, const typename Store<ST>::T *__restrict__ src,
+                                       const uint8_t *__restrict__ links, int x, int y, int z,
+                                       Node<L, typename Store<ST>::C> &n)
+{
+    using S = Store<ST>;
+    using C = typename S::C;
+    if constexpr (kSplitPull<ST>) {
+        Pulled<L, ST> r;
+        if (!gather_issue<L, ST, MASK, PULL, WIDE>(p, src, links, x, y, z, n, r)) return false;
+        gather_decode<L, ST>(p, r, n);
+        return true;
+    } else {
+        const auto own = grid_ix<WIDE>(x, y, z, p.ny, p.pitch);
+        unsigned lb = 0;
+        if (MASK) {
+            lb = *elem(links, own);
+            if (lb & 0x80u) return false;
+        }
+        load_sources<L, C>(p, ((long long)z * p.ny + y) * p.nx + x, n);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            int sx, sy, sz;
+            const int face = pull_face<L, MASK, PULL, WIDE>(p, links, lb, x, y, z, i, sx, sy, sz);
             const C w = C(L::w[i]);
             if (face < 0) {
                 const auto k = grid_ix<WIDE>(sx, sy, sz, p.ny, p.pitch);
@@ -628,34 +724,8 @@ __device__ __forceinline__ bool gather(const KCase &p, const typename Store<ST>:
                 }
             }
         }
+        return true;
     }
-    if constexpr (SPLIT) {
-        // decode and wall rule after every load has been issued (a direction
-        // and its opposite share their weight class, hence their rest value)
-#pragma unroll
-        for (int i = 0; i < L::Q; ++i) {
-            const C w = C(L::w[i]);
-#pragma unroll
-            for (int a = 0; a < L::NS; ++a) {
-                if (i >= qset<L>(a + L::A0)) { n.f[a][i] = C(0); continue; }
-                const C v = S::decode(raw[a][i], rest_value<L, C>(p, a, i), p.scale);
-                if (fc[i] < 0 || a + L::A0 == 0) {
-                    n.f[a][i] = v;
-                } else {
-                    const int b = a + L::A0 - 1;
-                    // the face's wall velocity, selected with constant indices
-                    // (a run-time index into the case parameters here copied
-                    // them to scratch memory)
-                    C uw = C(0);
-#pragma unroll
-                    for (int f = 0; f < 6; ++f)
-                        if (fc[i] == f) uw = kpar<C>(p.wallu[f][b], p.walluf[f][b]);
-                    n.f[a][i] = -v + C(2) * w * uw;
-                }
-            }
-        }
-    }
-    return true;
 }
 
 // Vector form of gather(): the thread owns the VX consecutive nodes
@@ -787,7 +857,7 @@ __device__ __forceinline__ void moments(const KCase &p, const Node<L, C> &n, Mom
         u2 += m.u[pa - 1] * m.u[pa - 1];
     }
     m.trJ = trJ;
-    m.P = (trJ + C(L::cs2) * kpar<C>(p.R, p.Rf) / kpar<C>(p.s1, p.s1f) - u2) * C(1.0 / L::D);
+    m.P = (trJ + kpar<C>(p.rps, p.rpsf) - u2) * C(1.0 / L::D);
 }
 
 // Equilibrium of one set (eq. 2-4), f^eq_i = w_i [ubar + c_i . flux / cs^2]
@@ -1296,6 +1366,7 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int gy, int t
     for (int k0 = 0; k0 < K1; k0 += G) {
         Node<L, C> n[G];
         bool fluid[G];
+        Pulled<L, ST> r[kSplitPull<ST> ? G : 1];
         // issue this batch's loads ahead of other waves' arithmetic
         __builtin_amdgcn_s_setprio(2);
 #pragma unroll
@@ -1313,12 +1384,17 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int gy, int t
                 if (p.bc[y < 0 ? 2 : 3] == MDF_WALL) continue;
                 y = ((y % p.ny) + p.ny) % p.ny;
             }
-            fluid[g] = gather<L, ST, MASK, true, WIDE>(p, src, links, x, y, 0, n[g]);   // false: solid node
+            // false: solid node
+            if constexpr (kSplitPull<ST>)
+                fluid[g] = gather_issue<L, ST, MASK, true, WIDE>(p, src, links, x, y, 0, n[g], r[g]);
+            else
+                fluid[g] = gather<L, ST, MASK, true, WIDE>(p, src, links, x, y, 0, n[g]);
         }
         __builtin_amdgcn_s_setprio(0);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             if (!fluid[g]) continue;
+            if constexpr (kSplitPull<ST>) gather_decode<L, ST>(p, r[g], n[g]);
             const int e = tid + (k0 + g) * NT;
             Moments<L, C> m;
             moments<L, C>(p, n[g], m);
@@ -1535,6 +1611,7 @@ __device__ __forceinline__ void step2z_plane1(const KCase &p, const typename Sto
     Node<L, C> n[G];
     bool fluid[G];
     int pos[G];
+    Pulled<L, ST> r[kSplitPull<ST> ? G : 1];
     __builtin_amdgcn_s_setprio(2);          // issue the loads ahead of other waves' arithmetic
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -1562,12 +1639,17 @@ __device__ __forceinline__ void step2z_plane1(const KCase &p, const typename Sto
             if (p.bc[y < 0 ? 2 : 3] == MDF_WALL) continue;
             y = ((y % p.ny) + p.ny) % p.ny;
         }
-        fluid[g] = gather<L, ST, MASK, true, WIDE>(p, src, links, x, y, z, n[g]);   // false: solid node
+        // false: solid node
+        if constexpr (kSplitPull<ST>)
+            fluid[g] = gather_issue<L, ST, MASK, true, WIDE>(p, src, links, x, y, z, n[g], r[g]);
+        else
+            fluid[g] = gather<L, ST, MASK, true, WIDE>(p, src, links, x, y, z, n[g]);
     }
     __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         if (!fluid[g]) continue;
+        if constexpr (kSplitPull<ST>) gather_decode<L, ST>(p, r[g], n[g]);
         const int e = pos[g];
         Moments<L, C> m;
         moments<L, C>(p, n[g], m);
@@ -2336,6 +2418,7 @@ LatOps make_lat_ops()
     o.batch_cap = op_batch_cap<L>;
     o.batch2_cap = op_batch2_cap<L>;
     o.links = op_links<L>;
+    o.cs2 = L::cs2;
     return o;
 }
 

@@ -89,6 +89,12 @@ bool axis_links(int lattice) { return lattice >= MDF_D2Q5 && lattice <= MDF_D3Q6
 
 }  // namespace
 
+double lattice_cs2(int lattice)
+{
+    const LatOps *o = ops_of(lattice);
+    return o ? o->cs2 : 0.0;
+}
+
 int step_vx(int storage, LaunchShape s)
 {
     if (s.vx <= 1) return 1;
