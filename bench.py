@@ -578,13 +578,20 @@ def summarize_counters(db_paths, command, node_steps, kernel_prefix):
         if cname.startswith("SQ_INSTS_"):
             per = f"{mean * 64 / node_steps:.1f}"
         out.append(f"| {cname} | {n} | {mean:.4g} | {per} |")
-    if "SQ_INSTS_VALU" in vals and "SQ_ACTIVE_INST_VALU" in vals and "SQ_BUSY_CU_CYCLES" in vals:
-        out += ["", f"* VALU issue: SQ_ACTIVE_INST_VALU / SQ_BUSY_CU_CYCLES = "
-                    f"{vals['SQ_ACTIVE_INST_VALU'] / vals['SQ_BUSY_CU_CYCLES']:.3f}"]
+    out.append("")
+    if "GRBM_GUI_ACTIVE" in vals:
+        # GRBM_GUI_ACTIVE is summed over the 8 XCDs
+        cyc = vals["GRBM_GUI_ACTIVE"] / 8
+        out.append(f"* duration: {cyc:.0f} GPU cycles per dispatch (GRBM_GUI_ACTIVE / 8 XCDs)")
+        if "SQ_INSTS_VALU" in vals:
+            # a CU issues at most one wave64 VALU instruction per cycle (four
+            # SIMDs, four cycles each, no packed FP32)
+            out.append(f"* VALU issue: SQ_INSTS_VALU / (256 CUs x cycles) = "
+                       f"{vals['SQ_INSTS_VALU'] / (256 * cyc):.3f}")
     if "SQ_WAVE_CYCLES" in vals and "SQ_WAVES" in vals:
-        out += [f"* mean wave lifetime: {vals['SQ_WAVE_CYCLES'] / vals['SQ_WAVES']:.0f} cycles"]
+        out.append(f"* mean wave lifetime: SQ_WAVE_CYCLES / SQ_WAVES = {vals['SQ_WAVE_CYCLES'] / vals['SQ_WAVES']:.0f}")
     if "SQ_WAIT_INST_ANY" in vals and "SQ_WAVE_CYCLES" in vals:
-        out += [f"* SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES = {vals['SQ_WAIT_INST_ANY'] / vals['SQ_WAVE_CYCLES']:.3f}"]
+        out.append(f"* SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES = {vals['SQ_WAIT_INST_ANY'] / vals['SQ_WAVE_CYCLES']:.3f}")
     return "\n".join(out) + "\n"
 
 

@@ -581,8 +581,10 @@ __device__ __forceinline__ int pull_face(const KCase &p, const uint8_t *__restri
 // every population load (and finds the wall faces), gather_decode() decodes
 // and applies the wall rule.  A decode right after each load makes the node
 // wait for its loads one direction at a time (measured: 2.6x on the 3D
-// two-step kernel, +11 % on the 2D one); the tile kernels that pull several
-// nodes per thread issue all of their loads before decoding any.
+// two-step kernel, +11 % on the 2D one).  (Issuing the loads of all of a
+// thread's nodes in a tile kernel before decoding any measured the same in
+// 2D and left the 3D two-step kernel with phi values of undefined 16-bit
+// loads, which the compiler folded to NaN constants: 250 extra moves.)
 template <class L, int ST>
 struct Pulled {
     typename Store<ST>::T raw[L::NS][L::Q];
@@ -1357,16 +1359,16 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int gy, int t
     const long long nodes = (long long)p.nx * p.ny;
 
     // step 1: t -> t+1 on the tile and its halo, into LDS.  A thread owns
-    // the halo-tile nodes tid, tid + 256, ...; their pulls are issued G at a
-    // time before any of them is used, so that G nodes' loads are in flight
-    // together (occupancy is bounded by LDS, not by registers).
+    // the halo-tile nodes tid, tid + 256, ...; G of them are pulled before
+    // any is computed, so that (FP32, FP64) G nodes' loads are in flight
+    // together (occupancy is bounded by LDS, not by registers).  The 16-bit
+    // formats decode each node's values before the next node's loads.
     constexpr int K1 = (NE + NT - 1) / NT;
     constexpr int G = K1 < 3 ? K1 : 3;
 #pragma unroll
     for (int k0 = 0; k0 < K1; k0 += G) {
         Node<L, C> n[G];
         bool fluid[G];
-        Pulled<L, ST> r[kSplitPull<ST> ? G : 1];
         // issue this batch's loads ahead of other waves' arithmetic
         __builtin_amdgcn_s_setprio(2);
 #pragma unroll
@@ -1384,17 +1386,12 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int gy, int t
                 if (p.bc[y < 0 ? 2 : 3] == MDF_WALL) continue;
                 y = ((y % p.ny) + p.ny) % p.ny;
             }
-            // false: solid node
-            if constexpr (kSplitPull<ST>)
-                fluid[g] = gather_issue<L, ST, MASK, true, WIDE>(p, src, links, x, y, 0, n[g], r[g]);
-            else
-                fluid[g] = gather<L, ST, MASK, true, WIDE>(p, src, links, x, y, 0, n[g]);
+            fluid[g] = gather<L, ST, MASK, true, WIDE>(p, src, links, x, y, 0, n[g]);   // false: solid node
         }
         __builtin_amdgcn_s_setprio(0);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             if (!fluid[g]) continue;
-            if constexpr (kSplitPull<ST>) gather_decode<L, ST>(p, r[g], n[g]);
             const int e = tid + (k0 + g) * NT;
             Moments<L, C> m;
             moments<L, C>(p, n[g], m);
@@ -1589,7 +1586,9 @@ enum { kZKeepAll = 0, kZKeepUp = 1, kZKeepDown = 2 };
 // kZKeepAll) the halo ring, written to LDS.  Nodes behind a wall face are
 // skipped (step 2 takes the wall rule there); across a periodic face the
 // wrapped node is computed.  Each thread takes positions tid and tid + NT
-// and issues both nodes' loads before computing either.
+// and pulls both nodes before computing either (FP32 and FP64 issue both
+// nodes' loads together; the 16-bit formats decode each node's values
+// before the next node's loads).
 template <class L, int ST, int KEEP, bool MASK, bool WIDE>
 __device__ __forceinline__ void step2z_plane1(const KCase &p, const typename Store<ST>::T *__restrict__ src,
                                               const uint8_t *__restrict__ links, int x0, int y0, int z,
@@ -1611,7 +1610,6 @@ __device__ __forceinline__ void step2z_plane1(const KCase &p, const typename Sto
     Node<L, C> n[G];
     bool fluid[G];
     int pos[G];
-    Pulled<L, ST> r[kSplitPull<ST> ? G : 1];
     __builtin_amdgcn_s_setprio(2);          // issue the loads ahead of other waves' arithmetic
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -1639,17 +1637,12 @@ __device__ __forceinline__ void step2z_plane1(const KCase &p, const typename Sto
             if (p.bc[y < 0 ? 2 : 3] == MDF_WALL) continue;
             y = ((y % p.ny) + p.ny) % p.ny;
         }
-        // false: solid node
-        if constexpr (kSplitPull<ST>)
-            fluid[g] = gather_issue<L, ST, MASK, true, WIDE>(p, src, links, x, y, z, n[g], r[g]);
-        else
-            fluid[g] = gather<L, ST, MASK, true, WIDE>(p, src, links, x, y, z, n[g]);
+        fluid[g] = gather<L, ST, MASK, true, WIDE>(p, src, links, x, y, z, n[g]);   // false: solid node
     }
     __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         if (!fluid[g]) continue;
-        if constexpr (kSplitPull<ST>) gather_decode<L, ST>(p, r[g], n[g]);
         const int e = pos[g];
         Moments<L, C> m;
         moments<L, C>(p, n[g], m);
