@@ -119,6 +119,15 @@ typedef enum { MDF_PERIODIC = 0, MDF_WALL = 1 } mdf_bc;
 #define MDF_FIELD_STRESS 0x10u
 #define MDF_FIELD_VORT 0x20u
 #define MDF_FIELD_ALL 0x3fu
+/* Modifier of a field selection for mdf_step_emit and mdf_run_steady:
+ * every step adds its fields to out[case] instead of overwriting them, in
+ * the compute dtype, one rounding per step (out <- out + field(t)), so that
+ * after n steps out holds the sum over the n new times (their time mean
+ * times n); the caller initialises out.  Solid nodes add nothing.  Two-step
+ * launches contribute both of their steps.  The selected fields of each
+ * step are bitwise those of a one-step launch, so the sum is bitwise the
+ * sequential sum of the per-step fields. */
+#define MDF_FIELD_ACCUMULATE 0x40u
 
 /* Initial state kinds for mdf_init (init_data[case] is a device pointer in
  * the compute dtype, channel-major, unpadded):
@@ -210,7 +219,9 @@ mdf_status mdf_step(mdf_ctx *ctx, int32_t nsteps, void *stream);
 
 /* As mdf_step, and every step also writes the selected fields (MDF_FIELD_*)
  * at the new time into out[case] (channel-major, compute dtype, overwritten
- * each step: on return they hold the fields at the final time). */
+ * each step: on return they hold the fields at the final time; with
+ * MDF_FIELD_ACCUMULATE every step adds them instead).  MDF_EINVAL for
+ * unknown bits or no field selected. */
 mdf_status mdf_step_emit(mdf_ctx *ctx, int32_t nsteps, uint32_t fields, void *const *out,
                          void *stream);
 

@@ -717,7 +717,9 @@ static mdf_status step_impl(mdf_ctx *ctx, int32_t nsteps, uint32_t fields, void 
     if (ctx->latched != hipSuccess) return fail(ctx, MDF_EDEVICE, "earlier device error: %s",
                                                 hipGetErrorString(ctx->latched));
     if (nsteps < 0) return fail(ctx, MDF_EINVAL, "mdf_step: nsteps < 0");
-    if (fields & ~MDF_FIELD_ALL) return fail(ctx, MDF_EINVAL, "mdf_step_emit: unknown field bits");
+    if (fields & ~(MDF_FIELD_ALL | MDF_FIELD_ACCUMULATE))
+        return fail(ctx, MDF_EINVAL, "mdf_step_emit: unknown field bits");
+    if (fields && !(fields & MDF_FIELD_ALL)) return fail(ctx, MDF_EINVAL, "mdf_step_emit: no fields selected");
     if (fields) {
         if (!out) return fail(ctx, MDF_EINVAL, "mdf_step_emit: out is NULL");
         for (int k = 0; k < ctx->ncases; ++k)
@@ -815,7 +817,9 @@ mdf_status mdf_run_steady(mdf_ctx *ctx, double tol, int32_t K, int64_t max_steps
 {
     if (!ctx) return fail(nullptr, MDF_EINVAL, "mdf_run_steady: ctx is NULL");
     if (!(tol > 0.0) || K < 1 || max_steps < 0) return fail(ctx, MDF_EINVAL, "mdf_run_steady: bad tol/K/max_steps");
-    if (fields & ~MDF_FIELD_ALL) return fail(ctx, MDF_EINVAL, "mdf_run_steady: unknown field bits");
+    if (fields & ~(MDF_FIELD_ALL | MDF_FIELD_ACCUMULATE))
+        return fail(ctx, MDF_EINVAL, "mdf_run_steady: unknown field bits");
+    if (fields && !(fields & MDF_FIELD_ALL)) return fail(ctx, MDF_EINVAL, "mdf_run_steady: no fields selected");
     if (fields) {
         if (!out) return fail(ctx, MDF_EINVAL, "mdf_run_steady: out is NULL");
         for (int k = 0; k < ctx->ncases; ++k)

@@ -987,10 +987,21 @@ __device__ __forceinline__ int field_channels(uint32_t fields)
     return nch;
 }
 
-// A solid node emits zero in every selected channel.
+// One emitted value: written, or (MDF_FIELD_ACCUMULATE) added to what the
+// channel holds.
+template <class C, class IX>
+__device__ __forceinline__ void emit_value(C *ch, IX node, C v, bool acc)
+{
+    if (acc) v += *elem(ch, node);
+    put_value<false>(ch, node, v);
+}
+
+// A solid node emits zero in every selected channel (adds nothing when
+// accumulating).
 template <class L, class C, class IX>
 __device__ __forceinline__ void write_zero_fields(uint32_t fields, C *__restrict__ out, IX node, long long nodes)
 {
+    if (fields & MDF_FIELD_ACCUMULATE) return;
     const int nch = field_channels<L>(fields);
     for (int ch = 0; ch < nch; ++ch) put_value<false>(out + ch * nodes, node, C(0));
 }
@@ -1026,30 +1037,31 @@ __device__ __forceinline__ void write_fields(const KCase &p, const Node<L, C> &n
     for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int b = 0; b < D; ++b) G[a][b] = gscale * mne[a][b];
+    const bool acc = (fields & MDF_FIELD_ACCUMULATE) != 0;
     long long ch = 0;
     if (fields & MDF_FIELD_MOMENTS) {
 #pragma unroll
-        for (int a = 0; a <= L::D; ++a) put_value<false>(out + (ch++) * nodes, node, m.ubar[a]);
-        put_value<false>(out + (ch++) * nodes, node, m.P);
+        for (int a = 0; a <= L::D; ++a) emit_value(out + (ch++) * nodes, node, m.ubar[a], acc);
+        emit_value(out + (ch++) * nodes, node, m.P, acc);
     }
     if (fields & MDF_FIELD_GRAD) {
 #pragma unroll
         for (int a = 0; a < D; ++a)
 #pragma unroll
-            for (int b = 0; b < D; ++b) put_value<false>(out + (ch++) * nodes, node, G[a][b]);
+            for (int b = 0; b < D; ++b) emit_value(out + (ch++) * nodes, node, G[a][b], acc);
     }
     if (fields & MDF_FIELD_DIV) {
         C dv = G[0][0];
 #pragma unroll
         for (int a = 1; a < D; ++a) dv += G[a][a];
-        put_value<false>(out + (ch++) * nodes, node, dv);                  // eq. 3-16a
+        emit_value(out + (ch++) * nodes, node, dv, acc);                  // eq. 3-16a
     }
     if (fields & MDF_FIELD_STRAIN) {
 #pragma unroll
         for (int a = 0; a < D; ++a)
 #pragma unroll
             for (int b = a; b < D; ++b)
-                put_value<false>(out + (ch++) * nodes, node, C(0.5) * (G[a][b] + G[b][a]));   // eq. 3-17
+                emit_value(out + (ch++) * nodes, node, C(0.5) * (G[a][b] + G[b][a]), acc);   // eq. 3-17
     }
     if (fields & MDF_FIELD_STRESS) {
         const C sc = -kpar<C>(p.rho0, p.rho0f) * (C(1) - C(0.5) * kpar<C>(p.s1, p.s1f));   // eq. 3-17a
@@ -1057,17 +1069,17 @@ __device__ __forceinline__ void write_fields(const KCase &p, const Node<L, C> &n
         for (int a = 0; a < D; ++a)
 #pragma unroll
             for (int b = a; b < D; ++b)
-                put_value<false>(out + (ch++) * nodes, node, sc * (mne[a][b] + mne[b][a]));
+                emit_value(out + (ch++) * nodes, node, sc * (mne[a][b] + mne[b][a]), acc);
     }
     if (fields & MDF_FIELD_VORT) {
         // omega = curl u; Omega_ab = (G_ab - G_ba)/2 (eq. 3-18) and
         // Omega_ab = -eps_abg omega_g / 2 (eq. 3-19)
         if (D == 2) {
-            put_value<false>(out + (ch++) * nodes, node, G[1][0] - G[0][1]);
+            emit_value(out + (ch++) * nodes, node, G[1][0] - G[0][1], acc);
         } else {
-            put_value<false>(out + (ch++) * nodes, node, G[2 % D][1 % D] - G[1 % D][2 % D]);
-            put_value<false>(out + (ch++) * nodes, node, G[0][2 % D] - G[2 % D][0]);
-            put_value<false>(out + (ch++) * nodes, node, G[1 % D][0] - G[0][1 % D]);
+            emit_value(out + (ch++) * nodes, node, G[2 % D][1 % D] - G[1 % D][2 % D], acc);
+            emit_value(out + (ch++) * nodes, node, G[0][2 % D] - G[2 % D][0], acc);
+            emit_value(out + (ch++) * nodes, node, G[1 % D][0] - G[0][1 % D], acc);
         }
     }
 }
@@ -1395,6 +1407,14 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int gy, int t
             const int e = tid + (k0 + g) * NT;
             Moments<L, C> m;
             moments<L, C>(p, n[g], m);
+            if (EMIT && (fields & MDF_FIELD_ACCUMULATE)) {
+                // accumulated fields count every step: step 1's fields of
+                // the tile's own nodes (not of its halo)
+                const int ex = e % W, ey = e / W;
+                const int x = x0 - 1 + ex, y = y0 - 1 + ey;
+                if (ex >= 1 && ex <= kF2X && ey >= 1 && ey <= TY && x < p.nx && y < p.ny)
+                    write_fields<L, C>(p, n[g], m, fields, out, grid_ix<WIDE>(x, y, 0, p.ny, p.nx), nodes);
+            }
 #pragma unroll
             for (int a = 0; a < L::NS; ++a) {
                 C fo[L::Q];
@@ -1589,9 +1609,10 @@ enum { kZKeepAll = 0, kZKeepUp = 1, kZKeepDown = 2 };
 // and pulls both nodes before computing either (FP32 and FP64 issue both
 // nodes' loads together; the 16-bit formats decode each node's values
 // before the next node's loads).
-template <class L, int ST, int KEEP, bool MASK, bool WIDE>
+template <class L, int ST, int KEEP, bool EMIT, bool MASK, bool WIDE>
 __device__ __forceinline__ void step2z_plane1(const KCase &p, const typename Store<ST>::T *__restrict__ src,
-                                              const uint8_t *__restrict__ links, int x0, int y0, int z,
+                                              const uint8_t *__restrict__ links, uint32_t fields,
+                                              typename Store<ST>::C *__restrict__ out, int x0, int y0, int z,
                                               typename Store<ST>::T *__restrict__ ip,
                                               typename Store<ST>::T *__restrict__ zs)
 {
@@ -1646,6 +1667,14 @@ __device__ __forceinline__ void step2z_plane1(const KCase &p, const typename Sto
         const int e = pos[g];
         Moments<L, C> m;
         moments<L, C>(p, n[g], m);
+        if (EMIT && KEEP == kZKeepAll && e < NI && (fields & MDF_FIELD_ACCUMULATE)) {
+            // accumulated fields count every step: step 1's fields of the
+            // tile's own nodes on the chunk's planes
+            const int x = x0 + e % TX, y = y0 + e / TX;
+            if (x < p.nx && y < p.ny)
+                write_fields<L, C>(p, n[g], m, fields, out, grid_ix<WIDE>(x, y, z, p.ny, p.nx),
+                                   (long long)p.nx * p.ny * p.nz);
+        }
 #pragma unroll
         for (int a = 0; a < L::NS; ++a) {
             C fo[L::Q];
@@ -1827,14 +1856,16 @@ k_step2z(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, type
     T *const base = lds.v;
     auto ips = [&](int r) { return base + (r & 1) * LD::IPS; };
     auto zsl = [&](int r) { return base + 2 * LD::IPS + (r % 3) * LD::ZS; };
-    step2z_plane1<L, ST, kZKeepUp, MASK, WIDE>(p, src, links, x0, y0, z0 - 1, ips(0), zsl(0));
-    step2z_plane1<L, ST, kZKeepAll, MASK, WIDE>(p, src, links, x0, y0, z0, ips(1), zsl(1));
+    step2z_plane1<L, ST, kZKeepUp, EMIT, MASK, WIDE>(p, src, links, fields, out, x0, y0, z0 - 1, ips(0), zsl(0));
+    step2z_plane1<L, ST, kZKeepAll, EMIT, MASK, WIDE>(p, src, links, fields, out, x0, y0, z0, ips(1), zsl(1));
     const int nzc = z1 - z0;
     for (int r = 1; r <= nzc; ++r) {
         if (r < nzc)
-            step2z_plane1<L, ST, kZKeepAll, MASK, WIDE>(p, src, links, x0, y0, z0 + r, ips(r + 1), zsl(r + 1));
+            step2z_plane1<L, ST, kZKeepAll, EMIT, MASK, WIDE>(p, src, links, fields, out, x0, y0, z0 + r,
+                                                              ips(r + 1), zsl(r + 1));
         else
-            step2z_plane1<L, ST, kZKeepDown, MASK, WIDE>(p, src, links, x0, y0, z0 + r, ips(r + 1), zsl(r + 1));
+            step2z_plane1<L, ST, kZKeepDown, EMIT, MASK, WIDE>(p, src, links, fields, out, x0, y0, z0 + r,
+                                                               ips(r + 1), zsl(r + 1));
         __syncthreads();
         step2z_plane2<L, ST, EMIT, MASK, NTST, WIDE>(p, dst, links, fields, out, x0, y0, z0 + r - 1, ips(r),
                                                      zsl(r - 1), zsl(r), zsl(r + 1));

@@ -29,6 +29,7 @@ F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
 PERIODIC, WALL = 0, 1
 FIELD_MOMENTS, FIELD_GRAD, FIELD_DIV, FIELD_STRAIN, FIELD_STRESS, FIELD_VORT = 1, 2, 4, 8, 16, 32
 FIELD_ALL = 0x3F
+FIELD_ACCUMULATE = 0x40        # with step_emit / run_steady: every step adds its fields to `out`
 INIT_REST, INIT_FIELDS, INIT_FIELDS_GRAD, INIT_POPULATIONS = 0, 1, 2, 3
 
 STORAGE_NAMES = {"f64": F64, "f32": F32, "f16dev": F16DEV, "bf16dev": BF16DEV}
