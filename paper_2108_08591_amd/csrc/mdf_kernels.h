@@ -609,7 +609,18 @@ __device__ __forceinline__ bool gather_issue(const KCase &p, const typename Stor
         int sx, sy, sz;
         const int face = pull_face<L, MASK, PULL, WIDE>(p, links, lb, x, y, z, i, sx, sy, sz);
         r.fc[i] = face;
-        if (face < 0) {
+        if constexpr (!WIDE) {
+            // every lane reads plane i, at the upstream node or (a wall or a
+            // solid link; gather() re-reads those lanes) at its own: one
+            // 32-bit offset per direction with each plane's scalar base, for
+            // every set.  The empty asm keeps the optimizer from widening the
+            // per-lane choice to a 64-bit address select.
+            uint32_t k = (face < 0) ? grid_ix<false>(sx, sy, sz, p.ny, p.pitch).k : own.k;
+            asm volatile("" : "+v"(k));
+#pragma unroll
+            for (int a = 0; a < L::NS; ++a)
+                if (i < qset<L>(a + L::A0)) r.raw[a][i] = *elem(src + plane_of<L>(a, i) * p.dstride, Ix32{k});
+        } else if (face < 0) {
             const auto k = grid_ix<WIDE>(sx, sy, sz, p.ny, p.pitch);
 #pragma unroll
             for (int a = 0; a < L::NS; ++a)
@@ -688,6 +699,25 @@ __device__ __forceinline__ bool gather(const KCase &p, const typename Store<ST>:
     if constexpr (kSplitPull<ST>) {
         Pulled<L, ST> r;
         if (!gather_issue<L, ST, MASK, PULL, WIDE>(p, src, links, x, y, z, n, r)) return false;
+        if constexpr (!WIDE) {
+            // the lanes that pulled across a wall or from a solid node read
+            // the opposite direction at their own node, in a branch that
+            // interior wavefronts skip
+            bool wall = false;
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) wall |= r.fc[i] >= 0;
+            if (__builtin_amdgcn_ballot_w64(wall) != 0) {
+                const auto own = grid_ix<false>(x, y, z, p.ny, p.pitch);
+#pragma unroll
+                for (int i = 0; i < L::Q; ++i) {
+                    if (r.fc[i] < 0) continue;
+                    const int j = L::opp[i];
+#pragma unroll
+                    for (int a = 0; a < L::NS; ++a)
+                        if (i < qset<L>(a + L::A0)) r.raw[a][i] = *elem(src + plane_of<L>(a, j) * p.dstride, own);
+                }
+            }
+        }
         gather_decode<L, ST>(p, r, n);
         return true;
     } else {

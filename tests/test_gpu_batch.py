@@ -73,25 +73,32 @@ def test_batch_bitwise_equals_single_cases(with_mask, form):
         assert b.time(k) == 22
 
 
-@pytest.mark.parametrize("form", [0, 2])
-def test_batch_beyond_the_cache_bitwise_equals_single_cases(form):
+@pytest.mark.parametrize("storage,form", [("f32", 0), ("f32", 2), ("f16dev", 0), ("f16dev", 2)])
+def test_batch_beyond_the_cache_bitwise_equals_single_cases(storage, form):
     """A batch whose population buffers together exceed the 256 MB Infinity
-    Cache (336 MB): its launches store with the non-temporal hint and address
-    nodes by 32-bit offsets, while each case alone fits the cache and runs the
-    plain form.  Populations and fields agree bit for bit."""
-    cav = C.cavity_case(N=1100, Re=1000.0)
-    ch = C.poiseuille_case(900, 700, umax=0.05, s1=1.3)
-    box = C.cavity_case(N=1000, Re=400.0, U=0.08)
-    box.shape = (1000, 900)
+    Cache (336 MB in FP32, 341 MB in FP16): its launches store with the
+    non-temporal hint and address nodes by 32-bit offsets (the 16-bit pull
+    then reads every set of a direction with one offset), while each case
+    alone fits the cache and runs the plain form.  Populations and fields
+    agree bit for bit, walls, a moving lid, a channel force and an obstacle
+    included."""
+    f = 1.0 if storage == "f32" else 1.45
+    n = lambda v: int(round(v * f / 4)) * 4
+    cav = C.cavity_case(N=n(1100), Re=1000.0)
+    ch = C.poiseuille_case(n(900), n(700), umax=0.05, s1=1.3)
+    box = C.cavity_case(N=n(1000), Re=400.0, U=0.08)
+    box.shape = (n(1000), n(900))
     specs = [cav, ch, box]
     mask = np.zeros(box.fshape, np.uint8)
     mask[300:360, 400:470] = 1
     masks = [None, None, mask]
     stream = torch.cuda.Stream()
-    _say(f"[batch] beyond the cache, bitwise vs single, form={form}")
-    b = mdf.Solver(specs, storage="f32", solid=masks, device=DEV, stream=stream)
-    total = sum(2 * 15 * 4 * ((s.shape[0] + 31) // 32 * 32) * s.shape[1] for s in specs)
-    assert total > 256 << 20
+    _say(f"[batch] beyond the cache, bitwise vs single, {storage} form={form}")
+    b = mdf.Solver(specs, storage=storage, solid=masks, device=DEV, stream=stream, u_ref=0.1)
+    sb = 4 if storage == "f32" else 2
+    pitch = 128 // sb
+    sizes = [2 * 15 * sb * ((s.shape[0] + pitch - 1) // pitch * pitch) * s.shape[1] for s in specs]
+    assert sum(sizes) > 256 << 20 and max(sizes) < 256 << 20
     b.set_launch(128, 2, 8, form)
     fields = mdf.FIELD_VORT | mdf.FIELD_STRAIN
     out_b = b.new_field_buffers(fields)
@@ -99,8 +106,8 @@ def test_batch_beyond_the_cache_bitwise_equals_single_cases(form):
     b.step_emit(6, fields, out_b)
     stream.synchronize()
     for k, s in enumerate(specs):
-        single = mdf.Solver([s], storage="f32", solid=[masks[k]] if masks[k] is not None else None, device=DEV,
-                            stream=stream)
+        single = mdf.Solver([s], storage=storage, solid=[masks[k]] if masks[k] is not None else None, device=DEV,
+                            stream=stream, u_ref=0.1)
         out_s = single.new_field_buffers(fields)
         single.step(5)
         single.step_emit(6, fields, out_s)
