@@ -1477,17 +1477,8 @@ __device__ __forceinline__ void step2_tile(const KCase &p, int gx, int gy, int t
         load_sources<L, C>(p, (long long)y * p.nx + x, n);
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
-            const int sx = x - L::cx[i], sy = y - L::cy[i];
-            int face = -1;
-            if (L::cx[i] != 0) {
-                if (sx < 0) { if (p.bc[0] == MDF_WALL) face = 0; }
-                else if (sx >= p.nx) { if (p.bc[1] == MDF_WALL) face = 1; }
-            }
-            if (L::cy[i] != 0) {
-                if (sy < 0) { if (p.bc[2] == MDF_WALL) { if (face < 0) face = 2; } }
-                else if (sy >= p.ny) { if (p.bc[3] == MDF_WALL) { if (face < 0) face = 3; } }
-            }
-            if (MASK && face < 0 && ((lb >> i) & 1u)) face = 6;
+            int sx, sy, sz;            // (upstream values come from the LDS tile)
+            const int face = pull_face<L, MASK, true, WIDE>(p, links, lb, x, y, 0, i, sx, sy, sz);
             const C w = C(L::w[i]);
             if (face < 0) {
                 const int k = le - L::cx[i] - L::cy[i] * W;
@@ -1785,21 +1776,8 @@ __device__ __forceinline__ void step2z_plane2(const KCase &p, typename Store<ST>
     load_sources<L, C>(p, ((long long)z * p.ny + y) * p.nx + x, n);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        const int sx = x - L::cx[i], sy = y - L::cy[i], sz = z - L::cz[i];
-        int face = -1;
-        if (L::cx[i] != 0) {
-            if (sx < 0) { if (p.bc[0] == MDF_WALL) face = 0; }
-            else if (sx >= p.nx) { if (p.bc[1] == MDF_WALL) face = 1; }
-        }
-        if (L::cy[i] != 0) {
-            if (sy < 0) { if (p.bc[2] == MDF_WALL) face = 2; }
-            else if (sy >= p.ny) { if (p.bc[3] == MDF_WALL) face = 3; }
-        }
-        if (L::cz[i] != 0) {
-            if (sz < 0) { if (p.bc[4] == MDF_WALL) face = 4; }
-            else if (sz >= p.nz) { if (p.bc[5] == MDF_WALL) face = 5; }
-        }
-        if (MASK && face < 0 && ((lb >> i) & 1u)) face = 6;
+        int sx, sy, sz;                // (upstream values come from the LDS slots)
+        const int face = pull_face<L, MASK, true, WIDE>(p, links, lb, x, y, z, i, sx, sy, sz);
         const C w = C(L::w[i]);
         if (face < 0) {
 #pragma unroll
