@@ -1569,9 +1569,14 @@ k_step2_batch(const BatchEntry *__restrict__ tab, const int *__restrict__ meta,
 // f*(t+1) (see Step2ZLds) is 68 KB for FP32, 70 KB for FP64 and 35 KB for
 // the 16-bit formats (D3Q7, four sets), so two (four) blocks fit a CU's
 // 160 KB.
-template <int ST> struct Fuse2Z { static constexpr int TX = 64, TY = 4; };
-template <> struct Fuse2Z<MDF_F32> { static constexpr int TX = 32, TY = 8; };
-template <> struct Fuse2Z<MDF_F64> { static constexpr int TX = 32, TY = 4; };
+// MINW: waves per SIMD the kernel is compiled for (its register budget).
+// Four blocks of the 16-bit formats fit a CU's LDS; at the 158 VGPRs the
+// compiler would otherwise take only three do, and the four-wave budget
+// (128 VGPRs, 15 of them spilled) measured +5 % (FP16) and +8 % (BF16).
+// FP32 and FP64 are bound to two blocks per CU by their LDS.
+template <int ST> struct Fuse2Z { static constexpr int TX = 64, TY = 4, MINW = 4; };
+template <> struct Fuse2Z<MDF_F32> { static constexpr int TX = 32, TY = 8, MINW = 1; };
+template <> struct Fuse2Z<MDF_F64> { static constexpr int TX = 32, TY = 4, MINW = 1; };
 
 // The directions of an axis-link 3D lattice by their z-component: the
 // in-plane ones (c_z = 0) in lattice order, and the +z and -z links.
@@ -1845,7 +1850,7 @@ __device__ __forceinline__ void step2z_plane2(const KCase &p, typename Store<ST>
 // halo ring ((TX + TY) 2 / (TX TY) of a read) and the two chunk-end planes
 // (2 / zc of a read).  Like k_step2, f*(t+1) never reaches HBM.
 template <class L, int ST, bool EMIT, bool MASK, bool NTST = false, bool WIDE = true>
-__global__ void __launch_bounds__(Fuse2Z<ST>::TX * Fuse2Z<ST>::TY)
+__global__ void __launch_bounds__(Fuse2Z<ST>::TX * Fuse2Z<ST>::TY, Fuse2Z<ST>::MINW)
 k_step2z(KCase p, Tiling tl, const typename Store<ST>::T *__restrict__ src, typename Store<ST>::T *__restrict__ dst,
          const uint8_t *__restrict__ links, uint32_t fields, typename Store<ST>::C *__restrict__ out)
 {
