@@ -611,7 +611,7 @@ __device__ __forceinline__ bool gather_issue(const KCase &p, const typename Stor
         r.fc[i] = face;
         if constexpr (!WIDE) {
             // every lane reads plane i, at the upstream node or (a wall or a
-            // solid link; gather() re-reads those lanes) at its own: one
+            // solid link; re-read below) at its own: one
             // 32-bit offset per direction with each plane's scalar base, for
             // every set.  The empty asm keeps the optimizer from widening the
             // per-lane choice to a 64-bit address select.
@@ -630,6 +630,24 @@ __device__ __forceinline__ bool gather_issue(const KCase &p, const typename Stor
 #pragma unroll
             for (int a = 0; a < L::NS; ++a)
                 if (i < qset<L>(a + L::A0)) r.raw[a][i] = *elem(src + plane_of<L>(a, j) * p.dstride, own);
+        }
+    }
+    if constexpr (!WIDE) {
+        // the lanes that pulled across a wall or from a solid node read the
+        // opposite direction at their own node, in a branch that interior
+        // wavefronts skip
+        bool wall = false;
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) wall |= r.fc[i] >= 0;
+        if (__builtin_amdgcn_ballot_w64(wall) != 0) {
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) {
+                if (r.fc[i] < 0) continue;
+                const int j = L::opp[i];
+#pragma unroll
+                for (int a = 0; a < L::NS; ++a)
+                    if (i < qset<L>(a + L::A0)) r.raw[a][i] = *elem(src + plane_of<L>(a, j) * p.dstride, own);
+            }
         }
     }
     return true;
@@ -699,25 +717,6 @@ __device__ __forceinline__ bool gather(const KCase &p, const typename Store<ST>:
     if constexpr (kSplitPull<ST>) {
         Pulled<L, ST> r;
         if (!gather_issue<L, ST, MASK, PULL, WIDE>(p, src, links, x, y, z, n, r)) return false;
-        if constexpr (!WIDE) {
-            // the lanes that pulled across a wall or from a solid node read
-            // the opposite direction at their own node, in a branch that
-            // interior wavefronts skip
-            bool wall = false;
-#pragma unroll
-            for (int i = 0; i < L::Q; ++i) wall |= r.fc[i] >= 0;
-            if (__builtin_amdgcn_ballot_w64(wall) != 0) {
-                const auto own = grid_ix<false>(x, y, z, p.ny, p.pitch);
-#pragma unroll
-                for (int i = 0; i < L::Q; ++i) {
-                    if (r.fc[i] < 0) continue;
-                    const int j = L::opp[i];
-#pragma unroll
-                    for (int a = 0; a < L::NS; ++a)
-                        if (i < qset<L>(a + L::A0)) r.raw[a][i] = *elem(src + plane_of<L>(a, j) * p.dstride, own);
-                }
-            }
-        }
         gather_decode<L, ST>(p, r, n);
         return true;
     } else {
@@ -1570,8 +1569,8 @@ k_step2_batch(const BatchEntry *__restrict__ tab, const int *__restrict__ meta,
 // the 16-bit formats (D3Q7, four sets), so two (four) blocks fit a CU's
 // 160 KB.
 // MINW: waves per SIMD the kernel is compiled for (its register budget).
-// Four blocks of the 16-bit formats fit a CU's LDS; at the 158 VGPRs the
-// compiler would otherwise take only three do, and the four-wave budget
+// Four blocks of the 16-bit formats fit a CU's LDS, but with the 158 VGPRs
+// the compiler would otherwise use only three fit; the four-wave budget
 // (128 VGPRs, 15 of them spilled) measured +5 % (FP16) and +8 % (BF16).
 // FP32 and FP64 are bound to two blocks per CU by their LDS.
 template <int ST> struct Fuse2Z { static constexpr int TX = 64, TY = 4, MINW = 4; };
