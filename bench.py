@@ -858,15 +858,46 @@ def warmstart_study(out_path, n_train=1024, n_test=32, N=128, epochs=30, batch=1
         json.dump(rec, fh, indent=1)
 
 
-def coarse_warmstart_study(out_path, n_train=4096, n_test=32, N=128, epochs=36, batch=16, lr=1e-3):
+def _coarse_levels(cases, levels, stream, log=None):
+    """The coarse solves of the coarse-informed warm start (FP32, residual
+    1e-6): with levels = 1 the grid twice as coarse from rest; with levels =
+    2 first the grid four times as coarse from rest, then the grid twice as
+    coarse started from it.  Returns the twice-coarse cases, their solver and
+    status and steps, the solutions interpolated to the fine grids (twice
+    coarse, and four times coarse or None), the four-times-coarse steps (or
+    None) and the wall time."""
+    import numpy as np
+    from paper_2108_08591_amd import warmstart as WS
+    t0 = time.perf_counter()
+    c2 = WS.coarse_cases(cases)
+    up4 = None
+    init2 = None
+    steps4 = None
+    if levels == 2:
+        c4 = WS.coarse_cases(cases, factor=4)
+        s4, st4, steps4, _, _ = WS.solve(c4, "f32", tol=1e-6, max_steps=300000, stream=stream, log=log)
+        init2 = [u if u is not None else np.zeros((7, c["N"], c["N"]), np.float32)
+                 for u, c in zip(WS.upsampled_init(c2, c4, s4, st4), c2)]
+        up4 = WS.upsampled_init(cases, c4, s4, st4, factor=4)
+        del s4
+    s2, st2, steps2, _, _ = WS.solve(c2, "f32", tol=1e-6, max_steps=300000, init=init2, stream=stream, log=log)
+    up2 = WS.upsampled_init(cases, c2, s2, st2)
+    import torch
+    torch.cuda.synchronize()
+    return c2, s2, st2, steps2, up2, up4, steps4, time.perf_counter() - t0
+
+
+def coarse_warmstart_study(out_path, n_train=4096, n_test=32, N=128, epochs=36, batch=16, lr=1e-3, levels=1):
     """Warm start informed by a coarse solve (an extension of the learned
     warm start): each case is first solved on a grid twice as coarse (FP32,
     residual 1e-6), its steady fields are interpolated to the fine grid, and
     the encoder-decoder, given them as extra inputs, predicts the correction
-    to them.  Compared on held-out cases (FP64, residual 1e-8): cold start,
-    the interpolated coarse solution alone (nested iteration, the method
-    without the network), and coarse solution + network.  Warm wall times
-    include the coarse solve and the inference."""
+    to them.  With levels = 2 a grid four times as coarse is solved first; it
+    starts the twice-coarse solve and is a second input of the network.
+    Compared on held-out cases (FP64, residual 1e-8): cold start, the
+    interpolated coarse solution alone (nested iteration, the method without
+    the network), and coarse solution + network.  Warm wall times include
+    the coarse solves and the inference."""
     import numpy as np
     import torch
     from paper_2108_08591_amd import nn
@@ -875,20 +906,19 @@ def coarse_warmstart_study(out_path, n_train=4096, n_test=32, N=128, epochs=36, 
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     rec = {"N": N, "n_train": n_train, "n_test": n_test, "epochs": epochs, "batch": batch, "lr": lr,
-           "coarse_factor": 2, "coarse_solve": "FP32, residual 1e-6"}
+           "coarse_factor": 2, "coarse_levels": levels, "coarse_solve": "FP32, residual 1e-6"}
     tr = WS.warmstart_cases(n_train, N, seed=20210819)
     te = WS.warmstart_cases(n_test, N, seed=20210820)
     solver, st, steps, _, wall = WS.solve(tr, "f32", tol=1e-7, max_steps=300000, stream=stream, log=log)
-    trc = WS.coarse_cases(tr)
-    csolver, cst, _, _, cwall_tr = WS.solve(trc, "f32", tol=1e-6, max_steps=300000, stream=stream, log=log)
-    up_tr = WS.upsampled_init(tr, trc, csolver, cst)
+    trc, csolver, cst, _, up_tr, up4_tr, _, cwall_tr = _coarse_levels(tr, levels, stream, log)
     del csolver
     good = [k for k in range(n_train) if st[k] == 0 and cst[k] == 0]
     rec.update({"datagen_wall_s": round(wall, 1), "coarse_datagen_wall_s": round(cwall_tr, 1),
                 "train_cases_used": len(good)})
     log(json.dumps({k: rec[k] for k in ("datagen_wall_s", "coarse_datagen_wall_s", "train_cases_used")}))
-    data = WS.dataset([tr[k] for k in good], _Subset(solver, good), log=log, coarse=[up_tr[k] for k in good])
-    del solver, up_tr
+    data = WS.dataset([tr[k] for k in good], _Subset(solver, good), log=log, coarse=[up_tr[k] for k in good],
+                      coarse2=None if up4_tr is None else [up4_tr[k] for k in good])
+    del solver, up_tr, up4_tr
     torch.cuda.empty_cache()
     nv = min(64, len(good) // 8)
     val = {k: v[-nv:] for k, v in data.items()}
@@ -902,14 +932,9 @@ def coarse_warmstart_study(out_path, n_train=4096, n_test=32, N=128, epochs=36, 
     del data, val
     # held-out cases
     cold, cst_te, csteps, _, cwall = WS.solve(te, "f64", tol=1e-8, max_steps=600000, stream=stream, log=log)
+    tec, cs_te, cst2, csteps2, up_te, up4_te, csteps4, t_coarse = _coarse_levels(te, levels, stream)
     t0 = time.perf_counter()
-    tec = WS.coarse_cases(te)
-    cs_te, cst2, csteps2, _, _ = WS.solve(tec, "f32", tol=1e-6, max_steps=300000, stream=stream)
-    up_te = WS.upsampled_init(te, tec, cs_te, cst2)
-    torch.cuda.synchronize()
-    t_coarse = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    pred = WS.predict(model, te, with_grad=True, coarse=up_te)
+    pred = WS.predict(model, te, with_grad=True, coarse=up_te, coarse2=up4_te)
     torch.cuda.synchronize()
     t_inf = time.perf_counter() - t0
     rest = np.zeros((7, N, N))
@@ -922,6 +947,8 @@ def coarse_warmstart_study(out_path, n_train=4096, n_test=32, N=128, epochs=36, 
     exact = [WS.solution_init(cold, k) for k in range(n_test)]
     ok = [k for k in range(n_test) if cst_te[k] == 0 and wst[k] == 0 and nst[k] == 0]
     coarse_equiv = float(csteps2.sum()) / 4.0          # coarse node-steps in fine node-steps
+    if csteps4 is not None:
+        coarse_equiv += float(csteps4.sum()) / 16.0
     perr_net = [WS.prediction_error(init_net[k], exact[k], te[k]["mask"]) for k in ok]
     perr_nest = [WS.prediction_error(init_nested[k], exact[k], te[k]["mask"]) for k in ok]
     errs = [WS.field_error(cold, where[k][0], k, where[k][1]) for k in ok]
@@ -1249,6 +1276,8 @@ def main():
     ap.add_argument("--ws-lr", type=float, default=1e-3)
     ap.add_argument("--ws-batch", type=int, default=16)
     ap.add_argument("--ws-clip", type=float, default=0.0, help="target clip in standard deviations (0: none)")
+    ap.add_argument("--ws-levels", type=int, default=1, choices=[1, 2],
+                    help="coarse-informed warm start: coarse grids solved first (2: four and two times coarser)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -1270,7 +1299,7 @@ def main():
         return
     if args.coarse_warmstart_study:
         coarse_warmstart_study(args.coarse_warmstart_study, n_train=args.ws_train, N=args.ws_n,
-                               epochs=args.ws_epochs, lr=args.ws_lr, batch=args.ws_batch)
+                               epochs=args.ws_epochs, lr=args.ws_lr, batch=args.ws_batch, levels=args.ws_levels)
         return
     if args.restart_study:
         restart_study(args.restart_study)

@@ -23,7 +23,7 @@ import torch
 from . import mdf
 
 FEATURES = 6          # solid mask, Re feature, lid-speed feature, x, y, wall distance
-COARSE_FEATURES = 8   # optional: a coarse-grid solution in target scales (7) and its validity flag
+COARSE_FEATURES = 8   # optional, once or twice: a coarse-grid solution in target scales (7) and its flag
 IN_CH = 32            # features padded to the 32-channel granularity of the kernels
 OUT_CH = 7            # P, u, v, du/dx, du/dy, dv/dx, dv/dy
 LEVELS = (32, 64, 128, 256)
@@ -405,10 +405,11 @@ class UNet:
 
 # ---------------------------------------------------------------- data
 
-def input_features(N, mask, Re, U, coarse=None):
+def input_features(N, mask, Re, U, coarse=None, coarse2=None):
     """Per-node features: solid flag, (log10 Re - 2), U / 0.1 - 0.75, the
     node coordinates in [-1, 1] and the distance to the nearest solid node or
-    cavity wall (in units of N; 0 inside solids); zero-padded to IN_CH
+    cavity wall (in units of N; 0 inside solids); optionally one or two
+    interpolated coarse-grid solutions with their flags; zero-padded to IN_CH
     channels.  Returns float32 [N, N, IN_CH] ([y, x, c])."""
     from scipy.ndimage import distance_transform_edt
     f = np.zeros((N, N, IN_CH), np.float32)
@@ -429,6 +430,12 @@ def input_features(N, mask, Re, U, coarse=None):
         # raw_targets ([N, N, OUT_CH]) and a flag saying it exists
         f[..., FEATURES:FEATURES + OUT_CH] = coarse
         f[..., FEATURES + OUT_CH] = 1.0
+    if coarse2 is not None:
+        # a second, coarser solution in the same scales: with the first it
+        # tells the network how the solution moves with the grid spacing
+        k = FEATURES + COARSE_FEATURES
+        f[..., k:k + OUT_CH] = coarse2
+        f[..., k + OUT_CH] = 1.0
     return f
 
 

@@ -148,11 +148,13 @@ def upsampled_init(cases: List[dict], coarse: List[dict], solver, status, factor
 
 
 def dataset(cases: List[dict], solver, log: Optional[Callable[[str], None]] = None,
-            coarse: Optional[List[Optional[np.ndarray]]] = None) -> Dict[str, torch.Tensor]:
+            coarse: Optional[List[Optional[np.ndarray]]] = None,
+            coarse2: Optional[List[Optional[np.ndarray]]] = None) -> Dict[str, torch.Tensor]:
     """Inputs (bf16 [n, N, N, IN_CH]), raw targets (f32 [n, N*N, OUT_CH])
     and fluid weights (f32 [n, N*N]) from solved cases.  With `coarse`
     (upsampled coarse solutions, or None per case) the inputs carry them and
-    the targets are the corrections to them."""
+    the targets are the corrections to them; `coarse2` (a second, coarser
+    level) is an input only."""
     X, T, Wt = [], [], []
     for k, c in enumerate(cases):
         if log and k % 2048 == 0:
@@ -161,7 +163,10 @@ def dataset(cases: List[dict], solver, log: Optional[Callable[[str], None]] = No
         base = None
         if coarse is not None and coarse[k] is not None:
             base = nn.scaled_fields(coarse[k], N, c["U"], c["Re"], c["mask"])
-        X.append(torch.tensor(nn.input_features(N, c["mask"], c["Re"], c["U"], base)))
+        base2 = None
+        if coarse2 is not None and coarse2[k] is not None:
+            base2 = nn.scaled_fields(coarse2[k], N, c["U"], c["Re"], c["mask"])
+        X.append(torch.tensor(nn.input_features(N, c["mask"], c["Re"], c["U"], base, base2)))
         f = solver.fields(FIELDS, k)
         t = nn.raw_targets(f, N, c["U"], c["Re"]).cpu()
         if base is not None:
@@ -241,20 +246,24 @@ def train(model: nn.UNet, data: Dict[str, torch.Tensor], epochs=30, batch=16, lr
 
 
 def predict(model: nn.UNet, cases: List[dict], with_grad=True, batch=16,
-            coarse: Optional[List[Optional[np.ndarray]]] = None) -> List[np.ndarray]:
+            coarse: Optional[List[Optional[np.ndarray]]] = None,
+            coarse2: Optional[List[Optional[np.ndarray]]] = None) -> List[np.ndarray]:
     """Initial fields per case from the network ([P, u, v] or
     [P, u, v, grad(4)], channel-major float64); with `coarse`, the network
-    corrects the upsampled coarse solutions it is given."""
+    corrects the upsampled coarse solutions it is given (`coarse2`: a second,
+    coarser level as further input)."""
     out = []
     dev = model.device
     for s in range(0, len(cases), batch):
         part = cases[s:s + batch]
         N = part[0]["N"]
-        bases = []
+        bases, bases2 = [], []
         for k, c in enumerate(part):
             cf = coarse[s + k] if coarse is not None else None
             bases.append(None if cf is None else nn.scaled_fields(cf, N, c["U"], c["Re"], c["mask"]))
-        X = torch.stack([torch.tensor(nn.input_features(N, c["mask"], c["Re"], c["U"], bases[k]))
+            cf2 = coarse2[s + k] if coarse2 is not None else None
+            bases2.append(None if cf2 is None else nn.scaled_fields(cf2, N, c["U"], c["Re"], c["mask"]))
+        X = torch.stack([torch.tensor(nn.input_features(N, c["mask"], c["Re"], c["U"], bases[k], bases2[k]))
                          for k, c in enumerate(part)])
         y = model.forward(nn.to_bf16(X.to(dev)))
         y = y.reshape(len(part), N, N, nn.OUT_CH).cpu().numpy()

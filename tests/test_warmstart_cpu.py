@@ -86,3 +86,25 @@ def test_upsampled_init_interpolates_and_rescales_gradients():
     assert up[1] is None
     other = WS.upsampled_init(cases, coarse, _ConstSolver([a, a]), [1, 0])
     assert other[0] is None and other[1] is not None
+
+
+def test_input_features_carry_one_or_two_coarse_levels():
+    """The coarse solutions sit in their own channel blocks, each followed by
+    a flag; absent levels leave zeros; everything fits the padded width."""
+    N = 32
+    mask = np.zeros((N, N), np.uint8)
+    mask[10:14, 8:12] = 1
+    a = np.full((N, N, nn.OUT_CH), 0.25, np.float32)
+    b = np.full((N, N, nn.OUT_CH), -0.5, np.float32)
+    k1, k2 = nn.FEATURES, nn.FEATURES + nn.COARSE_FEATURES
+    assert k2 + nn.COARSE_FEATURES <= nn.IN_CH
+    none = nn.input_features(N, mask, 100.0, 0.08)
+    one = nn.input_features(N, mask, 100.0, 0.08, coarse=a)
+    two = nn.input_features(N, mask, 100.0, 0.08, coarse=a, coarse2=b)
+    assert np.array_equal(none[..., :k1], two[..., :k1])
+    assert not none[..., k1:].any()
+    assert np.all(one[..., k1:k1 + nn.OUT_CH] == 0.25) and np.all(one[..., k1 + nn.OUT_CH] == 1.0)
+    assert not one[..., k2:].any()
+    assert np.array_equal(two[..., :k2], one[..., :k2])
+    assert np.all(two[..., k2:k2 + nn.OUT_CH] == -0.5) and np.all(two[..., k2 + nn.OUT_CH] == 1.0)
+    assert not two[..., k2 + nn.COARSE_FEATURES:].any()
