@@ -1565,15 +1565,19 @@ k_step2_batch(const BatchEntry *__restrict__ tab, const int *__restrict__ meta,
 // thread each, walking a chunk of z-planes.  A tile row is TX x (bytes per
 // value) = 128 bytes (FP32, 16-bit) or 256 bytes (FP64): whole cache lines
 // for every population plane.  The LDS copy of the intermediate state
-// f*(t+1) (see Step2ZLds) is 68 KB for FP32, 70 KB for FP64 and 35 KB for
-// the 16-bit formats (D3Q7, four sets), so two (four) blocks fit a CU's
-// 160 KB.
+// f*(t+1) (see Step2ZLds) is 68 KB for FP32, 70 KB for FP64 and 68 KB for
+// the 16-bit formats' 64 x 8 tile (D3Q7, four sets), so two blocks fit a
+// CU's 160 KB.
 // MINW: waves per SIMD the kernel is compiled for (its register budget).
-// Four blocks of the 16-bit formats fit a CU's LDS, but with the 158 VGPRs
-// the compiler would otherwise use only three fit; the four-wave budget
-// (128 VGPRs, 15 of them spilled) measured +5 % (FP16) and +8 % (BF16).
-// FP32 and FP64 are bound to two blocks per CU by their LDS.
-template <int ST> struct Fuse2Z { static constexpr int TX = 64, TY = 4, MINW = 4; };
+// The 16-bit formats take the 64 x 8 tile (a one-node ring of 28 % of the
+// tile, against 53 % for 64 x 4) only with a budget of four waves per SIMD
+// (128 VGPRs, some spilled), so that both 8-wave blocks fit a CU: at the
+// 158 VGPRs the compiler would otherwise use, one does and the tile
+// measured -13 %; with the budget it runs 3-4 % (FP16) and 2-5 % (BF16)
+// faster than the 64 x 4 tile at the same budget, itself 5 % and 8 % faster
+// than at the compiler's.  FP32 and FP64 are bound to two 4-wave blocks per
+// CU by their LDS and keep the compiler's budget.
+template <int ST> struct Fuse2Z { static constexpr int TX = 64, TY = 8, MINW = 4; };
 template <> struct Fuse2Z<MDF_F32> { static constexpr int TX = 32, TY = 8, MINW = 1; };
 template <> struct Fuse2Z<MDF_F64> { static constexpr int TX = 32, TY = 4, MINW = 1; };
 
