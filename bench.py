@@ -154,7 +154,7 @@ def summarize_trace(db_path, command):
         "select name, grid_x * grid_y * grid_z as g, count(*), sum(duration) / 1000.0, "
         "avg(duration) / 1000.0 from kernels group by name, g order by sum(duration) desc"))
     total = sum(r[3] for r in rows)
-    out = ["# rocprofv3 kernel trace", "", "Command (run from the repository root on the GPU box):", "",
+    out = ["# rocprofv3 kernel trace", "", "Command (run from the repository root on an MI355X):", "",
            "```", command, "```", "",
            "| kernel | grid (work-items) | calls | total (us) | average (us) | % |", "|---|---|---|---|---|---|"]
     for name, g, calls, tot, avg in rows:
@@ -194,7 +194,7 @@ def summarize_traffic(fetch_db, write_db, copy_fetch_db, copy_write_db, kernel_p
     fetch_b = f[kf][1] * 1024 * fetch_scale
     write_b = w[kw][1] * 1024 * write_scale
     total = fetch_b + write_b
-    md = ["# HBM traffic of `" + kernel_prefix + "`", "", "Commands (repository root, GPU box):", "", "```"]
+    md = ["# HBM traffic of `" + kernel_prefix + "`", "", "Commands (repository root, on an MI355X):", "", "```"]
     md += commands + ["```", "",
                       f"* copy calibration (256 MiB read + 256 MiB written per launch): FETCH_SIZE reads "
                       f"{cf[ck][1]:.1f} KiB (scale {fetch_scale:.4f}), WRITE_SIZE reads {cw[ck][1]:.1f} KiB "
@@ -566,7 +566,7 @@ def summarize_counters(db_paths, command, node_steps, kernel_prefix):
             acc.setdefault((k, g, cname), []).append(val)
         for (k, g, cname), v in acc.items():
             rows.setdefault(cname, []).append((len(v), statistics.mean(v), k, g))
-    out = ["# rocprofv3 counters of `" + kernel_prefix + "`", "", "Commands (repository root, GPU box):", "",
+    out = ["# rocprofv3 counters of `" + kernel_prefix + "`", "", "Commands (repository root, on an MI355X):", "",
            "```"] + command.split(" ;; ") + ["```", "",
            f"Node-steps per dispatch: {node_steps}.", "",
            "| counter | dispatches | mean per dispatch | per node-step |", "|---|---|---|---|"]
