@@ -2162,10 +2162,18 @@ hipError_t step_dispatch(const KCase &p, const CaseBufs &b, int src, bool check,
     return hipGetLastError();
 }
 
-// z-planes per block of k_step2z: long enough that the two chunk-end
-// planes cost little (2/32 of a read), short enough for several blocks per
-// resident slot on 256^3-class grids.
-inline int step2z_chunk(int nz) { return nz < 32 ? nz : 32; }
+// z-planes per block of k_step2z: 32 where the grid gives enough blocks
+// (the two chunk-end planes then cost 2/32 of a read), halved, down to 8,
+// while a launch would have fewer than 512 blocks, the two per CU that every
+// storage's LDS copy allows, so that small grids still fill the chip (at
+// 128^3, chunks of 32 planes left 128 blocks of the 16-bit tile and 256 of
+// the FP32 one).
+inline int step2z_chunk(int nz, int tiles_xy)
+{
+    int zc = nz < 32 ? nz : 32;
+    while (zc > 8 && (long long)tiles_xy * ((nz + zc - 1) / zc) < 512) zc /= 2;
+    return zc;
+}
 
 template <class L, int ST>
 hipError_t step2_dispatch(const KCase &p, const CaseBufs &b, int src, uint32_t fields, void *out, LaunchShape s,
@@ -2184,7 +2192,7 @@ hipError_t step2_dispatch(const KCase &p, const CaseBufs &b, int src, uint32_t f
         Tiling tl;
         tl.gx = (p.nx + TX - 1) / TX;
         tl.gy = (p.ny + TY - 1) / TY;
-        tl.zc = step2z_chunk(p.nz);
+        tl.zc = step2z_chunk(p.nz, tl.gx * tl.gy);
         tl.nb = tl.gx * tl.gy * ((p.nz + tl.zc - 1) / tl.zc);
         tl.groups = s.groups > 1 ? s.groups : 1;
         const bool emit_on = (fields != 0) && out != nullptr;
