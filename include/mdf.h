@@ -358,8 +358,10 @@ mdf_status mdf_autotune(mdf_ctx *ctx, int32_t trial_steps, int32_t *chosen, doub
 mdf_status mdf_graph_stats(const mdf_ctx *ctx, int64_t *stats, const char **capture_error);
 
 /* Device address and size in bytes of one population buffer of a case, in
- * the storage layout [set][direction][z][y][row pitch] (the ping-pong pair
- * of the pull scheme of eq. 3-21).  which = 0: the buffer holding the
+ * the storage layout [set][direction][z][y][row pitch]: rows padded to 128
+ * bytes, each (set, direction) plane followed by a gap of 2304 bytes (plane
+ * stride = bytes / number of planes).  The ping-pong pair is that of the pull
+ * scheme of eq. 3-21.  which = 0: the buffer holding the
  * post-collision state f*(t) that the next step reads; which = 1: the other
  * one, which the next step overwrites and from which the read calls
  * (mdf_moments, mdf_gradients, mdf_populations, mdf_check) pull f(t).  The

@@ -19,7 +19,7 @@ constexpr int kNRed = 8;
 struct KCase {
     int nx, ny, nz;
     int pitch;              // row stride of the population planes, elements
-    long long dstride;      // elements per (set, direction) plane = nz*ny*pitch
+    long long dstride;      // elements from one (set, direction) plane to the next: nz*ny*pitch and a gap
     double s0, s1, s2;
     double rho0;
     double R;

@@ -12,7 +12,8 @@
 //
 // Data layout in HBM (structure of arrays): one plane per (set a, direction i),
 //     pop[(a*Q + i) * dstride + (z*ny + y) * pitch + x],
-// x fastest, rows padded so that a row is a whole number of 128-byte lines.
+// x fastest, rows padded so that a row is a whole number of 128-byte lines,
+// planes dstride elements apart (nz*ny*pitch and a gap of 2304 bytes).
 // Two such buffers ping-pong: buffer `src` holds the post-collision state
 // f*(., t) of every node, a step pulls f_{i,a}(x, t+1) = f*_{i,a}(x - c_i, t)
 // (so every lane's loads of one plane are consecutive addresses), collides it

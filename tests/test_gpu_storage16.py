@@ -124,8 +124,10 @@ def _stored(solver, spec, storage, case=0):
     ny, nx = spec.shape[1], spec.shape[0]
     q0 = C.NQ[C.SET0_LATTICE[spec.lattice]] if spec.lattice in C.SET0_LATTICE else spec.q
     nplanes = q0 + (solver.nsets - 1) * spec.q
-    pitch = raw.numel() // (nplanes * nz * ny)
-    raw = raw.reshape(nplanes, nz, ny, pitch)[..., :nx].contiguous()
+    stride = raw.numel() // nplanes                 # a plane and the gap after it
+    pitch = (nx + 63) // 64 * 64                    # rows of whole 128-byte lines
+    assert stride >= nz * ny * pitch
+    raw = raw.reshape(nplanes, stride)[:, :nz * ny * pitch].reshape(nplanes, nz, ny, pitch)[..., :nx].contiguous()
     dt = torch.float16 if storage == "f16dev" else torch.bfloat16
     q = _planes_to_sets(spec, solver.nsets, raw.view(dt).to(torch.float32).cpu().numpy())
     rest32 = _rest(spec, (solver.nsets, spec.q) + (1,) * (spec.d)).astype(np.float32)
