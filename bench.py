@@ -482,12 +482,12 @@ def sweep(out_path):
             torch.cuda.empty_cache()
 
 
-def tgv3d_timing(storage, form, N=256, groups=8, quiet=False):
+def tgv3d_timing(storage, form, N=256, groups=8, quiet=False, bx=64, by=4):
     """The 3D Taylor-Green vortex of the precision configuration (D3Q7, four
     sets, Re 100, u0 = 0.05) at N^3: time per step of the step kernel in one
-    storage and form, HIP events, median of 5, and its per-step fraction of
-    the HBM roofline (2 x 28 values per node and step).  Returns the record
-    (and prints it unless quiet)."""
+    storage and form on bx x by threads per block, HIP events, median of
+    5, and its per-step fraction of the HBM roofline (2 x 28 values per
+    node and step).  Returns the record (and prints it unless quiet)."""
     import numpy as np
     import torch
     from paper_2108_08591_amd import cases as C
@@ -501,14 +501,14 @@ def tgv3d_timing(storage, form, N=256, groups=8, quiet=False):
     del P, u
     solver = mdf.Solver([spec], storage=storage, init=("fields", [init]), device=dev, stream=stream, u_ref=0.05)
     del init
-    solver.set_launch(64, 4, groups, form)
+    solver.set_launch(bx, by, groups, form)
     solver.step(3)
     n = 41 if form == 2 else 40
     ms = time_launches(solver, stream, n, reps=5)
     sb = {"f64": 8, "f32": 4, "f16dev": 2, "bf16dev": 2}[storage]
     mlups = spec.nodes / ms / 1e3
     rec = {"workload": f"3D Taylor-Green {N}^3, D3Q7 x 4 sets", "storage": storage, "form": form,
-           "groups": groups, "ms_per_step": round(ms, 5), "MLUPS": round(mlups, 1),
+           "groups": groups, "block": f"{bx}x{by}", "ms_per_step": round(ms, 5), "MLUPS": round(mlups, 1),
            "per_step_frac": round(mlups * 1e6 * 2 * 28 * sb / (HBM_PEAK_GBS * 1e9), 4)}
     del solver
     torch.cuda.empty_cache()
@@ -1249,9 +1249,9 @@ def main():
     ap.add_argument("--traffic-kernel", default="batch2", choices=["batch2", "step2z", "step2"],
                     help="kernel whose counters --summarize-traffic reads: the headline's batched two-step "
                          "kernel, the 3D two-step kernel, or the 1024^2 cavity's two-step kernel")
-    ap.add_argument("--tgv3d", nargs="+", metavar="STORAGE FORM [GROUPS]",
+    ap.add_argument("--tgv3d", nargs="+", metavar="STORAGE FORM [GROUPS [BX BY]]",
                     help="time the 3D Taylor-Green step kernel (256^3) in one storage and form (XCD groups, "
-                         "default 8)")
+                         "default 8; block, default 64 x 4)")
     ap.add_argument("--grid2d", nargs="+", metavar="STORAGE FORM [N [GROUPS]]",
                     help="time the 2D cavity step kernel (D2Q5 x 3 sets, default 8192^2, no emission) in one "
                          "storage and form")
@@ -1315,7 +1315,9 @@ def main():
         lattice_per_set_study(args.lattice_per_set_study)
         return
     if args.tgv3d:
-        tgv3d_timing(args.tgv3d[0], int(args.tgv3d[1]), groups=int(args.tgv3d[2]) if len(args.tgv3d) > 2 else 8)
+        tgv3d_timing(args.tgv3d[0], int(args.tgv3d[1]), groups=int(args.tgv3d[2]) if len(args.tgv3d) > 2 else 8,
+                     bx=int(args.tgv3d[3]) if len(args.tgv3d) > 4 else 64,
+                     by=int(args.tgv3d[4]) if len(args.tgv3d) > 4 else 4)
         return
     if args.grid2d:
         g = args.grid2d
@@ -1375,9 +1377,11 @@ def main():
         result["cavity1024_f32"] = cavity_leg(args, dev, stream, 1024, 4000)
         result["cavity8192_f32"] = cavity_leg(args, dev, stream, 8192, 41)
         # the 3D Taylor-Green vortex of the precision configuration at 256^3 in
-        # each storage's default form (two steps per launch for FP64 and FP32)
-        result["tgv3d256"] = {st: tgv3d_timing(st, form, groups=1, quiet=True)
-                              for st, form in (("f64", 2), ("f32", 2), ("f16dev", 0))}
+        # each storage's fastest form and block (two steps per launch for FP64
+        # and FP32; one step per launch on 128 x 2 blocks for FP16)
+        result["tgv3d256"] = {st: tgv3d_timing(st, form, groups=1, quiet=True, bx=bx, by=by)
+                              for st, form, bx, by in (("f64", 2, 64, 4), ("f32", 2, 64, 4),
+                                                       ("f16dev", 0, 128, 2))}
         result["device_copy"] = device_copy_bandwidth()
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline_batch()

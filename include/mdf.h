@@ -333,8 +333,9 @@ mdf_status mdf_set_active(mdf_ctx *ctx, const int32_t *active);
 /* Choose the launch shape of this context by timing candidate shapes
  * (vector tiles 64x4, 128x2, 256x1, 64x2, 64x1 with XCD bands and 64x4
  * without; one-node tiles 64x4, 128x2, 256x1, 128x1, 32x8 with bands and
- * 64x4 without; for D2Q5 contexts also two steps per launch with and
- * without bands) on `trial_steps` real steps each and keeping the
+ * 64x4, 128x2, 128x1 without; for lattices with axis links also two steps
+ * per launch with and without bands) on `trial_steps` real steps each and
+ * keeping the
  * fastest.  Every case advances by (trial_steps + 1) steps per candidate
  * tried (results are bitwise independent of the shape).  chosen: host
  * int[4] (bx, by, groups, form) or NULL; best_ms: host double, time per

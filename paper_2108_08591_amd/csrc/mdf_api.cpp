@@ -968,7 +968,7 @@ mdf_status mdf_autotune(mdf_ctx *ctx, int32_t trial_steps, int32_t *chosen, doub
     static const int cand[][4] = {{64, 4, 8, 1}, {128, 2, 8, 1}, {256, 1, 8, 1}, {64, 2, 8, 1},
                                   {64, 1, 8, 1}, {64, 4, 1, 1}, {64, 4, 8, 0}, {128, 2, 8, 0},
                                   {256, 1, 8, 0}, {64, 4, 1, 0}, {128, 1, 8, 0}, {32, 8, 8, 0},
-                                  {128, 2, 8, 2}, {64, 4, 1, 2}};
+                                  {128, 2, 1, 0}, {128, 1, 1, 0}, {128, 2, 8, 2}, {64, 4, 1, 2}};
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
