@@ -482,12 +482,13 @@ def sweep(out_path):
             torch.cuda.empty_cache()
 
 
-def tgv3d_timing(storage, form, N=256, groups=8, quiet=False, bx=64, by=4):
+def tgv3d_timing(storage, form, N=256, groups=8, quiet=False, bx=64, by=4, tune=False):
     """The 3D Taylor-Green vortex of the precision configuration (D3Q7, four
     sets, Re 100, u0 = 0.05) at N^3: time per step of the step kernel in one
-    storage and form on bx x by threads per block, HIP events, median of
-    5, and its per-step fraction of the HBM roofline (2 x 28 values per
-    node and step).  Returns the record (and prints it unless quiet)."""
+    storage and form on bx x by threads per block (tune: the form and
+    shape mdf_autotune picks instead), HIP events, median of 5, and its
+    per-step fraction of the HBM roofline (2 x 28 values per node and
+    step).  Returns the record (and prints it unless quiet)."""
     import numpy as np
     import torch
     from paper_2108_08591_amd import cases as C
@@ -501,7 +502,10 @@ def tgv3d_timing(storage, form, N=256, groups=8, quiet=False, bx=64, by=4):
     del P, u
     solver = mdf.Solver([spec], storage=storage, init=("fields", [init]), device=dev, stream=stream, u_ref=0.05)
     del init
-    solver.set_launch(bx, by, groups, form)
+    if tune:
+        bx, by, groups, form = solver.autotune(trial_steps=20)[0]
+    else:
+        solver.set_launch(bx, by, groups, form)
     solver.step(3)
     n = 41 if form == 2 else 40
     ms = time_launches(solver, stream, n, reps=5)
@@ -1377,11 +1381,8 @@ def main():
         result["cavity1024_f32"] = cavity_leg(args, dev, stream, 1024, 4000)
         result["cavity8192_f32"] = cavity_leg(args, dev, stream, 8192, 41)
         # the 3D Taylor-Green vortex of the precision configuration at 256^3 in
-        # each storage's fastest form and block (two steps per launch for FP64
-        # and FP32; one step per launch on 128 x 2 blocks for FP16)
-        result["tgv3d256"] = {st: tgv3d_timing(st, form, groups=1, quiet=True, bx=bx, by=by)
-                              for st, form, bx, by in (("f64", 2, 64, 4), ("f32", 2, 64, 4),
-                                                       ("f16dev", 0, 128, 2))}
+        # each storage, in the form and launch shape the autotuner picks
+        result["tgv3d256"] = {st: tgv3d_timing(st, None, quiet=True, tune=True) for st in ("f64", "f32", "f16dev")}
         result["device_copy"] = device_copy_bandwidth()
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline_batch()
