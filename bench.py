@@ -450,8 +450,8 @@ def sweep(out_path):
     for N in (128, 256, 384):
         for st in ("f32", "f64", "f16dev", "bf16dev"):
             runs.append(("d3q7", N, st))
-    shapes = [(64, 4, 8, 1), (128, 2, 8, 1), (256, 1, 8, 1), (64, 2, 8, 1), (64, 4, 8, 0), (128, 2, 8, 0),
-              (256, 1, 8, 0), (128, 2, 8, 2), (128, 2, 1, 2)]
+    shapes = [(64, 4, 8, 1), (128, 2, 8, 1), (256, 1, 8, 1), (64, 2, 8, 1), (128, 2, 1, 1), (64, 4, 8, 0),
+              (128, 2, 8, 0), (256, 1, 8, 0), (64, 4, 1, 0), (128, 2, 1, 0), (128, 2, 8, 2), (128, 2, 1, 2)]
     with open(out_path, "w") as fh:
         for lat, N, st in runs:
             if lat == "d2q5":
