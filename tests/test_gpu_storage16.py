@@ -126,7 +126,7 @@ def _stored(solver, spec, storage, case=0):
     nplanes = q0 + (solver.nsets - 1) * spec.q
     stride = raw.numel() // nplanes                 # a plane and the gap after it
     pitch = (nx + 63) // 64 * 64                    # rows of whole 128-byte lines
-    assert stride >= nz * ny * pitch
+    assert raw.numel() % nplanes == 0 and stride == nz * ny * pitch + 2304 // 2
     raw = raw.reshape(nplanes, stride)[:, :nz * ny * pitch].reshape(nplanes, nz, ny, pitch)[..., :nx].contiguous()
     dt = torch.float16 if storage == "f16dev" else torch.bfloat16
     q = _planes_to_sets(spec, solver.nsets, raw.view(dt).to(torch.float32).cpu().numpy())
