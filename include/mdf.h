@@ -285,7 +285,8 @@ mdf_status mdf_invariants(const mdf_ctx *ctx, int32_t case_id, double *out, void
  *      bx, by; batched 3D contexts run every step as form 0.
  * The read kernels always use one node per thread.  Default 64 x 4, 8
  * groups, form 2 on the axis-link lattices (in 3D with FP64 and FP32
- * storage) and form 0 elsewhere.
+ * storage) and form 0 elsewhere; 3D axis-link lattices with 16-bit storage
+ * default to 128 x 2, one group, form 0.
  * MDF_EINVAL otherwise (also forms 1 and 2 on D2Q9 / D3Q15).  Any shape
  * and form give bitwise identical populations and fields; only the
  * summation order of the FP64 sums of mdf_check, mdf_run_steady and

@@ -645,6 +645,14 @@ mdf_status mdf_init(mdf_ctx **out, mdf_lattice lattice, mdf_storage storage, con
     mdf_ctx *ctx = new mdf_ctx;
     ctx->lattice = lattice;
     ctx->shape.fuse = lat_fused_default(lattice, storage) ? 1 : 0;
+    if (!lat_2d(lattice) && !lat_diag(lattice) && (storage == MDF_F16DEV || storage == MDF_BF16DEV)) {
+        // one step per launch in 3D: 128 x 2 blocks without XCD bands ran
+        // 0-3 % faster than 64 x 4 with bands at 128^3 and 9-12 % at 256^3
+        // and 384^3 (D3Q7, FP16 and BF16)
+        ctx->shape.bx = 128;
+        ctx->shape.by = 2;
+        ctx->shape.groups = 1;
+    }
     ctx->storage = storage;
     ctx->d = lat_d(lattice);
     ctx->q = lat_q(lattice);
